@@ -1,0 +1,379 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the printed
+gamma matrices and their algebra, dense brute-force matrices assembled from
+the definitions (eq. (eo0); eqs. (DW)/(covariant); the literal twisted
+boundary condition), free-field closed forms, plane waves, gamma_5
+hermiticity, gauge covariance, the kappa = 0 limit, and a dense linear solve.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import dense
+
+THETA_AP = np.array([1.0, 0.0, 0.0, 0.0])  # antiperiodic in time
+THETA_GEN = np.array([1.0, 0.3, -0.7, 0.45])  # generic twisted boundary phases
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+# ----------------------------------------------------------------- gammas
+
+
+def test_gammas_match_appendix_A():
+    g = oracle.gammas()
+    assert np.array_equal(g, dense.G)
+
+
+def test_gamma_algebra():
+    g = dense.G
+    for m in range(4):
+        assert np.allclose(g[m], g[m].conj().T)  # Hermitian
+        for n in range(4):
+            ac = g[m] @ g[n] + g[n] @ g[m]
+            assert np.allclose(ac, 2 * (m == n) * np.eye(4))
+        assert np.allclose(g[4] @ g[m] + g[m] @ g[4], 0)
+    assert np.allclose(g[0] @ g[1] @ g[2] @ g[3], g[4])  # gamma_5 = gamma_0 gamma_1 gamma_2 gamma_3
+
+
+# --------------------------------------------------------------- geometry
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 6, 2, 4), (8, 4, 4, 6)])
+def test_odd_sites(dims):
+    odd = oracle.odd_sites(dims)
+    V = int(np.prod(dims))
+    assert len(odd) == V // 2
+    assert np.all(np.diff(odd) > 0)
+    assert np.all(dense.parities(dims)[odd] == 1)
+    # with LX even, consecutive (x even, x odd) pairs hold one site of each parity,
+    # so the k-th odd site is at index 2k or 2k+1
+    assert np.array_equal(odd >> 1, np.arange(V // 2))
+
+
+# ------------------------------------------------------- dense operators
+
+SMALL = [(2, 2, 2, 2), (4, 6, 2, 4)]
+
+
+@pytest.fixture(scope="module", params=SMALL, ids=lambda d: "x".join(map(str, d)))
+def small_case(request):
+    dims = request.param
+    U = synth.random_gauge(dims, eps=0.6, seed=11)
+    return dims, U
+
+
+def _oracle_M_dense(U, kappa, mut, sign, theta):
+    dims = U.shape[:4]
+    n = 12 * int(np.prod(dims))
+    return dense.dense_of(lambda v: oracle.M(U, v, kappa, mut, sign, theta), n, dims + (4, 3))
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_M_matches_eo0_assembly(small_case, sign):
+    dims, U = small_case
+    A = _oracle_M_dense(U, 0.17, 0.05, sign, THETA_GEN)
+    B = dense.M_hopping(U, 0.17, 0.05, sign, THETA_GEN)
+    assert rel(A, B) < 1e-14
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_M_matches_covariant_wilson_form(small_case, sign):
+    """eq. (eo0) = gamma_5 [2 kappa (D_W + m0) + i mut g5] gamma_5 with D_W from eq. (DW)."""
+    dims, U = small_case
+    kappa, mut = 0.13, 0.07
+    A = _oracle_M_dense(U, kappa, mut, sign, THETA_GEN)
+    B = dense.M_covariant(U, kappa, mut, sign, THETA_GEN)
+    V = int(np.prod(dims))
+    g5 = np.kron(np.eye(V), np.kron(dense.G5, dense.I3))
+    assert rel(A, g5 @ B @ g5) < 1e-13
+
+
+def test_spread_phase_equals_twisted_boundary_condition(small_case):
+    """The per-hop phase is the BC psi(x+L) = e^{i theta pi} psi(x) after a site-diagonal unitary."""
+    dims, U = small_case
+    A = _oracle_M_dense(U, 0.15, 0.02, +1, THETA_GEN)
+    B = dense.M_hopping(U, 0.15, 0.02, +1, THETA_GEN, mode="boundary")
+    w = dense.boundary_gauge_transform(dims, THETA_GEN)
+    assert rel(A, (w.conj()[:, None] * B) * w[None, :]) < 1e-14
+    # and the phase is not trivially absent: with theta = 0 the operator differs
+    C = _oracle_M_dense(U, 0.15, 0.02, +1, np.zeros(4))
+    assert rel(A, C) > 1e-3
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_Qhat_matches_dense_schur_complement(small_case, sign):
+    dims, U = small_case
+    kappa, mut = 0.16, 0.03
+    V = int(np.prod(dims))
+    A = dense.dense_of(lambda v: oracle.Qhat(U, v, kappa, mut, sign, THETA_GEN), 6 * V, (V // 2, 4, 3))
+    M = dense.M_hopping(U, kappa, mut, sign, THETA_GEN)
+    B = dense.schur_Qhat(M, dims)
+    assert rel(A, B) < 1e-13
+
+
+def test_Q_full_is_gamma5_M(small_case):
+    dims, U = small_case
+    psi = synth.gaussian_spinor(dims + (4, 3), seed=5)
+    a = oracle.Q(U, psi, 0.16, 0.01, -1, THETA_AP)
+    b = oracle.M(U, psi, 0.16, 0.01, -1, THETA_AP)
+    b[..., 2:, :] *= -1
+    assert rel(a, b) == 0.0
+
+
+# -------------------------------------------------------------- free field
+
+
+def _momenta(dims, theta):
+    L = dense.extents(dims)
+    grids = np.meshgrid(*[(2 * np.pi * np.arange(L[m]) + theta[m] * np.pi) / L[m] for m in range(4)],
+                        indexing="ij")
+    return np.stack([g.ravel() for g in grids], axis=1)  # (V, 4) over mu = t, x, y, z
+
+
+@pytest.mark.parametrize("dims", [(4, 6, 2, 4), (6, 4, 4, 2)])
+def test_free_plane_waves(dims):
+    """U = 1: H e^{iqx} u = sum_mu (2 cos p_mu + 2 i gamma_mu sin p_mu) e^{iqx} u, p = q + theta pi / L."""
+    U = synth.unit_gauge(dims)
+    L = dense.extents(dims)
+    c = dense.site_coords(dims)
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        n = np.array([rng.integers(0, L[m]) for m in range(4)])
+        q = 2 * np.pi * n / L
+        p = q + THETA_GEN * np.pi / L
+        u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+        wave = np.exp(1j * (c @ q))
+        psi = (wave[:, None, None] * u[None]).reshape(dims + (4, 3))
+        h = sum(2 * np.cos(p[m]) * np.eye(4) + 2j * np.sin(p[m]) * dense.G[m] for m in range(4))
+        expect = (wave[:, None, None] * (h @ u)[None]).reshape(dims + (4, 3))
+        assert rel(oracle.hop(U, psi, THETA_GEN), expect) < 1e-14
+
+
+def test_free_field_M_spectrum():
+    """Eigenvalues a(p) +- i sqrt(sum_mu b_mu^2 + mut^2), a = 1 - 2k sum cos p, b = 2k sin p."""
+    dims = (4, 2, 2, 4)
+    kappa, mut = 0.16, 0.05
+    U = synth.unit_gauge(dims)
+    A = _oracle_M_dense(U, kappa, mut, +1, THETA_GEN)
+    p = _momenta(dims, THETA_GEN)
+    a = 1 - 2 * kappa * np.cos(p).sum(axis=1)
+    w = np.sqrt((2 * kappa * np.sin(p)) ** 2 @ np.ones(4) + mut ** 2)
+    expect = np.concatenate([np.repeat(a + 1j * w, 6), np.repeat(a - 1j * w, 6)])
+    got = np.linalg.eigvals(A)
+
+    def canon(z):
+        return z[np.lexsort((np.round(z.imag, 8), np.round(z.real, 8)))]
+
+    assert np.max(np.abs(canon(got) - canon(expect))) < 1e-12
+
+
+def qq_free_eigenvalues(dims, kappa, mut, theta):
+    """Closed form of the Qhat^+Qhat^- spectrum for U = 1 (each momentum of the full zone 6-fold)."""
+    p = _momenta(dims, theta)
+    c = 2 * np.cos(p).sum(axis=1)
+    s2 = 4 * (np.sin(p) ** 2).sum(axis=1)
+    d = 1 + mut ** 2
+    alpha = 1 - kappa ** 2 * (c ** 2 - s2) / d
+    beta = mut * (1 + kappa ** 2 * (c ** 2 + s2) / d)
+    delta = 2 * kappa ** 2 * c / d
+    return np.repeat(alpha ** 2 + beta ** 2 + delta ** 2 * s2, 6)
+
+
+def test_free_field_QhatQhat_spectrum():
+    dims = (4, 4, 4, 4)
+    kappa, mut = 0.1632, 0.004
+    U = synth.unit_gauge(dims)
+    n = 6 * int(np.prod(dims))
+    A = dense.dense_of(lambda v: oracle.QhatQhat(U, v, kappa, mut, THETA_AP), n, (n // 12, 4, 3))
+    assert np.allclose(A, A.conj().T, atol=1e-14)
+    got = np.sort(np.linalg.eigvalsh(A))
+    expect = np.sort(qq_free_eigenvalues(dims, kappa, mut, THETA_AP))
+    assert np.max(np.abs(got - expect)) < 1e-13
+
+
+# ------------------------------------------------------------- invariants
+
+
+def test_gamma5_hermiticity_dense(small_case):
+    dims, U = small_case
+    A = _oracle_M_dense(U, 0.16, 0.04, +1, THETA_GEN)
+    B = _oracle_M_dense(U, 0.16, 0.04, -1, THETA_GEN)
+    V = int(np.prod(dims))
+    g5 = np.kron(np.eye(V), np.kron(dense.G5, dense.I3))
+    assert rel(g5 @ A @ g5, B.conj().T) < 1e-15
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 6, 4)])
+def test_Qhat_adjoint(dims):
+    """(Qhat^+)^dagger = Qhat^-: <y, Qhat^+ x> = <Qhat^- y, x>."""
+    U = synth.random_gauge(dims, seed=21)
+    x = synth.gaussian_odd(dims, seed=1)
+    y = synth.gaussian_odd(dims, seed=2)
+    kappa, mut = 0.1632, 0.004
+    lhs = np.vdot(y, oracle.Qhat(U, x, kappa, mut, +1, THETA_AP))
+    rhs = np.vdot(oracle.Qhat(U, y, kappa, mut, -1, THETA_AP), x)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-13
+    # Qhat itself is not Hermitian
+    lhs2 = np.vdot(y, oracle.Qhat(U, x, kappa, mut, -1, THETA_AP))
+    assert abs(lhs - lhs2) / abs(lhs) > 1e-6
+
+
+def _colour(Om, psi):
+    return np.einsum("sab,sib->sia", Om, psi)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 2, 6), (4, 4, 4, 4)])
+def test_gauge_covariance(dims):
+    """U -> Om(x) U(x,mu) Om(x+mu)^+, psi -> Om psi: M[U^Om] Om psi = Om M[U] psi; same for Qhat."""
+    U = synth.random_gauge(dims, seed=31)
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(32)
+    Om = synth.random_su3(V, 1.5, rng)
+    c = dense.site_coords(dims)
+    L = dense.extents(dims)
+    Ug = np.empty_like(U).reshape(V, 4, 3, 3)
+    Uf = U.reshape(V, 4, 3, 3)
+    for mu in range(4):
+        cn = c.copy()
+        cn[:, mu] = (cn[:, mu] + 1) % L[mu]
+        fwd = dense.site_index(dims, cn)
+        Ug[:, mu] = Om @ Uf[:, mu] @ Om[fwd].conj().transpose(0, 2, 1)
+    Ug = Ug.reshape(U.shape)
+    psi = synth.gaussian_spinor((V, 4, 3), seed=33)
+    a = oracle.M(Ug, _colour(Om, psi).reshape(dims + (4, 3)), 0.16, 0.01, +1, THETA_GEN)
+    b = _colour(Om, oracle.M(U, psi.reshape(dims + (4, 3)), 0.16, 0.01, +1, THETA_GEN).reshape(V, 4, 3))
+    assert rel(a.reshape(V, 4, 3), b) < 1e-14
+    odd = oracle.odd_sites(dims)
+    po = synth.gaussian_odd(dims, seed=34)
+    a = oracle.Qhat(Ug, _colour(Om[odd], po), 0.1632, 0.004, -1, THETA_AP)
+    b = _colour(Om[odd], oracle.Qhat(U, po, 0.1632, 0.004, -1, THETA_AP))
+    assert rel(a, b) < 1e-14
+
+
+def test_kappa_zero():
+    """kappa = 0: Qhat^+Qhat^- = (1 + mut^2) 1, so CG converges in one step to b/(1+mut^2)."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_gauge(dims, seed=41)
+    b = synth.gaussian_odd(dims, seed=42)
+    mut = 0.3
+    assert rel(oracle.QhatQhat(U, b, 0.0, mut, THETA_AP), (1 + mut ** 2) * b) < 1e-15
+    x, info = oracle.cg(U, b, 0.0, mut, THETA_AP, tol=1e-12)
+    assert info["converged"] and info["iters"] == 1
+    assert rel(x, b / (1 + mut ** 2)) < 1e-14  # alpha carries the rounding of two sums over 1536 terms
+
+
+def test_mee_inverse_closed_form():
+    """eq. (eo3): (1 +- i mut g5)^{-1} = (1 -+ i mut g5) / (1 + mut^2)."""
+    for mut in (0.004, 0.3, 2.0):
+        for s in (+1, -1):
+            A = np.eye(4) + 1j * s * mut * dense.G5
+            B = (np.eye(4) - 1j * s * mut * dense.G5) / (1 + mut ** 2)
+            assert np.allclose(A @ B, np.eye(4), atol=1e-15)
+
+
+# --------------------------------------------------------------------- CG
+
+
+def test_cg_matches_dense_solve():
+    dims = (2, 2, 2, 2)
+    U = synth.random_gauge(dims, seed=51)
+    kappa, mut = 0.1632, 0.004
+    n = 6 * 16
+    A = dense.dense_of(lambda v: oracle.QhatQhat(U, v, kappa, mut, THETA_AP), n, (8, 4, 3))
+    b = synth.gaussian_odd(dims, seed=52)
+    xs = np.linalg.solve(A, b.ravel())
+    ev = np.linalg.eigvalsh(A)
+    x, info = oracle.cg(U, b, kappa, mut, THETA_AP, tol=1e-10, history=True)
+    assert info["converged"]
+    assert rel(x.ravel(), xs) <= (ev[-1] / ev[0]) * 1e-10
+    # Ritz values of the Lanczos matrix built from the CG coefficients lie inside
+    # the spectrum and the largest one reaches lambda_max
+    a, bt = info["alpha"], info["beta"]
+    k = len(a)
+    T = np.zeros((k, k))
+    for i in range(k):
+        T[i, i] = 1 / a[i] + (bt[i - 1] / a[i - 1] if i else 0.0)
+        if i + 1 < k:
+            T[i, i + 1] = T[i + 1, i] = np.sqrt(bt[i]) / a[i]
+    ritz = np.linalg.eigvalsh(T)
+    assert ritz.min() >= ev[0] * (1 - 1e-8) and ritz.max() <= ev[-1] * (1 + 1e-8)
+    # CG stops once the residual is small, so the extreme Ritz values are close but not exact
+    assert abs(ritz.max() - ev[-1]) / ev[-1] < 1e-3
+    assert abs(ritz.min() - ev[0]) / ev[0] < 1e-2
+
+
+def test_cg_full_operator_4444():
+    """Plain FP64 full-lattice Q^+Q^- solve on 4^4, kappa 0.16, 2 kappa mu 0.01, tol 1e-10."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_gauge(dims, seed=1000)
+    b = synth.gaussian_spinor(dims + (4, 3), seed=2000).reshape(-1, 4, 3)
+    x, info = oracle.cg(U, b, 0.16, 0.01, THETA_AP, eo=False, tol=1e-10)
+    assert info["converged"]
+    assert oracle.true_residual(U, b, x, 0.16, 0.01, THETA_AP, eo=False) < 2e-10
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 4, 4)])
+def test_cg_free_field_terminates(dims):
+    """In exact arithmetic CG stops after at most as many steps as A has distinct eigenvalues."""
+    kappa, mut = 0.1632, 0.004
+    U = synth.unit_gauge(dims)
+    b = synth.gaussian_odd(dims, seed=61)
+    ndist = len(np.unique(np.round(qq_free_eigenvalues(dims, kappa, mut, THETA_AP), 10)))
+    x, info = oracle.cg(U, b, kappa, mut, THETA_AP, tol=1e-10)
+    assert info["converged"] and info["iters"] <= ndist + 1
+    assert oracle.true_residual(U, b, x, kappa, mut, THETA_AP) < 2e-10
+
+
+def test_cg_eo_residual_and_max_iter():
+    dims = (8, 4, 4, 4)
+    U = synth.random_gauge(dims, seed=71)
+    b = synth.gaussian_odd(dims, seed=72)
+    x, info = oracle.cg(U, b, 0.1632, 0.004, THETA_AP, tol=1e-10)
+    assert info["converged"] and 20 < info["iters"] < 80
+    assert oracle.true_residual(U, b, x, 0.1632, 0.004, THETA_AP) < 2e-10
+    x2, info2 = oracle.cg(U, b, 0.1632, 0.004, THETA_AP, tol=1e-10, max_iter=3)
+    assert not info2["converged"] and info2["iters"] == 3
+
+
+# -------------------------------------------------------------- generators
+
+
+def test_su3_generator():
+    rng = np.random.default_rng(81)
+    U = synth.random_su3(20000, 0.3, rng)
+    eye = np.eye(3)
+    assert np.max(np.abs(U @ U.conj().transpose(0, 2, 1) - eye)) < 1e-14
+    assert np.max(np.abs(np.linalg.det(U) - 1)) < 1e-14
+    # <Re tr U>/3 ~ 1 - eps^2 <tr H^2>/6 = 1 - 0.09 * 4 / 6 = 0.94 (to O(eps^4))
+    m = np.mean(np.real(np.trace(U, axis1=1, axis2=2))) / 3
+    assert abs(m - 0.941) < 0.003
+
+
+# ------------------------------------------------------------------- codec
+
+
+@pytest.mark.parametrize("kind", ["fp16", "bf16"])
+def test_codec_reference(kind):
+    import torch
+
+    psi = synth.gaussian_odd((4, 4, 4, 4), seed=91) * np.exp(np.random.default_rng(1).normal(size=(128, 1, 1)))
+    psi[3] = 0
+    codes, scale = oracle.encode_site_scaled(psi, kind)
+    # the rounding agrees with torch's FP32 -> FP16 / BF16 conversion (RNE)
+    re = psi.reshape(-1, 12).view(np.float64).reshape(-1, 24)
+    s = np.where(scale > 0, scale.astype(np.float64), 1.0)
+    y = torch.from_numpy((re / s[:, None]).astype(np.float32))
+    tdt = torch.float16 if kind == "fp16" else torch.bfloat16
+    ref = y.to(tdt).view(torch.int16).numpy().view(np.uint16)
+    ref[3] = 0
+    assert np.array_equal(codes, ref)
+    back = oracle.decode_site_scaled(codes, scale, kind)
+    bound = 2.0 ** (-11 if kind == "fp16" else -8)
+    err = np.abs(back.reshape(-1, 12).view(np.float64).reshape(-1, 24) - re)
+    assert np.all(err <= bound * scale[:, None] * (1 + 1e-6))
+    assert scale[3] == 0 and np.all(back[3] == 0)
