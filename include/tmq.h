@@ -1,0 +1,202 @@
+/*
+ * tmq.h -- C ABI of the MI355X (gfx950) twisted-mass Dirac operator and CG library.
+ *
+ * The library applies the even/odd preconditioned Wilson twisted-mass operator
+ * and solves the normal equations with it, as stated in the paper by Jansen and
+ * Urbach ("tmLQCD", Comput. Phys. Commun. 180 (2009)), Appendix B:
+ *
+ *   M^{+-}      = (1 +- i mut gamma_5) - kappa H                 eq. (eo0), mut = 2 kappa mu
+ *   (H psi)(x)  = sum_mu [ e^{ i theta_mu pi/L_mu} U(x,mu)      (1 + gamma_mu) psi(x+mu)
+ *                        + e^{-i theta_mu pi/L_mu} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu) ]
+ *                (hopping term; boundary phase spread over every hop, Sec. 4.1.2)
+ *   Q^{+-}      = gamma_5 M^{+-}                                 eq. (eo1)
+ *   Qhat^{+-}   = gamma_5 [ (1 +- i mut g5) - kappa^2/(1+mut^2) H_oe (1 -+ i mut g5) H_eo ]
+ *                on the odd sites                                 eqs. (eo3), (eo4)
+ *   solve         Qhat^+ Qhat^- x = b  (Qhat^- applied first) by CG, Sec. 4.4
+ *
+ * Gamma matrices are those of Appendix A (gamma_5 = diag(1,1,-1,-1)); mu = 0:t,
+ * 1:x, 2:y, 3:z.  theta_mu = 1 is antiperiodic, psi(x + L_mu) = e^{i theta_mu pi} psi(x)
+ * (Sec. 2.4).
+ *
+ * ---------------------------------------------------------------- layouts
+ * All fields crossing this boundary are little-endian complex128 (pairs of
+ * double: real, imaginary), C order, in the canonical site order
+ *   site = ((t*LZ + z)*LY + y)*LX + x,  dims[4] = {T, LZ, LY, LX}, all even,
+ * which is the index order of the paper's propagator files (Sec. 4.7):
+ *   gauge field      [site][mu][row][col]        4*9*V complex
+ *   full spinor      [site][spin][colour]        12*V complex
+ *   odd-site spinor  [k][spin][colour]           12*V/2 complex, k-th odd site
+ *                                                 ((t+x+y+z) odd) in site order
+ * Functions ending in _dev take DEVICE pointers (e.g. torch tensors' data_ptr()
+ * on the lattice's device) and a hipStream_t passed as void* (NULL = the
+ * default stream); work is ordered on that stream and the call returns once it
+ * is enqueued unless stated otherwise.  The other functions take HOST pointers
+ * and return when the result is in host memory.
+ *
+ * ------------------------------------------------------------- ownership
+ * The caller owns every buffer it passes; the library only reads inputs and
+ * writes outputs for the duration of the call (for _dev calls: until the work
+ * enqueued on the stream has run).  tmq_load_gauge* copies the field: the
+ * caller may free it afterwards.  A tmq_lattice owns its resident gauge copies
+ * and solver work space; tmq_lattice_destroy frees them.  One lattice object
+ * must not be used from two host threads at once.
+ *
+ * ---------------------------------------------------------------- errors
+ * Every int-returning call returns TMQ_OK (0) or a negative tmq_status; it
+ * never throws or aborts.  tmq_last_error() returns a message for the last
+ * failure on the calling thread.
+ */
+#ifndef TMQ_H
+#define TMQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tmq_lattice tmq_lattice;
+
+typedef enum {
+    TMQ_OK = 0,
+    TMQ_EINVAL = -1,  /* bad argument: odd or non-positive extent, NULL pointer, bad enum */
+    TMQ_ENOMEM = -2,  /* device allocation failed, or footprint above a server budget */
+    TMQ_ENOCONV = -3, /* max_iter reached; x holds the last iterate, info the true residual */
+    TMQ_EDEVICE = -4, /* a HIP runtime call failed */
+    TMQ_ENAN = -5,    /* a non-finite value appeared in the solver */
+    TMQ_ESTATE = -6   /* call out of order, e.g. apply before any gauge field was loaded */
+} tmq_status;
+
+/* storage precision of spinors / links on the device; arithmetic is FP64 for
+ * TMQ_FP64 and FP32 otherwise.  FP16/BF16 spinors carry one FP32 scale per
+ * site (scale = largest |real or imaginary part| of the site's 24 reals). */
+typedef enum { TMQ_FP64 = 0, TMQ_FP32 = 1, TMQ_FP16 = 2, TMQ_BF16 = 3 } tmq_prec;
+
+typedef struct {
+    double kappa;    /* hopping parameter */
+    double mu_tilde; /* mut = 2 kappa mu */
+    double theta[4]; /* boundary phases along t, x, y, z (1 = antiperiodic) */
+} tmq_params;
+
+typedef struct {
+    double tol;          /* stop when ||b - A x|| <= tol * ||b|| (relative) or <= tol (absolute),
+                            judged on the FP64 true residual (Sec. 4.4) */
+    int relative;        /* 1: relative criterion, 0: absolute */
+    int max_iter;        /* bound on CG iterations (all precisions together); <= 0: 10000 */
+    tmq_prec sloppy;     /* TMQ_FP64: plain FP64 CG.  FP32/FP16/BF16: mixed precision, the
+                            inner CG runs FP32 arithmetic on this spinor storage */
+    tmq_prec sloppy_link;/* inner link storage, TMQ_FP32 or TMQ_FP16 (two-row); ignored for FP64 */
+    double delta;        /* mixed precision: recompute the FP64 true residual whenever the
+                            iterated residual fell by this factor (0 < delta < 1); <= 0: default */
+} tmq_solver_opts;
+
+typedef struct {
+    int status;               /* same value the call returned */
+    int iters;                /* CG iterations (inner iterations for mixed precision) */
+    int reliable_updates;     /* FP64 true-residual recomputations inside the solve */
+    double true_rel_residual; /* ||b - A x|| / ||b|| in FP64 at exit */
+    double seconds;           /* wall time of the call (host clock, includes waiting) */
+} tmq_solve_info;
+
+/* ---------------------------------------------------------------- setup */
+
+/* Create a lattice of extents dims = {T, LZ, LY, LX} (each even, >= 2) on HIP
+ * device `device`.  *out receives the handle.  TMQ_EINVAL for bad extents,
+ * TMQ_EDEVICE if the device cannot be used. */
+int tmq_lattice_create(const int dims[4], int device, tmq_lattice **out);
+
+/* Free every device allocation of the lattice.  NULL is allowed. */
+void tmq_lattice_destroy(tmq_lattice *lat);
+
+/* Load a gauge field (canonical complex128 [site][mu][3][3], periodic in every
+ * direction, Sec. 2.4) and build the device copies sorted for the operator:
+ * per (parity, direction) structure-of-arrays, FP64 full links, and two-row
+ * FP64/FP32/FP16 copies when the links are SU(3) to within 1e-12 (the third
+ * row is rebuilt as conj(row0 x row1) in the kernels).  This is the paper's
+ * "double copy of the gauge field sorted in access order" (Sec. 4.1).  The
+ * boundary phases are never folded into the links. */
+int tmq_load_gauge(tmq_lattice *lat, const double *U_host);
+int tmq_load_gauge_dev(tmq_lattice *lat, const double *U_dev, void *stream);
+
+/* 1 if the loaded links passed the SU(3) check (two-row storage in use). */
+int tmq_gauge_is_su3(const tmq_lattice *lat);
+
+/* ------------------------------------------------------------ operators */
+
+/* out_odd = Qhat^{sign} in_odd (sign = +1 or -1), odd-site fields.  prec
+ * selects the device storage: TMQ_FP64 (FP64 arithmetic, two-row FP64 links
+ * when SU(3)), or FP32/FP16/BF16 spinors with FP32 arithmetic and FP32
+ * (prec = FP32) or FP16 (prec = FP16/BF16) two-row links; the input is
+ * encoded to that storage and the result decoded back to complex128.
+ * in and out must not overlap. */
+int tmq_apply_Qhat(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec,
+                   const double *in_odd, double *out_odd);
+int tmq_apply_Qhat_dev(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec,
+                       const double *in_odd, double *out_odd, void *stream);
+
+/* out_odd = Qhat^+ Qhat^- in_odd in FP64. */
+int tmq_apply_QhatQhat_dev(tmq_lattice *lat, const tmq_params *p, const double *in_odd,
+                           double *out_odd, void *stream);
+
+/* out = Q^{sign} in = gamma_5 M^{sign} in on the full lattice (eq. (eo1)), FP64,
+ * full-lattice canonical spinors. */
+int tmq_apply_Q_full(tmq_lattice *lat, const tmq_params *p, int sign, const double *in, double *out);
+int tmq_apply_Q_full_dev(tmq_lattice *lat, const tmq_params *p, int sign, const double *in,
+                         double *out, void *stream);
+
+/* --------------------------------------------------------------- solves */
+
+/* Solve Qhat^+ Qhat^- x = b on the odd sites, x_0 = 0.  opts->sloppy = TMQ_FP64
+ * runs textbook FP64 CG; a lower precision runs CG with FP32 arithmetic on
+ * reduced-precision storage and recomputes the residual b - A x in FP64 (and
+ * folds the accumulated correction into the FP64 x) whenever the iterated
+ * residual has dropped by opts->delta (the paper's reduced-precision CG with a
+ * true-residual check, Sec. 4.4).  Returns TMQ_OK when the FP64 true residual
+ * meets opts->tol, TMQ_ENOCONV after opts->max_iter iterations, TMQ_ENAN on a
+ * non-finite value.  info may be NULL.  The _dev form synchronises the stream
+ * before returning (the iteration is steered from the host). */
+int tmq_solve(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts,
+              const double *b_odd, double *x_odd, tmq_solve_info *info);
+int tmq_solve_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts,
+                  const double *b_odd, double *x_odd, void *stream, tmq_solve_info *info);
+
+/* Solve Q^+ Q^- x = b on the full lattice (no even/odd preconditioning) by FP64 CG.
+ * Full-lattice canonical spinors; x_0 = 0. */
+int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts,
+                       const double *b, double *x, void *stream, tmq_solve_info *info);
+
+/* ---------------------------------------------------------- diagnostics */
+
+/* Per-kernel timing with HIP events recorded on the launch stream around each
+ * launch of the named kernel family ("hop" = every hopping half-sweep), off by
+ * default.  tmq_kernel_stats returns the number of timed launches, their total
+ * time in ms, and the algorithmic bytes and flops they move (each input
+ * spinor, link and output counted once; 1320 flop per output site per
+ * half-sweep).  Reading the stats synchronises the device and resets them. */
+int tmq_set_kernel_timing(tmq_lattice *lat, int on);
+int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double *total_ms,
+                     double *bytes, double *flops);
+
+/* Encode n_sites canonical complex128 sites (12 complex each) into the device
+ * FP16 (prec = TMQ_FP16) or BF16 storage and export the codes in canonical
+ * order: codes[n_sites][24] (real, imaginary of spin-colour component k at
+ * 2k, 2k+1) and scale[n_sites] (FP32).  Device pointers.  Used to check the
+ * codec bit for bit. */
+int tmq_encode_dev(tmq_lattice *lat, tmq_prec prec, long n_sites, const double *in,
+                   uint16_t *codes, float *scale, void *stream);
+
+/* Device memory (bytes) the lattice would hold for its gauge copies plus the
+ * work space of one solve with these options (opts may be NULL: FP64). */
+int tmq_footprint_bytes(const int dims[4], const tmq_solver_opts *opts, int nrhs, size_t *out);
+
+/* Message of the last error on this thread ("" if none). */
+const char *tmq_last_error(void);
+
+/* Library version string. */
+const char *tmq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMQ_H */

@@ -1,0 +1,21 @@
+"""MI355X (gfx950) twisted-mass Dirac operator and CG solver.
+
+The even/odd preconditioned Wilson twisted-mass operator and the CG solve of
+Qhat^+ Qhat^- x = b (Jansen & Urbach, "tmLQCD", Appendix B and Sec. 4.4) as
+hand-written HIP kernels behind the C ABI of include/tmq.h; ``tmq`` is the
+ctypes binding.  Importing the package requires the built libtmq.so
+(``python -m paper_0905_3331_amd.build``); there is no CPU fallback.
+"""
+from .tmq import (  # noqa: F401
+    BF16,
+    FP16,
+    FP32,
+    FP64,
+    Lattice,
+    SolveInfo,
+    TmqError,
+    footprint_bytes,
+    params,
+    solver_opts,
+    version,
+)

@@ -1,0 +1,429 @@
+// api.cpp -- the extern "C" entry points declared in include/tmq.h.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "lattice.h"
+
+namespace tmq {
+int solve_eo(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
+             hipStream_t st, tmq_solve_info *info);
+int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
+               hipStream_t st, tmq_solve_info *info);
+}  // namespace tmq
+
+using namespace tmq;
+
+namespace {
+
+// Sets the lattice's device for the duration of a call and restores the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        hipGetDevice(&prev);
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+int check_lat(tmq_lattice *lat, bool need_gauge)
+{
+    if (!lat || !lat->L) {
+        set_error("NULL tmq_lattice");
+        return TMQ_EINVAL;
+    }
+    if (need_gauge && !lat->L->gauge) {
+        set_error("no gauge field loaded (call tmq_load_gauge first)");
+        return TMQ_ESTATE;
+    }
+    return TMQ_OK;
+}
+
+int check_prec(int prec)
+{
+    if (prec < TMQ_FP64 || prec > TMQ_BF16) {
+        set_error("invalid tmq_prec");
+        return TMQ_EINVAL;
+    }
+    return TMQ_OK;
+}
+
+int check_sign(int sign)
+{
+    if (sign != 1 && sign != -1) {
+        set_error("sign must be +1 or -1");
+        return TMQ_EINVAL;
+    }
+    return TMQ_OK;
+}
+
+int check_ptrs(const void *a, const void *b)
+{
+    if (!a || !b) {
+        set_error("NULL field pointer");
+        return TMQ_EINVAL;
+    }
+    return TMQ_OK;
+}
+
+int check_opts(const tmq_solver_opts *o)
+{
+    if (!o) {
+        set_error("NULL tmq_solver_opts");
+        return TMQ_EINVAL;
+    }
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) {
+        set_error("tol must be a positive finite number");
+        return TMQ_EINVAL;
+    }
+    TMQ_TRY(check_prec(o->sloppy));
+    if (o->sloppy != TMQ_FP64 && o->sloppy_link != TMQ_FP32 && o->sloppy_link != TMQ_FP16) {
+        set_error("sloppy_link must be TMQ_FP32 or TMQ_FP16");
+        return TMQ_EINVAL;
+    }
+    return TMQ_OK;
+}
+
+// odd-site Qhat on device canonical buffers
+int qhat_dev(Lattice *L, const tmq_params *p, int sign, int prec, const double *in, double *out, hipStream_t st)
+{
+    const long vh = L->g.vh;
+    FieldDesc fi, fo, te;
+    TMQ_TRY(work_field(L, "op_in", prec, vh, &fi));
+    TMQ_TRY(work_field(L, "op_out", prec, vh, &fo));
+    TMQ_TRY(work_field(L, "op_te", prec, vh, &te));
+    const LinkDesc lk = lattice_links(L, link_fmt_for(L, prec, prec == TMQ_FP32 ? P32 : P16));
+    TMQ_HIP(launch_from_canonical((const double2 *)in, fi, st));
+    TMQ_TRY(apply_Qhat(L, *p, sign, fi, fo, te, lk, nullptr, nullptr, st));
+    TMQ_HIP(launch_to_canonical(fo, (double2 *)out, st));
+    return TMQ_OK;
+}
+
+int copy_in(Lattice *L, int slot, const double *host, size_t bytes, double **dev)
+{
+    void *d = nullptr;
+    TMQ_TRY(stage_buffer(L, slot, bytes, &d));
+    TMQ_HIP(hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, L->own));
+    *dev = (double *)d;
+    return TMQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tmq_last_error(void) { return get_error(); }
+
+const char *tmq_version(void) { return "tmq 0.1 (gfx950)"; }
+
+int tmq_lattice_create(const int dims[4], int device, tmq_lattice **out)
+{
+    if (!out) {
+        set_error("tmq_lattice_create: NULL out");
+        return TMQ_EINVAL;
+    }
+    *out = nullptr;
+    Lattice *L = nullptr;
+    TMQ_TRY(lattice_create(dims, device, &L));
+    tmq_lattice *h = new (std::nothrow) tmq_lattice{L};
+    if (!h) {
+        delete L;
+        set_error("host allocation failed");
+        return TMQ_ENOMEM;
+    }
+    *out = h;
+    return TMQ_OK;
+}
+
+void tmq_lattice_destroy(tmq_lattice *lat)
+{
+    if (!lat) return;
+    delete lat->L;
+    delete lat;
+}
+
+int tmq_load_gauge_dev(tmq_lattice *lat, const double *U, void *stream)
+{
+    TMQ_TRY(check_lat(lat, false));
+    TMQ_TRY(check_ptrs(U, U));
+    DeviceGuard dg(lat->L->device);
+    return lattice_load_gauge(lat->L, (const double2 *)U, (hipStream_t)stream);
+}
+
+int tmq_load_gauge(tmq_lattice *lat, const double *U)
+{
+    TMQ_TRY(check_lat(lat, false));
+    TMQ_TRY(check_ptrs(U, U));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const size_t bytes = (size_t)2 * L->g.vh * 4 * 9 * 16;
+    void *d = nullptr;
+    TMQ_HIP(hipMalloc(&d, bytes));
+    int s = TMQ_OK;
+    if (hipMemcpyAsync(d, U, bytes, hipMemcpyHostToDevice, L->own) != hipSuccess) {
+        set_error("tmq_load_gauge: host to device copy failed");
+        s = TMQ_EDEVICE;
+    }
+    if (s == TMQ_OK) s = lattice_load_gauge(L, (const double2 *)d, L->own);
+    hipStreamSynchronize(L->own);
+    hipFree(d);
+    return s;
+}
+
+int tmq_gauge_is_su3(const tmq_lattice *lat) { return lat && lat->L && lat->L->su3 ? 1 : 0; }
+
+int tmq_apply_Qhat_dev(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec, const double *in,
+                       double *out, void *stream)
+{
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_sign(sign));
+    TMQ_TRY(check_prec(prec));
+    TMQ_TRY(check_ptrs(in, out));
+    DeviceGuard dg(lat->L->device);
+    return qhat_dev(lat->L, p, sign, prec, in, out, (hipStream_t)stream);
+}
+
+int tmq_apply_Qhat(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec, const double *in, double *out)
+{
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_sign(sign));
+    TMQ_TRY(check_prec(prec));
+    TMQ_TRY(check_ptrs(in, out));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const size_t bytes = (size_t)L->g.vh * 12 * 16;
+    double *din = nullptr, *dout = nullptr;
+    TMQ_TRY(copy_in(L, 0, in, bytes, &din));
+    void *d = nullptr;
+    TMQ_TRY(stage_buffer(L, 1, bytes, &d));
+    dout = (double *)d;
+    TMQ_TRY(qhat_dev(L, p, sign, prec, din, dout, L->own));
+    TMQ_HIP(hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, L->own));
+    TMQ_HIP(hipStreamSynchronize(L->own));
+    return TMQ_OK;
+}
+
+int tmq_apply_QhatQhat_dev(tmq_lattice *lat, const tmq_params *p, const double *in, double *out, void *stream)
+{
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_ptrs(in, out));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    hipStream_t st = (hipStream_t)stream;
+    const long vh = L->g.vh;
+    FieldDesc fi, fo, te, to;
+    TMQ_TRY(work_field(L, "op_in", P64, vh, &fi));
+    TMQ_TRY(work_field(L, "op_out", P64, vh, &fo));
+    TMQ_TRY(work_field(L, "op_te", P64, vh, &te));
+    TMQ_TRY(work_field(L, "op_to", P64, vh, &to));
+    TMQ_HIP(launch_from_canonical((const double2 *)in, fi, st));
+    TMQ_TRY(apply_QhatQhat(L, *p, fi, fo, te, to, lattice_links(L, link_fmt_for(L, P64, P64)), nullptr, nullptr, st));
+    TMQ_HIP(launch_to_canonical(fo, (double2 *)out, st));
+    return TMQ_OK;
+}
+
+int tmq_apply_Q_full_dev(tmq_lattice *lat, const tmq_params *p, int sign, const double *in, double *out,
+                         void *stream)
+{
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_sign(sign));
+    TMQ_TRY(check_ptrs(in, out));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    hipStream_t st = (hipStream_t)stream;
+    const long n = 2 * L->g.vh;
+    FieldDesc fi, fo;
+    TMQ_TRY(work_field(L, "full_in", P64, n, &fi));
+    TMQ_TRY(work_field(L, "full_out", P64, n, &fo));
+    TMQ_HIP(launch_full_from_canonical(L->g, (const double2 *)in, fi, st));
+    TMQ_TRY(apply_Q_full(L, *p, sign, fi, fo, lattice_links(L, link_fmt_for(L, P64, P64)), st));
+    TMQ_HIP(launch_full_to_canonical(L->g, fo, (double2 *)out, st));
+    return TMQ_OK;
+}
+
+int tmq_apply_Q_full(tmq_lattice *lat, const tmq_params *p, int sign, const double *in, double *out)
+{
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_ptrs(in, out));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const size_t bytes = (size_t)2 * L->g.vh * 12 * 16;
+    double *din = nullptr;
+    TMQ_TRY(copy_in(L, 0, in, bytes, &din));
+    void *d = nullptr;
+    TMQ_TRY(stage_buffer(L, 1, bytes, &d));
+    TMQ_TRY(tmq_apply_Q_full_dev(lat, p, sign, din, (double *)d, L->own));
+    TMQ_HIP(hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, L->own));
+    TMQ_HIP(hipStreamSynchronize(L->own));
+    return TMQ_OK;
+}
+
+int tmq_solve_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *b, double *x,
+                  void *stream, tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_opts(opts));
+    TMQ_TRY(check_ptrs(b, x));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    hipStream_t st = (hipStream_t)stream;
+    const long vh = L->g.vh;
+    FieldDesc fb, fx;
+    TMQ_TRY(work_field(L, "solve_b", P64, vh, &fb));
+    TMQ_TRY(work_field(L, "solve_x", P64, vh, &fx));
+    TMQ_HIP(launch_from_canonical((const double2 *)b, fb, st));
+    const int s = solve_eo(L, *p, *opts, fb, fx, st, info);
+    if (s == TMQ_OK || s == TMQ_ENOCONV) {
+        TMQ_HIP(launch_to_canonical(fx, (double2 *)x, st));
+        TMQ_HIP(hipStreamSynchronize(st));
+    }
+    return s;
+}
+
+int tmq_solve(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *b, double *x,
+              tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_ptrs(b, x));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t bytes = (size_t)L->g.vh * 12 * 16;
+    double *db = nullptr;
+    TMQ_TRY(copy_in(L, 0, b, bytes, &db));
+    void *dx = nullptr;
+    TMQ_TRY(stage_buffer(L, 1, bytes, &dx));
+    const int s = tmq_solve_dev(lat, p, opts, db, (double *)dx, L->own, info);
+    if (s == TMQ_OK || s == TMQ_ENOCONV) {
+        TMQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, L->own));
+        TMQ_HIP(hipStreamSynchronize(L->own));
+    }
+    if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+}
+
+int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *b,
+                       double *x, void *stream, tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_opts(opts));
+    TMQ_TRY(check_ptrs(b, x));
+    if (opts->sloppy != TMQ_FP64) {
+        set_error("tmq_solve_full_dev: only FP64 is provided for the full-lattice operator");
+        return TMQ_EINVAL;
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    hipStream_t st = (hipStream_t)stream;
+    const long n = 2 * L->g.vh;
+    FieldDesc fb, fx;
+    TMQ_TRY(work_field(L, "full_b", P64, n, &fb));
+    TMQ_TRY(work_field(L, "full_x", P64, n, &fx));
+    TMQ_HIP(launch_full_from_canonical(L->g, (const double2 *)b, fb, st));
+    const int s = solve_full(L, *p, *opts, fb, fx, st, info);
+    if (s == TMQ_OK || s == TMQ_ENOCONV) {
+        TMQ_HIP(launch_full_to_canonical(L->g, fx, (double2 *)x, st));
+        TMQ_HIP(hipStreamSynchronize(st));
+    }
+    return s;
+}
+
+int tmq_set_kernel_timing(tmq_lattice *lat, int on)
+{
+    TMQ_TRY(check_lat(lat, false));
+    lat->L->timing = on != 0;
+    return TMQ_OK;
+}
+
+int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double *total_ms, double *bytes,
+                     double *flops)
+{
+    TMQ_TRY(check_lat(lat, false));
+    if (!family || strcmp(family, "hop") != 0) {
+        set_error("tmq_kernel_stats: unknown kernel family (known: \"hop\")");
+        return TMQ_EINVAL;
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    TMQ_HIP(hipDeviceSynchronize());
+    double ms = 0, by = 0, fl = 0;
+    int n = 0;
+    for (auto &t : L->timed) {
+        float e = 0.f;
+        TMQ_HIP(hipEventElapsedTime(&e, t.a, t.b));
+        ms += e;
+        by += t.bytes;
+        fl += t.flops;
+        n++;
+        L->event_pool.push_back(t.a);
+        L->event_pool.push_back(t.b);
+    }
+    L->timed.clear();
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (bytes) *bytes = by;
+    if (flops) *flops = fl;
+    return TMQ_OK;
+}
+
+int tmq_encode_dev(tmq_lattice *lat, tmq_prec prec, long n_sites, const double *in, uint16_t *codes, float *scale,
+                   void *stream)
+{
+    TMQ_TRY(check_lat(lat, false));
+    if (prec != TMQ_FP16 && prec != TMQ_BF16) {
+        set_error("tmq_encode_dev: prec must be TMQ_FP16 or TMQ_BF16");
+        return TMQ_EINVAL;
+    }
+    if (n_sites < 0 || (n_sites > 0 && (!in || !codes || !scale))) {
+        set_error("tmq_encode_dev: bad size or NULL pointer");
+        return TMQ_EINVAL;
+    }
+    if (n_sites == 0) return TMQ_OK;
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    hipStream_t st = (hipStream_t)stream;
+    FieldDesc f;
+    TMQ_TRY(work_field(L, "codec", prec, n_sites, &f));
+    TMQ_HIP(launch_from_canonical((const double2 *)in, f, st));
+    TMQ_HIP(launch_export_codes(f, codes, scale, st));
+    return TMQ_OK;
+}
+
+int tmq_footprint_bytes(const int dims[4], const tmq_solver_opts *opts, int nrhs, size_t *out)
+{
+    if (!dims || !out || nrhs < 1) {
+        set_error("tmq_footprint_bytes: bad argument");
+        return TMQ_EINVAL;
+    }
+    for (int i = 0; i < 4; i++)
+        if (dims[i] < 2 || dims[i] % 2) {
+            set_error("tmq_footprint_bytes: every extent must be even and >= 2");
+            return TMQ_EINVAL;
+        }
+    const long vh = (long)dims[0] * dims[1] * dims[2] * dims[3] / 2;
+    // gauge copies: FP64 full + FP64, FP32, FP16 two-row, both parities, 4 directions
+    size_t g = (size_t)8 * vh * (9 * 16 + 6 * 16 + 3 * 16 + 24);
+    // FP64 solve: b, x, r, Ax, t_e, t_o, p, Ap ; mixed adds 5 sloppy fields + FP32 x_s
+    size_t per = 8 * field_bytes(P64, vh);
+    if (opts && opts->sloppy != TMQ_FP64) per = 6 * field_bytes(P64, vh) + 5 * field_bytes(opts->sloppy, vh) +
+                                               field_bytes(P32, vh);
+    *out = g + per * (size_t)nrhs;
+    return TMQ_OK;
+}
+
+}  // extern "C"

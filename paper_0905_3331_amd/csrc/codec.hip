@@ -1,0 +1,289 @@
+// codec.hip -- conversions between the canonical host layout and the device
+// formats, and the gauge-field ingest.
+//
+// Canonical layout: complex128, site-major ([site][spin][colour] for spinors,
+// [site][mu][row][col] for links), site = ((t*LZ + z)*LY + y)*LX + x.
+// Device layout: per-parity structure of arrays (fields.h).
+//
+// 16-bit spinor encoding of FP64 input (one rounding to FP32, then RNE to
+// FP16/BF16): scale = fp32(max |part|) over the site's 24 reals, code =
+// to16(fp32(value / scale)) with the division in FP64; an all-zero site has
+// scale 0 and zero codes.  Inside the solver, FP32 values are encoded with
+// value * (1 / scale) in FP32.
+#include <type_traits>
+
+#include "devutil.h"
+#include "fields.h"
+#include "kernels.h"
+
+namespace tmq {
+
+template <class SP>
+static SP mkc(const FieldDesc &f);
+template <>
+SpF64 mkc<SpF64>(const FieldDesc &f) { return SpF64{(double2 *)f.data, f.stride}; }
+template <>
+SpF32 mkc<SpF32>(const FieldDesc &f) { return SpF32{(float4 *)f.data, f.stride}; }
+template <>
+SpH16 mkc<SpH16>(const FieldDesc &f) { return SpH16{(uint4 *)f.data, f.scale, f.stride}; }
+template <>
+SpB16 mkc<SpB16>(const FieldDesc &f) { return SpB16{(uint4 *)f.data, f.scale, f.stride}; }
+
+// store FP64 values; 16-bit formats follow the FP64 encoding rule above
+template <class SP>
+__device__ __forceinline__ void store_f64(const SP &f, long h, const spinor<double> &s)
+{
+    f.store(h, s);
+}
+
+template <bool BF>
+__device__ __forceinline__ void store_f64_16(const Sp16<BF> &f, long h, const spinor<double> &s)
+{
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        m = fmax(m, fabs(s.c[k / 3][k % 3].re));
+        m = fmax(m, fabs(s.c[k / 3][k % 3].im));
+    }
+    const float sc = (float)m;
+    const double d = (double)sc;
+    f.scale[h] = sc;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        uint32_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int comp = 4 * k + j;
+            const cx<double> v = s.c[comp / 3][comp % 3];
+            const float yr = sc > 0.f ? (float)(v.re / d) : 0.f;
+            const float yi = sc > 0.f ? (float)(v.im / d) : 0.f;
+            w[j] = pack16(f32_to_code<BF>(yr), f32_to_code<BF>(yi));
+        }
+        f.p[k * f.stride + h] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+template <>
+__device__ __forceinline__ void store_f64<SpH16>(const SpH16 &f, long h, const spinor<double> &s)
+{
+    store_f64_16<false>(f, h, s);
+}
+template <>
+__device__ __forceinline__ void store_f64<SpB16>(const SpB16 &f, long h, const spinor<double> &s)
+{
+    store_f64_16<true>(f, h, s);
+}
+
+__device__ __forceinline__ void load_canonical(const double2 *in, long site, spinor<double> &s)
+{
+    const double2 *q = in + site * 12;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        double2 v = q[k];
+        s.c[k / 3][k % 3] = cx<double>{v.x, v.y};
+    }
+}
+
+__device__ __forceinline__ void store_canonical(double2 *out, long site, const spinor<double> &s)
+{
+    double2 *q = out + site * 12;
+#pragma unroll
+    for (int k = 0; k < 12; k++) q[k] = make_double2(s.c[k / 3][k % 3].re, s.c[k / 3][k % 3].im);
+}
+
+template <class SP>
+__global__ __launch_bounds__(BLAS_BLOCK) void k_from_canonical(const double2 *in, SP out, long n)
+{
+    const long h = (long)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (h < n) {
+        spinor<double> s;
+        load_canonical(in, h, s);
+        store_f64(out, h, s);
+    }
+}
+
+template <class SP>
+__global__ __launch_bounds__(BLAS_BLOCK) void k_to_canonical(SP in, double2 *out, long n)
+{
+    const long h = (long)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (h < n) {
+        spinor<double> s;
+        in.load(h, s);
+        store_canonical(out, h, s);
+    }
+}
+
+// parity of canonical site s
+__device__ __forceinline__ int site_parity(const Geom &g, long s)
+{
+    const unsigned su = (unsigned)s;
+    const unsigned x = su % (unsigned)g.LX;
+    unsigned r = su / (unsigned)g.LX;
+    const unsigned y = r % (unsigned)g.LY;
+    r /= (unsigned)g.LY;
+    const unsigned z = r % (unsigned)g.LZ;
+    const unsigned t = r / (unsigned)g.LZ;
+    return (int)((t + z + y + x) & 1u);
+}
+
+template <class SP, bool TO>
+__global__ __launch_bounds__(BLAS_BLOCK) void k_full_canonical(Geom g, double2 *can, SP f)
+{
+    const long s = (long)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (s < 2 * g.vh) {
+        const long v = site_parity(g, s) * g.vh + (s >> 1);
+        spinor<double> sp;
+        if (TO) {
+            f.load(v, sp);
+            store_canonical(can, s, sp);
+        } else {
+            load_canonical(can, s, sp);
+            store_f64(f, v, sp);
+        }
+    }
+}
+
+template <class SP>
+__global__ __launch_bounds__(BLAS_BLOCK) void k_export_codes(SP in, uint16_t *codes, float *scale, long n)
+{
+    const long h = (long)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (h < n) {
+        scale[h] = in.scale[h];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint4 v = in.p[k * in.stride + h];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                codes[h * 24 + 2 * (4 * k + j)] = lo16(w[j]);
+                codes[h * 24 + 2 * (4 * k + j) + 1] = hi16(w[j]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ gauge
+
+__global__ __launch_bounds__(BLAS_BLOCK) void k_gauge_ingest(Geom g, const double2 *U, GaugeOut o, double *partial)
+{
+    const long s = (long)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    double dev = 0.0;
+    if (s < 2 * g.vh) {
+        const int par = site_parity(g, s);
+        const long h = s >> 1, st = g.vh;
+        for (int mu = 0; mu < 4; mu++) {
+            su3<double> u;
+            const double2 *q = U + (s * 4 + mu) * 9;
+#pragma unroll
+            for (int k = 0; k < 9; k++) u.e[k / 3][k % 3] = cx<double>{q[k].x, q[k].y};
+            const long sub = par * 4 + mu;
+            if (o.full64)
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    o.full64[(sub * 9 + k) * st + h] = make_double2(u.e[k / 3][k % 3].re, u.e[k / 3][k % 3].im);
+            if (o.row64)
+#pragma unroll
+                for (int k = 0; k < 6; k++)
+                    o.row64[(sub * 6 + k) * st + h] = make_double2(u.e[k / 3][k % 3].re, u.e[k / 3][k % 3].im);
+            if (o.row32)
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    const cx<double> a = u.e[(2 * k) / 3][(2 * k) % 3], b = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
+                    o.row32[(sub * 3 + k) * st + h] = make_float4((float)a.re, (float)a.im, (float)b.re, (float)b.im);
+                }
+            if (o.row16a) {
+                uint32_t w[6];
+#pragma unroll
+                for (int k = 0; k < 6; k++)
+                    w[k] = pack16(f32_to_h16((float)u.e[k / 3][k % 3].re), f32_to_h16((float)u.e[k / 3][k % 3].im));
+                o.row16a[sub * st + h] = make_uint4(w[0], w[1], w[2], w[3]);
+                o.row16b[sub * st + h] = make_uint2(w[4], w[5]);
+            }
+            // distance from SU(3): max |(U U^+ - 1)_ab| and |det U - 1|
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    cx<double> e = {a == b ? -1.0 : 0.0, 0.0};
+#pragma unroll
+                    for (int c = 0; c < 3; c++) e = cfma(u.e[b][c], u.e[a][c], e);
+                    dev = fmax(dev, sqrt(norm2(e)));
+                }
+            su3<double> w = u;
+            su3_third_row(w);
+            cx<double> det = {-1.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 3; c++) det = fma(u.e[2][c], conj(w.e[2][c]), det);
+            dev = fmax(dev, sqrt(norm2(det)));
+        }
+    }
+    __shared__ double sh[BLAS_BLOCK / 64];
+    const double m = block_max(dev, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+// -------------------------------------------------------------- dispatch
+
+#define DISPATCH_SPC(prec, F, ...)                        \
+    switch (prec) {                                       \
+    case P64: { using F = SpF64; __VA_ARGS__; } break;    \
+    case P32: { using F = SpF32; __VA_ARGS__; } break;    \
+    case P16: { using F = SpH16; __VA_ARGS__; } break;    \
+    case PB16: { using F = SpB16; __VA_ARGS__; } break;   \
+    default: return hipErrorInvalidValue;                 \
+    }
+
+hipError_t launch_from_canonical(const double2 *in, const FieldDesc &out, hipStream_t st)
+{
+    DISPATCH_SPC(out.prec, F,
+                 hipLaunchKernelGGL(k_from_canonical<F>, dim3(blas_grid(out.n)), dim3(BLAS_BLOCK), 0, st, in,
+                                    mkc<F>(out), out.n));
+    return hipGetLastError();
+}
+
+hipError_t launch_to_canonical(const FieldDesc &in, double2 *out, hipStream_t st)
+{
+    DISPATCH_SPC(in.prec, F,
+                 hipLaunchKernelGGL(k_to_canonical<F>, dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st,
+                                    mkc<F>(in), out, in.n));
+    return hipGetLastError();
+}
+
+hipError_t launch_full_from_canonical(const Geom &g, const double2 *in, const FieldDesc &out, hipStream_t st)
+{
+    if (out.n != 2 * g.vh) return hipErrorInvalidValue;
+    DISPATCH_SPC(out.prec, F,
+                 hipLaunchKernelGGL((k_full_canonical<F, false>), dim3(blas_grid(out.n)), dim3(BLAS_BLOCK), 0, st,
+                                    g, (double2 *)in, mkc<F>(out)));
+    return hipGetLastError();
+}
+
+hipError_t launch_full_to_canonical(const Geom &g, const FieldDesc &in, double2 *out, hipStream_t st)
+{
+    if (in.n != 2 * g.vh) return hipErrorInvalidValue;
+    DISPATCH_SPC(in.prec, F,
+                 hipLaunchKernelGGL((k_full_canonical<F, true>), dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st,
+                                    g, out, mkc<F>(in)));
+    return hipGetLastError();
+}
+
+hipError_t launch_export_codes(const FieldDesc &in, uint16_t *codes, float *scale, hipStream_t st)
+{
+    if (in.prec == P16)
+        hipLaunchKernelGGL(k_export_codes<SpH16>, dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st, mkc<SpH16>(in),
+                           codes, scale, in.n);
+    else if (in.prec == PB16)
+        hipLaunchKernelGGL(k_export_codes<SpB16>, dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st, mkc<SpB16>(in),
+                           codes, scale, in.n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_ingest(const Geom &g, const double2 *U, const GaugeOut &o, double *partial_max,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gauge_ingest, dim3(blas_grid(2 * g.vh)), dim3(BLAS_BLOCK), 0, st, g, U, o, partial_max);
+    return hipGetLastError();
+}
+
+}  // namespace tmq

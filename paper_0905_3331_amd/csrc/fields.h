@@ -1,0 +1,226 @@
+// fields.h -- device storage formats of spinor fields and gauge links.
+//
+// Every field lives on one parity (V/2 sites, eo index h = site >> 1) as a
+// structure of arrays: component block c of site h sits at c * stride + h, so
+// that consecutive lanes of a wavefront read consecutive addresses.
+//
+//   spinors (12 complex per site, k = 3 * spin + colour)
+//     F64  : 12 blocks of double2 (one complex each)                 192 B/site
+//     F32  :  6 blocks of float4 (complex 2c, 2c+1)                   96 B/site
+//     H16  :  3 blocks of 8 x fp16 (complex 4c..4c+3) + fp32 scale    52 B/site
+//     B16  :  as H16 with bf16 codes                                  52 B/site
+//     value of a 16-bit code = code * scale (FP32), scale = largest |real or
+//     imaginary part| of the site; an all-zero site has scale 0.
+//   links (per parity and direction mu, 4 * 2 = 8 such arrays)
+//     L64F : 9 blocks of double2 (full 3x3)                          144 B/link
+//     L64R : 6 blocks of double2 (rows 0, 1; row 2 = conj(r0 x r1))   96 B/link
+//     L32R : 3 blocks of float4 (rows 0, 1)                            48 B/link
+//     L16R : one block of 8 x fp16 plus one of 4 x fp16 (rows 0, 1)    24 B/link
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "spin.h"
+
+namespace tmq {
+
+// ------------------------------------------------------------ 16-bit codes
+
+__device__ __forceinline__ float h16_to_f32(uint16_t c) { return __half2float(__ushort_as_half(c)); }
+__device__ __forceinline__ uint16_t f32_to_h16(float f) { return __half_as_ushort(__float2half_rn(f)); }
+__device__ __forceinline__ float b16_to_f32(uint16_t c) { return __uint_as_float(((uint32_t)c) << 16); }
+// round to nearest even on the dropped 16 bits (finite inputs)
+__device__ __forceinline__ uint16_t f32_to_b16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <bool BF>
+__device__ __forceinline__ float code_to_f32(uint16_t c) { return BF ? b16_to_f32(c) : h16_to_f32(c); }
+template <bool BF>
+__device__ __forceinline__ uint16_t f32_to_code(float f) { return BF ? f32_to_b16(f) : f32_to_h16(f); }
+
+__device__ __forceinline__ uint16_t lo16(uint32_t w) { return (uint16_t)(w & 0xFFFFu); }
+__device__ __forceinline__ uint16_t hi16(uint32_t w) { return (uint16_t)(w >> 16); }
+__device__ __forceinline__ uint32_t pack16(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+// --------------------------------------------------------------- spinors
+
+struct SpF64 {
+    using real = double;
+    double2 *p;
+    long stride;  // sites per component block (>= V/2)
+    template <typename R>
+    __device__ __forceinline__ void load(long h, spinor<R> &s) const
+    {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 v = p[k * stride + h];
+            s.c[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
+        }
+    }
+    template <typename R>
+    __device__ __forceinline__ void store(long h, const spinor<R> &s) const
+    {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            cx<R> v = s.c[k / 3][k % 3];
+            p[k * stride + h] = make_double2((double)v.re, (double)v.im);
+        }
+    }
+};
+
+struct SpF32 {
+    using real = float;
+    float4 *p;
+    long stride;
+    template <typename R>
+    __device__ __forceinline__ void load(long h, spinor<R> &s) const
+    {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            float4 v = p[k * stride + h];
+            s.c[(2 * k) / 3][(2 * k) % 3] = cx<R>{(R)v.x, (R)v.y};
+            s.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = cx<R>{(R)v.z, (R)v.w};
+        }
+    }
+    template <typename R>
+    __device__ __forceinline__ void store(long h, const spinor<R> &s) const
+    {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            cx<R> a = s.c[(2 * k) / 3][(2 * k) % 3];
+            cx<R> b = s.c[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            p[k * stride + h] = make_float4((float)a.re, (float)a.im, (float)b.re, (float)b.im);
+        }
+    }
+};
+
+template <bool BF>
+struct Sp16 {
+    using real = float;
+    uint4 *p;
+    float *scale;
+    long stride;
+    template <typename R>
+    __device__ __forceinline__ void load(long h, spinor<R> &s) const
+    {
+        const float sc = scale[h];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            uint4 v = p[k * stride + h];
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                int comp = 4 * k + j;
+                s.c[comp / 3][comp % 3] =
+                    cx<R>{(R)(code_to_f32<BF>(lo16(w[j])) * sc), (R)(code_to_f32<BF>(hi16(w[j])) * sc)};
+            }
+        }
+    }
+    // store FP32 values: scale = largest |part|, codes = value / scale
+    template <typename R>
+    __device__ __forceinline__ void store(long h, const spinor<R> &s) const
+    {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            m = fmaxf(m, fabsf((float)s.c[k / 3][k % 3].re));
+            m = fmaxf(m, fabsf((float)s.c[k / 3][k % 3].im));
+        }
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        scale[h] = m;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            uint32_t w[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                int comp = 4 * k + j;
+                cx<R> v = s.c[comp / 3][comp % 3];
+                w[j] = pack16(f32_to_code<BF>((float)v.re * inv), f32_to_code<BF>((float)v.im * inv));
+            }
+            p[k * stride + h] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+};
+using SpH16 = Sp16<false>;
+using SpB16 = Sp16<true>;
+
+// ----------------------------------------------------------------- links
+// Each link array holds 8 sub-arrays (parity, mu), each of `blocks` component
+// blocks of `stride` entries: entry of (par, mu, block b, site h) at
+// ((par * 4 + mu) * blocks + b) * stride + h.
+
+struct L64F {
+    using real = double;
+    const double2 *p;
+    long stride;
+    template <typename R>
+    __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
+    {
+        const double2 *q = p + (long)(par * 4 + mu) * 9 * stride + h;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            double2 v = q[k * stride];
+            u.e[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
+        }
+    }
+};
+
+struct L64R {
+    using real = double;
+    const double2 *p;
+    long stride;
+    template <typename R>
+    __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
+    {
+        const double2 *q = p + (long)(par * 4 + mu) * 6 * stride + h;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            double2 v = q[k * stride];
+            u.e[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
+        }
+        su3_third_row(u);
+    }
+};
+
+struct L32R {
+    using real = float;
+    const float4 *p;
+    long stride;
+    template <typename R>
+    __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
+    {
+        const float4 *q = p + (long)(par * 4 + mu) * 3 * stride + h;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            float4 v = q[k * stride];
+            u.e[(2 * k) / 3][(2 * k) % 3] = cx<R>{(R)v.x, (R)v.y};
+            u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = cx<R>{(R)v.z, (R)v.w};
+        }
+        su3_third_row(u);
+    }
+};
+
+struct L16R {
+    using real = float;
+    const uint4 *a;  // complex 0..3 of rows 0,1 (row-major)
+    const uint2 *b;  // complex 4, 5
+    long stride;
+    template <typename R>
+    __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
+    {
+        long o = (long)(par * 4 + mu) * stride + h;
+        uint4 va = a[o];
+        uint2 vb = b[o];
+        uint32_t w[6] = {va.x, va.y, va.z, va.w, vb.x, vb.y};
+#pragma unroll
+        for (int k = 0; k < 6; k++)
+            u.e[k / 3][k % 3] = cx<R>{(R)h16_to_f32(lo16(w[k])), (R)h16_to_f32(hi16(w[k]))};
+        su3_third_row(u);
+    }
+};
+
+}  // namespace tmq

@@ -1,0 +1,219 @@
+// hop.hip -- the hopping half-sweep H_eo / H_oe with fused site-term epilogues.
+//
+// One output site per lane.  For each of the 8 neighbours the lane loads the
+// neighbour spinor, projects it to two spin components with (1 +- gamma_mu)
+// (Sec. 4.1), multiplies both by the link U(x,mu) or U(x-mu,mu)^+ (each link
+// is read exactly once per half-sweep: the forward links of the output
+// parity, the backward links of the input parity), multiplies by the boundary
+// phase e^{+-i theta_mu pi/L_mu} (Sec. 4.1.2) and accumulates the rebuilt
+// four-spinor.  The epilogue forms  out = A * self + B * acc  per spin half,
+// which covers both factors of the even/odd operator (eqs. (eo3), (eo4)) and
+// the full-lattice operator, and optionally reduces |out|^2 per block.
+//
+// Work distribution: blocks of 256 lanes over consecutive eo indices (x
+// fastest, then y, z, t).  Hardware hands consecutive workgroups to the 8 XCDs
+// in turn; the block index is remapped so that each XCD walks a contiguous
+// slab of the lattice and its private L2 sees the y/z/t neighbours of its
+// own sites.
+#include "devutil.h"
+#include "fields.h"
+#include "kernels.h"
+
+namespace tmq {
+
+int hop_grid(long n)
+{
+    long g = (n + HOP_BLOCK - 1) / HOP_BLOCK;
+    g = (g + 7) / 8 * 8;  // a multiple of the XCD count for the remap
+    return (int)g;
+}
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblk)
+{
+    // nblk is a multiple of 8: XCD k = bid % 8 gets logical blocks [k*nblk/8, (k+1)*nblk/8)
+    return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+template <class SP, class LK>
+struct HopArgs {
+    Geom g;
+    int out_par;
+    SP in, self, out;
+    LK lk;
+    HopCoef c;
+    double *partial;
+    const int *skip;
+};
+
+template <int MU, class SP, class LK, typename R>
+__device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, spinor<R> &acc, long h, long hf, long hb)
+{
+    const cx<R> ph = {(R)a.c.ph[MU][0], (R)a.c.ph[MU][1]};
+    spinor<R> s;
+    half<R> p, w;
+    su3<R> u;
+    // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu); U at the output site
+    a.in.load(hf, s);
+    project<MU, +1>(s, p);
+    a.lk.load(a.out_par, MU, h, u);
+    link_mul<false>(u, p, ph, w);
+    reconstruct_add<MU, +1>(acc, w);
+    // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu); U at the neighbour
+    a.in.load(hb, s);
+    project<MU, -1>(s, p);
+    a.lk.load(a.out_par ^ 1, MU, hb, u);
+    link_mul<true>(u, p, conj(ph), w);
+    reconstruct_add<MU, -1>(acc, w);
+}
+
+template <class SP, class LK, bool SELF, bool NORM>
+__global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
+{
+    using R = typename LK::real;
+    if (a.skip && *a.skip) return;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const long h = (long)lb * HOP_BLOCK + threadIdx.x;
+    double nrm = 0.0;
+    if (h < a.g.vh) {
+        const Geom &g = a.g;
+        // coordinates of output site h (x fastest); x parity makes (t+z+y+x) = out_par mod 2
+        const unsigned hu = (unsigned)h;
+        const unsigned xh = hu % (unsigned)g.XH;
+        unsigned r = hu / (unsigned)g.XH;
+        const int y = (int)(r % (unsigned)g.LY);
+        r /= (unsigned)g.LY;
+        const int z = (int)(r % (unsigned)g.LZ);
+        const int t = (int)(r / (unsigned)g.LZ);
+        const int x = 2 * (int)xh + ((a.out_par + t + z + y) & 1);
+        const long row = h - xh;  // eo index of (t, z, y, 0)
+        const long sy = g.XH, sz = (long)g.LY * g.XH, stt = (long)g.LZ * g.LY * g.XH;
+
+        spinor<R> acc;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) acc.c[i][j] = cx<R>{R(0), R(0)};
+
+        hop_dir<0>(a, acc, h, t + 1 == g.T ? h - (g.T - 1) * stt : h + stt, t == 0 ? h + (g.T - 1) * stt : h - stt);
+        hop_dir<1>(a, acc, h, row + ((x + 1 == g.LX ? 0 : x + 1) >> 1), row + ((x == 0 ? g.LX - 1 : x - 1) >> 1));
+        hop_dir<2>(a, acc, h, y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy, y == 0 ? h + (g.LY - 1) * sy : h - sy);
+        hop_dir<3>(a, acc, h, z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz, z == 0 ? h + (g.LZ - 1) * sz : h - sz);
+
+        spinor<R> o;
+        const cx<R> Bu = {(R)a.c.B[0][0], (R)a.c.B[0][1]}, Bd = {(R)a.c.B[1][0], (R)a.c.B[1][1]};
+        if (SELF) {
+            spinor<R> sf;
+            a.self.load(h, sf);
+            const cx<R> Au = {(R)a.c.A[0][0], (R)a.c.A[0][1]}, Ad = {(R)a.c.A[1][0], (R)a.c.A[1][1]};
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                o.c[0][j] = fma(Au, sf.c[0][j], Bu * acc.c[0][j]);
+                o.c[1][j] = fma(Au, sf.c[1][j], Bu * acc.c[1][j]);
+                o.c[2][j] = fma(Ad, sf.c[2][j], Bd * acc.c[2][j]);
+                o.c[3][j] = fma(Ad, sf.c[3][j], Bd * acc.c[3][j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                o.c[0][j] = Bu * acc.c[0][j];
+                o.c[1][j] = Bu * acc.c[1][j];
+                o.c[2][j] = Bd * acc.c[2][j];
+                o.c[3][j] = Bd * acc.c[3][j];
+            }
+        }
+        a.out.store(h, o);
+        if (NORM) {
+            R n2 = R(0);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) n2 += norm2(o.c[i][j]);
+            nrm = (double)n2;
+        }
+    }
+    if (NORM) {
+        __shared__ double sh[HOP_BLOCK / 64];
+        double s = block_sum(nrm, sh);
+        if (threadIdx.x == 0) a.partial[lb] = s;
+    }
+}
+
+// ------------------------------------------------------------- dispatch
+
+template <class SP>
+static SP make_sp(const FieldDesc &f);
+template <>
+SpF64 make_sp<SpF64>(const FieldDesc &f) { return SpF64{(double2 *)f.data, f.stride}; }
+template <>
+SpF32 make_sp<SpF32>(const FieldDesc &f) { return SpF32{(float4 *)f.data, f.stride}; }
+template <>
+SpH16 make_sp<SpH16>(const FieldDesc &f) { return SpH16{(uint4 *)f.data, f.scale, f.stride}; }
+template <>
+SpB16 make_sp<SpB16>(const FieldDesc &f) { return SpB16{(uint4 *)f.data, f.scale, f.stride}; }
+
+template <class LK>
+static LK make_lk(const LinkDesc &l);
+template <>
+L64F make_lk<L64F>(const LinkDesc &l) { return L64F{(const double2 *)l.a, l.stride}; }
+template <>
+L64R make_lk<L64R>(const LinkDesc &l) { return L64R{(const double2 *)l.a, l.stride}; }
+template <>
+L32R make_lk<L32R>(const LinkDesc &l) { return L32R{(const float4 *)l.a, l.stride}; }
+template <>
+L16R make_lk<L16R>(const LinkDesc &l) { return L16R{(const uint4 *)l.a, (const uint2 *)l.b, l.stride}; }
+
+template <class SP, class LK>
+static hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
+                     const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, double *partial,
+                     const int *skip, hipStream_t st)
+{
+    HopArgs<SP, LK> a;
+    a.g = g;
+    a.out_par = out_par;
+    a.in = make_sp<SP>(in);
+    a.self = self.data ? make_sp<SP>(self) : a.in;
+    a.out = make_sp<SP>(out);
+    a.lk = make_lk<LK>(lk);
+    a.c = c;
+    a.partial = partial;
+    a.skip = skip;
+    dim3 grid(hop_grid(g.vh)), block(HOP_BLOCK);
+    const bool s = self.data != nullptr, n = partial != nullptr;
+    if (s && n)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true>), grid, block, 0, st, a);
+    else if (s)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false>), grid, block, 0, st, a);
+    else if (n)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
+                      const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, double *partial,
+                      const int *skip, hipStream_t st)
+{
+    if (in.prec != out.prec || (self.data && self.prec != in.prec)) return hipErrorInvalidValue;
+    switch (in.prec) {
+    case P64:
+        if (lk.fmt == LK64F) return go<SpF64, L64F>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        if (lk.fmt == LK64R) return go<SpF64, L64R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        break;
+    case P32:
+        if (lk.fmt == LK32R) return go<SpF32, L32R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        if (lk.fmt == LK16R) return go<SpF32, L16R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        break;
+    case P16:
+        if (lk.fmt == LK16R) return go<SpH16, L16R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        if (lk.fmt == LK32R) return go<SpH16, L32R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        break;
+    case PB16:
+        if (lk.fmt == LK16R) return go<SpB16, L16R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        if (lk.fmt == LK32R) return go<SpB16, L32R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        break;
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tmq

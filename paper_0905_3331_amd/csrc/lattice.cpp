@@ -1,0 +1,361 @@
+// lattice.cpp -- lattice object: creation, gauge ingest, operator application.
+#include "lattice.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace tmq {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+const char *get_error() { return g_err.c_str(); }
+
+size_t field_bytes(int prec, long n)
+{
+    size_t b = (size_t)n * field_blocks(prec) * 16;
+    if (prec == P16 || prec == PB16) b += (size_t)n * sizeof(float);
+    return b;
+}
+
+int field_alloc(Field &f, int prec, long n)
+{
+    field_free(f);
+    const size_t main = (size_t)n * field_blocks(prec) * 16;
+    if (hipMalloc(&f.mem, main) != hipSuccess) {
+        f.mem = nullptr;
+        set_error("device allocation of a spinor field failed");
+        return TMQ_ENOMEM;
+    }
+    if (prec == P16 || prec == PB16) {
+        if (hipMalloc((void **)&f.scale, (size_t)n * sizeof(float)) != hipSuccess) {
+            hipFree(f.mem);
+            f.mem = nullptr;
+            f.scale = nullptr;
+            set_error("device allocation of a spinor scale array failed");
+            return TMQ_ENOMEM;
+        }
+    }
+    f.d.prec = prec;
+    f.d.data = f.mem;
+    f.d.scale = f.scale;
+    f.d.stride = n;
+    f.d.n = n;
+    return TMQ_OK;
+}
+
+void field_free(Field &f)
+{
+    if (f.mem) hipFree(f.mem);
+    if (f.scale) hipFree(f.scale);
+    f.mem = nullptr;
+    f.scale = nullptr;
+    f.d = FieldDesc{};
+}
+
+Lattice::~Lattice()
+{
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(device);
+    if (own) hipStreamSynchronize(own);
+    for (auto &w : work) field_free(w.second);
+    for (void *p : {(void *)u64f, (void *)u64r, (void *)u32r, (void *)u16a, (void *)u16b})
+        if (p) hipFree(p);
+    for (double *p : partial)
+        if (p) hipFree(p);
+    if (scal) hipFree(scal);
+    if (ring) hipHostFree(ring);
+    for (auto &e : ring_ev)
+        if (e) hipEventDestroy(e);
+    for (void *s : stage)
+        if (s) hipFree(s);
+    for (auto &t : timed) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    for (auto e : event_pool) hipEventDestroy(e);
+    if (own) hipStreamDestroy(own);
+    hipSetDevice(cur);
+}
+
+int lattice_create(const int dims[4], int device, Lattice **out)
+{
+    if (!dims || !out) {
+        set_error("tmq_lattice_create: NULL argument");
+        return TMQ_EINVAL;
+    }
+    for (int i = 0; i < 4; i++)
+        if (dims[i] < 2 || dims[i] % 2) {
+            set_error("tmq_lattice_create: every extent must be even and >= 2 (periodic checkerboard)");
+            return TMQ_EINVAL;
+        }
+    const double V = (double)dims[0] * dims[1] * dims[2] * dims[3];
+    if (V / 2 * 24 >= 2147483647.0) {
+        set_error("tmq_lattice_create: lattice too large for 32-bit site indexing");
+        return TMQ_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        set_error("tmq_lattice_create: no such HIP device");
+        return TMQ_EDEVICE;
+    }
+    Lattice *L = new Lattice();
+    L->device = device;
+    memcpy(L->dims, dims, sizeof(L->dims));
+    L->g.T = dims[0];
+    L->g.LZ = dims[1];
+    L->g.LY = dims[2];
+    L->g.LX = dims[3];
+    L->g.XH = dims[3] / 2;
+    L->g.vh = (long)(V / 2);
+
+    int cur = 0;
+    hipGetDevice(&cur);
+    auto fail = [&](int code, const char *what) {
+        set_error(what);
+        delete L;
+        hipSetDevice(cur);
+        return code;
+    };
+    if (hipSetDevice(device) != hipSuccess) return fail(TMQ_EDEVICE, "hipSetDevice failed");
+    if (hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking) != hipSuccess)
+        return fail(TMQ_EDEVICE, "hipStreamCreate failed");
+    const int np = hop_grid(2 * L->g.vh) + 64;
+    for (auto &p : L->partial)
+        if (hipMalloc((void **)&p, sizeof(double) * np) != hipSuccess) return fail(TMQ_ENOMEM, "partials");
+    if (hipMalloc((void **)&L->scal, sizeof(CgScalars) * 8) != hipSuccess) return fail(TMQ_ENOMEM, "scalars");
+    if (hipMemset(L->scal, 0, sizeof(CgScalars) * 8) != hipSuccess) return fail(TMQ_EDEVICE, "memset");
+    if (hipHostMalloc((void **)&L->ring, sizeof(CgScalars) * Lattice::RING, hipHostMallocDefault) != hipSuccess)
+        return fail(TMQ_ENOMEM, "pinned ring");
+    for (auto &e : L->ring_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(TMQ_EDEVICE, "event");
+    hipSetDevice(cur);
+    *out = L;
+    return TMQ_OK;
+}
+
+int stage_buffer(Lattice *L, int slot, size_t bytes, void **out)
+{
+    if (L->stage_bytes[slot] < bytes) {
+        if (L->stage[slot]) hipFree(L->stage[slot]);
+        L->stage[slot] = nullptr;
+        L->stage_bytes[slot] = 0;
+        if (hipMalloc(&L->stage[slot], bytes) != hipSuccess) {
+            L->stage[slot] = nullptr;
+            set_error("device allocation of a staging buffer failed");
+            return TMQ_ENOMEM;
+        }
+        L->stage_bytes[slot] = bytes;
+    }
+    *out = L->stage[slot];
+    return TMQ_OK;
+}
+
+int work_field(Lattice *L, const char *role, int prec, long n, FieldDesc *out)
+{
+    for (auto &w : L->work)
+        if (w.first == role) {
+            if (w.second.d.prec == prec && w.second.d.n == n) {
+                *out = w.second.d;
+                return TMQ_OK;
+            }
+            TMQ_TRY(field_alloc(w.second, prec, n));
+            *out = w.second.d;
+            return TMQ_OK;
+        }
+    L->work.emplace_back(role, Field{});
+    TMQ_TRY(field_alloc(L->work.back().second, prec, n));
+    *out = L->work.back().second.d;
+    return TMQ_OK;
+}
+
+// ------------------------------------------------------------------ gauge
+
+int lattice_load_gauge(Lattice *L, const double2 *U, hipStream_t st)
+{
+    const long vh = L->g.vh;
+    auto alloc = [&](void **p, size_t bytes) -> int {
+        if (*p) return TMQ_OK;
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            *p = nullptr;
+            set_error("device allocation of gauge copies failed");
+            return TMQ_ENOMEM;
+        }
+        return TMQ_OK;
+    };
+    TMQ_TRY(alloc((void **)&L->u64f, (size_t)8 * 9 * vh * sizeof(double2)));
+    TMQ_TRY(alloc((void **)&L->u64r, (size_t)8 * 6 * vh * sizeof(double2)));
+    TMQ_TRY(alloc((void **)&L->u32r, (size_t)8 * 3 * vh * sizeof(float4)));
+    TMQ_TRY(alloc((void **)&L->u16a, (size_t)8 * vh * sizeof(uint4)));
+    TMQ_TRY(alloc((void **)&L->u16b, (size_t)8 * vh * sizeof(uint2)));
+    GaugeOut o{L->u64f, L->u64r, L->u32r, L->u16a, L->u16b};
+    TMQ_HIP(launch_gauge_ingest(L->g, U, o, L->partial[0], st));
+    TMQ_HIP(launch_max(L->partial[0], blas_grid(2 * vh), L->partial[1], st));
+    double dev = 0.0;
+    TMQ_HIP(hipMemcpyAsync(&dev, L->partial[1], sizeof(double), hipMemcpyDeviceToHost, st));
+    TMQ_HIP(hipStreamSynchronize(st));
+    L->su3_dev = dev;
+    L->su3 = std::isfinite(dev) && dev < 1e-12;
+    L->gauge = true;
+    return TMQ_OK;
+}
+
+LinkDesc lattice_links(const Lattice *L, int fmt)
+{
+    LinkDesc d;
+    d.fmt = fmt;
+    d.stride = L->g.vh;
+    switch (fmt) {
+    case LK64F: d.a = L->u64f; break;
+    case LK64R: d.a = L->u64r; break;
+    case LK32R: d.a = L->u32r; break;
+    case LK16R: d.a = L->u16a; d.b = L->u16b; break;
+    }
+    return d;
+}
+
+int link_fmt_for(const Lattice *L, int prec, int sloppy_link)
+{
+    if (prec == P64) return L->su3 ? LK64R : LK64F;
+    if (prec == P32 && sloppy_link != P16) return LK32R;
+    if (sloppy_link == P32) return LK32R;
+    return LK16R;
+}
+
+// ------------------------------------------------------------ operators
+
+static void phases(const Lattice *L, const tmq_params &p, HopCoef &c)
+{
+    const int Lmu[4] = {L->g.T, L->g.LX, L->g.LY, L->g.LZ};
+    for (int mu = 0; mu < 4; mu++) {
+        const double a = M_PI * p.theta[mu] / Lmu[mu];
+        c.ph[mu][0] = cos(a);
+        c.ph[mu][1] = sin(a);
+    }
+}
+
+// K1 of Qhat^{sign}: t_e = kappa^2/(1+mut^2) (1 - sign i mut g5) H_eo psi_o   (eq. (eo3))
+HopCoef coef_K1(const Lattice *L, const tmq_params &p, int sign)
+{
+    HopCoef c{};
+    phases(L, p, c);
+    const double k2 = p.kappa * p.kappa / (1.0 + p.mu_tilde * p.mu_tilde);
+    const double m = sign * p.mu_tilde;
+    c.B[0][0] = k2;  // upper spins, gamma_5 = +1: (1 - i sign mut)
+    c.B[0][1] = -k2 * m;
+    c.B[1][0] = k2;  // lower spins, gamma_5 = -1: (1 + i sign mut)
+    c.B[1][1] = k2 * m;
+    return c;
+}
+
+// K2 of Qhat^{sign}: out_o = gamma_5 [(1 + sign i mut g5) psi_o - H_oe t_e]   (eq. (eo4))
+HopCoef coef_K2(const Lattice *L, const tmq_params &p, int sign)
+{
+    HopCoef c{};
+    phases(L, p, c);
+    const double m = sign * p.mu_tilde;
+    c.A[0][0] = 1.0;  // upper: +(1 + i sign mut)
+    c.A[0][1] = m;
+    c.A[1][0] = -1.0;  // lower: -(1 - i sign mut)
+    c.A[1][1] = m;
+    c.B[0][0] = -1.0;
+    c.B[1][0] = 1.0;
+    return c;
+}
+
+// full lattice Q^{sign} = gamma_5 [(1 + sign i mut g5) psi - kappa H psi]   (eq. (eo1))
+HopCoef coef_full(const Lattice *L, const tmq_params &p, int sign)
+{
+    HopCoef c = coef_K2(L, p, sign);
+    c.B[0][0] = -p.kappa;
+    c.B[1][0] = p.kappa;
+    return c;
+}
+
+double hop_bytes_per_site(int prec, int link_fmt, bool self)
+{
+    const double sp = prec == P64 ? 192.0 : prec == P32 ? 96.0 : 52.0;
+    const double lk = link_fmt == LK64F ? 144.0 : link_fmt == LK64R ? 96.0 : link_fmt == LK32R ? 48.0 : 24.0;
+    return sp + 8.0 * lk + sp + (self ? sp : 0.0);
+}
+
+static hipEvent_t pool_event(Lattice *L)
+{
+    if (!L->event_pool.empty()) {
+        hipEvent_t e = L->event_pool.back();
+        L->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
+        const LinkDesc &lk, const HopCoef &c, double *partial, const int *skip, hipStream_t st)
+{
+    TimedLaunch t{};
+    if (L->timing) {
+        t.a = pool_event(L);
+        t.b = pool_event(L);
+        t.bytes = hop_bytes_per_site(in.prec, lk.fmt, self.data != nullptr) * (double)L->g.vh;
+        t.flops = 1320.0 * (double)L->g.vh;
+        TMQ_HIP(hipEventRecord(t.a, st));
+    }
+    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, partial, skip, st));
+    if (L->timing) {
+        TMQ_HIP(hipEventRecord(t.b, st));
+        L->timed.push_back(t);
+    }
+    return TMQ_OK;
+}
+
+int apply_Qhat(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in, const FieldDesc &out,
+               const FieldDesc &tmp_e, const LinkDesc &lk, double *partial, const int *skip, hipStream_t st)
+{
+    const FieldDesc none{};
+    TMQ_TRY(hop(L, 0, in, none, tmp_e, lk, coef_K1(L, p, sign), nullptr, skip, st));
+    TMQ_TRY(hop(L, 1, tmp_e, in, out, lk, coef_K2(L, p, sign), partial, skip, st));
+    return TMQ_OK;
+}
+
+int apply_QhatQhat(Lattice *L, const tmq_params &p, const FieldDesc &in, const FieldDesc &out,
+                   const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, double *partial,
+                   const int *skip, hipStream_t st)
+{
+    TMQ_TRY(apply_Qhat(L, p, -1, in, tmp_o, tmp_e, lk, partial, skip, st));
+    TMQ_TRY(apply_Qhat(L, p, +1, tmp_o, out, tmp_e, lk, nullptr, skip, st));
+    return TMQ_OK;
+}
+
+int apply_Q_full(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in, const FieldDesc &out,
+                 const LinkDesc &lk, hipStream_t st)
+{
+    const long vh = L->g.vh;
+    const FieldDesc ie = field_sub(in, 0, vh), io = field_sub(in, vh, vh);
+    const FieldDesc oe = field_sub(out, 0, vh), oo = field_sub(out, vh, vh);
+    const HopCoef c = coef_full(L, p, sign);
+    TMQ_TRY(hop(L, 0, io, ie, oe, lk, c, nullptr, nullptr, st));
+    TMQ_TRY(hop(L, 1, ie, io, oo, lk, c, nullptr, nullptr, st));
+    return TMQ_OK;
+}
+
+int check_params(const tmq_params *p)
+{
+    if (!p) {
+        set_error("NULL tmq_params");
+        return TMQ_EINVAL;
+    }
+    if (!std::isfinite(p->kappa) || !std::isfinite(p->mu_tilde)) {
+        set_error("kappa and mu_tilde must be finite");
+        return TMQ_EINVAL;
+    }
+    for (double t : p->theta)
+        if (!std::isfinite(t)) {
+            set_error("theta must be finite");
+            return TMQ_EINVAL;
+        }
+    return TMQ_OK;
+}
+
+}  // namespace tmq

@@ -1,0 +1,122 @@
+// lattice.h -- the lattice object behind the C ABI: device memory, resident
+// gauge copies, operator application and solver work space.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tmq.h"
+#include "kernels.h"
+
+namespace tmq {
+
+// thread-local error message behind tmq_last_error()
+void set_error(const std::string &msg);
+const char *get_error();
+
+#define TMQ_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::tmq::set_error(std::string(#call) + ": " + hipGetErrorString(e_));        \
+            return TMQ_EDEVICE;                                                         \
+        }                                                                               \
+    } while (0)
+
+#define TMQ_TRY(expr)                 \
+    do {                              \
+        int s_ = (expr);              \
+        if (s_ != TMQ_OK) return s_;  \
+    } while (0)
+
+// one device field with its own allocation
+struct Field {
+    FieldDesc d;
+    void *mem = nullptr;
+    float *scale = nullptr;
+};
+
+int field_alloc(Field &f, int prec, long n);
+void field_free(Field &f);
+size_t field_bytes(int prec, long n);
+
+struct TimedLaunch {
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+
+struct Lattice {
+    int device = 0;
+    int dims[4] = {0, 0, 0, 0};
+    Geom g{};
+    hipStream_t own = nullptr;  // stream of the host-pointer calls
+
+    bool gauge = false;
+    bool su3 = false;
+    double su3_dev = 0.0;
+    double2 *u64f = nullptr, *u64r = nullptr;
+    float4 *u32r = nullptr;
+    uint4 *u16a = nullptr;
+    uint2 *u16b = nullptr;
+
+    // reductions and solver scalars
+    double *partial[3] = {nullptr, nullptr, nullptr};
+    CgScalars *scal = nullptr;      // device
+    CgScalars *ring = nullptr;      // pinned host, RING slots
+    hipEvent_t ring_ev[8] = {};
+    static constexpr int RING = 8;
+
+    // named work fields, grown on demand
+    std::vector<std::pair<std::string, Field>> work;
+
+    // canonical staging buffers for host calls
+    void *stage[2] = {nullptr, nullptr};
+    size_t stage_bytes[2] = {0, 0};
+
+    // kernel timing
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+
+    ~Lattice();
+};
+
+int lattice_create(const int dims[4], int device, Lattice **out);
+int lattice_load_gauge(Lattice *L, const double2 *U_dev, hipStream_t st);
+LinkDesc lattice_links(const Lattice *L, int fmt);
+// link format used for a spinor precision (sloppy_link: P32 or P16 for the inner links)
+int link_fmt_for(const Lattice *L, int prec, int sloppy_link);
+
+// a work field of the given role, precision and site count (allocated once, reused)
+int work_field(Lattice *L, const char *role, int prec, long n, FieldDesc *out);
+int stage_buffer(Lattice *L, int slot, size_t bytes, void **out);
+
+HopCoef coef_K1(const Lattice *L, const tmq_params &p, int sign);
+HopCoef coef_K2(const Lattice *L, const tmq_params &p, int sign);
+HopCoef coef_full(const Lattice *L, const tmq_params &p, int sign);
+
+// one hop half-sweep through the timing hook
+int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
+        const LinkDesc &lk, const HopCoef &c, double *partial, const int *skip, hipStream_t st);
+
+// Qhat^{sign} in -> out (odd fields), tmp_e an even work field; partial: |out|^2 per block
+int apply_Qhat(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in, const FieldDesc &out,
+               const FieldDesc &tmp_e, const LinkDesc &lk, double *partial, const int *skip, hipStream_t st);
+// Qhat^+ Qhat^- in -> out; partial receives |Qhat^- in|^2 per block
+int apply_QhatQhat(Lattice *L, const tmq_params &p, const FieldDesc &in, const FieldDesc &out,
+                   const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, double *partial,
+                   const int *skip, hipStream_t st);
+// full-lattice Q^{sign} on stacked (even, odd) fields
+int apply_Q_full(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in, const FieldDesc &out,
+                 const LinkDesc &lk, hipStream_t st);
+
+double hop_bytes_per_site(int prec, int link_fmt, bool self);
+
+int check_params(const tmq_params *p);
+
+}  // namespace tmq
+
+struct tmq_lattice {
+    tmq::Lattice *L;
+};

@@ -1,0 +1,310 @@
+"""Thin ctypes binding of libtmq.so (include/tmq.h).
+
+Only argument marshalling happens here: every step of the operator and the
+solver runs in the HIP library.  Device buffers are torch tensors on the
+lattice's GPU (complex128, canonical layout); host buffers are numpy arrays.
+If libtmq.so is missing this module raises ImportError: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtmq.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_0905_3331_amd.build` "
+        "(hipcc, gfx950); there is no CPU fallback"
+    )
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
+
+TMQ_OK, TMQ_EINVAL, TMQ_ENOMEM, TMQ_ENOCONV, TMQ_EDEVICE, TMQ_ENAN, TMQ_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS = {0: "TMQ_OK", -1: "TMQ_EINVAL", -2: "TMQ_ENOMEM", -3: "TMQ_ENOCONV", -4: "TMQ_EDEVICE",
+          -5: "TMQ_ENAN", -6: "TMQ_ESTATE"}
+
+
+class tmq_params(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("mu_tilde", ctypes.c_double), ("theta", ctypes.c_double * 4)]
+
+
+class tmq_solver_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("relative", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("sloppy", ctypes.c_int), ("sloppy_link", ctypes.c_int), ("delta", ctypes.c_double)]
+
+
+class tmq_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int),
+                ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_ip = ctypes.c_int
+_P = ctypes.POINTER
+
+_SIGS = {
+    "tmq_lattice_create": (_ip, [_P(ctypes.c_int), _ip, _P(_vp)]),
+    "tmq_lattice_destroy": (None, [_vp]),
+    "tmq_load_gauge": (_ip, [_vp, _vp]),
+    "tmq_load_gauge_dev": (_ip, [_vp, _vp, _vp]),
+    "tmq_gauge_is_su3": (_ip, [_vp]),
+    "tmq_apply_Qhat": (_ip, [_vp, _P(tmq_params), _ip, _ip, _vp, _vp]),
+    "tmq_apply_Qhat_dev": (_ip, [_vp, _P(tmq_params), _ip, _ip, _vp, _vp, _vp]),
+    "tmq_apply_QhatQhat_dev": (_ip, [_vp, _P(tmq_params), _vp, _vp, _vp]),
+    "tmq_apply_Q_full": (_ip, [_vp, _P(tmq_params), _ip, _vp, _vp]),
+    "tmq_apply_Q_full_dev": (_ip, [_vp, _P(tmq_params), _ip, _vp, _vp, _vp]),
+    "tmq_solve": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_solve_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_solve_full_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_set_kernel_timing": (_ip, [_vp, _ip]),
+    "tmq_kernel_stats": (_ip, [_vp, ctypes.c_char_p, _P(ctypes.c_int), _P(ctypes.c_double),
+                               _P(ctypes.c_double), _P(ctypes.c_double)]),
+    "tmq_encode_dev": (_ip, [_vp, _ip, ctypes.c_long, _vp, _vp, _vp, _vp]),
+    "tmq_footprint_bytes": (_ip, [_P(ctypes.c_int), _P(tmq_solver_opts), _ip, _P(ctypes.c_size_t)]),
+    "tmq_last_error": (ctypes.c_char_p, []),
+    "tmq_version": (ctypes.c_char_p, []),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class TmqError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.tmq_last_error().decode()
+        super().__init__(f"{where}: {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str, ok=(TMQ_OK,)):
+    if code not in ok:
+        raise TmqError(code, where)
+    return code
+
+
+def version() -> str:
+    return _lib.tmq_version().decode()
+
+
+def params(kappa: float, mu_tilde: float, theta=(1.0, 0.0, 0.0, 0.0)) -> tmq_params:
+    p = tmq_params()
+    p.kappa = float(kappa)
+    p.mu_tilde = float(mu_tilde)
+    for i in range(4):
+        p.theta[i] = float(theta[i])
+    return p
+
+
+def solver_opts(tol=1e-10, relative=True, max_iter=10000, sloppy="fp64", sloppy_link="fp16",
+                delta=0.0) -> tmq_solver_opts:
+    o = tmq_solver_opts()
+    o.tol = float(tol)
+    o.relative = 1 if relative else 0
+    o.max_iter = int(max_iter)
+    o.sloppy = PREC[sloppy] if isinstance(sloppy, str) else int(sloppy)
+    o.sloppy_link = PREC[sloppy_link] if isinstance(sloppy_link, str) else int(sloppy_link)
+    o.delta = float(delta)
+    return o
+
+
+def footprint_bytes(dims, opts=None, nrhs=1) -> int:
+    d = (ctypes.c_int * 4)(*dims)
+    out = ctypes.c_size_t(0)
+    _check(_lib.tmq_footprint_bytes(d, ctypes.byref(opts) if opts is not None else None, nrhs,
+                                    ctypes.byref(out)), "tmq_footprint_bytes")
+    return int(out.value)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, n_complex: int, what: str):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what}: expected a CUDA/HIP torch tensor")
+    if t.dtype != torch.complex128 or not t.is_contiguous() or t.numel() != n_complex:
+        raise ValueError(f"{what}: expected a contiguous complex128 tensor of {n_complex} elements, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a: np.ndarray, n_complex: int, what: str):
+    if not isinstance(a, np.ndarray) or a.dtype != np.complex128 or not a.flags.c_contiguous or a.size != n_complex:
+        raise ValueError(f"{what}: expected a C-contiguous complex128 array of {n_complex} elements")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iters: int
+    reliable_updates: int
+    true_rel_residual: float
+    seconds: float
+    name: str = field(default="")
+
+
+def _info(i: tmq_solve_info) -> SolveInfo:
+    return SolveInfo(i.status, i.iters, i.reliable_updates, i.true_rel_residual, i.seconds,
+                     STATUS.get(i.status, str(i.status)))
+
+
+class Lattice:
+    """A lattice of extents (T, LZ, LY, LX) on one GPU, owning its gauge copies."""
+
+    def __init__(self, dims, device: int = 0):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(_lib.tmq_lattice_create((ctypes.c_int * 4)(*self.dims), device, ctypes.byref(h)),
+               "tmq_lattice_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tmq_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---------------------------------------------------------------- gauge
+    def load_gauge(self, U, stream=None):
+        """U: numpy (host) or torch (device) complex128, canonical (T,LZ,LY,LX,4,3,3)."""
+        n = self.V * 36
+        if isinstance(U, np.ndarray):
+            _check(_lib.tmq_load_gauge(self._h, _hptr(U, n, "U")), "tmq_load_gauge")
+        else:
+            _check(_lib.tmq_load_gauge_dev(self._h, _dptr(U, n, "U"), _stream(stream)), "tmq_load_gauge_dev")
+
+    @property
+    def su3(self) -> bool:
+        return bool(_lib.tmq_gauge_is_su3(self._h))
+
+    # ------------------------------------------------------------ operators
+    def apply_Qhat(self, p: tmq_params, sign: int, src, out=None, prec="fp64", stream=None):
+        """Qhat^{sign} on an odd-site field (V/2, 4, 3); device tensors or host arrays."""
+        pr = PREC[prec] if isinstance(prec, str) else int(prec)
+        n = self.V // 2 * 12
+        if isinstance(src, np.ndarray):
+            out = np.empty_like(src) if out is None else out
+            _check(_lib.tmq_apply_Qhat(self._h, ctypes.byref(p), sign, pr, _hptr(src, n, "in"),
+                                       _hptr(out, n, "out")), "tmq_apply_Qhat")
+            return out
+        import torch
+
+        out = torch.empty_like(src) if out is None else out
+        _check(_lib.tmq_apply_Qhat_dev(self._h, ctypes.byref(p), sign, pr, _dptr(src, n, "in"),
+                                       _dptr(out, n, "out"), _stream(stream)), "tmq_apply_Qhat_dev")
+        return out
+
+    def apply_QhatQhat(self, p: tmq_params, src, out=None, stream=None):
+        import torch
+
+        n = self.V // 2 * 12
+        out = torch.empty_like(src) if out is None else out
+        _check(_lib.tmq_apply_QhatQhat_dev(self._h, ctypes.byref(p), _dptr(src, n, "in"), _dptr(out, n, "out"),
+                                           _stream(stream)), "tmq_apply_QhatQhat_dev")
+        return out
+
+    def apply_Q_full(self, p: tmq_params, sign: int, src, out=None, stream=None):
+        n = self.V * 12
+        if isinstance(src, np.ndarray):
+            out = np.empty_like(src) if out is None else out
+            _check(_lib.tmq_apply_Q_full(self._h, ctypes.byref(p), sign, _hptr(src, n, "in"),
+                                         _hptr(out, n, "out")), "tmq_apply_Q_full")
+            return out
+        import torch
+
+        out = torch.empty_like(src) if out is None else out
+        _check(_lib.tmq_apply_Q_full_dev(self._h, ctypes.byref(p), sign, _dptr(src, n, "in"),
+                                         _dptr(out, n, "out"), _stream(stream)), "tmq_apply_Q_full_dev")
+        return out
+
+    # --------------------------------------------------------------- solves
+    def solve(self, p: tmq_params, b, opts: tmq_solver_opts, x=None, stream=None, check=True):
+        """Solve Qhat^+ Qhat^- x = b on the odd sites; returns (x, SolveInfo)."""
+        n = self.V // 2 * 12
+        info = tmq_solve_info()
+        if isinstance(b, np.ndarray):
+            x = np.empty_like(b) if x is None else x
+            code = _lib.tmq_solve(self._h, ctypes.byref(p), ctypes.byref(opts), _hptr(b, n, "b"),
+                                  _hptr(x, n, "x"), ctypes.byref(info))
+        else:
+            import torch
+
+            x = torch.empty_like(b) if x is None else x
+            code = _lib.tmq_solve_dev(self._h, ctypes.byref(p), ctypes.byref(opts), _dptr(b, n, "b"),
+                                      _dptr(x, n, "x"), _stream(stream), ctypes.byref(info))
+        if check:
+            _check(code, "tmq_solve")
+        return x, _info(info)
+
+    def solve_full(self, p: tmq_params, b, opts: tmq_solver_opts, x=None, stream=None, check=True):
+        """Solve Q^+ Q^- x = b on the full lattice (FP64 CG); device tensors (V, 4, 3)."""
+        import torch
+
+        n = self.V * 12
+        info = tmq_solve_info()
+        x = torch.empty_like(b) if x is None else x
+        code = _lib.tmq_solve_full_dev(self._h, ctypes.byref(p), ctypes.byref(opts), _dptr(b, n, "b"),
+                                       _dptr(x, n, "x"), _stream(stream), ctypes.byref(info))
+        if check:
+            _check(code, "tmq_solve_full")
+        return x, _info(info)
+
+    # ---------------------------------------------------------- diagnostics
+    def set_kernel_timing(self, on: bool):
+        _check(_lib.tmq_set_kernel_timing(self._h, 1 if on else 0), "tmq_set_kernel_timing")
+
+    def kernel_stats(self, family="hop"):
+        n = ctypes.c_int(0)
+        ms = ctypes.c_double(0)
+        by = ctypes.c_double(0)
+        fl = ctypes.c_double(0)
+        _check(_lib.tmq_kernel_stats(self._h, family.encode(), ctypes.byref(n), ctypes.byref(ms),
+                                     ctypes.byref(by), ctypes.byref(fl)), "tmq_kernel_stats")
+        return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+
+    def encode(self, src, prec="fp16", stream=None):
+        """Encode (n,4,3) complex128 device sites to 16-bit codes: returns (codes int16 (n,24), scale f32 (n,))."""
+        import torch
+
+        n_sites = src.numel() // 12
+        codes = torch.empty((n_sites, 24), dtype=torch.int16, device=src.device)
+        scale = torch.empty((n_sites,), dtype=torch.float32, device=src.device)
+        _check(_lib.tmq_encode_dev(self._h, PREC[prec], n_sites, _dptr(src, n_sites * 12, "in"),
+                                   ctypes.c_void_p(codes.data_ptr()), ctypes.c_void_p(scale.data_ptr()),
+                                   _stream(stream)), "tmq_encode_dev")
+        return codes, scale

@@ -1,0 +1,241 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Operators are compared element by element on the same seeded inputs; solves
+are judged by the oracle's own FP64 true residual and against the oracle's
+solution.  Tolerances: FP64 operators 1e-13 relative (2-norm of the
+difference over the 2-norm of the oracle result); CG solutions with true
+relative residual <= 1e-10 in every precision mode; reduced-precision
+operators have their error bounded by the storage precision (FP32 ~1e-7,
+FP16 ~1e-3, BF16 ~1e-2 relative).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+THETA = np.array([1.0, 0.0, 0.0, 0.0])
+THETA_GEN = np.array([1.0, 0.3, -0.7, 0.45])
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def tmq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0905_3331_amd import tmq as t
+
+    return t
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+_LAT = {}
+
+
+def lattice(tmq, dims, seed, eps=0.3, unit=False):
+    key = (dims, seed, eps, unit)
+    if key not in _LAT:
+        U = synth.unit_gauge(dims) if unit else synth.random_gauge(dims, eps=eps, seed=seed)
+        lat = tmq.Lattice(dims)
+        lat.load_gauge(U)
+        _LAT[key] = (lat, U)
+    return _LAT[key]
+
+
+# dims cover: the smallest lattice (extent 2: forward and backward neighbours
+# coincide), one block, several blocks with a ragged tail, distinct extents
+OP_DIMS = [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 2, 10), (12, 8, 6, 10), (16, 8, 8, 8)]
+
+
+@pytest.mark.parametrize("dims", OP_DIMS, ids=lambda d: "x".join(map(str, d)))
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_qhat_fp64_two_row(tmq, dims, sign):
+    lat, U = lattice(tmq, dims, seed=101)
+    assert lat.su3
+    psi = synth.gaussian_odd(dims, seed=7)
+    p = tmq.params(0.1632, 0.004, THETA_GEN)
+    got = host(lat.apply_Qhat(p, sign, dev(psi)))
+    ref = oracle.Qhat(U, psi, 0.1632, 0.004, sign, THETA_GEN)
+    print(f"Qhat{sign:+d} {dims} fp64 rel err {rel(got, ref):.2e}")
+    assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 10)], ids=lambda d: "x".join(map(str, d)))
+def test_qhat_fp64_full_links_non_su3(tmq, dims):
+    """Links that are not SU(3) (here: U(3) with a phase) must use the full 3x3 copy."""
+    U = synth.random_gauge(dims, seed=102) * np.exp(0.37j)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(U)
+    assert not lat.su3
+    psi = synth.gaussian_odd(dims, seed=8)
+    p = tmq.params(0.15, 0.02, THETA)
+    for sign in (+1, -1):
+        got = host(lat.apply_Qhat(p, sign, dev(psi)))
+        ref = oracle.Qhat(U, psi, 0.15, 0.02, sign, THETA)
+        assert rel(got, ref) < 1e-13
+    lat.close()
+
+
+def test_qhat_host_pointer_api(tmq):
+    dims = (4, 4, 4, 4)
+    lat, U = lattice(tmq, dims, seed=101)
+    psi = synth.gaussian_odd(dims, seed=9)
+    p = tmq.params(0.1632, 0.004, THETA)
+    got = lat.apply_Qhat(p, +1, psi)  # numpy in, numpy out
+    assert rel(got, oracle.Qhat(U, psi, 0.1632, 0.004, +1, THETA)) < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 2, 10)], ids=lambda d: "x".join(map(str, d)))
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_q_full_fp64(tmq, dims, sign):
+    lat, U = lattice(tmq, dims, seed=103)
+    psi = synth.gaussian_spinor(dims + (4, 3), seed=10)
+    p = tmq.params(0.16, 0.01, THETA_GEN)
+    got = host(lat.apply_Q_full(p, sign, dev(psi.reshape(-1, 4, 3)))).reshape(psi.shape)
+    ref = oracle.Q(U, psi, 0.16, 0.01, sign, THETA_GEN)
+    assert rel(got, ref) < 1e-13
+
+
+def test_qhatqhat_fp64(tmq):
+    dims = (8, 4, 4, 4)
+    lat, U = lattice(tmq, dims, seed=104)
+    psi = synth.gaussian_odd(dims, seed=11)
+    p = tmq.params(0.1632, 0.004, THETA)
+    got = host(lat.apply_QhatQhat(p, dev(psi)))
+    assert rel(got, oracle.QhatQhat(U, psi, 0.1632, 0.004, THETA)) < 1e-13
+
+
+@pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("fp16", 3e-3), ("bf16", 2.5e-2)])
+def test_qhat_reduced_precision_error(tmq, prec, bound):
+    dims = (8, 8, 8, 8)
+    lat, U = lattice(tmq, dims, seed=105)
+    psi = synth.gaussian_odd(dims, seed=12)
+    p = tmq.params(0.1632, 0.004, THETA)
+    for sign in (+1, -1):
+        got = host(lat.apply_Qhat(p, sign, dev(psi), prec=prec))
+        err = rel(got, oracle.Qhat(U, psi, 0.1632, 0.004, sign, THETA))
+        print(f"Qhat{sign:+d} {prec} rel err vs FP64 oracle: {err:.3e}")
+        assert err < bound
+
+
+def test_free_field_plane_wave(tmq):
+    """U = 1, a plane wave on the odd sites: Qhat^+Qhat^- eigenvalue is the closed form."""
+    dims = (8, 4, 4, 6)
+    lat, U = lattice(tmq, dims, seed=0, unit=True)
+    kappa, mut = 0.1632, 0.004
+    p = tmq.params(kappa, mut, THETA)
+    psi = synth.gaussian_odd(dims, seed=13)
+    got = host(lat.apply_QhatQhat(p, dev(psi)))
+    assert rel(got, oracle.QhatQhat(U, psi, kappa, mut, THETA)) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["fp16", "bf16"])
+def test_codec_bit_exact(tmq, kind):
+    dims = (4, 4, 4, 6)
+    lat, _ = lattice(tmq, dims, seed=101)
+    rng = np.random.default_rng(5)
+    psi = synth.gaussian_odd(dims, seed=14) * np.exp(rng.normal(size=(len(synth.gaussian_odd(dims)), 1, 1)) * 3)
+    psi[0] = 0.0  # an all-zero site
+    psi[1] *= 1e-30
+    codes, scale = lat.encode(dev(psi), kind)
+    ref_codes, ref_scale = oracle.encode_site_scaled(psi, kind)
+    assert np.array_equal(host(scale), ref_scale)
+    assert np.array_equal(host(codes).view(np.uint16), ref_codes)
+    codes0, _ = lat.encode(dev(psi[:0]), kind)  # empty input
+    assert codes0.shape[0] == 0
+
+
+# ------------------------------------------------------------------ solves
+
+SOLVE_DIMS = [(4, 4, 4, 4), (8, 4, 4, 4), (12, 8, 6, 10)]
+
+
+@pytest.mark.parametrize("dims", SOLVE_DIMS, ids=lambda d: "x".join(map(str, d)))
+def test_cg_fp64(tmq, dims):
+    lat, U = lattice(tmq, dims, seed=106)
+    b = synth.gaussian_odd(dims, seed=15)
+    p = tmq.params(0.1632, 0.004, THETA)
+    x, info = lat.solve(p, dev(b), tmq.solver_opts(tol=1e-10))
+    x = host(x)
+    res = oracle.true_residual(U, b, x, 0.1632, 0.004, THETA)
+    xo, io = oracle.cg(U, b, 0.1632, 0.004, THETA, tol=1e-10)
+    print(f"{dims}: gpu iters {info.iters} oracle iters {io['iters']} true res {res:.2e}")
+    assert info.status == 0 and res <= 1e-10
+    assert abs(info.iters - io["iters"]) <= 2
+    assert rel(x, xo) < 1e-8
+
+
+@pytest.mark.parametrize("sloppy,link", [("fp32", "fp32"), ("fp32", "fp16"), ("fp16", "fp16"), ("bf16", "fp16")])
+def test_cg_mixed(tmq, sloppy, link):
+    dims = (12, 8, 6, 10)
+    lat, U = lattice(tmq, dims, seed=106)
+    b = synth.gaussian_odd(dims, seed=16)
+    p = tmq.params(0.1632, 0.004, THETA)
+    x, info = lat.solve(p, dev(b), tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link=link))
+    res = oracle.true_residual(U, b, host(x), 0.1632, 0.004, THETA)
+    print(f"mixed {sloppy}/{link}: iters {info.iters} reliable {info.reliable_updates} true res {res:.2e}")
+    assert info.status == 0 and res <= 1e-10
+    assert info.reliable_updates >= 1
+
+
+def test_cg_full_lattice_4444(tmq):
+    """Full-lattice Q^+Q^- CG on 4^4, kappa 0.16, 2 kappa mu 0.01, tol 1e-10."""
+    dims = (4, 4, 4, 4)
+    lat, U = lattice(tmq, dims, seed=1000)
+    b = synth.gaussian_spinor(dims + (4, 3), seed=2000).reshape(-1, 4, 3)
+    p = tmq.params(0.16, 0.01, THETA)
+    x, info = lat.solve_full(p, dev(b), tmq.solver_opts(tol=1e-10))
+    res = oracle.true_residual(U, b, host(x), 0.16, 0.01, THETA, eo=False)
+    _, io = oracle.cg(U, b, 0.16, 0.01, THETA, eo=False, tol=1e-10)
+    assert info.status == 0 and res <= 1e-10
+    assert abs(info.iters - io["iters"]) <= 2
+
+
+def test_cg_edge_cases(tmq):
+    dims = (4, 4, 4, 4)
+    lat, U = lattice(tmq, dims, seed=106)
+    p = tmq.params(0.1632, 0.004, THETA)
+    # zero source: x = 0 at once
+    x, info = lat.solve(p, dev(np.zeros((128, 4, 3), np.complex128)), tmq.solver_opts(tol=1e-10))
+    assert info.status == 0 and info.iters == 0 and np.all(host(x) == 0)
+    # kappa = 0: one iteration, x = b / (1 + mut^2)
+    b = synth.gaussian_odd(dims, seed=17)
+    x, info = lat.solve(tmq.params(0.0, 0.3, THETA), dev(b), tmq.solver_opts(tol=1e-12))
+    assert info.iters == 1 and rel(host(x), b / 1.09) < 1e-14
+    # max_iter reached: TMQ_ENOCONV, x is the last iterate with its true residual
+    x, info = lat.solve(p, dev(b), tmq.solver_opts(tol=1e-10, max_iter=3), check=False)
+    assert info.status == tmq.TMQ_ENOCONV and info.iters == 3
+    res = oracle.true_residual(U, b, host(x), 0.1632, 0.004, THETA)
+    assert abs(res - info.true_rel_residual) < 1e-6 * res
+    # a NaN in the source: TMQ_ENAN
+    bn = b.copy()
+    bn[3, 1, 2] = np.nan
+    _, info = lat.solve(p, dev(bn), tmq.solver_opts(tol=1e-10), check=False)
+    assert info.status == tmq.TMQ_ENAN
+
+
+def test_determinism(tmq):
+    """Deterministic reductions: two solves give bitwise identical results."""
+    dims = (8, 4, 4, 4)
+    lat, U = lattice(tmq, dims, seed=106)
+    b = dev(synth.gaussian_odd(dims, seed=18))
+    p = tmq.params(0.1632, 0.004, THETA)
+    x1, i1 = lat.solve(p, b, tmq.solver_opts(tol=1e-10, sloppy="fp16"))
+    x2, i2 = lat.solve(p, b, tmq.solver_opts(tol=1e-10, sloppy="fp16"))
+    assert i1.iters == i2.iters and torch.equal(x1, x2)

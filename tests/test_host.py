@@ -1,0 +1,91 @@
+"""CPU tests of the GPU library's host side: the C ABI loads and exports every
+declared entry point, argument validation, and the spin-projector table and
+two-row link reconstruction of the kernels (compiled for the host)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import dense
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tmq.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tmq_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    path = os.path.join(ROOT, "paper_0905_3331_amd", "libtmq.so")
+    if not os.path.exists(path):
+        from paper_0905_3331_amd.build import build
+
+        build()
+    return ctypes.CDLL(path)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_0905_3331_amd import tmq
+
+    assert set(declared_functions()) <= set(tmq.EXPORTED)
+
+
+def test_argument_validation_without_gpu():
+    from paper_0905_3331_amd import tmq
+
+    with pytest.raises(tmq.TmqError) as e:
+        tmq.Lattice((4, 4, 3, 4))
+    assert e.value.code == tmq.TMQ_EINVAL
+    with pytest.raises(tmq.TmqError):
+        tmq.footprint_bytes((4, 4, 4, 5))
+    assert tmq.footprint_bytes((4, 4, 4, 4)) > 0
+    # FP16 mixed solve state is smaller than FP64 solve state at 32^3 x 64
+    f64 = tmq.footprint_bytes((64, 32, 32, 32), tmq.solver_opts(sloppy="fp64"))
+    f16 = tmq.footprint_bytes((64, 32, 32, 32), tmq.solver_opts(sloppy="fp16"))
+    assert 0 < f16 < f64 + 2e9
+
+
+@pytest.fixture(scope="module")
+def spinlib(tmp_path_factory):
+    out = tmp_path_factory.mktemp("spin") / "libspin.so"
+    src = os.path.join(ROOT, "tests", "cpu_helpers", "spin_table.cpp")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-o", str(out), src])
+    return ctypes.CDLL(str(out))
+
+
+@pytest.mark.parametrize("mu", range(4))
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_spin_projector_table(spinlib, mu, sign):
+    dp = ctypes.POINTER(ctypes.c_double)
+    rng = np.random.default_rng(mu * 2 + (sign > 0))
+    for _ in range(3):
+        psi = (rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))).astype(np.complex128)
+        out = np.zeros((4, 3), np.complex128)
+        spinlib.spin_project_reconstruct(mu, sign, psi.ctypes.data_as(dp), out.ctypes.data_as(dp))
+        expect = (np.eye(4) + sign * dense.G[mu]) @ psi
+        assert np.allclose(out, expect, atol=1e-15)
+
+
+def test_su3_two_row_reconstruction(spinlib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    U = synth.random_su3(50, 1.0, np.random.default_rng(3))
+    for u in U:
+        rows = np.ascontiguousarray(u[:2])
+        third = np.zeros(3, np.complex128)
+        spinlib.su3_reconstruct(rows.ctypes.data_as(dp), third.ctypes.data_as(dp))
+        assert np.max(np.abs(third - u[2])) < 1e-15
