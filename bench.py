@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Benchmark: even/odd twisted-mass CG at 32^3 x 64 on one MI355X.
+
+A step is one solve of Qhat^+ Qhat^- x = b to a true relative residual of
+1e-10 with the mixed-precision solver (FP16 spinors with per-site FP32 scale,
+FP16 two-row links, FP32 arithmetic, FP64 reliable updates), with the gauge
+field and the source already resident in HBM.  The hopping half-sweeps inside
+the timed steps are timed with HIP events on their launch stream; the
+reported value is their algorithmic bandwidth (each input spinor, link and
+output counted once).  The same solve in plain FP64 CG is timed beside it for
+the mixed-vs-FP64 time-to-solution, and the FP64 oracle is timed on the host
+cores on a bounded sample of the same operator.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+WORKLOAD = {
+    "dims": (64, 32, 32, 32),  # T, LZ, LY, LX
+    "kappa": 0.1632,
+    "mu_tilde": 0.004,
+    "theta": (1.0, 0.0, 0.0, 0.0),
+    "eps": 0.3,
+    "gauge_seed": 1002,
+    "source_seed": 2200,
+    "tol": 1e-10,
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("hop.hip", "fields.h", "spin.h", "devutil.h"):
+        with open(os.path.join(ROOT, "paper_0905_3331_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family, key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hop_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get(family, {}).get(key)
+
+
+def cpu_baseline(U, b, w, budget_s):
+    import numpy as np
+
+    import oracle
+
+    vh = b.shape[0]
+    bytes_qq = 2 * (1536 + 1728) * vh  # same algorithmic model, full 3x3 links (what the oracle reads)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.QhatQhat(U, b, w["kappa"], w["mu_tilde"], w["theta"])
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 50:
+            break
+        log(f"cpu oracle Qhat^+Qhat^- #{n}: {el:.1f}s")
+    return {
+        "value": round(bytes_qq * n / el / 1e9, 3),
+        "unit": "GB/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{n} applications of the FP64 oracle's Qhat^+Qhat^- (4 hopping half-sweeps) on the "
+                  f"32^3x64 workload, {el:.1f} s; bytes counted with the same algorithmic model",
+        "seconds_per_QhatQhat": round(el / n, 3),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sloppy", default="fp16", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--link", default="fp16", choices=["fp32", "fp16"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "a lattice would shard by domain decomposition, which is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0905_3331_amd import tmq
+
+    w = WORKLOAD
+    dims = w["dims"]
+    log(f"generating the {dims} gauge field (eps {w['eps']}, seed {w['gauge_seed']})")
+    U = synth.random_gauge(dims, eps=w["eps"], seed=w["gauge_seed"])
+    b = synth.gaussian_odd(dims, seed=w["source_seed"])
+    lat = tmq.Lattice(dims, device=0)
+    lat.load_gauge(U)
+    bd = torch.from_numpy(b).to("cuda:0")
+    xd = torch.empty_like(bd)
+    p = tmq.params(w["kappa"], w["mu_tilde"], w["theta"])
+    mixed = tmq.solver_opts(tol=w["tol"], sloppy=args.sloppy, sloppy_link=args.link)
+    fp64 = tmq.solver_opts(tol=w["tol"], sloppy="fp64")
+    vh = b.shape[0]
+
+    log(f"warmup: {args.warmup} mixed solves")
+    for _ in range(args.warmup):
+        lat.solve(p, bd, mixed, x=xd)
+    torch.cuda.synchronize()
+
+    # ---------------------------------------------------------- timed region
+    log(f"timed: {args.steps} mixed solves with per-launch hop timing")
+    lat.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        _, info = lat.solve(p, bd, mixed, x=xd)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = {f: lat.kernel_stats(f) for f in ("hop", "hop64", "hop16" if args.sloppy != "fp32" else "hop32")}
+    lat.set_kernel_timing(False)
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    hop = stats["hop"]
+    value = hop["bytes"] / (hop["ms"] * 1e-3) / 1e9
+    log(f"mixed: {ms_per_step:.2f} ms/solve, {infos[-1].iters} iters, {infos[-1].reliable_updates} reliable updates, "
+        f"hop {value:.0f} GB/s")
+
+    # un-instrumented time to solution, mixed and FP64
+    def timed_solves(opts, k):
+        for _ in range(max(1, args.warmup)):
+            lat.solve(p, bd, opts, x=xd)
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        for _ in range(k):
+            _, inf = lat.solve(p, bd, opts, x=xd)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - s) / k * 1e3, inf
+
+    mixed_ms, mixed_info = timed_solves(mixed, args.steps)
+    x_mixed = xd.cpu().numpy()
+    log(f"mixed (no events): {mixed_ms:.2f} ms/solve")
+    lat.set_kernel_timing(True)
+    fp64_ms_ev, fp64_info = timed_solves(fp64, 1)
+    st64 = lat.kernel_stats("hop64")
+    lat.set_kernel_timing(False)
+    fp64_ms, fp64_info = timed_solves(fp64, args.steps)
+    x_fp64 = xd.cpu().numpy()
+    log(f"fp64: {fp64_ms:.2f} ms/solve, {fp64_info.iters} iters")
+
+    dom_name = "hop16" if args.sloppy != "fp32" else "hop32"
+    dom = stats[dom_name]
+    dom_gbs = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    per_launch_bytes = dom["bytes"] / max(dom["launches"], 1)
+    traffic = measured_traffic(dom_name, "hbm_bytes_per_launch")
+
+    verify = None
+    if not args.no_verify:
+        import oracle
+
+        log("oracle true residuals of the GPU solutions (FP64, host)")
+        verify = {
+            "mixed_true_rel_residual": oracle.true_residual(U, b, x_mixed, w["kappa"], w["mu_tilde"], w["theta"]),
+            "fp64_true_rel_residual": oracle.true_residual(U, b, x_fp64, w["kappa"], w["mu_tilde"], w["theta"]),
+        }
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"cpu baseline: oracle on the host cores for ~{args.cpu_seconds:.0f} s")
+        cpu = cpu_baseline(U, b, w, args.cpu_seconds)
+
+    line = {
+        "metric": "Hopping-matrix GB/s (% HBM peak); mixed vs FP64 CG time-to-1e-10 at 32^3x64",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"even/odd twisted-mass CG on Qhat^+Qhat^-, 32^3x64, tol 1e-10; inner {args.sloppy} spinors "
+                        f"+ {args.link} two-row links with f32 arithmetic, f64 reliable updates",
+            "lattice": "32^3x64",
+            "kappa": w["kappa"],
+            "two_kappa_mu": w["mu_tilde"],
+            "theta": list(w["theta"]),
+            "links": "random SU(3) exp(i 0.3 H), reunitarised",
+            "source": "Gaussian complex, unit variance per component",
+            "tol": w["tol"],
+        },
+        "hbm_frac": round(value / HBM_PEAK_GBS, 4),
+        "hop_gflops": round(hop["flops"] / (hop["ms"] * 1e-3) / 1e9, 1),
+        "hop_launches": hop["launches"],
+        "mixed_ms_to_1e-10": round(mixed_ms, 3),
+        "mixed_iters": mixed_info.iters,
+        "mixed_reliable_updates": mixed_info.reliable_updates,
+        "fp64_ms_to_1e-10": round(fp64_ms, 3),
+        "fp64_iters": fp64_info.iters,
+        "speedup_mixed_vs_fp64": round(fp64_ms / mixed_ms, 3),
+        "fp64_hop_GBps": round(st64["bytes"] / (st64["ms"] * 1e-3) / 1e9, 1) if st64["ms"] > 0 else None,
+        "roofline": {
+            "kernel": f"hop half-sweep ({dom_name}: {args.sloppy} spinors, {args.link} two-row links)",
+            "bound": "hbm",
+            "achieved": round(dom_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(per_launch_bytes),
+            "avg_launch_us": round(dom["ms"] / max(dom["launches"], 1) * 1e3, 2),
+            "launches": dom["launches"],
+        },
+        "cpu_baseline": cpu,
+        "verify": verify,
+        "autotune": lat.tuning_report(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -88,7 +88,8 @@ typedef struct {
                             inner CG runs FP32 arithmetic on this spinor storage */
     tmq_prec sloppy_link;/* inner link storage, TMQ_FP32 or TMQ_FP16 (two-row); ignored for FP64 */
     double delta;        /* mixed precision: recompute the FP64 true residual whenever the
-                            iterated residual fell by this factor (0 < delta < 1); <= 0: default */
+                            iterated residual fell by this factor (0 < delta < 1); <= 0: default
+                            (1e-4 for FP32, 0.02 for FP16, 0.05 for BF16 storage) */
 } tmq_solver_opts;
 
 typedef struct {
@@ -169,14 +170,31 @@ int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_o
 /* ---------------------------------------------------------- diagnostics */
 
 /* Per-kernel timing with HIP events recorded on the launch stream around each
- * launch of the named kernel family ("hop" = every hopping half-sweep), off by
- * default.  tmq_kernel_stats returns the number of timed launches, their total
- * time in ms, and the algorithmic bytes and flops they move (each input
- * spinor, link and output counted once; 1320 flop per output site per
- * half-sweep).  Reading the stats synchronises the device and resets them. */
+ * hopping half-sweep launch, off by default.  tmq_set_kernel_timing
+ * synchronises the device and clears the records.  tmq_kernel_stats returns,
+ * for the launches recorded since then, their number, total time in ms, and
+ * the algorithmic bytes and flops they move (each input spinor, link and
+ * output counted once; 1320 flop per output site per half-sweep).  family is
+ * "hop" (all), "hop64", "hop32" or "hop16" (FP16 and BF16 spinor storage).
+ * Reading the stats synchronises the device. */
 int tmq_set_kernel_timing(tmq_lattice *lat, int on);
 int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double *total_ms,
                      double *bytes, double *flops);
+
+/* Calibration: copy `bytes` (rounded down to 16) between two device buffers
+ * with a plain 16-byte-per-lane kernel, `reps` times after one warm-up, and
+ * report the achieved read + write bandwidth in GB/s.  Allocates and frees
+ * its own buffers on `device`. */
+int tmq_stream_copy(int device, size_t bytes, int reps, double *gbps);
+
+/* JSON text of the autotuner's choices so far: for every (spinor storage,
+ * link format) used on this lattice, the hop kernel variant picked and the
+ * measured microseconds per launch of each variant.  The autotuner times the
+ * variants (0: compiler register allocation, 1: 0 with non-temporal link
+ * loads, 2: at least 2 waves per SIMD, 3: 2 with non-temporal link loads) at
+ * the first launch of each format on a lattice; TMQ_HOP_VARIANT=0..3 in the
+ * environment forces one.  TMQ_EINVAL if buf (len bytes) is too small. */
+int tmq_tuning_report(tmq_lattice *lat, char *buf, size_t len);
 
 /* Encode n_sites canonical complex128 sites (12 complex each) into the device
  * FP16 (prec = TMQ_FP16) or BF16 storage and export the codes in canonical

@@ -1,6 +1,7 @@
 // api.cpp -- the extern "C" entry points declared in include/tmq.h.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -343,10 +344,23 @@ int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_o
     return s;
 }
 
+static void recycle_timed(Lattice *L)
+{
+    for (auto &t : L->timed) {
+        L->event_pool.push_back(t.a);
+        L->event_pool.push_back(t.b);
+    }
+    L->timed.clear();
+}
+
 int tmq_set_kernel_timing(tmq_lattice *lat, int on)
 {
     TMQ_TRY(check_lat(lat, false));
-    lat->L->timing = on != 0;
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    TMQ_HIP(hipDeviceSynchronize());
+    recycle_timed(L);
+    L->timing = on != 0;
     return TMQ_OK;
 }
 
@@ -354,8 +368,13 @@ int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double
                      double *flops)
 {
     TMQ_TRY(check_lat(lat, false));
-    if (!family || strcmp(family, "hop") != 0) {
-        set_error("tmq_kernel_stats: unknown kernel family (known: \"hop\")");
+    int want = -2;  // -1: every hop launch
+    if (family && strcmp(family, "hop") == 0) want = -1;
+    if (family && strcmp(family, "hop64") == 0) want = P64;
+    if (family && strcmp(family, "hop32") == 0) want = P32;
+    if (family && strcmp(family, "hop16") == 0) want = P16;
+    if (want == -2) {
+        set_error("tmq_kernel_stats: unknown kernel family (hop, hop64, hop32, hop16)");
         return TMQ_EINVAL;
     }
     Lattice *L = lat->L;
@@ -364,21 +383,72 @@ int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double
     double ms = 0, by = 0, fl = 0;
     int n = 0;
     for (auto &t : L->timed) {
+        const int fam = t.prec == PB16 ? P16 : t.prec;
+        if (want >= 0 && fam != want) continue;
         float e = 0.f;
         TMQ_HIP(hipEventElapsedTime(&e, t.a, t.b));
         ms += e;
         by += t.bytes;
         fl += t.flops;
         n++;
-        L->event_pool.push_back(t.a);
-        L->event_pool.push_back(t.b);
     }
-    L->timed.clear();
     if (launches) *launches = n;
     if (total_ms) *total_ms = ms;
     if (bytes) *bytes = by;
     if (flops) *flops = fl;
     return TMQ_OK;
+}
+
+int tmq_stream_copy(int device, size_t bytes, int reps, double *gbps)
+{
+    if (bytes < 16 || reps < 1 || !gbps) {
+        set_error("tmq_stream_copy: bytes >= 16, reps >= 1 and an output pointer are required");
+        return TMQ_EINVAL;
+    }
+    bytes &= ~(size_t)15;
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+        set_error("tmq_stream_copy: no such HIP device");
+        return TMQ_EDEVICE;
+    }
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int status = TMQ_OK;
+    float ms = 0.f;
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+        set_error("tmq_stream_copy: allocation failed");
+        status = TMQ_ENOMEM;
+    } else if (hipMemset(a, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+               hipEventCreate(&e1) != hipSuccess || launch_stream_copy(a, b, bytes, nullptr) != hipSuccess ||
+               hipEventRecord(e0, nullptr) != hipSuccess) {
+        set_error("tmq_stream_copy: HIP call failed");
+        status = TMQ_EDEVICE;
+    } else {
+        for (int r = 0; r < reps && status == TMQ_OK; r++)
+            if (launch_stream_copy(a, b, bytes, nullptr) != hipSuccess) status = TMQ_EDEVICE;
+        if (status == TMQ_OK && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            status = TMQ_EDEVICE;
+        if (status != TMQ_OK) set_error("tmq_stream_copy: HIP call failed");
+    }
+    if (status == TMQ_OK) *gbps = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (a) hipFree(a);
+    if (b) hipFree(b);
+    return status;
+}
+
+int tmq_tuning_report(tmq_lattice *lat, char *buf, size_t len)
+{
+    TMQ_TRY(check_lat(lat, false));
+    if (!buf || len == 0) {
+        set_error("tmq_tuning_report: NULL buffer");
+        return TMQ_EINVAL;
+    }
+    const std::string s = tuning_report(lat->L);
+    snprintf(buf, len, "%s", s.c_str());
+    return s.size() < len ? TMQ_OK : TMQ_EINVAL;
 }
 
 int tmq_encode_dev(tmq_lattice *lat, tmq_prec prec, long n_sites, const double *in, uint16_t *codes, float *scale,

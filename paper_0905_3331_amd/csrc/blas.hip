@@ -214,10 +214,16 @@ __device__ __forceinline__ double det_sum(const double *partial, int n, double *
 
 __device__ __forceinline__ int finite(double v) { return isfinite(v) ? 1 : 0; }
 
+// publish != nullptr: thread 0 finally copies the scalars to that (host-mapped)
+// slot, also when the kernel is skipped, so the host always sees the state.
 __global__ __launch_bounds__(SC_THREADS) void k_scalar(int op, const double *partial, int n, CgScalars *s,
-                                                       double tol2, int relative, const int *skip)
+                                                       double tol2, int relative, const int *skip,
+                                                       CgScalars *publish)
 {
-    if (skip && *skip) return;
+    if (skip && *skip) {
+        if (publish && threadIdx.x == 0) *publish = *s;
+        return;
+    }
     __shared__ double sh[SC_THREADS / 64];
     const double sum = det_sum(partial, n, sh);
     if (threadIdx.x != 0) return;
@@ -256,6 +262,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_scalar(int op, const double *par
         s->done = (sum < s->target || sum == 0.0 || s->nan) ? 1 : 0;
         break;
     }
+    if (publish) *publish = *s;
 }
 
 constexpr int SUM_THREADS = 1024;
@@ -353,9 +360,25 @@ hipError_t launch_axpy_host(double a, const FieldDesc &x, const FieldDesc &y, hi
 }
 
 hipError_t launch_scalar(int op, const double *partial, int n, CgScalars *s, double tol2, int relative,
-                         const int *skip, hipStream_t st)
+                         const int *skip, hipStream_t st, CgScalars *publish)
 {
-    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(SC_THREADS), 0, st, op, partial, n, s, tol2, relative, skip);
+    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(SC_THREADS), 0, st, op, partial, n, s, tol2, relative, skip,
+                       publish);
+    return hipGetLastError();
+}
+
+// plain streaming copy, 16 bytes per lane, for bandwidth calibration
+__global__ __launch_bounds__(256) void k_stream_copy(const float4 *__restrict__ a, float4 *__restrict__ b, long n)
+{
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
+{
+    const long n = (long)(bytes / 16);
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const float4 *)src,
+                       (float4 *)dst, n);
     return hipGetLastError();
 }
 

@@ -25,6 +25,52 @@
 
 namespace tmq {
 
+// ------------------------------------------------------- streaming loads
+// Loads of data that is used once per kernel (the links) can bypass the
+// caches' retention (non-temporal), leaving L2 and the Infinity Cache to the
+// spinors, which every site reads 8 times through its neighbours.
+typedef double nv_d2 __attribute__((ext_vector_type(2)));
+typedef float nv_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nv_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nv_u2 __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ double2 ld(const double2 *p)
+{
+    if (NT) {
+        nv_d2 v = __builtin_nontemporal_load((const nv_d2 *)p);
+        return make_double2(v.x, v.y);
+    }
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ float4 ld(const float4 *p)
+{
+    if (NT) {
+        nv_f4 v = __builtin_nontemporal_load((const nv_f4 *)p);
+        return make_float4(v.x, v.y, v.z, v.w);
+    }
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ uint4 ld(const uint4 *p)
+{
+    if (NT) {
+        nv_u4 v = __builtin_nontemporal_load((const nv_u4 *)p);
+        return make_uint4(v.x, v.y, v.z, v.w);
+    }
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ uint2 ld(const uint2 *p)
+{
+    if (NT) {
+        nv_u2 v = __builtin_nontemporal_load((const nv_u2 *)p);
+        return make_uint2(v.x, v.y);
+    }
+    return *p;
+}
+
 // ------------------------------------------------------------ 16-bit codes
 
 __device__ __forceinline__ float h16_to_f32(uint16_t c) { return __half2float(__ushort_as_half(c)); }
@@ -157,13 +203,13 @@ struct L64F {
     using real = double;
     const double2 *p;
     long stride;
-    template <typename R>
+    template <bool NT, typename R>
     __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
     {
         const double2 *q = p + (long)(par * 4 + mu) * 9 * stride + h;
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            double2 v = q[k * stride];
+            double2 v = ld<NT>(q + k * stride);
             u.e[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
         }
     }
@@ -173,13 +219,13 @@ struct L64R {
     using real = double;
     const double2 *p;
     long stride;
-    template <typename R>
+    template <bool NT, typename R>
     __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
     {
         const double2 *q = p + (long)(par * 4 + mu) * 6 * stride + h;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            double2 v = q[k * stride];
+            double2 v = ld<NT>(q + k * stride);
             u.e[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
         }
         su3_third_row(u);
@@ -190,13 +236,13 @@ struct L32R {
     using real = float;
     const float4 *p;
     long stride;
-    template <typename R>
+    template <bool NT, typename R>
     __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
     {
         const float4 *q = p + (long)(par * 4 + mu) * 3 * stride + h;
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            float4 v = q[k * stride];
+            float4 v = ld<NT>(q + k * stride);
             u.e[(2 * k) / 3][(2 * k) % 3] = cx<R>{(R)v.x, (R)v.y};
             u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = cx<R>{(R)v.z, (R)v.w};
         }
@@ -209,12 +255,12 @@ struct L16R {
     const uint4 *a;  // complex 0..3 of rows 0,1 (row-major)
     const uint2 *b;  // complex 4, 5
     long stride;
-    template <typename R>
+    template <bool NT, typename R>
     __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
     {
         long o = (long)(par * 4 + mu) * stride + h;
-        uint4 va = a[o];
-        uint2 vb = b[o];
+        uint4 va = ld<NT>(a + o);
+        uint2 vb = ld<NT>(b + o);
         uint32_t w[6] = {va.x, va.y, va.z, va.w, vb.x, vb.y};
 #pragma unroll
         for (int k = 0; k < 6; k++)

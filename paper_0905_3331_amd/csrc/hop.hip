@@ -45,7 +45,7 @@ struct HopArgs {
     const int *skip;
 };
 
-template <int MU, class SP, class LK, typename R>
+template <int MU, bool NT, class SP, class LK, typename R>
 __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, spinor<R> &acc, long h, long hf, long hb)
 {
     const cx<R> ph = {(R)a.c.ph[MU][0], (R)a.c.ph[MU][1]};
@@ -55,19 +55,24 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, spinor<R> &acc
     // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu); U at the output site
     a.in.load(hf, s);
     project<MU, +1>(s, p);
-    a.lk.load(a.out_par, MU, h, u);
+    a.lk.template load<NT>(a.out_par, MU, h, u);
     link_mul<false>(u, p, ph, w);
     reconstruct_add<MU, +1>(acc, w);
     // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu); U at the neighbour
     a.in.load(hb, s);
     project<MU, -1>(s, p);
-    a.lk.load(a.out_par ^ 1, MU, hb, u);
+    a.lk.template load<NT>(a.out_par ^ 1, MU, hb, u);
     link_mul<true>(u, p, conj(ph), w);
     reconstruct_add<MU, -1>(acc, w);
 }
 
-template <class SP, class LK, bool SELF, bool NORM>
-__global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
+// Variant bits: W > 0 asks the compiler for at least W waves per SIMD (a
+// register budget of 512 / W per lane), W = 0 leaves the choice to the
+// compiler; NT makes the link loads non-temporal.  The autotuner picks the
+// fastest variant per format and lattice.
+template <class SP, class LK, bool SELF, bool NORM, int W, bool NT>
+__global__ __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, W > 0 ? 8 : 8)))
+void hop_kernel(HopArgs<SP, LK> a)
 {
     using R = typename LK::real;
     if (a.skip && *a.skip) return;
@@ -94,10 +99,10 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 #pragma unroll
             for (int j = 0; j < 3; j++) acc.c[i][j] = cx<R>{R(0), R(0)};
 
-        hop_dir<0>(a, acc, h, t + 1 == g.T ? h - (g.T - 1) * stt : h + stt, t == 0 ? h + (g.T - 1) * stt : h - stt);
-        hop_dir<1>(a, acc, h, row + ((x + 1 == g.LX ? 0 : x + 1) >> 1), row + ((x == 0 ? g.LX - 1 : x - 1) >> 1));
-        hop_dir<2>(a, acc, h, y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy, y == 0 ? h + (g.LY - 1) * sy : h - sy);
-        hop_dir<3>(a, acc, h, z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz, z == 0 ? h + (g.LZ - 1) * sz : h - sz);
+        hop_dir<0, NT>(a, acc, h, t + 1 == g.T ? h - (g.T - 1) * stt : h + stt, t == 0 ? h + (g.T - 1) * stt : h - stt);
+        hop_dir<1, NT>(a, acc, h, row + ((x + 1 == g.LX ? 0 : x + 1) >> 1), row + ((x == 0 ? g.LX - 1 : x - 1) >> 1));
+        hop_dir<2, NT>(a, acc, h, y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy, y == 0 ? h + (g.LY - 1) * sy : h - sy);
+        hop_dir<3, NT>(a, acc, h, z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz, z == 0 ? h + (g.LZ - 1) * sz : h - sz);
 
         spinor<R> o;
         const cx<R> Bu = {(R)a.c.B[0][0], (R)a.c.B[0][1]}, Bd = {(R)a.c.B[1][0], (R)a.c.B[1][1]};
@@ -162,10 +167,23 @@ L32R make_lk<L32R>(const LinkDesc &l) { return L32R{(const float4 *)l.a, l.strid
 template <>
 L16R make_lk<L16R>(const LinkDesc &l) { return L16R{(const uint4 *)l.a, (const uint2 *)l.b, l.stride}; }
 
+template <class SP, class LK, int W, bool NT>
+static void go_w(const HopArgs<SP, LK> &a, bool s, bool n, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (s && n)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, W, NT>), grid, block, 0, st, a);
+    else if (s)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, W, NT>), grid, block, 0, st, a);
+    else if (n)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true, W, NT>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, W, NT>), grid, block, 0, st, a);
+}
+
 template <class SP, class LK>
 static hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
                      const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, double *partial,
-                     const int *skip, hipStream_t st)
+                     const int *skip, int variant, hipStream_t st)
 {
     HopArgs<SP, LK> a;
     a.g = g;
@@ -179,40 +197,40 @@ static hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const Fiel
     a.skip = skip;
     dim3 grid(hop_grid(g.vh)), block(HOP_BLOCK);
     const bool s = self.data != nullptr, n = partial != nullptr;
-    if (s && n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true>), grid, block, 0, st, a);
-    else if (s)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false>), grid, block, 0, st, a);
-    else if (n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false>), grid, block, 0, st, a);
+    switch (variant) {
+    case 1: go_w<SP, LK, 0, true>(a, s, n, grid, block, st); break;
+    case 2: go_w<SP, LK, 2, false>(a, s, n, grid, block, st); break;
+    case 3: go_w<SP, LK, 2, true>(a, s, n, grid, block, st); break;
+    default: go_w<SP, LK, 0, false>(a, s, n, grid, block, st); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, double *partial,
-                      const int *skip, hipStream_t st)
+                      const int *skip, int variant, hipStream_t st)
 {
     if (in.prec != out.prec || (self.data && self.prec != in.prec)) return hipErrorInvalidValue;
+#define GO(SPT, LKT) return go<SPT, LKT>(g, out_par, in, self, out, lk, c, partial, skip, variant, st)
     switch (in.prec) {
     case P64:
-        if (lk.fmt == LK64F) return go<SpF64, L64F>(g, out_par, in, self, out, lk, c, partial, skip, st);
-        if (lk.fmt == LK64R) return go<SpF64, L64R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        if (lk.fmt == LK64F) GO(SpF64, L64F);
+        if (lk.fmt == LK64R) GO(SpF64, L64R);
         break;
     case P32:
-        if (lk.fmt == LK32R) return go<SpF32, L32R>(g, out_par, in, self, out, lk, c, partial, skip, st);
-        if (lk.fmt == LK16R) return go<SpF32, L16R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        if (lk.fmt == LK32R) GO(SpF32, L32R);
+        if (lk.fmt == LK16R) GO(SpF32, L16R);
         break;
     case P16:
-        if (lk.fmt == LK16R) return go<SpH16, L16R>(g, out_par, in, self, out, lk, c, partial, skip, st);
-        if (lk.fmt == LK32R) return go<SpH16, L32R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        if (lk.fmt == LK16R) GO(SpH16, L16R);
+        if (lk.fmt == LK32R) GO(SpH16, L32R);
         break;
     case PB16:
-        if (lk.fmt == LK16R) return go<SpB16, L16R>(g, out_par, in, self, out, lk, c, partial, skip, st);
-        if (lk.fmt == LK32R) return go<SpB16, L32R>(g, out_par, in, self, out, lk, c, partial, skip, st);
+        if (lk.fmt == LK16R) GO(SpB16, L16R);
+        if (lk.fmt == LK32R) GO(SpB16, L32R);
         break;
     }
+#undef GO
     return hipErrorInvalidValue;
 }
 

@@ -78,9 +78,12 @@ int blas_grid(long n);
 // 1 - out_par; `self` (may have data == nullptr) holds parity out_par.
 // partial != nullptr: per-block sums of |out|^2 written to partial[0..hop_grid(n)).
 // skip != nullptr: the launch does nothing when *skip != 0.
+// variant: 0 = compiler's register allocation, 1 = same with non-temporal link
+// loads, 2 = at least 2 waves per SIMD, 3 = 2 waves and non-temporal links
+constexpr int HOP_VARIANTS = 4;
 hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, double *partial,
-                      const int *skip, hipStream_t st);
+                      const int *skip, int variant, hipStream_t st);
 
 // BLAS-1 over the sites of the given views; every launch with `partial` writes
 // blas_grid(n) per-block sums.  Scalars come from device memory.
@@ -110,7 +113,9 @@ enum ScalarOp {
     SC_RELIABLE = 3  // rr = sum (true residual) ; beta = rr / rr_prev ; done = rr < target
 };
 hipError_t launch_scalar(int op, const double *partial, int n, CgScalars *s, double tol2, int relative,
-                         const int *skip, hipStream_t st);
+                         const int *skip, hipStream_t st, CgScalars *publish = nullptr);
+// b = a, bytes / 16 lanes of 16 bytes (bandwidth calibration)
+hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 // out[0] = deterministic sum of partial[0..n)
 hipError_t launch_sum(const double *partial, int n, double *out, hipStream_t st);
 

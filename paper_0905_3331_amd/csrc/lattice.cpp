@@ -2,6 +2,8 @@
 #include "lattice.h"
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace tmq {
@@ -101,6 +103,14 @@ int lattice_create(const int dims[4], int device, Lattice **out)
     }
     Lattice *L = new Lattice();
     L->device = device;
+    for (int k = 0; k < 16; k++) {
+        L->hop_variant[k] = -1;
+        for (int v = 0; v < HOP_VARIANTS; v++) L->hop_tune_us[k][v] = -1.f;
+    }
+    if (const char *fv = getenv("TMQ_HOP_VARIANT")) {
+        const int v = atoi(fv);
+        if (v >= 0 && v < HOP_VARIANTS) L->forced_variant = v;
+    }
     memcpy(L->dims, dims, sizeof(L->dims));
     L->g.T = dims[0];
     L->g.LZ = dims[1];
@@ -125,8 +135,10 @@ int lattice_create(const int dims[4], int device, Lattice **out)
         if (hipMalloc((void **)&p, sizeof(double) * np) != hipSuccess) return fail(TMQ_ENOMEM, "partials");
     if (hipMalloc((void **)&L->scal, sizeof(CgScalars) * 8) != hipSuccess) return fail(TMQ_ENOMEM, "scalars");
     if (hipMemset(L->scal, 0, sizeof(CgScalars) * 8) != hipSuccess) return fail(TMQ_EDEVICE, "memset");
-    if (hipHostMalloc((void **)&L->ring, sizeof(CgScalars) * Lattice::RING, hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&L->ring, sizeof(CgScalars) * Lattice::RING, hipHostMallocMapped) != hipSuccess)
         return fail(TMQ_ENOMEM, "pinned ring");
+    if (hipHostGetDevicePointer((void **)&L->ring_dev, L->ring, 0) != hipSuccess)
+        return fail(TMQ_EDEVICE, "device view of the pinned ring");
     for (auto &e : L->ring_ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(TMQ_EDEVICE, "event");
     hipSetDevice(cur);
@@ -291,18 +303,75 @@ static hipEvent_t pool_event(Lattice *L)
     return e;
 }
 
+// Time every register-budget variant of this hop launch (same operands, the
+// reduction redirected to a scratch array, no skip flag) and keep the fastest
+// for this lattice, spinor precision and link format.
+static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const FieldDesc &self,
+                    const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, bool norm, hipStream_t st)
+{
+    hipEvent_t e0 = pool_event(L), e1 = pool_event(L);
+    double *tp = norm ? L->partial[2] : nullptr;
+    const int reps = L->g.vh >= (1L << 18) ? 3 : 10;
+    int best = 0;
+    float best_us = 0.f;
+    for (int v = 0; v < HOP_VARIANTS; v++) {
+        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, tp, nullptr, v, st));
+        TMQ_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; r++) TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, tp, nullptr, v, st));
+        TMQ_HIP(hipEventRecord(e1, st));
+        TMQ_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const float us = ms * 1e3f / reps;
+        L->hop_tune_us[key][v] = us;
+        if (v == 0 || us < best_us) {
+            best = v;
+            best_us = us;
+        }
+    }
+    L->event_pool.push_back(e0);
+    L->event_pool.push_back(e1);
+    L->hop_variant[key] = best;
+    return TMQ_OK;
+}
+
+std::string tuning_report(const Lattice *L)
+{
+    static const char *pn[4] = {"fp64", "fp32", "fp16", "bf16"};
+    static const char *ln[4] = {"fp64_full", "fp64_two_row", "fp32_two_row", "fp16_two_row"};
+    std::string s = "{\"hop\": [";
+    bool first = true;
+    for (int k = 0; k < 16; k++) {
+        if (L->hop_variant[k] < 0) continue;
+        char buf[256];
+        snprintf(buf, sizeof(buf), "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"variant\": %d, \"us\": [%.2f, %.2f, %.2f, %.2f]}",
+                 first ? "" : ", ", pn[k / 4], ln[k % 4], L->hop_variant[k], L->hop_tune_us[k][0],
+                 L->hop_tune_us[k][1], L->hop_tune_us[k][2], L->hop_tune_us[k][3]);
+        s += buf;
+        first = false;
+    }
+    s += "]}";
+    return s;
+}
+
 int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
         const LinkDesc &lk, const HopCoef &c, double *partial, const int *skip, hipStream_t st)
 {
+    const int key = in.prec * 4 + lk.fmt;
+    if (L->forced_variant >= 0)
+        L->hop_variant[key] = L->forced_variant;
+    else if (L->hop_variant[key] < 0)
+        TMQ_TRY(tune_hop(L, key, out_par, in, self, out, lk, c, partial != nullptr, st));
     TimedLaunch t{};
     if (L->timing) {
         t.a = pool_event(L);
         t.b = pool_event(L);
         t.bytes = hop_bytes_per_site(in.prec, lk.fmt, self.data != nullptr) * (double)L->g.vh;
         t.flops = 1320.0 * (double)L->g.vh;
+        t.prec = in.prec;
         TMQ_HIP(hipEventRecord(t.a, st));
     }
-    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, partial, skip, st));
+    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, partial, skip, L->hop_variant[key], st));
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));
         L->timed.push_back(t);

@@ -44,6 +44,7 @@ size_t field_bytes(int prec, long n);
 struct TimedLaunch {
     hipEvent_t a, b;
     double bytes, flops;
+    int prec;  // spinor storage of the launch
 };
 
 struct Lattice {
@@ -63,7 +64,8 @@ struct Lattice {
     // reductions and solver scalars
     double *partial[3] = {nullptr, nullptr, nullptr};
     CgScalars *scal = nullptr;      // device
-    CgScalars *ring = nullptr;      // pinned host, RING slots
+    CgScalars *ring = nullptr;      // pinned host-mapped, RING slots (host view)
+    CgScalars *ring_dev = nullptr;  // device view of the same slots
     hipEvent_t ring_ev[8] = {};
     static constexpr int RING = 8;
 
@@ -73,6 +75,11 @@ struct Lattice {
     // canonical staging buffers for host calls
     void *stage[2] = {nullptr, nullptr};
     size_t stage_bytes[2] = {0, 0};
+
+    // autotuned hop variant per (spinor precision, link format); -1 = not tuned yet
+    int hop_variant[16];
+    float hop_tune_us[16][HOP_VARIANTS];
+    int forced_variant = -1;  // TMQ_HOP_VARIANT in the environment
 
     // kernel timing
     bool timing = false;
@@ -114,6 +121,7 @@ int apply_Q_full(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in,
 double hop_bytes_per_site(int prec, int link_fmt, bool self);
 
 int check_params(const tmq_params *p);
+std::string tuning_report(const Lattice *L);
 
 }  // namespace tmq
 

@@ -37,13 +37,14 @@ struct SolveWork {
 };
 
 static int reliable_update(Lattice *L, const tmq_params &p, SolveWork &w, const tmq_solver_opts &o,
-                           hipStream_t st)
+                           hipStream_t st, CgScalars *publish = nullptr)
 {
     CgScalars *S = L->scal;
     if (w.mixed) TMQ_HIP(launch_accumulate(w.x, w.xs, st));
     TMQ_TRY(apply_QhatQhat(L, p, w.x, w.ax64, w.te64, w.to64, w.lk64, nullptr, nullptr, st));
     TMQ_HIP(launch_residual(w.b, w.ax64, w.r64, L->partial[2], st));
-    TMQ_HIP(launch_scalar(SC_RELIABLE, L->partial[2], blas_grid(w.b.n), S, o.tol * o.tol, o.relative, nullptr, st));
+    TMQ_HIP(launch_scalar(SC_RELIABLE, L->partial[2], blas_grid(w.b.n), S, o.tol * o.tol, o.relative, nullptr, st,
+                          publish));
     if (w.mixed) TMQ_HIP(launch_convert(w.r64, w.rs, st));
     return TMQ_OK;
 }
@@ -56,8 +57,10 @@ static int read_scalars(Lattice *L, hipStream_t st, CgScalars *out)
     return TMQ_OK;
 }
 
-// body of one CG iteration; all kernels skip once S->done is set
-static int cg_body(Lattice *L, const tmq_params &p, SolveWork &w, hipStream_t st)
+// body of one CG iteration; all kernels skip once S->done is set.  The scalars
+// after the iteration are published to `publish` (host-mapped) unless a
+// reliable update follows, which publishes them itself.
+static int cg_body(Lattice *L, const tmq_params &p, SolveWork &w, hipStream_t st, CgScalars *publish)
 {
     CgScalars *S = L->scal;
     const int *skip = &S->done;
@@ -67,7 +70,7 @@ static int cg_body(Lattice *L, const tmq_params &p, SolveWork &w, hipStream_t st
     TMQ_TRY(apply_Qhat(L, p, +1, w.tos, w.aps, w.tes, w.lks, nullptr, skip, st));
     // x_s += alpha p ; r -= alpha A p ; |r|^2 ; beta
     TMQ_HIP(launch_axpy_norm(w.xs, w.ps, w.rs, w.aps, S, L->partial[1], skip, st));
-    TMQ_HIP(launch_scalar(SC_BETA, L->partial[1], blas_grid(w.ps.n), S, 0, 0, skip, st));
+    TMQ_HIP(launch_scalar(SC_BETA, L->partial[1], blas_grid(w.ps.n), S, 0, 0, skip, st, publish));
     return TMQ_OK;
 }
 
@@ -103,7 +106,12 @@ int solve_eo(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const Fi
         w.tes = w.te64;
         w.tos = w.to64;
     }
-    const double delta = o.delta > 0.0 && o.delta < 1.0 ? o.delta : (o.sloppy == TMQ_FP32 ? 1e-3 : 0.1);
+    // default trigger: the FP32 recursion stays faithful over 4 decades, FP16 over
+    // about 2, BF16 (8-bit mantissa) over a little more than 1
+    const double delta = o.delta > 0.0 && o.delta < 1.0 ? o.delta
+                         : o.sloppy == TMQ_FP32                ? 1e-4
+                         : o.sloppy == TMQ_BF16                ? 0.05
+                                                               : 0.02;
     const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
     CgScalars *S = L->scal;
 
@@ -128,12 +136,15 @@ int solve_eo(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const Fi
         bool leave = false;
         int k0 = enq;
         while (!leave && enq < max_iter) {
-            TMQ_TRY(cg_body(L, p, w, st));
+            // enqueue iteration `enq` (its scalars go to ring slot `slot`), then,
+            // while the GPU runs it, read the scalars of iteration enq - 1
+            const int slot = enq % Lattice::RING;
+            TMQ_TRY(cg_body(L, p, w, st, &L->ring_dev[slot]));
             bool ru = false;
             if (enq > k0) {
-                const int slot = (enq - 1) % Lattice::RING;
-                TMQ_HIP(hipEventSynchronize(L->ring_ev[slot]));
-                const CgScalars prev = L->ring[slot];
+                const int ps = (enq - 1) % Lattice::RING;
+                TMQ_HIP(hipEventSynchronize(L->ring_ev[ps]));
+                const CgScalars prev = L->ring[ps];
                 if (prev.nan || prev.done) leave = true;
                 if (prev.last_true)
                     maxr2 = prev.rr;
@@ -141,10 +152,9 @@ int solve_eo(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const Fi
                     maxr2 = prev.rr;
                 ru = !leave && w.mixed && prev.rr < delta * delta * maxr2;
             }
-            if (ru) TMQ_TRY(reliable_update(L, p, w, o, st));
+            // a reliable update after this iteration republishes the scalars to the same slot
+            if (ru) TMQ_TRY(reliable_update(L, p, w, o, st, &L->ring_dev[slot]));
             TMQ_HIP(launch_xpay(w.rs, w.ps, S, &S->done, st));
-            const int slot = enq % Lattice::RING;
-            TMQ_HIP(hipMemcpyAsync(&L->ring[slot], S, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
             TMQ_HIP(hipEventRecord(L->ring_ev[slot], st));
             enq++;
         }

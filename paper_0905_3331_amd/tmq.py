@@ -68,6 +68,8 @@ _SIGS = {
     "tmq_set_kernel_timing": (_ip, [_vp, _ip]),
     "tmq_kernel_stats": (_ip, [_vp, ctypes.c_char_p, _P(ctypes.c_int), _P(ctypes.c_double),
                                _P(ctypes.c_double), _P(ctypes.c_double)]),
+    "tmq_stream_copy": (_ip, [_ip, ctypes.c_size_t, _ip, _P(ctypes.c_double)]),
+    "tmq_tuning_report": (_ip, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "tmq_encode_dev": (_ip, [_vp, _ip, ctypes.c_long, _vp, _vp, _vp, _vp]),
     "tmq_footprint_bytes": (_ip, [_P(ctypes.c_int), _P(tmq_solver_opts), _ip, _P(ctypes.c_size_t)]),
     "tmq_last_error": (ctypes.c_char_p, []),
@@ -118,6 +120,13 @@ def solver_opts(tol=1e-10, relative=True, max_iter=10000, sloppy="fp64", sloppy_
     o.sloppy_link = PREC[sloppy_link] if isinstance(sloppy_link, str) else int(sloppy_link)
     o.delta = float(delta)
     return o
+
+
+def stream_copy_gbps(nbytes: int = 1 << 30, reps: int = 10, device: int = 0) -> float:
+    """Read + write bandwidth of a plain device-to-device copy kernel (calibration)."""
+    g = ctypes.c_double(0)
+    _check(_lib.tmq_stream_copy(device, nbytes, reps, ctypes.byref(g)), "tmq_stream_copy")
+    return g.value
 
 
 def footprint_bytes(dims, opts=None, nrhs=1) -> int:
@@ -296,6 +305,13 @@ class Lattice:
         _check(_lib.tmq_kernel_stats(self._h, family.encode(), ctypes.byref(n), ctypes.byref(ms),
                                      ctypes.byref(by), ctypes.byref(fl)), "tmq_kernel_stats")
         return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+
+    def tuning_report(self) -> dict:
+        import json
+
+        buf = ctypes.create_string_buffer(1 << 14)
+        _check(_lib.tmq_tuning_report(self._h, buf, len(buf)), "tmq_tuning_report")
+        return json.loads(buf.value.decode())
 
     def encode(self, src, prec="fp16", stream=None):
         """Encode (n,4,3) complex128 device sites to 16-bit codes: returns (codes int16 (n,24), scale f32 (n,))."""
