@@ -189,11 +189,13 @@ int tmq_stream_copy(int device, size_t bytes, int reps, double *gbps);
 
 /* JSON text of the autotuner's choices so far: for every (spinor storage,
  * link format) used on this lattice, the hop kernel variant picked and the
- * measured microseconds per launch of each variant.  The autotuner times the
- * variants (0: compiler register allocation, 1: 0 with non-temporal link
- * loads, 2: at least 2 waves per SIMD, 3: 2 with non-temporal link loads) at
- * the first launch of each format on a lattice; TMQ_HOP_VARIANT=0..3 in the
- * environment forces one.  TMQ_EINVAL if buf (len bytes) is too small. */
+ * measured microseconds per launch of each variant (-1: not applicable).  The
+ * autotuner times the variants (0: lexicographic block order; 1: each XCD
+ * walks its own range of z-planes time-slice by time-slice, needs LZ >= 8;
+ * 2: 1 with scheduling barriers between directions; 3, 4: 2 with at least 2,
+ * 3 waves per SIMD; 5: 0 with barriers and 2 waves per SIMD) at the first
+ * launch of each format on a lattice; TMQ_HOP_VARIANT=0..5 in the environment
+ * forces one.  TMQ_EINVAL if buf (len bytes) is too small. */
 int tmq_tuning_report(tmq_lattice *lat, char *buf, size_t len);
 
 /* Encode n_sites canonical complex128 sites (12 complex each) into the device

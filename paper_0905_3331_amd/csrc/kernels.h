@@ -78,9 +78,14 @@ int blas_grid(long n);
 // 1 - out_par; `self` (may have data == nullptr) holds parity out_par.
 // partial != nullptr: per-block sums of |out|^2 written to partial[0..hop_grid(n)).
 // skip != nullptr: the launch does nothing when *skip != 0.
-// variant: 0 = compiler's register allocation, 1 = same with non-temporal link
-// loads, 2 = at least 2 waves per SIMD, 3 = 2 waves and non-temporal links
-constexpr int HOP_VARIANTS = 4;
+// hop kernel variants (see hop.hip): 0 plain order, 1 XCD slabs, 2 slabs +
+// scheduling barriers, 3/4 as 2 with >= 2/3 waves per SIMD, 5 plain order with
+// barriers and >= 2 waves; every variant loads links non-temporally.  Slab
+// variants need LZ >= 8.
+constexpr int HOP_VARIANTS = 6;
+bool hop_variant_valid(const Geom &g, int v);
+// blocks (= per-block partial sums written with NORM) of a launch of variant v
+int hop_grid_variant(const Geom &g, int v);
 hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, double *partial,
                       const int *skip, int variant, hipStream_t st);

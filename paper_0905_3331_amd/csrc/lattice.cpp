@@ -315,6 +315,7 @@ static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const
     int best = 0;
     float best_us = 0.f;
     for (int v = 0; v < HOP_VARIANTS; v++) {
+        if (!hop_variant_valid(L->g, v)) continue;
         TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, tp, nullptr, v, st));
         TMQ_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < reps; r++) TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, tp, nullptr, v, st));
@@ -324,7 +325,7 @@ static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const
         TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
         const float us = ms * 1e3f / reps;
         L->hop_tune_us[key][v] = us;
-        if (v == 0 || us < best_us) {
+        if (best_us == 0.f || us < best_us) {
             best = v;
             best_us = us;
         }
@@ -344,10 +345,14 @@ std::string tuning_report(const Lattice *L)
     for (int k = 0; k < 16; k++) {
         if (L->hop_variant[k] < 0) continue;
         char buf[256];
-        snprintf(buf, sizeof(buf), "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"variant\": %d, \"us\": [%.2f, %.2f, %.2f, %.2f]}",
-                 first ? "" : ", ", pn[k / 4], ln[k % 4], L->hop_variant[k], L->hop_tune_us[k][0],
-                 L->hop_tune_us[k][1], L->hop_tune_us[k][2], L->hop_tune_us[k][3]);
+        snprintf(buf, sizeof(buf), "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"variant\": %d, \"us\": [",
+                 first ? "" : ", ", pn[k / 4], ln[k % 4], L->hop_variant[k]);
         s += buf;
+        for (int v = 0; v < HOP_VARIANTS; v++) {
+            snprintf(buf, sizeof(buf), "%s%.2f", v ? ", " : "", L->hop_tune_us[k][v]);
+            s += buf;
+        }
+        s += "]}";
         first = false;
     }
     s += "]}";
@@ -359,7 +364,7 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
 {
     const int key = in.prec * 4 + lk.fmt;
     if (L->forced_variant >= 0)
-        L->hop_variant[key] = L->forced_variant;
+        L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;
     else if (L->hop_variant[key] < 0)
         TMQ_TRY(tune_hop(L, key, out_par, in, self, out, lk, c, partial != nullptr, st));
     TimedLaunch t{};
@@ -372,6 +377,7 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
         TMQ_HIP(hipEventRecord(t.a, st));
     }
     TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, partial, skip, L->hop_variant[key], st));
+    L->hop_blocks_last = hop_grid_variant(L->g, L->hop_variant[key]);
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));
         L->timed.push_back(t);

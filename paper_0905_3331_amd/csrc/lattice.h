@@ -80,6 +80,7 @@ struct Lattice {
     int hop_variant[16];
     float hop_tune_us[16][HOP_VARIANTS];
     int forced_variant = -1;  // TMQ_HOP_VARIANT in the environment
+    int hop_blocks_last = 0;  // blocks (partial sums) of the last hop launch
 
     // kernel timing
     bool timing = false;

@@ -66,7 +66,7 @@ static int cg_body(Lattice *L, const tmq_params &p, SolveWork &w, hipStream_t st
     const int *skip = &S->done;
     // t = Qhat^- p, <p, A p> = |t|^2 ; Ap = Qhat^+ t
     TMQ_TRY(apply_Qhat(L, p, -1, w.ps, w.tos, w.tes, w.lks, L->partial[0], skip, st));
-    TMQ_HIP(launch_scalar(SC_ALPHA, L->partial[0], hop_grid(L->g.vh), S, 0, 0, skip, st));
+    TMQ_HIP(launch_scalar(SC_ALPHA, L->partial[0], L->hop_blocks_last, S, 0, 0, skip, st));
     TMQ_TRY(apply_Qhat(L, p, +1, w.tos, w.aps, w.tes, w.lks, nullptr, skip, st));
     // x_s += alpha p ; r -= alpha A p ; |r|^2 ; beta
     TMQ_HIP(launch_axpy_norm(w.xs, w.ps, w.rs, w.aps, S, L->partial[1], skip, st));

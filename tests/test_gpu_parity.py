@@ -239,3 +239,28 @@ def test_determinism(tmq):
     x1, i1 = lat.solve(p, b, tmq.solver_opts(tol=1e-10, sloppy="fp16"))
     x2, i2 = lat.solve(p, b, tmq.solver_opts(tol=1e-10, sloppy="fp16"))
     assert i1.iters == i2.iters and torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("dims", [(8, 8, 6, 10), (6, 10, 4, 6)], ids=lambda d: "x".join(map(str, d)))
+def test_every_hop_variant(tmq, variant, dims, monkeypatch):
+    """Each autotuner variant (block order, register budget) gives the same operator."""
+    monkeypatch.setenv("TMQ_HOP_VARIANT", str(variant))
+    U = synth.random_gauge(dims, seed=107)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(U)
+    psi = synth.gaussian_odd(dims, seed=19)
+    p = tmq.params(0.1632, 0.004, THETA_GEN)
+    for prec, tol in (("fp64", 1e-13), ("fp32", 2e-6), ("fp16", 3e-3)):
+        for sign in (+1, -1):
+            got = host(lat.apply_Qhat(p, sign, dev(psi), prec=prec))
+            assert rel(got, oracle.Qhat(U, psi, 0.1632, 0.004, sign, THETA_GEN)) < tol, (prec, sign)
+    # the norm reduction of the variant feeds CG: a solve still converges
+    b = synth.gaussian_odd(dims, seed=20)
+    x, info = lat.solve(p, dev(b), tmq.solver_opts(tol=1e-10))
+    assert info.status == 0
+    assert oracle.true_residual(U, b, host(x), 0.1632, 0.004, THETA_GEN) <= 1e-10
+    rep = lat.tuning_report()["hop"]
+    want = variant if lat.dims[1] >= 8 or variant in (0, 5) else 0
+    assert all(e["variant"] == want for e in rep if e["spinor"] == "fp64")
+    lat.close()
