@@ -468,7 +468,8 @@ int tmq_encode_dev(tmq_lattice *lat, tmq_prec prec, long n_sites, const double *
     DeviceGuard dg(L->device);
     hipStream_t st = (hipStream_t)stream;
     FieldDesc f;
-    TMQ_TRY(work_field(L, "codec", prec, n_sites, &f));
+    TMQ_TRY(work_field(L, "codec", prec, (n_sites + 7) / 8 * 8, &f));  // whole 8-site chunks
+    f.n = n_sites;
     TMQ_HIP(launch_from_canonical((const double2 *)in, f, st));
     TMQ_HIP(launch_export_codes(f, codes, scale, st));
     return TMQ_OK;

@@ -6,23 +6,11 @@
 // kernel sums the partials in a fixed order, which makes norms, inner products
 // and therefore iteration counts bit-reproducible from run to run.
 #include "devutil.h"
-#include "fields.h"
-#include "kernels.h"
+#include "views.h"
 
 namespace tmq {
 
 int blas_grid(long n) { return (int)((n + BLAS_BLOCK - 1) / BLAS_BLOCK); }
-
-template <class SP>
-static SP mk(const FieldDesc &f);
-template <>
-SpF64 mk<SpF64>(const FieldDesc &f) { return SpF64{(double2 *)f.data, f.stride}; }
-template <>
-SpF32 mk<SpF32>(const FieldDesc &f) { return SpF32{(float4 *)f.data, f.stride}; }
-template <>
-SpH16 mk<SpH16>(const FieldDesc &f) { return SpH16{(uint4 *)f.data, f.scale, f.stride}; }
-template <>
-SpB16 mk<SpB16>(const FieldDesc &f) { return SpB16{(uint4 *)f.data, f.scale, f.stride}; }
 
 template <typename R>
 __device__ __forceinline__ R site_norm2(const spinor<R> &s)
@@ -285,34 +273,27 @@ __global__ __launch_bounds__(SUM_THREADS) void k_max(const double *partial, int 
 
 // ------------------------------------------------------------- dispatch
 
-#define DISPATCH_SP(prec, F, ...)                 \
-    switch (prec) {                               \
-    case P64: { using F = SpF64; __VA_ARGS__; } break;  \
-    case P32: { using F = SpF32; __VA_ARGS__; } break;  \
-    case P16: { using F = SpH16; __VA_ARGS__; } break;  \
-    case PB16: { using F = SpB16; __VA_ARGS__; } break; \
-    default: return hipErrorInvalidValue;         \
-    }
+#define DISPATCH_SP TMQ_DISPATCH_SP
 
 #define LAUNCH(kernel, n, st, ...) \
     hipLaunchKernelGGL(kernel, dim3(blas_grid(n)), dim3(BLAS_BLOCK), 0, st, __VA_ARGS__)
 
 hipError_t launch_norm2(const FieldDesc &v, double *partial, hipStream_t st)
 {
-    DISPATCH_SP(v.prec, F, LAUNCH(k_norm2<F>, v.n, st, mk<F>(v), v.n, partial));
+    DISPATCH_SP(v.prec, F, LAUNCH(k_norm2<F>, v.n, st, make_sp<F>(v), v.n, partial));
     return hipGetLastError();
 }
 
 hipError_t launch_zero(const FieldDesc &v, hipStream_t st)
 {
-    DISPATCH_SP(v.prec, F, LAUNCH(k_zero<F>, v.n, st, mk<F>(v), v.n));
+    DISPATCH_SP(v.prec, F, LAUNCH(k_zero<F>, v.n, st, make_sp<F>(v), v.n));
     return hipGetLastError();
 }
 
 hipError_t launch_convert(const FieldDesc &in, const FieldDesc &out, hipStream_t st)
 {
     if (in.n != out.n) return hipErrorInvalidValue;
-    DISPATCH_SP(in.prec, FI, DISPATCH_SP(out.prec, FO, LAUNCH((k_convert<FI, FO>), in.n, st, mk<FI>(in), mk<FO>(out), in.n)));
+    DISPATCH_SP(in.prec, FI, DISPATCH_SP(out.prec, FO, LAUNCH((k_convert<FI, FO>), in.n, st, make_sp<FI>(in), make_sp<FO>(out), in.n)));
     return hipGetLastError();
 }
 
@@ -322,9 +303,9 @@ hipError_t launch_axpy_norm(const FieldDesc &x, const FieldDesc &p, const FieldD
     if (p.prec != r.prec || p.prec != ap.prec) return hipErrorInvalidValue;
     const long n = p.n;
     if (x.prec == P64 && p.prec == P64)
-        LAUNCH((k_axpy_norm<SpF64, SpF64>), n, st, mk<SpF64>(x), mk<SpF64>(p), mk<SpF64>(r), mk<SpF64>(ap), n, s, partial, skip);
+        LAUNCH((k_axpy_norm<SpF64, SpF64>), n, st, make_sp<SpF64>(x), make_sp<SpF64>(p), make_sp<SpF64>(r), make_sp<SpF64>(ap), n, s, partial, skip);
     else if (x.prec == P32) {
-        DISPATCH_SP(p.prec, F, LAUNCH((k_axpy_norm<SpF32, F>), n, st, mk<SpF32>(x), mk<F>(p), mk<F>(r), mk<F>(ap), n, s, partial, skip));
+        DISPATCH_SP(p.prec, F, LAUNCH((k_axpy_norm<SpF32, F>), n, st, make_sp<SpF32>(x), make_sp<F>(p), make_sp<F>(r), make_sp<F>(ap), n, s, partial, skip));
     } else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -333,7 +314,7 @@ hipError_t launch_axpy_norm(const FieldDesc &x, const FieldDesc &p, const FieldD
 hipError_t launch_xpay(const FieldDesc &r, const FieldDesc &p, const CgScalars *s, const int *skip, hipStream_t st)
 {
     if (r.prec != p.prec) return hipErrorInvalidValue;
-    DISPATCH_SP(p.prec, F, LAUNCH(k_xpay<F>, p.n, st, mk<F>(r), mk<F>(p), p.n, s, skip));
+    DISPATCH_SP(p.prec, F, LAUNCH(k_xpay<F>, p.n, st, make_sp<F>(r), make_sp<F>(p), p.n, s, skip));
     return hipGetLastError();
 }
 
@@ -341,21 +322,21 @@ hipError_t launch_residual(const FieldDesc &b, const FieldDesc &ax, const FieldD
                            hipStream_t st)
 {
     if (b.prec != P64 || ax.prec != P64 || r.prec != P64) return hipErrorInvalidValue;
-    LAUNCH(k_residual, b.n, st, mk<SpF64>(b), mk<SpF64>(ax), mk<SpF64>(r), b.n, partial);
+    LAUNCH(k_residual, b.n, st, make_sp<SpF64>(b), make_sp<SpF64>(ax), make_sp<SpF64>(r), b.n, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_accumulate(const FieldDesc &x64, const FieldDesc &xs, hipStream_t st)
 {
     if (x64.prec != P64) return hipErrorInvalidValue;
-    DISPATCH_SP(xs.prec, F, LAUNCH(k_accumulate<F>, x64.n, st, mk<SpF64>(x64), mk<F>(xs), x64.n));
+    DISPATCH_SP(xs.prec, F, LAUNCH(k_accumulate<F>, x64.n, st, make_sp<SpF64>(x64), make_sp<F>(xs), x64.n));
     return hipGetLastError();
 }
 
 hipError_t launch_axpy_host(double a, const FieldDesc &x, const FieldDesc &y, hipStream_t st)
 {
     if (x.prec != P64 || y.prec != P64) return hipErrorInvalidValue;
-    LAUNCH(k_axpy_host, x.n, st, a, mk<SpF64>(x), mk<SpF64>(y), x.n);
+    LAUNCH(k_axpy_host, x.n, st, a, make_sp<SpF64>(x), make_sp<SpF64>(y), x.n);
     return hipGetLastError();
 }
 
@@ -397,7 +378,7 @@ hipError_t launch_max(const double *partial, int n, double *out, hipStream_t st)
 FieldDesc field_sub(const FieldDesc &f, long off, long n)
 {
     FieldDesc o = f;
-    o.data = (char *)f.data + off * (long)field_elem_bytes(f.prec);
+    o.data = (char *)f.data + off * (long)field_blocks(f.prec) * (long)field_elem_bytes(f.prec);
     o.scale = f.scale ? f.scale + off : nullptr;
     o.n = n;
     return o;

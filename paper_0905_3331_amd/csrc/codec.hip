@@ -3,7 +3,7 @@
 //
 // Canonical layout: complex128, site-major ([site][spin][colour] for spinors,
 // [site][mu][row][col] for links), site = ((t*LZ + z)*LY + y)*LX + x.
-// Device layout: per-parity structure of arrays (fields.h).
+// Device layout: per-parity arrays of 8-site chunks (fields.h).
 //
 // 16-bit spinor encoding of FP64 input (one rounding to FP32, then RNE to
 // FP16/BF16): scale = fp32(max |part|) over the site's 24 reals, code =
@@ -13,21 +13,9 @@
 #include <type_traits>
 
 #include "devutil.h"
-#include "fields.h"
-#include "kernels.h"
+#include "views.h"
 
 namespace tmq {
-
-template <class SP>
-static SP mkc(const FieldDesc &f);
-template <>
-SpF64 mkc<SpF64>(const FieldDesc &f) { return SpF64{(double2 *)f.data, f.stride}; }
-template <>
-SpF32 mkc<SpF32>(const FieldDesc &f) { return SpF32{(float4 *)f.data, f.stride}; }
-template <>
-SpH16 mkc<SpH16>(const FieldDesc &f) { return SpH16{(uint4 *)f.data, f.scale, f.stride}; }
-template <>
-SpB16 mkc<SpB16>(const FieldDesc &f) { return SpB16{(uint4 *)f.data, f.scale, f.stride}; }
 
 // store FP64 values; 16-bit formats follow the FP64 encoding rule above
 template <class SP>
@@ -48,6 +36,7 @@ __device__ __forceinline__ void store_f64_16(const Sp16<BF> &f, long h, const sp
     const float sc = (float)m;
     const double d = (double)sc;
     f.scale[h] = sc;
+    uint4 *q = f.p + aidx(h, 0, 3);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         uint32_t w[4];
@@ -59,7 +48,7 @@ __device__ __forceinline__ void store_f64_16(const Sp16<BF> &f, long h, const sp
             const float yi = sc > 0.f ? (float)(v.im / d) : 0.f;
             w[j] = pack16(f32_to_code<BF>(yr), f32_to_code<BF>(yi));
         }
-        f.p[k * f.stride + h] = make_uint4(w[0], w[1], w[2], w[3]);
+        q[k * 8] = make_uint4(w[0], w[1], w[2], w[3]);
     }
 }
 template <>
@@ -150,7 +139,7 @@ __global__ __launch_bounds__(BLAS_BLOCK) void k_export_codes(SP in, uint16_t *co
         scale[h] = in.scale[h];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            const uint4 v = in.p[k * in.stride + h];
+            const uint4 v = in.p[aidx(h, k, 3)];
             const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int j = 0; j < 4; j++) {
@@ -175,28 +164,32 @@ __global__ __launch_bounds__(BLAS_BLOCK) void k_gauge_ingest(Geom g, const doubl
             const double2 *q = U + (s * 4 + mu) * 9;
 #pragma unroll
             for (int k = 0; k < 9; k++) u.e[k / 3][k % 3] = cx<double>{q[k].x, q[k].y};
-            const long sub = par * 4 + mu;
-            if (o.full64)
+            if (o.full64) {
+                double2 *q = o.full64 + par * 36 * st + lidx(h, mu, 0, 9);
 #pragma unroll
-                for (int k = 0; k < 9; k++)
-                    o.full64[(sub * 9 + k) * st + h] = make_double2(u.e[k / 3][k % 3].re, u.e[k / 3][k % 3].im);
-            if (o.row64)
+                for (int k = 0; k < 9; k++) q[k * 8] = make_double2(u.e[k / 3][k % 3].re, u.e[k / 3][k % 3].im);
+            }
+            if (o.row64) {
+                double2 *q = o.row64 + par * 24 * st + lidx(h, mu, 0, 6);
 #pragma unroll
-                for (int k = 0; k < 6; k++)
-                    o.row64[(sub * 6 + k) * st + h] = make_double2(u.e[k / 3][k % 3].re, u.e[k / 3][k % 3].im);
-            if (o.row32)
+                for (int k = 0; k < 6; k++) q[k * 8] = make_double2(u.e[k / 3][k % 3].re, u.e[k / 3][k % 3].im);
+            }
+            if (o.row32) {
+                float4 *q = o.row32 + par * 12 * st + lidx(h, mu, 0, 3);
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
                     const cx<double> a = u.e[(2 * k) / 3][(2 * k) % 3], b = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
-                    o.row32[(sub * 3 + k) * st + h] = make_float4((float)a.re, (float)a.im, (float)b.re, (float)b.im);
+                    q[k * 8] = make_float4((float)a.re, (float)a.im, (float)b.re, (float)b.im);
                 }
+            }
             if (o.row16a) {
                 uint32_t w[6];
 #pragma unroll
                 for (int k = 0; k < 6; k++)
                     w[k] = pack16(f32_to_h16((float)u.e[k / 3][k % 3].re), f32_to_h16((float)u.e[k / 3][k % 3].im));
-                o.row16a[sub * st + h] = make_uint4(w[0], w[1], w[2], w[3]);
-                o.row16b[sub * st + h] = make_uint2(w[4], w[5]);
+                const long e = par * 4 * st + lidx(h, mu, 0, 1);
+                o.row16a[e] = make_uint4(w[0], w[1], w[2], w[3]);
+                o.row16b[e] = make_uint2(w[4], w[5]);
             }
             // distance from SU(3): max |(U U^+ - 1)_ab| and |det U - 1|
 #pragma unroll
@@ -223,20 +216,13 @@ __global__ __launch_bounds__(BLAS_BLOCK) void k_gauge_ingest(Geom g, const doubl
 
 // -------------------------------------------------------------- dispatch
 
-#define DISPATCH_SPC(prec, F, ...)                        \
-    switch (prec) {                                       \
-    case P64: { using F = SpF64; __VA_ARGS__; } break;    \
-    case P32: { using F = SpF32; __VA_ARGS__; } break;    \
-    case P16: { using F = SpH16; __VA_ARGS__; } break;    \
-    case PB16: { using F = SpB16; __VA_ARGS__; } break;   \
-    default: return hipErrorInvalidValue;                 \
-    }
+#define DISPATCH_SPC TMQ_DISPATCH_SP
 
 hipError_t launch_from_canonical(const double2 *in, const FieldDesc &out, hipStream_t st)
 {
     DISPATCH_SPC(out.prec, F,
                  hipLaunchKernelGGL(k_from_canonical<F>, dim3(blas_grid(out.n)), dim3(BLAS_BLOCK), 0, st, in,
-                                    mkc<F>(out), out.n));
+                                    make_sp<F>(out), out.n));
     return hipGetLastError();
 }
 
@@ -244,7 +230,7 @@ hipError_t launch_to_canonical(const FieldDesc &in, double2 *out, hipStream_t st
 {
     DISPATCH_SPC(in.prec, F,
                  hipLaunchKernelGGL(k_to_canonical<F>, dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st,
-                                    mkc<F>(in), out, in.n));
+                                    make_sp<F>(in), out, in.n));
     return hipGetLastError();
 }
 
@@ -253,7 +239,7 @@ hipError_t launch_full_from_canonical(const Geom &g, const double2 *in, const Fi
     if (out.n != 2 * g.vh) return hipErrorInvalidValue;
     DISPATCH_SPC(out.prec, F,
                  hipLaunchKernelGGL((k_full_canonical<F, false>), dim3(blas_grid(out.n)), dim3(BLAS_BLOCK), 0, st,
-                                    g, (double2 *)in, mkc<F>(out)));
+                                    g, (double2 *)in, make_sp<F>(out)));
     return hipGetLastError();
 }
 
@@ -262,17 +248,17 @@ hipError_t launch_full_to_canonical(const Geom &g, const FieldDesc &in, double2 
     if (in.n != 2 * g.vh) return hipErrorInvalidValue;
     DISPATCH_SPC(in.prec, F,
                  hipLaunchKernelGGL((k_full_canonical<F, true>), dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st,
-                                    g, out, mkc<F>(in)));
+                                    g, out, make_sp<F>(in)));
     return hipGetLastError();
 }
 
 hipError_t launch_export_codes(const FieldDesc &in, uint16_t *codes, float *scale, hipStream_t st)
 {
     if (in.prec == P16)
-        hipLaunchKernelGGL(k_export_codes<SpH16>, dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st, mkc<SpH16>(in),
+        hipLaunchKernelGGL(k_export_codes<SpH16>, dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st, make_sp<SpH16>(in),
                            codes, scale, in.n);
     else if (in.prec == PB16)
-        hipLaunchKernelGGL(k_export_codes<SpB16>, dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st, mkc<SpB16>(in),
+        hipLaunchKernelGGL(k_export_codes<SpB16>, dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st, make_sp<SpB16>(in),
                            codes, scale, in.n);
     else
         return hipErrorInvalidValue;

@@ -16,8 +16,7 @@
 // slab of the lattice and its private L2 sees the y/z/t neighbours of its
 // own sites.
 #include "devutil.h"
-#include "fields.h"
-#include "kernels.h"
+#include "views.h"
 
 namespace tmq {
 
@@ -199,28 +198,6 @@ void hop_kernel(HopArgs<SP, LK> a)
 }
 
 // ------------------------------------------------------------- dispatch
-
-template <class SP>
-static SP make_sp(const FieldDesc &f);
-template <>
-SpF64 make_sp<SpF64>(const FieldDesc &f) { return SpF64{(double2 *)f.data, f.stride}; }
-template <>
-SpF32 make_sp<SpF32>(const FieldDesc &f) { return SpF32{(float4 *)f.data, f.stride}; }
-template <>
-SpH16 make_sp<SpH16>(const FieldDesc &f) { return SpH16{(uint4 *)f.data, f.scale, f.stride}; }
-template <>
-SpB16 make_sp<SpB16>(const FieldDesc &f) { return SpB16{(uint4 *)f.data, f.scale, f.stride}; }
-
-template <class LK>
-static LK make_lk(const LinkDesc &l);
-template <>
-L64F make_lk<L64F>(const LinkDesc &l) { return L64F{(const double2 *)l.a, l.stride}; }
-template <>
-L64R make_lk<L64R>(const LinkDesc &l) { return L64R{(const double2 *)l.a, l.stride}; }
-template <>
-L32R make_lk<L32R>(const LinkDesc &l) { return L32R{(const float4 *)l.a, l.stride}; }
-template <>
-L16R make_lk<L16R>(const LinkDesc &l) { return L16R{(const uint4 *)l.a, (const uint2 *)l.b, l.stride}; }
 
 template <class SP, class LK, int W, bool NT, bool SLAB, bool SB>
 static void go_w(const HopArgs<SP, LK> &a, bool s, bool n, dim3 grid, dim3 block, hipStream_t st)

@@ -21,17 +21,16 @@ struct Geom {
     long vh;  // V / 2
 };
 
-// A spinor field view on one parity (or both parities stacked: even sites
-// 0..V/2-1, odd sites V/2..V-1): component block c of site h at c*stride + h.
+// A spinor field of n sites (one parity, or both parities stacked: even sites
+// 0..V/2-1, odd sites V/2..V-1) in the 8-site chunked layout of fields.h.
 struct FieldDesc {
     int prec = P64;
     void *data = nullptr;   // element type by prec: double2, float4, uint4
     float *scale = nullptr; // FP32 per-site scale of 16-bit formats
-    long stride = 0;        // distance between component blocks, in elements
-    long n = 0;             // number of sites
+    long n = 0;             // number of sites (a multiple of 8)
 };
 
-// sub-view starting at site `off`, n sites
+// sub-view starting at site `off` (a multiple of 8), n sites
 FieldDesc field_sub(const FieldDesc &f, long off, long n);
 size_t field_elem_bytes(int prec);
 int field_blocks(int prec);  // component blocks per site: 12, 6, 3, 3
@@ -40,7 +39,7 @@ struct LinkDesc {
     int fmt = LK64F;
     const void *a = nullptr;  // main array
     const void *b = nullptr;  // second array (LK16R)
-    long stride = 0;          // V/2
+    long vh = 0;              // sites per parity
 };
 
 // Epilogue of a hop half-sweep at output site h (spin s; u = upper spins 0,1,

@@ -22,6 +22,10 @@ size_t field_bytes(int prec, long n)
 int field_alloc(Field &f, int prec, long n)
 {
     field_free(f);
+    if (n % 8) {
+        set_error("internal: field sizes must be multiples of 8 sites");
+        return TMQ_EINVAL;
+    }
     const size_t main = (size_t)n * field_blocks(prec) * 16;
     if (hipMalloc(&f.mem, main) != hipSuccess) {
         f.mem = nullptr;
@@ -40,7 +44,6 @@ int field_alloc(Field &f, int prec, long n)
     f.d.prec = prec;
     f.d.data = f.mem;
     f.d.scale = f.scale;
-    f.d.stride = n;
     f.d.n = n;
     return TMQ_OK;
 }
@@ -216,7 +219,7 @@ LinkDesc lattice_links(const Lattice *L, int fmt)
 {
     LinkDesc d;
     d.fmt = fmt;
-    d.stride = L->g.vh;
+    d.vh = L->g.vh;
     switch (fmt) {
     case LK64F: d.a = L->u64f; break;
     case LK64R: d.a = L->u64r; break;
