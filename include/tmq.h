@@ -162,6 +162,23 @@ int tmq_solve(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts
 int tmq_solve_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts,
                   const double *b_odd, double *x_odd, void *stream, tmq_solve_info *info);
 
+/* Solve Qhat^+ Qhat^- x_r = b_r for nrhs right-hand sides at once
+ * (1 <= nrhs <= TMQ_MAX_RHS), each with its own kappa and mu_tilde in p[r]
+ * (the boundary phases must be the same for all).  The right-hand sides go
+ * through every kernel launch together, so each link is fetched from HBM once
+ * per half-sweep for the whole batch (many inversions per gauge field, Sec.
+ * 3.2); each one still runs its own CG with its own scalars and stopping
+ * test, and its result equals, bit for bit, the same solve done alone with
+ * tmq_solve on this lattice.  b[r], x[r]: odd-site fields as for tmq_solve
+ * (device pointers in the _dev form, host pointers otherwise); info: nrhs
+ * entries or NULL.  Returns TMQ_ENAN if any right-hand side hit a non-finite
+ * value, else TMQ_ENOCONV if any did not converge, else TMQ_OK. */
+#define TMQ_MAX_RHS 64
+int tmq_solve_batch(tmq_lattice *lat, int nrhs, const tmq_params *p, const tmq_solver_opts *opts,
+                    const double *const *b, double *const *x, tmq_solve_info *info);
+int tmq_solve_batch_dev(tmq_lattice *lat, int nrhs, const tmq_params *p, const tmq_solver_opts *opts,
+                        const double *const *b, double *const *x, void *stream, tmq_solve_info *info);
+
 /* Solve Q^+ Q^- x = b on the full lattice (no even/odd preconditioning) by FP64 CG.
  * Full-lattice canonical spinors; x_0 = 0. */
 int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts,
@@ -192,9 +209,9 @@ int tmq_stream_copy(int device, size_t bytes, int reps, double *gbps);
  * measured microseconds per launch of each variant (-1: not applicable).  The
  * autotuner times the variants (0: lexicographic block order; 1: each XCD
  * walks its own range of z-planes time-slice by time-slice, needs LZ >= 8;
- * 2: 1 with scheduling barriers between directions; 3, 4: 2 with at least 2,
- * 3 waves per SIMD; 5: 0 with barriers and 2 waves per SIMD) at the first
- * launch of each format on a lattice; TMQ_HOP_VARIANT=0..5 in the environment
+ * 2: 1 with scheduling barriers between directions; 3: 2 with at least 2
+ * waves per SIMD; 4: 0 with barriers and 2 waves per SIMD) at the first
+ * launch of each format on a lattice; TMQ_HOP_VARIANT=0..4 in the environment
  * forces one.  TMQ_EINVAL if buf (len bytes) is too small. */
 int tmq_tuning_report(tmq_lattice *lat, char *buf, size_t len);
 

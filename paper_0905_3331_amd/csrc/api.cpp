@@ -4,12 +4,13 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "lattice.h"
 
 namespace tmq {
-int solve_eo(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
-             hipStream_t st, tmq_solve_info *info);
+int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o, const FieldDesc &b,
+                const FieldDesc &x, hipStream_t st, tmq_solve_info *info);
 int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
                hipStream_t st, tmq_solve_info *info);
 }  // namespace tmq
@@ -101,7 +102,7 @@ int qhat_dev(Lattice *L, const tmq_params *p, int sign, int prec, const double *
     TMQ_TRY(work_field(L, "op_te", prec, vh, &te));
     const LinkDesc lk = lattice_links(L, link_fmt_for(L, prec, prec == TMQ_FP32 ? P32 : P16));
     TMQ_HIP(launch_from_canonical((const double2 *)in, fi, st));
-    TMQ_TRY(apply_Qhat(L, *p, sign, fi, fo, te, lk, nullptr, nullptr, st));
+    TMQ_TRY(apply_Qhat(L, make_op(L, p, 1), sign, fi, fo, te, lk, rhs_all(1), nullptr, nullptr, st));
     TMQ_HIP(launch_to_canonical(fo, (double2 *)out, st));
     return TMQ_OK;
 }
@@ -227,7 +228,8 @@ int tmq_apply_QhatQhat_dev(tmq_lattice *lat, const tmq_params *p, const double *
     TMQ_TRY(work_field(L, "op_te", P64, vh, &te));
     TMQ_TRY(work_field(L, "op_to", P64, vh, &to));
     TMQ_HIP(launch_from_canonical((const double2 *)in, fi, st));
-    TMQ_TRY(apply_QhatQhat(L, *p, fi, fo, te, to, lattice_links(L, link_fmt_for(L, P64, P64)), nullptr, nullptr, st));
+    TMQ_TRY(apply_QhatQhat(L, make_op(L, p, 1), fi, fo, te, to, lattice_links(L, link_fmt_for(L, P64, P64)),
+                           rhs_all(1), nullptr, nullptr, st));
     TMQ_HIP(launch_to_canonical(fo, (double2 *)out, st));
     return TMQ_OK;
 }
@@ -247,7 +249,8 @@ int tmq_apply_Q_full_dev(tmq_lattice *lat, const tmq_params *p, int sign, const 
     TMQ_TRY(work_field(L, "full_in", P64, n, &fi));
     TMQ_TRY(work_field(L, "full_out", P64, n, &fo));
     TMQ_HIP(launch_full_from_canonical(L->g, (const double2 *)in, fi, st));
-    TMQ_TRY(apply_Q_full(L, *p, sign, fi, fo, lattice_links(L, link_fmt_for(L, P64, P64)), st));
+    TMQ_TRY(apply_Q_full(L, make_op(L, p, 1), sign, fi, fo, lattice_links(L, link_fmt_for(L, P64, P64)),
+                         rhs_all(1), st));
     TMQ_HIP(launch_full_to_canonical(L->g, fo, (double2 *)out, st));
     return TMQ_OK;
 }
@@ -269,51 +272,86 @@ int tmq_apply_Q_full(tmq_lattice *lat, const tmq_params *p, int sign, const doub
     return TMQ_OK;
 }
 
-int tmq_solve_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *b, double *x,
-                  void *stream, tmq_solve_info *info)
+int tmq_solve_batch_dev(tmq_lattice *lat, int nrhs, const tmq_params *p, const tmq_solver_opts *opts,
+                        const double *const *b, double *const *x, void *stream, tmq_solve_info *info)
 {
-    if (info) memset(info, 0, sizeof(*info));
+    if (info && nrhs > 0) memset(info, 0, sizeof(*info) * (size_t)nrhs);
     TMQ_TRY(check_lat(lat, true));
-    TMQ_TRY(check_params(p));
+    if (nrhs < 1 || nrhs > TMQ_MAX_RHS || !p || !b || !x) {
+        set_error("tmq_solve_batch: need 1 <= nrhs <= TMQ_MAX_RHS and non-NULL arrays");
+        return TMQ_EINVAL;
+    }
+    for (int r = 0; r < nrhs; r++) {
+        TMQ_TRY(check_params(&p[r]));
+        TMQ_TRY(check_ptrs(b[r], x[r]));
+        for (int mu = 0; mu < 4; mu++)
+            if (p[r].theta[mu] != p[0].theta[mu]) {
+                set_error("tmq_solve_batch: every right-hand side must have the same boundary phases");
+                return TMQ_EINVAL;
+            }
+    }
     TMQ_TRY(check_opts(opts));
-    TMQ_TRY(check_ptrs(b, x));
     Lattice *L = lat->L;
     DeviceGuard dg(L->device);
     hipStream_t st = (hipStream_t)stream;
     const long vh = L->g.vh;
     FieldDesc fb, fx;
-    TMQ_TRY(work_field(L, "solve_b", P64, vh, &fb));
-    TMQ_TRY(work_field(L, "solve_x", P64, vh, &fx));
-    TMQ_HIP(launch_from_canonical((const double2 *)b, fb, st));
-    const int s = solve_eo(L, *p, *opts, fb, fx, st, info);
+    TMQ_TRY(work_field(L, "solve_b", P64, vh, &fb, nrhs));
+    TMQ_TRY(work_field(L, "solve_x", P64, vh, &fx, nrhs));
+    for (int r = 0; r < nrhs; r++) TMQ_HIP(launch_from_canonical((const double2 *)b[r], field_rhs(fb, r), st));
+    const int s = solve_batch(L, nrhs, p, *opts, fb, fx, st, info);
     if (s == TMQ_OK || s == TMQ_ENOCONV) {
-        TMQ_HIP(launch_to_canonical(fx, (double2 *)x, st));
+        for (int r = 0; r < nrhs; r++) TMQ_HIP(launch_to_canonical(field_rhs(fx, r), (double2 *)x[r], st));
         TMQ_HIP(hipStreamSynchronize(st));
     }
     return s;
 }
 
-int tmq_solve(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *b, double *x,
-              tmq_solve_info *info)
+int tmq_solve_batch(tmq_lattice *lat, int nrhs, const tmq_params *p, const tmq_solver_opts *opts,
+                    const double *const *b, double *const *x, tmq_solve_info *info)
 {
-    if (info) memset(info, 0, sizeof(*info));
+    if (info && nrhs > 0) memset(info, 0, sizeof(*info) * (size_t)nrhs);
     TMQ_TRY(check_lat(lat, true));
-    TMQ_TRY(check_ptrs(b, x));
+    if (nrhs < 1 || nrhs > TMQ_MAX_RHS || !b || !x) {
+        set_error("tmq_solve_batch: need 1 <= nrhs <= TMQ_MAX_RHS and non-NULL arrays");
+        return TMQ_EINVAL;
+    }
     Lattice *L = lat->L;
     DeviceGuard dg(L->device);
     const auto t0 = std::chrono::steady_clock::now();
     const size_t bytes = (size_t)L->g.vh * 12 * 16;
-    double *db = nullptr;
-    TMQ_TRY(copy_in(L, 0, b, bytes, &db));
-    void *dx = nullptr;
-    TMQ_TRY(stage_buffer(L, 1, bytes, &dx));
-    const int s = tmq_solve_dev(lat, p, opts, db, (double *)dx, L->own, info);
+    void *db = nullptr, *dx = nullptr;
+    TMQ_TRY(stage_buffer(L, 0, bytes * nrhs, &db));
+    TMQ_TRY(stage_buffer(L, 1, bytes * nrhs, &dx));
+    std::vector<const double *> bp(nrhs);
+    std::vector<double *> xp(nrhs);
+    for (int r = 0; r < nrhs; r++) {
+        TMQ_TRY(check_ptrs(b[r], x[r]));
+        bp[r] = (const double *)((char *)db + bytes * r);
+        xp[r] = (double *)((char *)dx + bytes * r);
+        TMQ_HIP(hipMemcpyAsync((void *)bp[r], b[r], bytes, hipMemcpyHostToDevice, L->own));
+    }
+    const int s = tmq_solve_batch_dev(lat, nrhs, p, opts, bp.data(), xp.data(), L->own, info);
     if (s == TMQ_OK || s == TMQ_ENOCONV) {
-        TMQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, L->own));
+        for (int r = 0; r < nrhs; r++) TMQ_HIP(hipMemcpyAsync(x[r], xp[r], bytes, hipMemcpyDeviceToHost, L->own));
         TMQ_HIP(hipStreamSynchronize(L->own));
     }
-    if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        for (int r = 0; r < nrhs; r++) info[r].seconds = secs;
     return s;
+}
+
+int tmq_solve_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *b, double *x,
+                  void *stream, tmq_solve_info *info)
+{
+    return tmq_solve_batch_dev(lat, 1, p, opts, &b, &x, stream, info);
+}
+
+int tmq_solve(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *b, double *x,
+              tmq_solve_info *info)
+{
+    return tmq_solve_batch(lat, 1, p, opts, &b, &x, info);
 }
 
 int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *b,

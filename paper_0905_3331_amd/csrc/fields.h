@@ -185,18 +185,24 @@ struct Sp16 {
             }
         }
     }
-    // store FP32 values: scale = largest |part|, codes = value / scale
+    // store FP32 values: scale = largest |part|, codes = value * (1 / scale).
+    // A site whose largest part is below the smallest normal FP32 number is
+    // stored as zero (its reciprocal would overflow); a non-finite site keeps
+    // a NaN scale so that the solver's checks see it.
     template <typename R>
     __device__ __forceinline__ void store(long h, const spinor<R> &s) const
     {
         float m = 0.f;
+        bool bad = false;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            m = fmaxf(m, fabsf((float)s.c[k / 3][k % 3].re));
-            m = fmaxf(m, fabsf((float)s.c[k / 3][k % 3].im));
+            const float a = fabsf((float)s.c[k / 3][k % 3].re), b = fabsf((float)s.c[k / 3][k % 3].im);
+            bad |= !(a <= 3.0e38f) || !(b <= 3.0e38f);
+            m = fmaxf(m, fmaxf(a, b));
         }
-        const float inv = m > 0.f ? 1.0f / m : 0.f;
-        scale[h] = m;
+        const bool tiny = m < 1.17549435e-38f;
+        const float inv = tiny ? 0.f : 1.0f / m;
+        scale[h] = bad ? __int_as_float(0x7fc00000) : (tiny ? 0.f : m);
         uint4 *q = p + aidx(h, 0, 3);
 #pragma unroll
         for (int k = 0; k < 3; k++) {

@@ -1,0 +1,302 @@
+// hop_impl.h -- the hopping half-sweep H_eo / H_oe with fused site-term epilogues.
+//
+// Included by one translation unit per spinor format (hop_f64.hip, ...), so
+// that the many template instantiations compile in parallel; hop.hip holds
+// the dispatch.
+//
+// One output site per lane.  For each of the 8 neighbours the lane loads the
+// neighbour spinor, projects it to two spin components with (1 +- gamma_mu)
+// (Sec. 4.1), multiplies both by the link U(x,mu) or U(x-mu,mu)^+ (each link
+// is read exactly once per half-sweep: the forward links of the output
+// parity, the backward links of the input parity), multiplies by the boundary
+// phase e^{+-i theta_mu pi/L_mu} (Sec. 4.1.2; skipped where the phase is 1)
+// and accumulates the rebuilt four-spinor.  The epilogue forms
+// out = A * self + B * acc per spin half, which covers both factors of the
+// even/odd operator (eqs. (eo3), (eo4)) and the full-lattice operator, and
+// optionally reduces |out|^2 per block.
+//
+// Work distribution: blocks of 256 lanes over consecutive eo indices (x
+// fastest, then y, z, t).  Hardware hands consecutive workgroups to the 8 XCDs
+// in turn; the block index is remapped so that each XCD walks a contiguous
+// slab of the lattice and its private L2 sees the y/z/t neighbours of its
+// own sites.
+#pragma once
+#include "devutil.h"
+#include "views.h"
+
+namespace tmq {
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblk)
+{
+    // nblk is a multiple of 8: XCD k = bid % 8 gets logical blocks [k*nblk/8, (k+1)*nblk/8)
+    return (bid & 7) * (nblk >> 3) + (bid >> 3);
+}
+
+template <class SP, class LK>
+struct HopArgs {
+    Geom g;
+    int out_par;
+    int epi, sign;
+    int phase_mask;  // bit mu set when the boundary phase of direction mu is not 1
+    int nblk;        // blocks per RHS
+    int group;       // RHS processed together per site block (see the kernel)
+    BatchView<SP> in, self, out;
+    LK lk;
+    OpParams op;
+    RhsList rl;
+    double *partial;
+    long pstride;
+    const CgScalars *scal;
+};
+
+template <int MU, bool NT, class SP, class LK, typename R>
+__device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP &in, spinor<R> &acc, long h, long hf,
+                                        long hb)
+{
+    const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
+    const cx<R> ph = {(R)a.op.ph[MU][0], (R)a.op.ph[MU][1]};
+    spinor<R> s;
+    half<R> p, w;
+    su3<R> u;
+    // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu); U at the output site
+    in.load(hf, s);
+    project<MU, +1>(s, p);
+    a.lk.template load<NT>(a.out_par, MU, h, u);
+    link_mul<false>(u, p, w);
+    if (phase) half_scale(w, ph);
+    reconstruct_add<MU, +1>(acc, w);
+    // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu); U at the neighbour
+    in.load(hb, s);
+    project<MU, -1>(s, p);
+    a.lk.template load<NT>(a.out_par ^ 1, MU, hb, u);
+    link_mul<true>(u, p, w);
+    if (phase) half_scale(w, conj(ph));
+    reconstruct_add<MU, -1>(acc, w);
+}
+
+// Variant bits: W > 0 asks the compiler for at least W waves per SIMD (a
+// register budget of 512 / W per lane), W = 0 leaves the choice to the
+// compiler; NT makes the link loads non-temporal (single RHS); SLAB gives XCD k = block % 8
+// its own range of z-planes, walked with t outermost, so that the sites of
+// time-slices t-1, t, t+1 that one XCD needs at a time fit its L2; SB puts a
+// scheduling barrier between directions.  The autotuner picks the fastest
+// variant per format and lattice.
+//
+// Batches: physical block b runs on XCD j = b % 8.  The RHS are taken in
+// groups of `group`; an XCD sweeps its whole share of sites for one group
+// before the next, and within a group its consecutive blocks apply the same
+// links to every RHS of the group in turn.  The links are then fetched from
+// HBM once per group, while the neighbour spinors of a group (three
+// time-slices of the XCD's share per RHS) still fit its L2; the host sizes the
+// group for that.  With one RHS this is the single-field order, and each RHS's
+// arithmetic and partial sums do not depend on the batch around it.
+template <class SP, class LK, bool SELF, bool NORM, int W, bool NT, bool SLAB, bool SB>
+__global__ __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, W > 0 ? 8 : 8)))
+void hop_kernel(HopArgs<SP, LK> a)
+{
+    using R = typename LK::real;
+    const Geom &g = a.g;
+    const int j = blockIdx.x & 7;
+    const int k = blockIdx.x >> 3;
+    const int nb = a.nblk >> 3;                      // site blocks of this XCD's share
+    const int G = a.group, gi = k / (nb * G);        // group of this block
+    const int gsize = min(G, a.rl.n - gi * G);       // the last group may be smaller
+    const int within = k - gi * nb * G;
+    const int sb = within / gsize;                   // site block within the XCD's share
+    const int ri = gi * G + (within - sb * gsize);
+    const int rhs = a.rl.idx[ri];
+    if (a.scal && a.scal[rhs].done) return;
+    const long plane = (long)g.LY * g.XH;  // sites of one (t, z) plane
+    long h;
+    int t, z, y, pidx;
+    unsigned xh;
+    bool active;
+    if (SLAB) {
+        const int zb = g.LZ >> 3, zr = g.LZ & 7;
+        const int zc = zb + (j < zr ? 1 : 0), z0 = j * zb + (j < zr ? j : zr);
+        const long S = (long)zc * plane;  // sites of one time-slice of this slab
+        const long l = (long)sb * HOP_BLOCK + threadIdx.x;
+        active = l < (long)g.T * S;
+        const unsigned lu = active ? (unsigned)l : 0u;
+        t = (int)(lu / (unsigned)S);
+        const unsigned rem = lu - (unsigned)t * (unsigned)S;
+        z = z0 + (int)(rem / (unsigned)plane);
+        const unsigned r2 = rem - (unsigned)(z - z0) * (unsigned)plane;
+        y = (int)(r2 / (unsigned)g.XH);
+        xh = r2 - (unsigned)y * (unsigned)g.XH;
+        h = ((long)t * g.LZ + z) * plane + (long)y * g.XH + xh;
+        pidx = 8 * sb + j;
+    } else {
+        const int lb = j * (a.nblk >> 3) + sb;
+        h = (long)lb * HOP_BLOCK + threadIdx.x;
+        active = h < g.vh;
+        const unsigned hu = active ? (unsigned)h : 0u;
+        xh = hu % (unsigned)g.XH;
+        unsigned r = hu / (unsigned)g.XH;
+        y = (int)(r % (unsigned)g.LY);
+        r /= (unsigned)g.LY;
+        z = (int)(r % (unsigned)g.LZ);
+        t = (int)(r / (unsigned)g.LZ);
+        pidx = lb;
+    }
+    double nrm = 0.0;
+    if (active) {
+        const SP in = a.in.at(rhs);
+        // x parity makes (t+z+y+x) = out_par mod 2
+        const int x = 2 * (int)xh + ((a.out_par + t + z + y) & 1);
+        const long row = h - xh;  // eo index of (t, z, y, 0)
+        const long sy = g.XH, sz = plane, stt = (long)g.LZ * plane;
+
+        spinor<R> acc;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc.c[i][c] = cx<R>{R(0), R(0)};
+
+        hop_dir<0, NT>(a, in, acc, h, t + 1 == g.T ? h - (g.T - 1) * stt : h + stt,
+                       t == 0 ? h + (g.T - 1) * stt : h - stt);
+        if (SB) __builtin_amdgcn_sched_barrier(0);
+        hop_dir<1, NT>(a, in, acc, h, row + ((x + 1 == g.LX ? 0 : x + 1) >> 1),
+                       row + ((x == 0 ? g.LX - 1 : x - 1) >> 1));
+        if (SB) __builtin_amdgcn_sched_barrier(0);
+        hop_dir<2, NT>(a, in, acc, h, y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy,
+                       y == 0 ? h + (g.LY - 1) * sy : h - sy);
+        if (SB) __builtin_amdgcn_sched_barrier(0);
+        hop_dir<3, NT>(a, in, acc, h, z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz,
+                       z == 0 ? h + (g.LZ - 1) * sz : h - sz);
+
+        // epilogue coefficients of this RHS (upper spins: gamma_5 = +1, lower: -1)
+        const double kap = a.op.kappa[rhs], m = a.sign * a.op.mut[rhs];
+        cx<R> Au, Ad, Bu, Bd;
+        if (a.epi == EPI_K1) {
+            const double c = kap * kap / (1.0 + m * m);
+            Au = Ad = cx<R>{R(0), R(0)};
+            Bu = cx<R>{(R)c, (R)(-c * m)};
+            Bd = cx<R>{(R)c, (R)(c * m)};
+        } else {
+            const double b = a.epi == EPI_FULL ? kap : 1.0;
+            Au = cx<R>{R(1), (R)m};
+            Ad = cx<R>{R(-1), (R)m};
+            Bu = cx<R>{(R)(-b), R(0)};
+            Bd = cx<R>{(R)b, R(0)};
+        }
+        spinor<R> o;
+        if (SELF) {
+            spinor<R> sf;
+            a.self.at(rhs).load(h, sf);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                o.c[0][c] = fma(Au, sf.c[0][c], Bu * acc.c[0][c]);
+                o.c[1][c] = fma(Au, sf.c[1][c], Bu * acc.c[1][c]);
+                o.c[2][c] = fma(Ad, sf.c[2][c], Bd * acc.c[2][c]);
+                o.c[3][c] = fma(Ad, sf.c[3][c], Bd * acc.c[3][c]);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                o.c[0][c] = Bu * acc.c[0][c];
+                o.c[1][c] = Bu * acc.c[1][c];
+                o.c[2][c] = Bd * acc.c[2][c];
+                o.c[3][c] = Bd * acc.c[3][c];
+            }
+        }
+        a.out.at(rhs).store(h, o);
+        if (NORM) {
+            R n2 = R(0);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) n2 += norm2(o.c[i][c]);
+            nrm = (double)n2;
+        }
+    }
+    if (NORM) {
+        __shared__ double sh[HOP_BLOCK / 64];
+        const double s = block_sum(nrm, sh);
+        if (threadIdx.x == 0) a.partial[rhs * a.pstride + pidx] = s;
+    }
+}
+
+// ------------------------------------------------------------- dispatch
+
+template <class SP, class LK, int W, bool NT, bool SLAB, bool SB>
+void go_w(const HopArgs<SP, LK> &a, bool s, bool n, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (s && n)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, W, NT, SLAB, SB>), grid, block, 0, st, a);
+    else if (s)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, W, NT, SLAB, SB>), grid, block, 0, st, a);
+    else if (n)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true, W, NT, SLAB, SB>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, W, NT, SLAB, SB>), grid, block, 0, st, a);
+}
+
+// ALL = false: only variant 0 is instantiated (rarely used format pairs)
+// RHS per group: three time-slices of an XCD's share of the sites (its slab,
+// or 1/8 of a time-slice) for every RHS of the group within about 2 MB of L2
+inline int rhs_group(const Geom &g, int prec, int n)
+{
+    const double sp = prec == P64 ? 192.0 : prec == P32 ? 96.0 : 52.0;
+    const double slice = (double)((g.LZ + 7) / 8) * g.LY * g.XH * sp;
+    int G = (int)(2.0e6 / (3.0 * slice));
+    return G < 1 ? 1 : (G > n ? n : G);
+}
+
+template <class SP, class LK, bool ALL>
+hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
+                     const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl,
+                     double *partial, long pstride, const CgScalars *scal, int variant, int group, hipStream_t st)
+{
+    if (rl.n <= 0) return hipSuccess;
+    HopArgs<SP, LK> a;
+    a.g = g;
+    a.out_par = out_par;
+    a.epi = epi;
+    a.sign = sign;
+    a.phase_mask = 0;
+    for (int mu = 0; mu < 4; mu++)
+        if (op.ph[mu][0] != 1.0 || op.ph[mu][1] != 0.0) a.phase_mask |= 1 << mu;
+    a.in = make_bv<SP>(in);
+    a.self = self.data ? make_bv<SP>(self) : a.in;
+    a.out = make_bv<SP>(out);
+    a.lk = make_lk<LK>(lk);
+    a.op = op;
+    a.rl = rl;
+    a.partial = partial;
+    a.pstride = pstride;
+    a.scal = scal;
+    if (!ALL || !hop_variant_valid(g, variant)) variant = 0;
+    a.nblk = hop_grid_variant(g, variant);
+    a.group = group > 0 ? (group < rl.n ? group : rl.n) : rhs_group(g, in.prec, rl.n);
+    dim3 grid(a.nblk * rl.n), block(HOP_BLOCK);
+    const bool s = epi != EPI_K1, n = partial != nullptr;
+    if (s && !self.data) return hipErrorInvalidValue;
+    const bool nt = rl.n == 1;
+    if (!ALL) {
+        if (nt)
+            go_w<SP, LK, 0, true, false, false>(a, s, n, grid, block, st);
+        else
+            go_w<SP, LK, 0, false, false, false>(a, s, n, grid, block, st);
+        return hipGetLastError();
+    }
+#define GOV(W, SLAB, SB)                                                 \
+    do {                                                                 \
+        if (nt)                                                          \
+            go_w<SP, LK, W, true, SLAB, SB>(a, s, n, grid, block, st);   \
+        else                                                             \
+            go_w<SP, LK, W, false, SLAB, SB>(a, s, n, grid, block, st);  \
+    } while (0)
+    switch (variant) {
+    case 1: GOV(0, true, false); break;
+    case 2: GOV(0, true, true); break;
+    case 3: GOV(2, true, true); break;
+    case 4: GOV(2, false, true); break;
+    default: GOV(0, false, false); break;
+    }
+#undef GOV
+    return hipGetLastError();
+}
+
+
+}  // namespace tmq

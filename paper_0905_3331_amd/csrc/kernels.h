@@ -3,6 +3,12 @@
 // Host code (the lattice object, the solvers, the C ABI) is format-agnostic:
 // it passes FieldDesc / LinkDesc descriptors and the wrappers dispatch to the
 // template instantiations in hop.hip, blas.hip and codec.hip.
+//
+// Every vector kernel works on a batch of right-hand sides (RHS): a field
+// holds nrhs fields of n sites each, and a launch covers the RHS named in an
+// RhsList.  One block handles one RHS, so per-RHS scalars, "done" flags and
+// partial sums stay separate, and each RHS is computed exactly as if it were
+// alone (a single solve is the batch of one).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -13,6 +19,8 @@ namespace tmq {
 enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };  // same values as tmq_prec
 enum LinkFmt { LK64F = 0, LK64R = 1, LK32R = 2, LK16R = 3 };
 
+constexpr int MAX_RHS = 64;
+
 // Lattice geometry.  Extents (T, LZ, LY, LX) all even; V/2 sites per parity,
 // eo index h = site >> 1 with site = ((t*LZ + z)*LY + y)*LX + x.
 struct Geom {
@@ -21,19 +29,33 @@ struct Geom {
     long vh;  // V / 2
 };
 
-// A spinor field of n sites (one parity, or both parities stacked: even sites
-// 0..V/2-1, odd sites V/2..V-1) in the 8-site chunked layout of fields.h.
+// A batch of spinor fields, each of n sites (one parity, or both parities
+// stacked: even sites 0..V/2-1, odd sites V/2..V-1) in the 8-site chunked
+// layout of fields.h; RHS r starts rhs_elems elements (and rhs_sites scales)
+// after RHS 0.
 struct FieldDesc {
     int prec = P64;
     void *data = nullptr;   // element type by prec: double2, float4, uint4
     float *scale = nullptr; // FP32 per-site scale of 16-bit formats
-    long n = 0;             // number of sites (a multiple of 8)
+    long n = 0;             // sites per RHS (a multiple of 8)
+    int nrhs = 1;
+    long rhs_elems = 0;
+    long rhs_sites = 0;
 };
 
-// sub-view starting at site `off` (a multiple of 8), n sites
+// sub-view starting at site `off` (a multiple of 8), n sites, every RHS
 FieldDesc field_sub(const FieldDesc &f, long off, long n);
+// the single field of RHS r
+FieldDesc field_rhs(const FieldDesc &f, int r);
 size_t field_elem_bytes(int prec);
 int field_blocks(int prec);  // component blocks per site: 12, 6, 3, 3
+
+// The RHS a launch covers (indices into the batch).
+struct RhsList {
+    int n = 0;
+    unsigned char idx[MAX_RHS];
+};
+RhsList rhs_all(int n);
 
 struct LinkDesc {
     int fmt = LK64F;
@@ -42,13 +64,20 @@ struct LinkDesc {
     long vh = 0;              // sites per parity
 };
 
-// Epilogue of a hop half-sweep at output site h (spin s; u = upper spins 0,1,
-// d = lower spins 2,3):  out_s = A_{u|d} * self_s + B_{u|d} * (sum of hops)_s.
-struct HopCoef {
+// Operator parameters of a launch: boundary phases common to the batch,
+// kappa and mut = 2 kappa mu per RHS (indexed by the batch index).
+struct OpParams {
     double ph[4][2];  // e^{i theta_mu pi / L_mu} (re, im), mu = t, x, y, z
-    double A[2][2];   // (re, im) for upper, lower
-    double B[2][2];
+    double kappa[MAX_RHS];
+    double mut[MAX_RHS];
 };
+
+// Epilogue of a hop half-sweep at output site h (spin s; upper = spins 0,1
+// where gamma_5 = +1, lower = spins 2,3), with sigma = sign of Qhat^{+-}:
+//   EPI_K1   out = kappa^2/(1+mut^2) (1 - sigma i mut g5) acc              (eq. (eo3))
+//   EPI_K2   out = g5 [(1 + sigma i mut g5) self - acc]                    (eq. (eo4))
+//   EPI_FULL out = g5 [(1 + sigma i mut g5) self - kappa acc]              (eq. (eo1))
+enum HopEpi { EPI_K1 = 0, EPI_K2 = 1, EPI_FULL = 2 };
 
 // Device scalars of a CG solve (one struct per right-hand side).
 struct CgScalars {
@@ -59,7 +88,7 @@ struct CgScalars {
     double bb;       // ||b||^2
     double target;   // stop when rr < target
     int iter;        // iterations done
-    int done;        // 1 once rr < target or nan (kernels given a skip pointer then do nothing)
+    int done;        // 1 once rr < target or nan (kernels told to skip done RHS then do nothing)
     int nan;         // 1 once a non-finite scalar appeared
     int reliable;    // number of true-residual recomputations
     int last_true;   // 1 if rr is a recomputed true residual
@@ -68,63 +97,67 @@ struct CgScalars {
 
 constexpr int HOP_BLOCK = 256;
 constexpr int BLAS_BLOCK = 256;
-constexpr int RED_MAX_BLOCKS = 1 << 16;
 
 int hop_grid(long n);
 int blas_grid(long n);
 
-// hop half-sweep: out(h) over the n sites of parity out_par; `in` holds parity
-// 1 - out_par; `self` (may have data == nullptr) holds parity out_par.
-// partial != nullptr: per-block sums of |out|^2 written to partial[0..hop_grid(n)).
-// skip != nullptr: the launch does nothing when *skip != 0.
 // hop kernel variants (see hop.hip): 0 plain order, 1 XCD slabs, 2 slabs +
-// scheduling barriers, 3/4 as 2 with >= 2/3 waves per SIMD, 5 plain order with
-// barriers and >= 2 waves; every variant loads links non-temporally.  Slab
-// variants need LZ >= 8.
-constexpr int HOP_VARIANTS = 6;
+// scheduling barriers, 3 as 2 with >= 2 waves per SIMD, 4 plain order with
+// barriers and >= 2 waves.  Slab variants need LZ >= 8.  Links are loaded
+// non-temporally in single-RHS launches and cached in batched ones.
+constexpr int HOP_VARIANTS = 5;
 bool hop_variant_valid(const Geom &g, int v);
-// blocks (= per-block partial sums written with NORM) of a launch of variant v
+// blocks per RHS (= per-block partial sums written with a norm) of variant v
 int hop_grid_variant(const Geom &g, int v);
+
+// Hop half-sweep: out(h) over the V/2 sites of parity out_par for every RHS
+// of rl; `in` holds parity 1 - out_par; `self` (data may be nullptr unless
+// the epilogue needs it) holds parity out_par.  partial != nullptr: per-block
+// sums of |out|^2 at partial[r * pstride + block].  scal != nullptr: blocks of
+// RHS r with scal[r].done set do nothing.
+// group: RHS per group in a batched launch (0: a size from the L2 capacity).
 hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
-                      const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, double *partial,
-                      const int *skip, int variant, hipStream_t st);
+                      const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
+                      const RhsList &rl, double *partial, long pstride, const CgScalars *scal, int variant,
+                      int group, hipStream_t st);
 
-// BLAS-1 over the sites of the given views; every launch with `partial` writes
-// blas_grid(n) per-block sums.  Scalars come from device memory.
-hipError_t launch_norm2(const FieldDesc &v, double *partial, hipStream_t st);
-hipError_t launch_convert(const FieldDesc &in, const FieldDesc &out, hipStream_t st);
-hipError_t launch_zero(const FieldDesc &v, hipStream_t st);
-// x += alpha p ; r -= alpha ap ; partial |r|^2   (alpha = s->alpha)
-hipError_t launch_axpy_norm(const FieldDesc &x, const FieldDesc &p, const FieldDesc &r,
-                            const FieldDesc &ap, const CgScalars *s, double *partial,
-                            const int *skip, hipStream_t st);
-// p = r + beta p   (beta = s->beta)
-hipError_t launch_xpay(const FieldDesc &r, const FieldDesc &p, const CgScalars *s, const int *skip,
-                       hipStream_t st);
-// r = b - ax (FP64 views), partial |r|^2
-hipError_t launch_residual(const FieldDesc &b, const FieldDesc &ax, const FieldDesc &r,
-                           double *partial, hipStream_t st);
+// Vector kernels over the n sites of each RHS of rl.  Reductions write
+// blas_grid(n) per-block sums at partial[r * pstride + block]; scalars come
+// from scal[r]; skip_done: blocks of RHS with scal[r].done do nothing.
+hipError_t launch_norm2(const FieldDesc &v, const RhsList &rl, double *partial, long pstride, hipStream_t st);
+hipError_t launch_convert(const FieldDesc &in, const FieldDesc &out, const RhsList &rl, hipStream_t st);
+hipError_t launch_zero(const FieldDesc &v, const RhsList &rl, hipStream_t st);
+// x += alpha p ; r -= alpha ap ; partial |r|^2
+hipError_t launch_axpy_norm(const FieldDesc &x, const FieldDesc &p, const FieldDesc &r, const FieldDesc &ap,
+                            const RhsList &rl, const CgScalars *scal, double *partial, long pstride,
+                            bool skip_done, hipStream_t st);
+// p = r + beta p
+hipError_t launch_xpay(const FieldDesc &r, const FieldDesc &p, const RhsList &rl, const CgScalars *scal,
+                       bool skip_done, hipStream_t st);
+// r = b - ax (FP64), partial |r|^2
+hipError_t launch_residual(const FieldDesc &b, const FieldDesc &ax, const FieldDesc &r, const RhsList &rl,
+                           double *partial, long pstride, hipStream_t st);
 // x64 += xs ; xs = 0
-hipError_t launch_accumulate(const FieldDesc &x64, const FieldDesc &xs, hipStream_t st);
-// y = a x + y with a host scalar (FP64 views)
-hipError_t launch_axpy_host(double a, const FieldDesc &x, const FieldDesc &y, hipStream_t st);
+hipError_t launch_accumulate(const FieldDesc &x64, const FieldDesc &xs, const RhsList &rl, hipStream_t st);
 
-// scalar kernels (one block): deterministic sums of the partials
+// Scalar kernels (one block per RHS): deterministic sums of nparts partials.
 enum ScalarOp {
     SC_INIT = 0,     // bb = rr = sum ; target = tol2 * (relative ? bb : 1) ; counters cleared
     SC_ALPHA = 1,    // pAp = sum ; alpha = rr / pAp
     SC_BETA = 2,     // rr_prev = rr ; rr = sum ; beta = rr / rr_prev ; iter++ ; done = rr < target
     SC_RELIABLE = 3  // rr = sum (true residual) ; beta = rr / rr_prev ; done = rr < target
 };
-hipError_t launch_scalar(int op, const double *partial, int n, CgScalars *s, double tol2, int relative,
-                         const int *skip, hipStream_t st, CgScalars *publish = nullptr);
+// publish != nullptr: the scalars of RHS r are finally copied to publish[r]
+// (host-mapped memory), also when the block is skipped.
+hipError_t launch_scalar(int op, const RhsList &rl, const double *partial, long pstride, int nparts,
+                         CgScalars *scal, double tol2, int relative, bool skip_done, CgScalars *publish,
+                         hipStream_t st);
+// out[0] = deterministic maximum of partial[0..n)
+hipError_t launch_max(const double *partial, int n, double *out, hipStream_t st);
 // b = a, bytes / 16 lanes of 16 bytes (bandwidth calibration)
 hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
-// out[0] = deterministic sum of partial[0..n)
-hipError_t launch_sum(const double *partial, int n, double *out, hipStream_t st);
 
-// codec: canonical complex128 [site][12] <-> device format
-// odd-site fields: canonical k-th site -> view site k
+// codec: canonical complex128 [site][12] <-> one device field (RHS 0 of the view)
 hipError_t launch_from_canonical(const double2 *in, const FieldDesc &out, hipStream_t st);
 hipError_t launch_to_canonical(const FieldDesc &in, double2 *out, hipStream_t st);
 // full-lattice fields: canonical site s of parity p -> stacked view site p * V/2 + (s >> 1)
@@ -144,6 +177,5 @@ struct GaugeOut {
 };
 hipError_t launch_gauge_ingest(const Geom &g, const double2 *U, const GaugeOut &o, double *partial_max,
                                hipStream_t st);
-hipError_t launch_max(const double *partial, int n, double *out, hipStream_t st);
 
 }  // namespace tmq

@@ -19,21 +19,21 @@ size_t field_bytes(int prec, long n)
     return b;
 }
 
-int field_alloc(Field &f, int prec, long n)
+int field_alloc(Field &f, int prec, long n, int nrhs)
 {
     field_free(f);
-    if (n % 8) {
+    if (n % 8 || nrhs < 1) {
         set_error("internal: field sizes must be multiples of 8 sites");
         return TMQ_EINVAL;
     }
-    const size_t main = (size_t)n * field_blocks(prec) * 16;
-    if (hipMalloc(&f.mem, main) != hipSuccess) {
+    const size_t per = (size_t)n * field_blocks(prec) * 16;
+    if (hipMalloc(&f.mem, per * nrhs) != hipSuccess) {
         f.mem = nullptr;
         set_error("device allocation of a spinor field failed");
         return TMQ_ENOMEM;
     }
     if (prec == P16 || prec == PB16) {
-        if (hipMalloc((void **)&f.scale, (size_t)n * sizeof(float)) != hipSuccess) {
+        if (hipMalloc((void **)&f.scale, (size_t)n * nrhs * sizeof(float)) != hipSuccess) {
             hipFree(f.mem);
             f.mem = nullptr;
             f.scale = nullptr;
@@ -45,6 +45,9 @@ int field_alloc(Field &f, int prec, long n)
     f.d.data = f.mem;
     f.d.scale = f.scale;
     f.d.n = n;
+    f.d.nrhs = nrhs;
+    f.d.rhs_elems = n * field_blocks(prec);
+    f.d.rhs_sites = n;
     return TMQ_OK;
 }
 
@@ -133,12 +136,15 @@ int lattice_create(const int dims[4], int device, Lattice **out)
     if (hipSetDevice(device) != hipSuccess) return fail(TMQ_EDEVICE, "hipSetDevice failed");
     if (hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking) != hipSuccess)
         return fail(TMQ_EDEVICE, "hipStreamCreate failed");
-    const int np = hop_grid(2 * L->g.vh) + 64;
+    // per RHS: at least as many partials as any hop variant or vector kernel writes
+    L->pstride = hop_grid(2 * L->g.vh) + 64;
     for (auto &p : L->partial)
-        if (hipMalloc((void **)&p, sizeof(double) * np) != hipSuccess) return fail(TMQ_ENOMEM, "partials");
-    if (hipMalloc((void **)&L->scal, sizeof(CgScalars) * 8) != hipSuccess) return fail(TMQ_ENOMEM, "scalars");
-    if (hipMemset(L->scal, 0, sizeof(CgScalars) * 8) != hipSuccess) return fail(TMQ_EDEVICE, "memset");
-    if (hipHostMalloc((void **)&L->ring, sizeof(CgScalars) * Lattice::RING, hipHostMallocMapped) != hipSuccess)
+        if (hipMalloc((void **)&p, sizeof(double) * L->pstride * MAX_RHS) != hipSuccess)
+            return fail(TMQ_ENOMEM, "partials");
+    if (hipMalloc((void **)&L->scal, sizeof(CgScalars) * MAX_RHS) != hipSuccess) return fail(TMQ_ENOMEM, "scalars");
+    if (hipMemset(L->scal, 0, sizeof(CgScalars) * MAX_RHS) != hipSuccess) return fail(TMQ_EDEVICE, "memset");
+    if (hipHostMalloc((void **)&L->ring, sizeof(CgScalars) * MAX_RHS * Lattice::RING, hipHostMallocMapped) !=
+        hipSuccess)
         return fail(TMQ_ENOMEM, "pinned ring");
     if (hipHostGetDevicePointer((void **)&L->ring_dev, L->ring, 0) != hipSuccess)
         return fail(TMQ_EDEVICE, "device view of the pinned ring");
@@ -166,20 +172,21 @@ int stage_buffer(Lattice *L, int slot, size_t bytes, void **out)
     return TMQ_OK;
 }
 
-int work_field(Lattice *L, const char *role, int prec, long n, FieldDesc *out)
+int work_field(Lattice *L, const char *role, int prec, long n, FieldDesc *out, int nrhs)
 {
     for (auto &w : L->work)
         if (w.first == role) {
-            if (w.second.d.prec == prec && w.second.d.n == n) {
+            if (w.second.d.prec == prec && w.second.d.n == n && w.second.d.nrhs >= nrhs) {
                 *out = w.second.d;
+                out->nrhs = nrhs;
                 return TMQ_OK;
             }
-            TMQ_TRY(field_alloc(w.second, prec, n));
+            TMQ_TRY(field_alloc(w.second, prec, n, nrhs));
             *out = w.second.d;
             return TMQ_OK;
         }
     L->work.emplace_back(role, Field{});
-    TMQ_TRY(field_alloc(L->work.back().second, prec, n));
+    TMQ_TRY(field_alloc(L->work.back().second, prec, n, nrhs));
     *out = L->work.back().second.d;
     return TMQ_OK;
 }
@@ -239,59 +246,27 @@ int link_fmt_for(const Lattice *L, int prec, int sloppy_link)
 
 // ------------------------------------------------------------ operators
 
-static void phases(const Lattice *L, const tmq_params &p, HopCoef &c)
+OpParams make_op(const Lattice *L, const tmq_params *p, int n)
 {
+    OpParams op{};
     const int Lmu[4] = {L->g.T, L->g.LX, L->g.LY, L->g.LZ};
     for (int mu = 0; mu < 4; mu++) {
-        const double a = M_PI * p.theta[mu] / Lmu[mu];
-        c.ph[mu][0] = cos(a);
-        c.ph[mu][1] = sin(a);
+        const double a = M_PI * p[0].theta[mu] / Lmu[mu];
+        op.ph[mu][0] = p[0].theta[mu] == 0.0 ? 1.0 : cos(a);
+        op.ph[mu][1] = p[0].theta[mu] == 0.0 ? 0.0 : sin(a);
     }
+    for (int r = 0; r < n && r < MAX_RHS; r++) {
+        op.kappa[r] = p[r].kappa;
+        op.mut[r] = p[r].mu_tilde;
+    }
+    return op;
 }
 
-// K1 of Qhat^{sign}: t_e = kappa^2/(1+mut^2) (1 - sign i mut g5) H_eo psi_o   (eq. (eo3))
-HopCoef coef_K1(const Lattice *L, const tmq_params &p, int sign)
-{
-    HopCoef c{};
-    phases(L, p, c);
-    const double k2 = p.kappa * p.kappa / (1.0 + p.mu_tilde * p.mu_tilde);
-    const double m = sign * p.mu_tilde;
-    c.B[0][0] = k2;  // upper spins, gamma_5 = +1: (1 - i sign mut)
-    c.B[0][1] = -k2 * m;
-    c.B[1][0] = k2;  // lower spins, gamma_5 = -1: (1 + i sign mut)
-    c.B[1][1] = k2 * m;
-    return c;
-}
-
-// K2 of Qhat^{sign}: out_o = gamma_5 [(1 + sign i mut g5) psi_o - H_oe t_e]   (eq. (eo4))
-HopCoef coef_K2(const Lattice *L, const tmq_params &p, int sign)
-{
-    HopCoef c{};
-    phases(L, p, c);
-    const double m = sign * p.mu_tilde;
-    c.A[0][0] = 1.0;  // upper: +(1 + i sign mut)
-    c.A[0][1] = m;
-    c.A[1][0] = -1.0;  // lower: -(1 - i sign mut)
-    c.A[1][1] = m;
-    c.B[0][0] = -1.0;
-    c.B[1][0] = 1.0;
-    return c;
-}
-
-// full lattice Q^{sign} = gamma_5 [(1 + sign i mut g5) psi - kappa H psi]   (eq. (eo1))
-HopCoef coef_full(const Lattice *L, const tmq_params &p, int sign)
-{
-    HopCoef c = coef_K2(L, p, sign);
-    c.B[0][0] = -p.kappa;
-    c.B[1][0] = p.kappa;
-    return c;
-}
-
-double hop_bytes_per_site(int prec, int link_fmt, bool self)
+double hop_bytes_per_site(int prec, int link_fmt, bool self, int nrhs)
 {
     const double sp = prec == P64 ? 192.0 : prec == P32 ? 96.0 : 52.0;
     const double lk = link_fmt == LK64F ? 144.0 : link_fmt == LK64R ? 96.0 : link_fmt == LK32R ? 48.0 : 24.0;
-    return sp + 8.0 * lk + sp + (self ? sp : 0.0);
+    return 8.0 * lk + nrhs * (sp + sp + (self ? sp : 0.0));
 }
 
 static hipEvent_t pool_event(Lattice *L)
@@ -306,22 +281,25 @@ static hipEvent_t pool_event(Lattice *L)
     return e;
 }
 
-// Time every register-budget variant of this hop launch (same operands, the
-// reduction redirected to a scratch array, no skip flag) and keep the fastest
-// for this lattice, spinor precision and link format.
+// Time every valid variant of this hop launch (same operands, the reduction
+// redirected to a scratch array, no skip flags) and keep the fastest for this
+// lattice, spinor precision and link format.
 static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const FieldDesc &self,
-                    const FieldDesc &out, const LinkDesc &lk, const HopCoef &c, bool norm, hipStream_t st)
+                    const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
+                    const RhsList &rl, bool norm, hipStream_t st)
 {
     hipEvent_t e0 = pool_event(L), e1 = pool_event(L);
     double *tp = norm ? L->partial[2] : nullptr;
-    const int reps = L->g.vh >= (1L << 18) ? 3 : 10;
+    const int reps = L->g.vh * rl.n >= (1L << 18) ? 3 : 10;
     int best = 0;
     float best_us = 0.f;
     for (int v = 0; v < HOP_VARIANTS; v++) {
         if (!hop_variant_valid(L->g, v)) continue;
-        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, tp, nullptr, v, st));
+        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, 0, st));
         TMQ_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < reps; r++) TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, tp, nullptr, v, st));
+        for (int r = 0; r < reps; r++)
+            TMQ_HIP(
+                launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, 0, st));
         TMQ_HIP(hipEventRecord(e1, st));
         TMQ_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -336,6 +314,45 @@ static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const
     L->event_pool.push_back(e0);
     L->event_pool.push_back(e1);
     L->hop_variant[key] = best;
+    return TMQ_OK;
+}
+
+// For a batched launch, time RHS groups of 1, 2, 4, ... (the variant fixed)
+// and keep the fastest for this format and batch size.  The group only
+// orders the blocks; it does not change any result.
+static int tune_group(Lattice *L, int key, int out_par, const FieldDesc &in, const FieldDesc &self,
+                      const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
+                      const RhsList &rl, bool norm, hipStream_t st, int *group)
+{
+    hipEvent_t e0 = pool_event(L), e1 = pool_event(L);
+    double *tp = norm ? L->partial[2] : nullptr;
+    const int v = L->hop_variant[key];
+    int best = 1;
+    float best_us = 0.f;
+    std::vector<float> us_all;
+    for (int G = 1;; G *= 2) {
+        if (G > rl.n) G = rl.n;
+        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, G, st));
+        TMQ_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 2; r++)
+            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, G, st));
+        TMQ_HIP(hipEventRecord(e1, st));
+        TMQ_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const float us = ms * 1e3f / 2;
+        us_all.push_back(us);
+        if (best_us == 0.f || us < best_us) {
+            best = G;
+            best_us = us;
+        }
+        if (G == rl.n) break;
+    }
+    L->event_pool.push_back(e0);
+    L->event_pool.push_back(e1);
+    L->hop_group.emplace_back(key * 128 + rl.n, best);
+    L->hop_group_us.emplace_back(key * 128 + rl.n, us_all);
+    *group = best;
     return TMQ_OK;
 }
 
@@ -358,28 +375,61 @@ std::string tuning_report(const Lattice *L)
         s += "]}";
         first = false;
     }
+    s += "], \"batch_group\": [";
+    for (size_t i = 0; i < L->hop_group.size(); i++) {
+        const int k = L->hop_group[i].first / 128, n = L->hop_group[i].first % 128;
+        char buf[256];
+        snprintf(buf, sizeof(buf), "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"nrhs\": %d, \"group\": %d, \"us\": [",
+                 i ? ", " : "", pn[k / 4], ln[k % 4], n, L->hop_group[i].second);
+        s += buf;
+        const auto &u = L->hop_group_us[i].second;
+        for (size_t j = 0; j < u.size(); j++) {
+            snprintf(buf, sizeof(buf), "%s%.1f", j ? ", " : "", u[j]);
+            s += buf;
+        }
+        s += "]}";
+    }
     s += "]}";
     return s;
 }
 
 int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
-        const LinkDesc &lk, const HopCoef &c, double *partial, const int *skip, hipStream_t st)
+        const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
+        const CgScalars *scal, hipStream_t st)
 {
+    if (rl.n <= 0) return TMQ_OK;
     const int key = in.prec * 4 + lk.fmt;
     if (L->forced_variant >= 0)
         L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;
     else if (L->hop_variant[key] < 0)
-        TMQ_TRY(tune_hop(L, key, out_par, in, self, out, lk, c, partial != nullptr, st));
+        TMQ_TRY(tune_hop(L, key, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st));
+    // batches of up to 4 RHS run as one group; larger ones use the group tuned
+    // for their power-of-two size class
+    int group = rl.n;
+    if (rl.n > 4) {
+        int cls = 8;
+        while (cls < rl.n) cls *= 2;
+        group = 0;
+        for (auto &e : L->hop_group)
+            if (e.first == key * 128 + cls) group = e.second;
+        if (!group) {
+            TMQ_TRY(tune_group(L, key, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st, &group));
+            L->hop_group.back().first = key * 128 + cls;
+            L->hop_group_us.back().first = key * 128 + cls;
+        }
+    }
     TimedLaunch t{};
     if (L->timing) {
         t.a = pool_event(L);
         t.b = pool_event(L);
-        t.bytes = hop_bytes_per_site(in.prec, lk.fmt, self.data != nullptr) * (double)L->g.vh;
-        t.flops = 1320.0 * (double)L->g.vh;
+        t.bytes = hop_bytes_per_site(in.prec, lk.fmt, epi != EPI_K1, rl.n) * (double)L->g.vh;
+        t.flops = 1320.0 * (double)L->g.vh * rl.n;
         t.prec = in.prec;
+        t.nrhs = rl.n;
         TMQ_HIP(hipEventRecord(t.a, st));
     }
-    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, c, partial, skip, L->hop_variant[key], st));
+    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal,
+                       L->hop_variant[key], group, st));
     L->hop_blocks_last = hop_grid_variant(L->g, L->hop_variant[key]);
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));
@@ -388,33 +438,33 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
     return TMQ_OK;
 }
 
-int apply_Qhat(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in, const FieldDesc &out,
-               const FieldDesc &tmp_e, const LinkDesc &lk, double *partial, const int *skip, hipStream_t st)
+int apply_Qhat(Lattice *L, const OpParams &op, int sign, const FieldDesc &in, const FieldDesc &out,
+               const FieldDesc &tmp_e, const LinkDesc &lk, const RhsList &rl, double *partial,
+               const CgScalars *scal, hipStream_t st)
 {
     const FieldDesc none{};
-    TMQ_TRY(hop(L, 0, in, none, tmp_e, lk, coef_K1(L, p, sign), nullptr, skip, st));
-    TMQ_TRY(hop(L, 1, tmp_e, in, out, lk, coef_K2(L, p, sign), partial, skip, st));
+    TMQ_TRY(hop(L, 0, in, none, tmp_e, lk, op, EPI_K1, sign, rl, nullptr, scal, st));
+    TMQ_TRY(hop(L, 1, tmp_e, in, out, lk, op, EPI_K2, sign, rl, partial, scal, st));
     return TMQ_OK;
 }
 
-int apply_QhatQhat(Lattice *L, const tmq_params &p, const FieldDesc &in, const FieldDesc &out,
-                   const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, double *partial,
-                   const int *skip, hipStream_t st)
+int apply_QhatQhat(Lattice *L, const OpParams &op, const FieldDesc &in, const FieldDesc &out,
+                   const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, const RhsList &rl,
+                   double *partial, const CgScalars *scal, hipStream_t st)
 {
-    TMQ_TRY(apply_Qhat(L, p, -1, in, tmp_o, tmp_e, lk, partial, skip, st));
-    TMQ_TRY(apply_Qhat(L, p, +1, tmp_o, out, tmp_e, lk, nullptr, skip, st));
+    TMQ_TRY(apply_Qhat(L, op, -1, in, tmp_o, tmp_e, lk, rl, partial, scal, st));
+    TMQ_TRY(apply_Qhat(L, op, +1, tmp_o, out, tmp_e, lk, rl, nullptr, scal, st));
     return TMQ_OK;
 }
 
-int apply_Q_full(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in, const FieldDesc &out,
-                 const LinkDesc &lk, hipStream_t st)
+int apply_Q_full(Lattice *L, const OpParams &op, int sign, const FieldDesc &in, const FieldDesc &out,
+                 const LinkDesc &lk, const RhsList &rl, hipStream_t st)
 {
     const long vh = L->g.vh;
     const FieldDesc ie = field_sub(in, 0, vh), io = field_sub(in, vh, vh);
     const FieldDesc oe = field_sub(out, 0, vh), oo = field_sub(out, vh, vh);
-    const HopCoef c = coef_full(L, p, sign);
-    TMQ_TRY(hop(L, 0, io, ie, oe, lk, c, nullptr, nullptr, st));
-    TMQ_TRY(hop(L, 1, ie, io, oo, lk, c, nullptr, nullptr, st));
+    TMQ_TRY(hop(L, 0, io, ie, oe, lk, op, EPI_FULL, sign, rl, nullptr, nullptr, st));
+    TMQ_TRY(hop(L, 1, ie, io, oo, lk, op, EPI_FULL, sign, rl, nullptr, nullptr, st));
     return TMQ_OK;
 }
 

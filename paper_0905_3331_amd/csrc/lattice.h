@@ -37,7 +37,7 @@ struct Field {
     float *scale = nullptr;
 };
 
-int field_alloc(Field &f, int prec, long n);
+int field_alloc(Field &f, int prec, long n, int nrhs = 1);
 void field_free(Field &f);
 size_t field_bytes(int prec, long n);
 
@@ -45,6 +45,7 @@ struct TimedLaunch {
     hipEvent_t a, b;
     double bytes, flops;
     int prec;  // spinor storage of the launch
+    int nrhs;  // right-hand sides in the launch
 };
 
 struct Lattice {
@@ -61,10 +62,11 @@ struct Lattice {
     uint4 *u16a = nullptr;
     uint2 *u16b = nullptr;
 
-    // reductions and solver scalars
+    // reductions and solver scalars: partial sums of RHS r at partial[k] + r * pstride
     double *partial[3] = {nullptr, nullptr, nullptr};
-    CgScalars *scal = nullptr;      // device
-    CgScalars *ring = nullptr;      // pinned host-mapped, RING slots (host view)
+    long pstride = 0;
+    CgScalars *scal = nullptr;      // device, MAX_RHS entries
+    CgScalars *ring = nullptr;      // pinned host-mapped, RING slots of MAX_RHS entries (host view)
     CgScalars *ring_dev = nullptr;  // device view of the same slots
     hipEvent_t ring_ev[8] = {};
     static constexpr int RING = 8;
@@ -80,6 +82,9 @@ struct Lattice {
     int hop_variant[16];
     float hop_tune_us[16][HOP_VARIANTS];
     int forced_variant = -1;  // TMQ_HOP_VARIANT in the environment
+    // autotuned RHS group of batched hops, per (spinor precision, link format, batch size)
+    std::vector<std::pair<int, int>> hop_group;  // (key * 128 + nrhs, group)
+    std::vector<std::pair<int, std::vector<float>>> hop_group_us;
     int hop_blocks_last = 0;  // blocks (partial sums) of the last hop launch
 
     // kernel timing
@@ -96,30 +101,33 @@ LinkDesc lattice_links(const Lattice *L, int fmt);
 // link format used for a spinor precision (sloppy_link: P32 or P16 for the inner links)
 int link_fmt_for(const Lattice *L, int prec, int sloppy_link);
 
-// a work field of the given role, precision and site count (allocated once, reused)
-int work_field(Lattice *L, const char *role, int prec, long n, FieldDesc *out);
+// a work field of the given role, precision, site count and RHS count (allocated once, reused)
+int work_field(Lattice *L, const char *role, int prec, long n, FieldDesc *out, int nrhs = 1);
 int stage_buffer(Lattice *L, int slot, size_t bytes, void **out);
 
-HopCoef coef_K1(const Lattice *L, const tmq_params &p, int sign);
-HopCoef coef_K2(const Lattice *L, const tmq_params &p, int sign);
-HopCoef coef_full(const Lattice *L, const tmq_params &p, int sign);
+// operator parameters of a batch (theta of p[0] for all; kappa, mut per RHS)
+OpParams make_op(const Lattice *L, const tmq_params *p, int n);
 
-// one hop half-sweep through the timing hook
+// one hop half-sweep through the autotuner and the timing hook
 int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
-        const LinkDesc &lk, const HopCoef &c, double *partial, const int *skip, hipStream_t st);
+        const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
+        const CgScalars *scal, hipStream_t st);
 
 // Qhat^{sign} in -> out (odd fields), tmp_e an even work field; partial: |out|^2 per block
-int apply_Qhat(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in, const FieldDesc &out,
-               const FieldDesc &tmp_e, const LinkDesc &lk, double *partial, const int *skip, hipStream_t st);
+int apply_Qhat(Lattice *L, const OpParams &op, int sign, const FieldDesc &in, const FieldDesc &out,
+               const FieldDesc &tmp_e, const LinkDesc &lk, const RhsList &rl, double *partial,
+               const CgScalars *scal, hipStream_t st);
 // Qhat^+ Qhat^- in -> out; partial receives |Qhat^- in|^2 per block
-int apply_QhatQhat(Lattice *L, const tmq_params &p, const FieldDesc &in, const FieldDesc &out,
-                   const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, double *partial,
-                   const int *skip, hipStream_t st);
+int apply_QhatQhat(Lattice *L, const OpParams &op, const FieldDesc &in, const FieldDesc &out,
+                   const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, const RhsList &rl,
+                   double *partial, const CgScalars *scal, hipStream_t st);
 // full-lattice Q^{sign} on stacked (even, odd) fields
-int apply_Q_full(Lattice *L, const tmq_params &p, int sign, const FieldDesc &in, const FieldDesc &out,
-                 const LinkDesc &lk, hipStream_t st);
+int apply_Q_full(Lattice *L, const OpParams &op, int sign, const FieldDesc &in, const FieldDesc &out,
+                 const LinkDesc &lk, const RhsList &rl, hipStream_t st);
 
-double hop_bytes_per_site(int prec, int link_fmt, bool self);
+// algorithmic bytes of one hop half-sweep per output site for nrhs RHS
+// (links once, spinors per RHS)
+double hop_bytes_per_site(int prec, int link_fmt, bool self, int nrhs = 1);
 
 int check_params(const tmq_params *p);
 std::string tuning_report(const Lattice *L);

@@ -34,6 +34,12 @@ struct cx {
     R re, im;
 };
 
+// Fused multiply-adds are written out (the device code is compiled without
+// floating-point contraction), so that every kernel instantiation that runs
+// the same operations rounds the same way.
+TMQ_HD float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+TMQ_HD double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename R>
 TMQ_HD cx<R> mk(R a, R b) { return cx<R>{a, b}; }
 template <typename R>
@@ -43,7 +49,10 @@ TMQ_HD cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
 template <typename R>
 TMQ_HD cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
 template <typename R>
-TMQ_HD cx<R> operator*(cx<R> a, cx<R> b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+TMQ_HD cx<R> operator*(cx<R> a, cx<R> b)
+{
+    return {fmad(a.re, b.re, -(a.im * b.im)), fmad(a.re, b.im, a.im * b.re)};
+}
 template <typename R>
 TMQ_HD cx<R> operator*(R a, cx<R> b) { return {a * b.re, a * b.im}; }
 template <typename R>
@@ -57,15 +66,15 @@ TMQ_HD cx<R> imi(cx<R> a) { return {a.im, -a.re}; }
 template <typename R>
 TMQ_HD cx<R> fma(cx<R> b, cx<R> c, cx<R> a)
 {
-    return {a.re + b.re * c.re - b.im * c.im, a.im + b.re * c.im + b.im * c.re};
+    return {fmad(b.re, c.re, fmad(-b.im, c.im, a.re)), fmad(b.re, c.im, fmad(b.im, c.re, a.im))};
 }
 template <typename R>
 TMQ_HD cx<R> cfma(cx<R> b, cx<R> c, cx<R> a)
 {
-    return {a.re + b.re * c.re + b.im * c.im, a.im + b.re * c.im - b.im * c.re};
+    return {fmad(b.re, c.re, fmad(b.im, c.im, a.re)), fmad(b.re, c.im, fmad(-b.im, c.re, a.im))};
 }
 template <typename R>
-TMQ_HD R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
+TMQ_HD R norm2(cx<R> a) { return fmad(a.re, a.re, a.im * a.im); }
 
 // A spinor: 4 spins x 3 colours; a half spinor: 2 x 3.
 template <typename R>
@@ -157,23 +166,29 @@ TMQ_HD void reconstruct_add(spinor<R> &acc, const half<R> &h)
     }
 }
 
-// out = ph * U h (DAG = false) or ph * U^+ h (DAG = true), on both rows of h
+// out = U h (DAG = false) or U^+ h (DAG = true), on both rows of h
 template <bool DAG, typename R>
-TMQ_HD void link_mul(const su3<R> &u, const half<R> &h, cx<R> ph, half<R> &out)
+TMQ_HD void link_mul(const su3<R> &u, const half<R> &h, half<R> &out)
 {
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
-        cx<R> t[3];
+    for (int k = 0; k < 2; k++)
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             cx<R> s = {R(0), R(0)};
 #pragma unroll
             for (int b = 0; b < 3; b++) s = DAG ? cfma(u.e[b][a], h.c[k][b], s) : fma(u.e[a][b], h.c[k][b], s);
-            t[a] = s;
+            out.c[k][a] = s;
         }
+}
+
+// h *= ph (a complex phase)
+template <typename R>
+TMQ_HD void half_scale(half<R> &h, cx<R> ph)
+{
 #pragma unroll
-        for (int a = 0; a < 3; a++) out.c[k][a] = ph * t[a];
-    }
+    for (int k = 0; k < 2; k++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) h.c[k][a] = ph * h.c[k][a];
 }
 
 }  // namespace tmq

@@ -27,6 +27,28 @@ inline L32R make_lk<L32R>(const LinkDesc &l) { return L32R{(const float4 *)l.a, 
 template <>
 inline L16R make_lk<L16R>(const LinkDesc &l) { return L16R{(const uint4 *)l.a, (const uint2 *)l.b, l.vh}; }
 
+// the view of RHS r of a batch (elems / sites: offsets of RHS r)
+__device__ __forceinline__ SpF64 rhs_view(const SpF64 &v, long elems, long) { return SpF64{v.p + elems}; }
+__device__ __forceinline__ SpF32 rhs_view(const SpF32 &v, long elems, long) { return SpF32{v.p + elems}; }
+template <bool BF>
+__device__ __forceinline__ Sp16<BF> rhs_view(const Sp16<BF> &v, long elems, long sites)
+{
+    return Sp16<BF>{v.p + elems, v.scale + sites};
+}
+
+// a batched field argument: RHS 0 view plus the per-RHS offsets
+template <class SP>
+struct BatchView {
+    SP v;
+    long rhs_elems, rhs_sites;
+    __device__ __forceinline__ SP at(int r) const { return rhs_view(v, r * rhs_elems, r * rhs_sites); }
+};
+template <class SP>
+inline BatchView<SP> make_bv(const FieldDesc &f)
+{
+    return BatchView<SP>{make_sp<SP>(f), f.rhs_elems, f.rhs_sites};
+}
+
 // dispatch a statement over the four spinor formats (F is the format type)
 #define TMQ_DISPATCH_SP(prec, F, ...)                      \
     switch (prec) {                                        \

@@ -26,6 +26,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+MAX_RHS = 64
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 
 TMQ_OK, TMQ_EINVAL, TMQ_ENOMEM, TMQ_ENOCONV, TMQ_EDEVICE, TMQ_ENAN, TMQ_ESTATE = 0, -1, -2, -3, -4, -5, -6
@@ -64,6 +65,10 @@ _SIGS = {
     "tmq_apply_Q_full_dev": (_ip, [_vp, _P(tmq_params), _ip, _vp, _vp, _vp]),
     "tmq_solve": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _P(tmq_solve_info)]),
     "tmq_solve_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_solve_batch": (_ip, [_vp, _ip, _P(tmq_params), _P(tmq_solver_opts), _P(_vp), _P(_vp),
+                              _P(tmq_solve_info)]),
+    "tmq_solve_batch_dev": (_ip, [_vp, _ip, _P(tmq_params), _P(tmq_solver_opts), _P(_vp), _P(_vp), _vp,
+                                  _P(tmq_solve_info)]),
     "tmq_solve_full_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
     "tmq_set_kernel_timing": (_ip, [_vp, _ip]),
     "tmq_kernel_stats": (_ip, [_vp, ctypes.c_char_p, _P(ctypes.c_int), _P(ctypes.c_double),
@@ -279,6 +284,34 @@ class Lattice:
         if check:
             _check(code, "tmq_solve")
         return x, _info(info)
+
+    def solve_batch(self, ps, bs, opts: tmq_solver_opts, xs=None, stream=None, check=True):
+        """Solve Qhat^+ Qhat^- x_r = b_r for a batch (list of params, list of sources,
+        device tensors or host arrays); returns (list of x, list of SolveInfo)."""
+        n = len(bs)
+        if len(ps) != n or not 1 <= n <= MAX_RHS:
+            raise ValueError(f"need 1..{MAX_RHS} sources and one params per source")
+        nc = self.V // 2 * 12
+        parr = (tmq_params * n)(*ps)
+        infos = (tmq_solve_info * n)()
+        host = isinstance(bs[0], np.ndarray)
+        if xs is None:
+            if host:
+                xs = [np.empty_like(b) for b in bs]
+            else:
+                import torch
+
+                xs = [torch.empty_like(b) for b in bs]
+        conv = _hptr if host else _dptr
+        bp = (ctypes.c_void_p * n)(*[conv(b, nc, "b").value for b in bs])
+        xp = (ctypes.c_void_p * n)(*[conv(x, nc, "x").value for x in xs])
+        if host:
+            code = _lib.tmq_solve_batch(self._h, n, parr, ctypes.byref(opts), bp, xp, infos)
+        else:
+            code = _lib.tmq_solve_batch_dev(self._h, n, parr, ctypes.byref(opts), bp, xp, _stream(stream), infos)
+        if check:
+            _check(code, "tmq_solve_batch")
+        return xs, [_info(i) for i in infos]
 
     def solve_full(self, p: tmq_params, b, opts: tmq_solver_opts, x=None, stream=None, check=True):
         """Solve Q^+ Q^- x = b on the full lattice (FP64 CG); device tensors (V, 4, 3)."""
