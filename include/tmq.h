@@ -42,8 +42,9 @@
  * must not be used from two host threads at once.
  *
  * ---------------------------------------------------------------- errors
- * Every int-returning call returns TMQ_OK (0) or a negative tmq_status; it
- * never throws or aborts.  tmq_last_error() returns a message for the last
+ * Every int-returning call returns TMQ_OK (0) or a negative tmq_status
+ * (tmq_server_poll and tmq_server_wait also TMQ_PENDING); it never throws or
+ * aborts.  tmq_last_error() returns a message for the last
  * failure on the calling thread.
  */
 #ifndef TMQ_H
@@ -65,7 +66,8 @@ typedef enum {
     TMQ_ENOCONV = -3, /* max_iter reached; x holds the last iterate, info the true residual */
     TMQ_EDEVICE = -4, /* a HIP runtime call failed */
     TMQ_ENAN = -5,    /* a non-finite value appeared in the solver */
-    TMQ_ESTATE = -6   /* call out of order, e.g. apply before any gauge field was loaded */
+    TMQ_ESTATE = -6,  /* call out of order, e.g. apply before any gauge field was loaded */
+    TMQ_PENDING = 1   /* tmq_server_poll / tmq_server_wait: the request has not finished yet */
 } tmq_status;
 
 /* storage precision of spinors / links on the device; arithmetic is FP64 for
@@ -183,6 +185,92 @@ int tmq_solve_batch_dev(tmq_lattice *lat, int nrhs, const tmq_params *p, const t
  * Full-lattice canonical spinors; x_0 = 0. */
 int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts,
                        const double *b, double *x, void *stream, tmq_solve_info *info);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A solve server: a stream of independent even/odd solves (each a request
+ * with its own lattice, kappa, mu_tilde, source and tolerance) served on one
+ * device, the pattern of the paper's inversion program that solves on many
+ * sources and masses per gauge configuration (Sec. 3.2) turned into a
+ * long-running service.
+ *
+ * Lattices (gauge fields) are registered once and stay resident.  A request
+ * runs in a CG engine: batch work fields with a number of slots, one engine
+ * per (lattice, inner precision, inner link format, boundary phases), each on
+ * its own HIP stream, so different lattice sizes overlap on the device.
+ * Continuous batching: a request joins a free slot of its engine at the next
+ * iteration boundary and leaves as soon as its FP64 true residual meets its
+ * tolerance; the others keep iterating.  Every iteration advances all slots of
+ * an engine in the same kernel launches (links read once per half-sweep for
+ * all of them).  A request computes exactly what tmq_solve computes for it
+ * on the server's lattice, whatever else is in flight: its result does not
+ * depend on the mix.
+ *
+ * Admission by device-memory footprint: engines hold the work fields of all
+ * their slots (tmq_footprint_bytes less the gauge copies, per slot); the sum
+ * over engines never exceeds the server's budget.  A request waits in the
+ * queue until a slot of its engine is free or memory for one can be found
+ * (idle engines of other keys are released for it); requests of other keys
+ * may pass a waiting one.  A request whose single slot exceeds the whole
+ * budget is rejected at submission with TMQ_ENOMEM.
+ *
+ * Threads: the server runs one worker thread that drives every engine; all
+ * tmq_server_* calls are thread-safe.  Fields are DEVICE pointers on the
+ * server's device in the odd-site canonical layout of tmq_solve_dev.  The
+ * server's streams do not wait for the caller's: b must hold its values when
+ * tmq_server_submit is called (work producing it has completed), and the
+ * caller keeps b and x alive and untouched until the request has finished
+ * (poll/wait returned something other than TMQ_PENDING); x is complete then. */
+typedef struct tmq_server tmq_server;
+
+typedef struct {
+    size_t budget_bytes; /* device memory for the engines' work fields; 0: 60% of the
+                            device memory free at creation */
+    int max_batch;       /* slots per engine, 1..TMQ_MAX_RHS; <= 0: 16 */
+} tmq_server_config;
+
+typedef struct {
+    long submitted, completed, failed, rejected; /* failed: finished with a non-OK status */
+    long queued, running;        /* now: waiting for admission / admitted and not finished */
+    double p50_s, p99_s, mean_s; /* latency submit -> result ready, completed requests */
+    double mean_wait_s;          /* time from submission to admission, completed requests */
+    double solves_per_s;         /* completed / (last completion - first submission) */
+    double elapsed_s;            /* first submission -> last completion */
+    size_t budget_bytes, bytes_in_use, peak_bytes;
+    int engines, peak_running;   /* engines now, largest number of requests admitted at once */
+    long steps;                  /* engine iteration steps driven */
+} tmq_server_stats;
+
+/* Create a server on HIP device `device`; cfg may be NULL (defaults). */
+int tmq_server_create(int device, const tmq_server_config *cfg, tmq_server **out);
+
+/* Register a lattice: extents dims as for tmq_lattice_create and its gauge
+ * field as for tmq_load_gauge_dev (device pointer; copied, the caller may free
+ * it on return).  *lattice_id receives the id used by tmq_server_submit. */
+int tmq_server_add_lattice(tmq_server *srv, const int dims[4], const double *U_dev, int *lattice_id);
+
+/* Queue a solve of Qhat^+ Qhat^- x = b on lattice lattice_id (options as for
+ * tmq_solve).  *ticket receives the request's id.  TMQ_EINVAL for bad
+ * arguments, TMQ_ENOMEM if one slot for it exceeds the budget, TMQ_EDEVICE
+ * if the server has failed. */
+int tmq_server_submit(tmq_server *srv, int lattice_id, const tmq_params *p, const tmq_solver_opts *opts,
+                      const double *b_dev, double *x_dev, uint64_t *ticket);
+
+/* TMQ_PENDING while the request is queued or running.  Once it has finished
+ * (x written), returns its status (as tmq_solve would), fills info (seconds =
+ * latency from submission to result) if non-NULL and retires the ticket;
+ * TMQ_EINVAL for an unknown or retired ticket. */
+int tmq_server_poll(tmq_server *srv, uint64_t ticket, tmq_solve_info *info);
+/* As poll, waiting up to timeout_s seconds (< 0: without limit). */
+int tmq_server_wait(tmq_server *srv, uint64_t ticket, double timeout_s, tmq_solve_info *info);
+
+/* Counters and latency figures since creation or the last reset. */
+int tmq_server_get_stats(tmq_server *srv, tmq_server_stats *out);
+int tmq_server_reset_stats(tmq_server *srv);
+
+/* Stop the worker after the requests in flight have finished (queued ones
+ * are dropped), free every engine and lattice.  NULL is allowed. */
+void tmq_server_destroy(tmq_server *srv);
 
 /* ---------------------------------------------------------- diagnostics */
 

@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libtmq.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 ARCH = os.environ.get("TMQ_OFFLOAD_ARCH", "gfx950")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 COMMON = [
     "-O3",
@@ -50,8 +51,8 @@ def _compile(src: str) -> str:
     cmd = [hipcc(), *COMMON]
     if src.endswith(".hip"):
         cmd += ["-x", "hip", *DEVICE]
-    else:
-        cmd += ["-D__HIP_PLATFORM_AMD__"]
+    else:  # host-only C++ against the HIP runtime
+        cmd += ["-x", "c++", "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -6,11 +6,12 @@
 #include <new>
 #include <vector>
 
+#include "engine.h"
 #include "lattice.h"
 
 namespace tmq {
-int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o, const FieldDesc &b,
-                const FieldDesc &x, hipStream_t st, tmq_solve_info *info);
+int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o, const double *const *b,
+                double *const *x, hipStream_t st, tmq_solve_info *info);
 int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
                hipStream_t st, tmq_solve_info *info);
 }  // namespace tmq
@@ -47,15 +48,6 @@ int check_lat(tmq_lattice *lat, bool need_gauge)
     return TMQ_OK;
 }
 
-int check_prec(int prec)
-{
-    if (prec < TMQ_FP64 || prec > TMQ_BF16) {
-        set_error("invalid tmq_prec");
-        return TMQ_EINVAL;
-    }
-    return TMQ_OK;
-}
-
 int check_sign(int sign)
 {
     if (sign != 1 && sign != -1) {
@@ -69,24 +61,6 @@ int check_ptrs(const void *a, const void *b)
 {
     if (!a || !b) {
         set_error("NULL field pointer");
-        return TMQ_EINVAL;
-    }
-    return TMQ_OK;
-}
-
-int check_opts(const tmq_solver_opts *o)
-{
-    if (!o) {
-        set_error("NULL tmq_solver_opts");
-        return TMQ_EINVAL;
-    }
-    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) {
-        set_error("tol must be a positive finite number");
-        return TMQ_EINVAL;
-    }
-    TMQ_TRY(check_prec(o->sloppy));
-    if (o->sloppy != TMQ_FP64 && o->sloppy_link != TMQ_FP32 && o->sloppy_link != TMQ_FP16) {
-        set_error("sloppy_link must be TMQ_FP32 or TMQ_FP16");
         return TMQ_EINVAL;
     }
     return TMQ_OK;
@@ -294,17 +268,7 @@ int tmq_solve_batch_dev(tmq_lattice *lat, int nrhs, const tmq_params *p, const t
     Lattice *L = lat->L;
     DeviceGuard dg(L->device);
     hipStream_t st = (hipStream_t)stream;
-    const long vh = L->g.vh;
-    FieldDesc fb, fx;
-    TMQ_TRY(work_field(L, "solve_b", P64, vh, &fb, nrhs));
-    TMQ_TRY(work_field(L, "solve_x", P64, vh, &fx, nrhs));
-    for (int r = 0; r < nrhs; r++) TMQ_HIP(launch_from_canonical((const double2 *)b[r], field_rhs(fb, r), st));
-    const int s = solve_batch(L, nrhs, p, *opts, fb, fx, st, info);
-    if (s == TMQ_OK || s == TMQ_ENOCONV) {
-        for (int r = 0; r < nrhs; r++) TMQ_HIP(launch_to_canonical(field_rhs(fx, r), (double2 *)x[r], st));
-        TMQ_HIP(hipStreamSynchronize(st));
-    }
-    return s;
+    return solve_batch(L, nrhs, p, *opts, b, x, st, info);
 }
 
 int tmq_solve_batch(tmq_lattice *lat, int nrhs, const tmq_params *p, const tmq_solver_opts *opts,
@@ -527,10 +491,8 @@ int tmq_footprint_bytes(const int dims[4], const tmq_solver_opts *opts, int nrhs
     const long vh = (long)dims[0] * dims[1] * dims[2] * dims[3] / 2;
     // gauge copies: FP64 full + FP64, FP32, FP16 two-row, both parities, 4 directions
     size_t g = (size_t)8 * vh * (9 * 16 + 6 * 16 + 3 * 16 + 24);
-    // FP64 solve: b, x, r, Ax, t_e, t_o, p, Ap ; mixed adds 5 sloppy fields + FP32 x_s
-    size_t per = 8 * field_bytes(P64, vh);
-    if (opts && opts->sloppy != TMQ_FP64) per = 6 * field_bytes(P64, vh) + 5 * field_bytes(opts->sloppy, vh) +
-                                               field_bytes(P32, vh);
+    // work fields of one right-hand side in a CG engine
+    const size_t per = engine_slot_bytes(vh, opts ? opts->sloppy : TMQ_FP64);
     *out = g + per * (size_t)nrhs;
     return TMQ_OK;
 }

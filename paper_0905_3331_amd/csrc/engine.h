@@ -1,0 +1,101 @@
+// engine.h -- the CG engine: right-hand sides in slots that join and leave.
+//
+// An engine owns batch work fields with `cap` slots on one lattice, for one
+// inner precision.  A right-hand side occupies a slot from join() until it
+// has finished and been taken; every step advances all occupied slots by one
+// CG iteration (Sec. 4.4) in shared launches.  The decisions per slot (when
+// to recompute the true residual, when to stop) depend only on that slot's
+// own scalars and on the number of steps since it joined, so a right-hand
+// side computes the same numbers whatever the other slots hold.
+//
+// A step has two halves, so that the GPU never waits for the host:
+//   begin_step()  enqueue the iteration body for the slots still iterating;
+//   end_step()    read the scalars the previous step published (waiting for
+//                 them if needed), decide per slot, enqueue the reliable
+//                 updates and p = r + beta p, record the step's event.
+// join() and take() are called between end_step() and the next begin_step().
+//
+// Per slot, with k = steps since the slot joined (its first body is step 0):
+//   bodies run for k = 0 .. max_iter-1; at step k >= 1 the scalars of step
+//   k-1 decide: non-finite -> finished (ENAN); a true residual below the
+//   target -> finished; an iterated residual below the target -> reliable
+//   update (true residual) now; mixed precision and the iterated residual
+//   below delta^2 times the largest since the last true one -> reliable
+//   update.  At k = max_iter a solution that has no true residual yet gets
+//   one, and the slot finishes one step later (ENOCONV unless converged).
+#pragma once
+#include <vector>
+
+#include "lattice.h"
+
+namespace tmq {
+
+struct Engine {
+    Lattice *L = nullptr;
+    int sloppy = P64;       // inner spinor precision (P64: plain FP64 CG)
+    int sloppy_link = P32;  // inner link precision (mixed only)
+    hipStream_t st = nullptr;
+    int cap = 0;
+    bool mixed = false;
+
+    std::vector<Field> fields;
+    FieldDesc b, x, r64, ax64, te64, to64, rs, ps, aps, tes, tos, xs;
+    LinkDesc lk64{}, lks{};
+    OpParams op{};
+    double *partial[3] = {nullptr, nullptr, nullptr};  // per slot at + slot * L->pstride
+    CgScalars *scal = nullptr;                         // device, cap entries
+    CgScalars *ring = nullptr, *ring_dev = nullptr;    // pinned, RING x cap entries
+    std::vector<hipEvent_t> step_ev;                   // RING events
+    size_t bytes = 0;                                  // device memory held
+
+    enum SlotState { FREE = 0, RUNNING = 1, FINISHED = 2 };
+    struct Slot {
+        int state = FREE;
+        long joined_step = 0;  // step whose body is the slot's first
+        double maxr2 = 0.0;    // largest |r|^2 since the last true residual
+        double tol = 0.0, delta = 0.0;
+        int relative = 1, max_iter = 0;
+        CgScalars last{};      // scalars at finish
+        int status = TMQ_OK;
+    };
+    std::vector<Slot> slots;
+
+    long step_no = 0;           // steps begun
+    bool body_pending = false;  // begin_step() done, end_step() not yet
+
+    Engine() = default;
+    Engine(const Engine &) = delete;
+    Engine &operator=(const Engine &) = delete;
+    ~Engine();
+};
+
+// Bytes of device memory one slot holds (work fields of one right-hand side).
+size_t engine_slot_bytes(long vh, int sloppy);
+// Bytes an engine of cap slots holds in total.
+size_t engine_bytes(const Lattice *L, int sloppy, int cap);
+
+// Allocate an engine with cap slots (1..MAX_RHS) on L for the inner
+// precision of o (sloppy, sloppy_link); commands go to stream st.
+int engine_create(Lattice *L, int sloppy, int sloppy_link, int cap, hipStream_t st, Engine **out);
+// Default delta of reliable updates for an inner precision.
+double engine_default_delta(int sloppy);
+
+// Put right-hand side b (device, canonical odd-site complex128 [V/2][12])
+// into free slot `slot` and enqueue its initialisation.  Boundary phases are
+// common to the engine: theta must equal that of the slots already running.
+// tol, relative, max_iter and delta of o apply to this slot.
+int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts &o, const double2 *b);
+int engine_free_slot(const Engine *E);  // a free slot, or -1
+int engine_begin_step(Engine *E);
+// True when the scalars end_step() reads are on the host (never blocks).
+bool engine_ready(Engine *E);
+// Blocks until ready, then decides; `finished` receives the slots that ended.
+int engine_end_step(Engine *E, std::vector<int> *finished);
+// Slots running (joined and not finished).
+int engine_running(const Engine *E);
+int engine_occupied(const Engine *E);
+// Enqueue the canonical copy of a finished slot's solution into x (device,
+// may be nullptr), fill info (seconds untouched) and free the slot.
+int engine_take(Engine *E, int slot, double2 *x, tmq_solve_info *info);
+
+}  // namespace tmq

@@ -1,6 +1,8 @@
 // lattice.cpp -- lattice object: creation, gauge ingest, operator application.
 #include "lattice.h"
 
+#include "engine.h"
+
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -66,6 +68,7 @@ Lattice::~Lattice()
     hipGetDevice(&cur);
     hipSetDevice(device);
     if (own) hipStreamSynchronize(own);
+    for (Engine *e : engines) delete e;
     for (auto &w : work) field_free(w.second);
     for (void *p : {(void *)u64f, (void *)u64r, (void *)u32r, (void *)u16a, (void *)u16b})
         if (p) hipFree(p);
@@ -465,6 +468,33 @@ int apply_Q_full(Lattice *L, const OpParams &op, int sign, const FieldDesc &in, 
     const FieldDesc oe = field_sub(out, 0, vh), oo = field_sub(out, vh, vh);
     TMQ_TRY(hop(L, 0, io, ie, oe, lk, op, EPI_FULL, sign, rl, nullptr, nullptr, st));
     TMQ_TRY(hop(L, 1, ie, io, oo, lk, op, EPI_FULL, sign, rl, nullptr, nullptr, st));
+    return TMQ_OK;
+}
+
+int check_prec(int prec)
+{
+    if (prec < TMQ_FP64 || prec > TMQ_BF16) {
+        set_error("invalid tmq_prec");
+        return TMQ_EINVAL;
+    }
+    return TMQ_OK;
+}
+
+int check_opts(const tmq_solver_opts *o)
+{
+    if (!o) {
+        set_error("NULL tmq_solver_opts");
+        return TMQ_EINVAL;
+    }
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) {
+        set_error("tol must be a positive finite number");
+        return TMQ_EINVAL;
+    }
+    TMQ_TRY(check_prec(o->sloppy));
+    if (o->sloppy != TMQ_FP64 && o->sloppy_link != TMQ_FP32 && o->sloppy_link != TMQ_FP16) {
+        set_error("sloppy_link must be TMQ_FP32 or TMQ_FP16");
+        return TMQ_EINVAL;
+    }
     return TMQ_OK;
 }
 

@@ -11,6 +11,8 @@
 
 namespace tmq {
 
+struct Engine;
+
 // thread-local error message behind tmq_last_error()
 void set_error(const std::string &msg);
 const char *get_error();
@@ -71,6 +73,9 @@ struct Lattice {
     hipEvent_t ring_ev[8] = {};
     static constexpr int RING = 8;
 
+    // CG engines of the even/odd solves, one per inner precision and link format
+    std::vector<Engine *> engines;
+
     // named work fields, grown on demand
     std::vector<std::pair<std::string, Field>> work;
 
@@ -130,6 +135,8 @@ int apply_Q_full(Lattice *L, const OpParams &op, int sign, const FieldDesc &in, 
 double hop_bytes_per_site(int prec, int link_fmt, bool self, int nrhs = 1);
 
 int check_params(const tmq_params *p);
+int check_prec(int prec);
+int check_opts(const tmq_solver_opts *o);
 std::string tuning_report(const Lattice *L);
 
 }  // namespace tmq

@@ -1,61 +1,85 @@
 // solver.cpp -- CG on Qhat^+ Qhat^- (even/odd) and on Q^+ Q^- (full lattice).
 //
-// Textbook CG (Sec. 4.4) with every vector operation, inner product and
-// scalar (alpha, beta, convergence) on the device: the host only enqueues
-// work and reads one small scalar record per right-hand side and iteration,
-// one iteration behind the device, so the GPU never waits for the host.
-// Kernels skip the blocks of right-hand sides that are done.
-//
-// A batch of right-hand sides (each with its own kappa and mu, common
-// boundary phases) advances in lock step through the same launches; one
-// right-hand side alone is the batch of one and goes through exactly the same
-// arithmetic, so a batched solution equals its solve alone bit for bit.
-//
-// Mixed precision (the paper's reduced-precision CG with a true-residual
-// check, Sec. 4.4): the iteration runs with FP32 arithmetic on FP32/FP16/BF16
-// spinors and reduced-precision two-row links, accumulating its correction
-// in an FP32 vector x_s.  Whenever the iterated residual has fallen by delta
-// relative to the largest residual since the last such step, a reliable
-// update folds x_s into the FP64 solution x, recomputes r = b - A x with the
-// FP64 operator, and continues the recursion from that true residual with the
-// same search direction.  Convergence is only declared on a recomputed FP64
-// true residual: when the iterated residual meets the tolerance, the next
-// step is a reliable update.  The host reads the scalars one iteration late,
-// so an update is triggered by the residual of the iteration before; this is
-// a deterministic rule of its own.
+// Even/odd solves run on a CG engine of the lattice (engine.h): the batch's
+// right-hand sides join the engine's slots together and step until every one
+// has finished.  A single solve is the batch of one, and each right-hand side
+// goes through exactly the same arithmetic whatever shares the batch, so a
+// batched solution equals its solve alone bit for bit.
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
 
-#include "lattice.h"
+#include "engine.h"
 
 namespace tmq {
 
-struct SolveWork {
-    FieldDesc b, x;          // FP64 odd
-    FieldDesc r64, ax64;     // FP64 odd
-    FieldDesc te64, to64;    // FP64 even / odd temporaries of A
-    FieldDesc rs, ps, aps;   // sloppy odd
-    FieldDesc tes, tos;      // sloppy even / odd temporaries
-    FieldDesc xs;            // sloppy solution correction (FP32, or the FP64 x itself)
-    LinkDesc lk64, lks;
-    OpParams op;
-    bool mixed;
-};
-
-static int reliable_update(Lattice *L, SolveWork &w, const RhsList &rl, const tmq_solver_opts &o, hipStream_t st,
-                           CgScalars *publish)
+// the lattice's engine for this inner precision and link format with at
+// least n slots (grown by reallocation when a larger batch comes)
+static int lattice_engine(Lattice *L, const tmq_solver_opts &o, int n, Engine **out)
 {
-    if (rl.n == 0) return TMQ_OK;
-    if (w.mixed) TMQ_HIP(launch_accumulate(w.x, w.xs, rl, st));
-    TMQ_TRY(apply_QhatQhat(L, w.op, w.x, w.ax64, w.te64, w.to64, w.lk64, rl, nullptr, nullptr, st));
-    TMQ_HIP(launch_residual(w.b, w.ax64, w.r64, rl, L->partial[2], L->pstride, st));
-    TMQ_HIP(launch_scalar(SC_RELIABLE, rl, L->partial[2], L->pstride, blas_grid(w.b.n), L->scal, o.tol * o.tol,
-                          o.relative, false, publish, st));
-    if (w.mixed) TMQ_HIP(launch_convert(w.r64, w.rs, rl, st));
+    const int sp = o.sloppy;
+    const int lk = sp == P64 ? link_fmt_for(L, P64, P64) : link_fmt_for(L, sp, o.sloppy_link);
+    for (size_t i = 0; i < L->engines.size(); i++) {
+        Engine *E = L->engines[i];
+        if (E->sloppy != sp || E->lks.fmt != lk) continue;
+        if (E->cap >= n) {
+            *out = E;
+            return TMQ_OK;
+        }
+        delete E;
+        L->engines.erase(L->engines.begin() + (long)i);
+        break;
+    }
+    Engine *E = nullptr;
+    TMQ_TRY(engine_create(L, sp, o.sloppy_link, n, nullptr, &E));
+    L->engines.push_back(E);
+    *out = E;
     return TMQ_OK;
 }
+
+// leaves the engine idle (every slot free, no stream) however the solve ends
+struct EngineScope {
+    Engine *E;
+    ~EngineScope()
+    {
+        if (E->st) hipStreamSynchronize(E->st);
+        E->st = nullptr;
+        for (auto &s : E->slots) s = Engine::Slot{};
+        E->body_pending = false;
+    }
+};
+
+int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o, const double *const *b,
+                double *const *x, hipStream_t st, tmq_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    Engine *E = nullptr;
+    TMQ_TRY(lattice_engine(L, o, n, &E));
+    E->st = st;
+    EngineScope scope{E};
+    for (int r = 0; r < n; r++) TMQ_TRY(engine_join(E, r, p[r], o, (const double2 *)b[r]));
+    while (engine_running(E) > 0) {
+        TMQ_TRY(engine_begin_step(E));
+        TMQ_TRY(engine_end_step(E, nullptr));
+    }
+    int status = TMQ_OK;
+    for (int r = 0; r < n; r++) {
+        tmq_solve_info ir{};
+        TMQ_TRY(engine_take(E, r, (double2 *)x[r], &ir));
+        if (ir.status == TMQ_ENAN || (ir.status == TMQ_ENOCONV && status == TMQ_OK)) status = ir.status;
+        if (info) info[r] = ir;
+    }
+    TMQ_HIP(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        for (int r = 0; r < n; r++) info[r].seconds = secs;
+    if (status == TMQ_ENAN) set_error("tmq_solve: non-finite value in CG");
+    if (status == TMQ_ENOCONV) set_error("tmq_solve: max_iter reached before the tolerance");
+    return status;
+}
+
+// ------------------------------------------------------ full lattice CG
 
 static int read_scalars(Lattice *L, int n, hipStream_t st, std::vector<CgScalars> &out)
 {
@@ -64,158 +88,6 @@ static int read_scalars(Lattice *L, int n, hipStream_t st, std::vector<CgScalars
     TMQ_HIP(hipMemcpy(out.data(), L->scal, sizeof(CgScalars) * n, hipMemcpyDeviceToHost));
     return TMQ_OK;
 }
-
-// one CG iteration for the RHS of rl (done ones skip); scalars published to `publish`
-static int cg_body(Lattice *L, SolveWork &w, const RhsList &rl, hipStream_t st, CgScalars *publish)
-{
-    CgScalars *S = L->scal;
-    // t = Qhat^- p, <p, A p> = |t|^2 ; Ap = Qhat^+ t
-    TMQ_TRY(apply_Qhat(L, w.op, -1, w.ps, w.tos, w.tes, w.lks, rl, L->partial[0], S, st));
-    TMQ_HIP(launch_scalar(SC_ALPHA, rl, L->partial[0], L->pstride, L->hop_blocks_last, S, 0, 0, true, nullptr, st));
-    TMQ_TRY(apply_Qhat(L, w.op, +1, w.tos, w.aps, w.tes, w.lks, rl, nullptr, S, st));
-    // x_s += alpha p ; r -= alpha A p ; |r|^2 ; beta
-    TMQ_HIP(launch_axpy_norm(w.xs, w.ps, w.rs, w.aps, rl, S, L->partial[1], L->pstride, true, st));
-    TMQ_HIP(launch_scalar(SC_BETA, rl, L->partial[1], L->pstride, blas_grid(w.ps.n), S, 0, 0, true, publish, st));
-    return TMQ_OK;
-}
-
-static RhsList make_list(const std::vector<int> &idx)
-{
-    RhsList l;
-    l.n = (int)idx.size();
-    for (int i = 0; i < l.n; i++) l.idx[i] = (unsigned char)idx[i];
-    return l;
-}
-
-int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o, const FieldDesc &b,
-                const FieldDesc &x, hipStream_t st, tmq_solve_info *info)
-{
-    const auto t0 = std::chrono::steady_clock::now();
-    const long vh = L->g.vh;
-    SolveWork w{};
-    w.b = b;
-    w.x = x;
-    w.mixed = o.sloppy != TMQ_FP64;
-    w.op = make_op(L, p, n);
-    w.lk64 = lattice_links(L, link_fmt_for(L, P64, P64));
-    TMQ_TRY(work_field(L, "r64", P64, vh, &w.r64, n));
-    TMQ_TRY(work_field(L, "ax64", P64, vh, &w.ax64, n));
-    TMQ_TRY(work_field(L, "te64", P64, vh, &w.te64, n));
-    TMQ_TRY(work_field(L, "to64", P64, vh, &w.to64, n));
-    if (w.mixed) {
-        const int sp = o.sloppy;
-        w.lks = lattice_links(L, link_fmt_for(L, sp, o.sloppy_link));
-        TMQ_TRY(work_field(L, "rs", sp, vh, &w.rs, n));
-        TMQ_TRY(work_field(L, "ps", sp, vh, &w.ps, n));
-        TMQ_TRY(work_field(L, "aps", sp, vh, &w.aps, n));
-        TMQ_TRY(work_field(L, "tes", sp, vh, &w.tes, n));
-        TMQ_TRY(work_field(L, "tos", sp, vh, &w.tos, n));
-        TMQ_TRY(work_field(L, "xs", P32, vh, &w.xs, n));
-    } else {
-        w.lks = w.lk64;
-        w.rs = w.r64;
-        w.xs = w.x;
-        TMQ_TRY(work_field(L, "ps64", P64, vh, &w.ps, n));
-        TMQ_TRY(work_field(L, "aps64", P64, vh, &w.aps, n));
-        w.tes = w.te64;
-        w.tos = w.to64;
-    }
-    // default trigger: the FP32 recursion stays faithful over 4 decades, FP16 over
-    // about 2, BF16 (8-bit mantissa) over a little more than 1
-    const double delta = o.delta > 0.0 && o.delta < 1.0 ? o.delta
-                         : o.sloppy == TMQ_FP32                ? 1e-4
-                         : o.sloppy == TMQ_BF16                ? 0.05
-                                                               : 0.02;
-    const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
-    CgScalars *S = L->scal;
-    const RhsList all = rhs_all(n);
-
-    // x = 0 ; r = b ; p = r ; bb = |b|^2
-    TMQ_HIP(launch_zero(w.x, all, st));
-    TMQ_HIP(launch_convert(w.b, w.r64, all, st));
-    TMQ_HIP(launch_norm2(w.r64, all, L->partial[1], L->pstride, st));
-    TMQ_HIP(launch_scalar(SC_INIT, all, L->partial[1], L->pstride, blas_grid(vh), S, o.tol * o.tol, o.relative, false,
-                          nullptr, st));
-    if (w.mixed) {
-        TMQ_HIP(launch_convert(w.r64, w.rs, all, st));
-        TMQ_HIP(launch_zero(w.xs, all, st));
-    }
-    TMQ_HIP(launch_convert(w.rs, w.ps, all, st));
-    std::vector<CgScalars> cur;
-    TMQ_TRY(read_scalars(L, n, st, cur));
-
-    std::vector<int> act;  // RHS still iterating
-    std::vector<double> maxr2(n);
-    for (int r = 0; r < n; r++) {
-        maxr2[r] = cur[r].rr;
-        if (!(cur[r].done || cur[r].nan)) act.push_back(r);
-    }
-
-    int enq = 0;  // iteration bodies enqueued
-    while (!act.empty() && enq < max_iter) {
-        const int slot = enq % Lattice::RING;
-        CgScalars *pub = L->ring_dev + (size_t)slot * MAX_RHS;
-        const RhsList al = make_list(act);
-        TMQ_TRY(cg_body(L, w, al, st, pub));
-        // while the GPU runs this iteration, read the previous one's scalars
-        std::vector<int> ru, keep;
-        if (enq > 0) {
-            const int ps = (enq - 1) % Lattice::RING;
-            TMQ_HIP(hipEventSynchronize(L->ring_ev[ps]));
-            const CgScalars *prev = L->ring + (size_t)ps * MAX_RHS;
-            for (int r : act) {
-                const CgScalars pv = prev[r];
-                if (pv.nan || (pv.done && pv.last_true)) continue;  // finished: leaves the active set
-                keep.push_back(r);
-                if (pv.done) {  // iterated residual met the tolerance: check the true one
-                    ru.push_back(r);
-                    continue;
-                }
-                if (pv.last_true || pv.rr > maxr2[r]) maxr2[r] = pv.rr;
-                if (w.mixed && pv.rr < delta * delta * maxr2[r]) ru.push_back(r);
-            }
-        } else {
-            keep = act;
-        }
-        // a reliable update after this iteration republishes its RHS's scalars to the same slot
-        TMQ_TRY(reliable_update(L, w, make_list(ru), o, st, pub));
-        TMQ_HIP(launch_xpay(w.rs, w.ps, al, S, true, st));
-        TMQ_HIP(hipEventRecord(L->ring_ev[slot], st));
-        enq++;
-        act = keep;
-    }
-    TMQ_TRY(read_scalars(L, n, st, cur));
-    // stopped by max_iter before a true residual: fold in x_s and measure it
-    std::vector<int> fin;
-    for (int r = 0; r < n; r++)
-        if (!cur[r].nan && !cur[r].last_true) fin.push_back(r);
-    if (!fin.empty()) {
-        TMQ_TRY(reliable_update(L, w, make_list(fin), o, st, nullptr));
-        TMQ_TRY(read_scalars(L, n, st, cur));
-    }
-    int status = TMQ_OK;
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    for (int r = 0; r < n; r++) {
-        int sr = TMQ_OK;
-        if (cur[r].nan)
-            sr = TMQ_ENAN;
-        else if (!cur[r].done)
-            sr = TMQ_ENOCONV;
-        if (sr == TMQ_ENAN || (sr == TMQ_ENOCONV && status == TMQ_OK)) status = sr;
-        if (info) {
-            info[r].status = sr;
-            info[r].iters = cur[r].iter;
-            info[r].reliable_updates = cur[r].reliable;
-            info[r].true_rel_residual = cur[r].bb > 0 ? std::sqrt(cur[r].rr / cur[r].bb) : std::sqrt(cur[r].rr);
-            info[r].seconds = secs;
-        }
-    }
-    if (status == TMQ_ENAN) set_error("tmq_solve: non-finite value in CG");
-    if (status == TMQ_ENOCONV) set_error("tmq_solve: max_iter reached before the tolerance");
-    return status;
-}
-
-// ------------------------------------------------------ full lattice CG
 
 int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
                hipStream_t st, tmq_solve_info *info)

@@ -30,8 +30,9 @@ MAX_RHS = 64
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 
 TMQ_OK, TMQ_EINVAL, TMQ_ENOMEM, TMQ_ENOCONV, TMQ_EDEVICE, TMQ_ENAN, TMQ_ESTATE = 0, -1, -2, -3, -4, -5, -6
+TMQ_PENDING = 1
 STATUS = {0: "TMQ_OK", -1: "TMQ_EINVAL", -2: "TMQ_ENOMEM", -3: "TMQ_ENOCONV", -4: "TMQ_EDEVICE",
-          -5: "TMQ_ENAN", -6: "TMQ_ESTATE"}
+          -5: "TMQ_ENAN", -6: "TMQ_ESTATE", 1: "TMQ_PENDING"}
 
 
 class tmq_params(ctypes.Structure):
@@ -46,6 +47,20 @@ class tmq_solver_opts(ctypes.Structure):
 class tmq_solve_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int),
                 ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class tmq_server_config(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int)]
+
+
+class tmq_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_long), ("completed", ctypes.c_long), ("failed", ctypes.c_long),
+                ("rejected", ctypes.c_long), ("queued", ctypes.c_long), ("running", ctypes.c_long),
+                ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("mean_wait_s", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("elapsed_s", ctypes.c_double), ("budget_bytes", ctypes.c_size_t),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("engines", ctypes.c_int),
+                ("peak_running", ctypes.c_int), ("steps", ctypes.c_long)]
 
 
 _vp = ctypes.c_void_p
@@ -77,6 +92,15 @@ _SIGS = {
     "tmq_tuning_report": (_ip, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "tmq_encode_dev": (_ip, [_vp, _ip, ctypes.c_long, _vp, _vp, _vp, _vp]),
     "tmq_footprint_bytes": (_ip, [_P(ctypes.c_int), _P(tmq_solver_opts), _ip, _P(ctypes.c_size_t)]),
+    "tmq_server_create": (_ip, [_ip, _P(tmq_server_config), _P(_vp)]),
+    "tmq_server_add_lattice": (_ip, [_vp, _P(ctypes.c_int), _vp, _P(ctypes.c_int)]),
+    "tmq_server_submit": (_ip, [_vp, _ip, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp,
+                                _P(ctypes.c_uint64)]),
+    "tmq_server_poll": (_ip, [_vp, ctypes.c_uint64, _P(tmq_solve_info)]),
+    "tmq_server_wait": (_ip, [_vp, ctypes.c_uint64, ctypes.c_double, _P(tmq_solve_info)]),
+    "tmq_server_get_stats": (_ip, [_vp, _P(tmq_server_stats)]),
+    "tmq_server_reset_stats": (_ip, [_vp]),
+    "tmq_server_destroy": (None, [_vp]),
     "tmq_last_error": (ctypes.c_char_p, []),
     "tmq_version": (ctypes.c_char_p, []),
 }
@@ -357,3 +381,100 @@ class Lattice:
                                    ctypes.c_void_p(codes.data_ptr()), ctypes.c_void_p(scale.data_ptr()),
                                    _stream(stream)), "tmq_encode_dev")
         return codes, scale
+
+
+class Server:
+    """A solve server on one GPU (tmq_server_*): registered lattices stay
+    resident; submitted solves are batched continuously per lattice and inner
+    precision, admitted within a device-memory budget, and finish
+    independently.  Sources and solutions are device tensors (V/2, 4, 3)
+    complex128; the server keeps references to them until the request has
+    been collected with poll() or wait()."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, max_batch: int = 0):
+        cfg = tmq_server_config()
+        cfg.budget_bytes = int(budget_bytes)
+        cfg.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        _check(_lib.tmq_server_create(device, ctypes.byref(cfg), ctypes.byref(h)), "tmq_server_create")
+        self._h = h
+        self.device = device
+        self._vh = {}
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tmq_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def add_lattice(self, dims, U) -> int:
+        """Register a lattice (T, LZ, LY, LX) with its gauge field U (device tensor)."""
+        dims = tuple(int(d) for d in dims)
+        V = int(np.prod(dims))
+        lid = ctypes.c_int(-1)
+        _check(_lib.tmq_server_add_lattice(self._h, (ctypes.c_int * 4)(*dims), _dptr(U, V * 36, "U"),
+                                           ctypes.byref(lid)), "tmq_server_add_lattice")
+        self._vh[lid.value] = V // 2
+        return lid.value
+
+    def submit(self, lattice_id: int, p: tmq_params, b, opts: tmq_solver_opts, x=None, sync=True) -> int:
+        """Queue a solve; sync: first wait for the current stream (the server's
+        streams do not order themselves after the caller's work on b)."""
+        import torch
+
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        if lattice_id not in self._vh:
+            raise ValueError(f"unknown lattice id {lattice_id}")
+        n = self._vh[lattice_id] * 12
+        x = torch.empty_like(b) if x is None else x
+        t = ctypes.c_uint64(0)
+        _check(_lib.tmq_server_submit(self._h, lattice_id, ctypes.byref(p), ctypes.byref(opts), _dptr(b, n, "b"),
+                                      _dptr(x, n, "x"), ctypes.byref(t)), "tmq_server_submit")
+        self._live[t.value] = (b, x)
+        return t.value
+
+    def _finish(self, ticket: int, code: int, info: tmq_solve_info, where: str):
+        # a finished request returns its solve status; EINVAL only for an unknown ticket
+        if code == TMQ_EINVAL:
+            _check(code, where)
+        _b, x = self._live.pop(ticket, (None, None))
+        return x, _info(info)
+
+    def poll(self, ticket: int):
+        """None while pending, else (x, SolveInfo) (the ticket is then retired)."""
+        info = tmq_solve_info()
+        code = _lib.tmq_server_poll(self._h, ticket, ctypes.byref(info))
+        if code == TMQ_PENDING:
+            return None
+        return self._finish(ticket, code, info, "tmq_server_poll")
+
+    def wait(self, ticket: int, timeout: float | None = None):
+        """(x, SolveInfo) once finished; TimeoutError after `timeout` seconds."""
+        info = tmq_solve_info()
+        code = _lib.tmq_server_wait(self._h, ticket, -1.0 if timeout is None else float(timeout),
+                                    ctypes.byref(info))
+        if code == TMQ_PENDING:
+            raise TimeoutError(f"request {ticket} still pending after {timeout} s")
+        return self._finish(ticket, code, info, "tmq_server_wait")
+
+    def stats(self) -> dict:
+        st = tmq_server_stats()
+        _check(_lib.tmq_server_get_stats(self._h, ctypes.byref(st)), "tmq_server_get_stats")
+        return {f: getattr(st, f) for f, _ in tmq_server_stats._fields_}
+
+    def reset_stats(self):
+        _check(_lib.tmq_server_reset_stats(self._h), "tmq_server_reset_stats")

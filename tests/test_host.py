@@ -60,6 +60,33 @@ def test_argument_validation_without_gpu():
     assert 0 < f16 < f64 + 2e9
 
 
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes structs of the binding have the compiler's layout of include/tmq.h."""
+    from paper_0905_3331_amd import tmq
+
+    exe = tmp_path / "abi_layout"
+    src = os.path.join(ROOT, "tests", "cpu_helpers", "abi_layout.c")
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), src])
+    want = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        k, v = line.split()
+        want[k] = int(v)
+    for cls in (tmq.tmq_params, tmq.tmq_solver_opts, tmq.tmq_solve_info, tmq.tmq_server_config,
+                tmq.tmq_server_stats):
+        name = cls.__name__
+        assert ctypes.sizeof(cls) == want[name], name
+        for f, _ in cls._fields_:
+            assert getattr(cls, f).offset == want[f"{name}.{f}"], (name, f)
+
+
+def test_server_needs_a_device():
+    from paper_0905_3331_amd import tmq
+
+    with pytest.raises(tmq.TmqError) as e:
+        tmq.Server(device=-1)
+    assert e.value.code in (tmq.TMQ_EDEVICE, tmq.TMQ_EINVAL)
+
+
 @pytest.fixture(scope="module")
 def spinlib(tmp_path_factory):
     out = tmp_path_factory.mktemp("spin") / "libspin.so"
