@@ -187,9 +187,8 @@ __global__ __launch_bounds__(BLAS_BLOCK) void k_gauge_ingest(Geom g, const doubl
 #pragma unroll
                 for (int k = 0; k < 6; k++)
                     w[k] = pack16(f32_to_h16((float)u.e[k / 3][k % 3].re), f32_to_h16((float)u.e[k / 3][k % 3].im));
-                const long e = par * 4 * st + lidx(h, mu, 0, 1);
-                o.row16a[e] = make_uint4(w[0], w[1], w[2], w[3]);
-                o.row16b[e] = make_uint2(w[4], w[5]);
+                o.row16a[par * 4 * st + lidx(h, mu, 0, 1)] = make_uint4(w[0], w[1], w[2], w[3]);
+                o.row16b[par * 4 * vh16(st) + lidx16(h, mu)] = make_uint2(w[4], w[5]);
             }
             // distance from SU(3): max |(U U^+ - 1)_ab| and |det U - 1|
 #pragma unroll

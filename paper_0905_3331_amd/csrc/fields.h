@@ -22,7 +22,7 @@
 //     L64R : 6 blocks of double2 (rows 0, 1; row 2 = conj(r0 x r1))   96 B/link
 //     L32R : 3 blocks of float4 (rows 0, 1)                            48 B/link
 //     L16R : one block of 8 x fp16 (in array a) and one of 4 x fp16
-//            (array b, 8-byte elements, same indexing)                 24 B/link
+//            (array b, 8-byte elements in 16-site chunks, lidx16)      24 B/link
 //   A field of n sites (n a multiple of 8) stacked from two parities is one
 //   such array of 2 * V/2 sites: the odd sites start at site V/2.
 #pragma once
@@ -41,6 +41,11 @@ __device__ __forceinline__ long lidx(long h, int mu, int b, int nb)
 {
     return ((h >> 3) * 4 * nb + mu * nb + b) * 8 + (h & 7);
 }
+// 8-byte link blocks use 16-site chunks, so that one direction of a chunk is
+// one whole 128-byte line: element ((h >> 4) * 4 + mu) * 16 + (h & 15) of an
+// array of 4 * vh16 elements per parity, vh16 = V/2 rounded up to 16
+__device__ __forceinline__ long lidx16(long h, int mu) { return ((h >> 4) * 4 + mu) * 16 + (h & 15); }
+__host__ __device__ __forceinline__ long vh16(long vh) { return (vh + 15) & ~15L; }
 
 // ------------------------------------------------------- streaming loads
 // Loads of data that is used once per kernel (the links) can bypass the
@@ -109,10 +114,28 @@ __device__ __forceinline__ uint16_t lo16(uint32_t w) { return (uint16_t)(w & 0xF
 __device__ __forceinline__ uint16_t hi16(uint32_t w) { return (uint16_t)(w >> 16); }
 __device__ __forceinline__ uint32_t pack16(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
 
+// Value of the low / high 16-bit code of a word as FP32.  For FP16 the result
+// is a plain widening conversion, which the compiler folds into the operand
+// of a following FMA (v_fma_mix_f32 reads FP16 halves directly); the kernels
+// therefore combine codes with FMAs, an opaque 1.0 standing in for a plain add.
+template <bool BF>
+__device__ __forceinline__ float code_lo(uint32_t w)
+{
+    if (BF) return __uint_as_float(w << 16);
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu));
+}
+template <bool BF>
+__device__ __forceinline__ float code_hi(uint32_t w)
+{
+    if (BF) return __uint_as_float(w & 0xFFFF0000u);
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
 // --------------------------------------------------------------- spinors
 
 struct SpF64 {
     using real = double;
+    static constexpr bool coded = false;
     double2 *p;
     template <typename R>
     __device__ __forceinline__ void load(long h, spinor<R> &s) const
@@ -138,6 +161,7 @@ struct SpF64 {
 
 struct SpF32 {
     using real = float;
+    static constexpr bool coded = false;
     float4 *p;
     template <typename R>
     __device__ __forceinline__ void load(long h, spinor<R> &s) const
@@ -166,8 +190,25 @@ struct SpF32 {
 template <bool BF>
 struct Sp16 {
     using real = float;
+    static constexpr bool coded = true;
+    static constexpr bool bf = BF;
     uint4 *p;
     float *scale;
+    // the 12 words of a site (word k: complex component k = 3 * spin + colour,
+    // real part in the low half) and its scale, undecoded
+    __device__ __forceinline__ void load_codes(long h, uint32_t w[12], float &sc) const
+    {
+        sc = scale[h];
+        const uint4 *q = p + aidx(h, 0, 3);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            uint4 v = q[k * 8];
+            w[4 * k] = v.x;
+            w[4 * k + 1] = v.y;
+            w[4 * k + 2] = v.z;
+            w[4 * k + 3] = v.w;
+        }
+    }
     template <typename R>
     __device__ __forceinline__ void load(long h, spinor<R> &s) const
     {
@@ -237,6 +278,14 @@ struct L64F {
             u.e[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
         }
     }
+    // out = U p or U^+ p for the link of direction mu at site h of parity par
+    template <bool DAG, bool NT, typename R>
+    __device__ __forceinline__ void mul(int par, int mu, long h, const half<R> &p, half<R> &out) const
+    {
+        su3<R> u;
+        load<NT>(par, mu, h, u);
+        link_mul<DAG>(u, p, out);
+    }
 };
 
 struct L64R {
@@ -253,6 +302,14 @@ struct L64R {
             u.e[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
         }
         su3_third_row(u);
+    }
+    // out = U p or U^+ p for the link of direction mu at site h of parity par
+    template <bool DAG, bool NT, typename R>
+    __device__ __forceinline__ void mul(int par, int mu, long h, const half<R> &p, half<R> &out) const
+    {
+        su3<R> u;
+        load<NT>(par, mu, h, u);
+        link_mul<DAG>(u, p, out);
     }
 };
 
@@ -272,6 +329,14 @@ struct L32R {
         }
         su3_third_row(u);
     }
+    // out = U p or U^+ p for the link of direction mu at site h of parity par
+    template <bool DAG, bool NT, typename R>
+    __device__ __forceinline__ void mul(int par, int mu, long h, const half<R> &p, half<R> &out) const
+    {
+        su3<R> u;
+        load<NT>(par, mu, h, u);
+        link_mul<DAG>(u, p, out);
+    }
 };
 
 struct L16R {
@@ -279,12 +344,61 @@ struct L16R {
     const uint4 *a;  // complex 0..3 of rows 0,1 (row-major)
     const uint2 *b;  // complex 4, 5
     long vh;
+    // out = U p or U^+ p in FP32 with the FP16 entries of rows 0 and 1 read
+    // directly by the FMAs; row 2 = conj(row0 x row1) is formed in FP32
+    template <bool DAG, bool NT>
+    __device__ __forceinline__ void mul(int par, int mu, long h, const half<float> &p, half<float> &out) const
+    {
+        const uint4 va = ld<NT>(a + par * 4 * vh + lidx(h, mu, 0, 1));
+        const uint2 vb = ld<NT>(b + par * 4 * vh16(vh) + lidx16(h, mu));
+        const uint32_t w[6] = {va.x, va.y, va.z, va.w, vb.x, vb.y};
+        // entry (i, j) of rows 0, 1 is word 3 i + j
+        auto re = [&](int i, int j) { return code_lo<false>(w[3 * i + j]); };
+        auto im = [&](int i, int j) { return code_hi<false>(w[3 * i + j]); };
+        // row 2, column c: conj(u0a u1b - u0b u1a) with (a, b) the other two columns in cyclic order
+        cx<float> r2[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const int ca = (c + 1) % 3, cb = (c + 2) % 3;
+            r2[c].re = fmad(re(0, ca), re(1, cb),
+                            fmad(-im(0, ca), im(1, cb), fmad(-re(0, cb), re(1, ca), fmad(im(0, cb), im(1, ca), 0.f))));
+            r2[c].im = fmad(-re(0, ca), im(1, cb),
+                            fmad(-im(0, ca), re(1, cb), fmad(re(0, cb), im(1, ca), fmad(im(0, cb), re(1, ca), 0.f))));
+        }
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                float sr = 0.f, si = 0.f;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const cx<float> x = p.c[k][c];
+                    if (!DAG) {  // + U[r][c] x
+                        if (r < 2) {
+                            sr = fmad(re(r, c), x.re, fmad(-im(r, c), x.im, sr));
+                            si = fmad(re(r, c), x.im, fmad(im(r, c), x.re, si));
+                        } else {
+                            sr = fmad(r2[c].re, x.re, fmad(-r2[c].im, x.im, sr));
+                            si = fmad(r2[c].re, x.im, fmad(r2[c].im, x.re, si));
+                        }
+                    } else {  // + conj(U[c][r]) x
+                        if (c < 2) {
+                            sr = fmad(re(c, r), x.re, fmad(im(c, r), x.im, sr));
+                            si = fmad(re(c, r), x.im, fmad(-im(c, r), x.re, si));
+                        } else {
+                            sr = fmad(r2[r].re, x.re, fmad(r2[r].im, x.im, sr));
+                            si = fmad(r2[r].re, x.im, fmad(-r2[r].im, x.re, si));
+                        }
+                    }
+                }
+                out.c[k][r] = cx<float>{sr, si};
+            }
+    }
     template <bool NT, typename R>
     __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
     {
-        const long o = par * 4 * vh + lidx(h, mu, 0, 1);
-        uint4 va = ld<NT>(a + o);
-        uint2 vb = ld<NT>(b + o);
+        uint4 va = ld<NT>(a + par * 4 * vh + lidx(h, mu, 0, 1));
+        uint2 vb = ld<NT>(b + par * 4 * vh16(vh) + lidx16(h, mu));
         uint32_t w[6] = {va.x, va.y, va.z, va.w, vb.x, vb.y};
 #pragma unroll
         for (int k = 0; k < 6; k++)

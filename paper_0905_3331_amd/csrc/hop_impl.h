@@ -47,7 +47,77 @@ struct HopArgs {
     double *partial;
     long pstride;
     const CgScalars *scal;
+    float one;  // 1.0, opaque to the compiler (see code_lo in fields.h)
 };
+
+// x + C y for C = 1, -1, i, -i (selector 0..3), x and y complex 16-bit codes
+template <int C, bool BF>
+__device__ __forceinline__ cx<float> addc(uint32_t x, uint32_t y, float one)
+{
+    const float xr = code_lo<BF>(x), xi = code_hi<BF>(x), yr = code_lo<BF>(y), yi = code_hi<BF>(y);
+    if (C == 0) return {fmad(xr, one, yr), fmad(xi, one, yi)};
+    if (C == 1) return {fmad(xr, one, -yr), fmad(xi, one, -yi)};
+    if (C == 2) return {fmad(xr, one, -yi), fmad(xi, one, yr)};
+    return {fmad(xr, one, yi), fmad(xi, one, -yr)};
+}
+
+// first two rows of (1 + S gamma_MU) s from the codes of s (same table as
+// project() in spin.h), unscaled
+template <int MU, int S, bool BF>
+__device__ __forceinline__ void project_codes(const uint32_t w[12], float one, half<float> &h)
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const uint32_t s0 = w[a], s1 = w[3 + a], s2 = w[6 + a], s3 = w[9 + a];
+        if (MU == 0) {
+            h.c[0][a] = S > 0 ? addc<1, BF>(s0, s2, one) : addc<0, BF>(s0, s2, one);
+            h.c[1][a] = S > 0 ? addc<1, BF>(s1, s3, one) : addc<0, BF>(s1, s3, one);
+        } else if (MU == 1) {
+            h.c[0][a] = S > 0 ? addc<3, BF>(s0, s3, one) : addc<2, BF>(s0, s3, one);
+            h.c[1][a] = S > 0 ? addc<3, BF>(s1, s2, one) : addc<2, BF>(s1, s2, one);
+        } else if (MU == 2) {
+            h.c[0][a] = S > 0 ? addc<1, BF>(s0, s3, one) : addc<0, BF>(s0, s3, one);
+            h.c[1][a] = S > 0 ? addc<0, BF>(s1, s2, one) : addc<1, BF>(s1, s2, one);
+        } else {
+            h.c[0][a] = S > 0 ? addc<3, BF>(s0, s2, one) : addc<2, BF>(s0, s2, one);
+            h.c[1][a] = S > 0 ? addc<2, BF>(s1, s3, one) : addc<3, BF>(s1, s3, one);
+        }
+    }
+}
+
+// acc += sc * T(h) for T = identity, negation, i, -i (selector 0..3)
+template <int T>
+__device__ __forceinline__ void acc_fma(cx<float> &acc, cx<float> h, float sc)
+{
+    if (T == 0) acc = {fmad(sc, h.re, acc.re), fmad(sc, h.im, acc.im)};
+    if (T == 1) acc = {fmad(-sc, h.re, acc.re), fmad(-sc, h.im, acc.im)};
+    if (T == 2) acc = {fmad(-sc, h.im, acc.re), fmad(sc, h.re, acc.im)};
+    if (T == 3) acc = {fmad(sc, h.im, acc.re), fmad(-sc, h.re, acc.im)};
+}
+
+// acc += sc * (1 + S gamma_MU) image rebuilt from h (reconstruct_add of spin.h, scaled)
+template <int MU, int S>
+__device__ __forceinline__ void reconstruct_fma(spinor<float> &acc, const half<float> &h, float sc)
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        acc_fma<0>(acc.c[0][a], h.c[0][a], sc);
+        acc_fma<0>(acc.c[1][a], h.c[1][a], sc);
+        if (MU == 0) {
+            acc_fma<(S > 0 ? 1 : 0)>(acc.c[2][a], h.c[0][a], sc);
+            acc_fma<(S > 0 ? 1 : 0)>(acc.c[3][a], h.c[1][a], sc);
+        } else if (MU == 1) {
+            acc_fma<(S > 0 ? 2 : 3)>(acc.c[2][a], h.c[1][a], sc);
+            acc_fma<(S > 0 ? 2 : 3)>(acc.c[3][a], h.c[0][a], sc);
+        } else if (MU == 2) {
+            acc_fma<(S > 0 ? 0 : 1)>(acc.c[2][a], h.c[1][a], sc);
+            acc_fma<(S > 0 ? 1 : 0)>(acc.c[3][a], h.c[0][a], sc);
+        } else {
+            acc_fma<(S > 0 ? 2 : 3)>(acc.c[2][a], h.c[0][a], sc);
+            acc_fma<(S > 0 ? 3 : 2)>(acc.c[3][a], h.c[1][a], sc);
+        }
+    }
+}
 
 template <int MU, bool NT, class SP, class LK, typename R>
 __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP &in, spinor<R> &acc, long h, long hf,
@@ -55,23 +125,47 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP &in, 
 {
     const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
     const cx<R> ph = {(R)a.op.ph[MU][0], (R)a.op.ph[MU][1]};
-    spinor<R> s;
     half<R> p, w;
-    su3<R> u;
-    // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu); U at the output site
-    in.load(hf, s);
-    project<MU, +1>(s, p);
-    a.lk.template load<NT>(a.out_par, MU, h, u);
-    link_mul<false>(u, p, w);
-    if (phase) half_scale(w, ph);
-    reconstruct_add<MU, +1>(acc, w);
-    // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu); U at the neighbour
-    in.load(hb, s);
-    project<MU, -1>(s, p);
-    a.lk.template load<NT>(a.out_par ^ 1, MU, hb, u);
-    link_mul<true>(u, p, w);
-    if (phase) half_scale(w, conj(ph));
-    reconstruct_add<MU, -1>(acc, w);
+    if constexpr (SP::coded) {
+        // 16-bit spinors: project the codes, multiply by the link, and apply
+        // the site's scale (times the phase) when accumulating
+        uint32_t c[12];
+        float sc;
+        // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu); U at the output site
+        in.load_codes(hf, c, sc);
+        project_codes<MU, +1, SP::bf>(c, a.one, p);
+        a.lk.template mul<false, NT>(a.out_par, MU, h, p, w);
+        if (phase) {
+            half_scale(w, cx<R>{sc * ph.re, sc * ph.im});
+            reconstruct_add<MU, +1>(acc, w);
+        } else {
+            reconstruct_fma<MU, +1>(acc, w, sc);
+        }
+        // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu); U at the neighbour
+        in.load_codes(hb, c, sc);
+        project_codes<MU, -1, SP::bf>(c, a.one, p);
+        a.lk.template mul<true, NT>(a.out_par ^ 1, MU, hb, p, w);
+        if (phase) {
+            half_scale(w, cx<R>{sc * ph.re, -(sc * ph.im)});
+            reconstruct_add<MU, -1>(acc, w);
+        } else {
+            reconstruct_fma<MU, -1>(acc, w, sc);
+        }
+    } else {
+        spinor<R> s;
+        // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu); U at the output site
+        in.load(hf, s);
+        project<MU, +1>(s, p);
+        a.lk.template mul<false, NT>(a.out_par, MU, h, p, w);
+        if (phase) half_scale(w, ph);
+        reconstruct_add<MU, +1>(acc, w);
+        // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu); U at the neighbour
+        in.load(hb, s);
+        project<MU, -1>(s, p);
+        a.lk.template mul<true, NT>(a.out_par ^ 1, MU, hb, p, w);
+        if (phase) half_scale(w, conj(ph));
+        reconstruct_add<MU, -1>(acc, w);
+    }
 }
 
 // Variant bits: W > 0 asks the compiler for at least W waves per SIMD (a
@@ -266,6 +360,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     a.partial = partial;
     a.pstride = pstride;
     a.scal = scal;
+    a.one = 1.0f;
     if (!ALL || !hop_variant_valid(g, variant)) variant = 0;
     a.nblk = hop_grid_variant(g, variant);
     a.group = group > 0 ? (group < rl.n ? group : rl.n) : rhs_group(g, in.prec, rl.n);

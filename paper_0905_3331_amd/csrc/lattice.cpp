@@ -212,7 +212,7 @@ int lattice_load_gauge(Lattice *L, const double2 *U, hipStream_t st)
     TMQ_TRY(alloc((void **)&L->u64r, (size_t)8 * 6 * vh * sizeof(double2)));
     TMQ_TRY(alloc((void **)&L->u32r, (size_t)8 * 3 * vh * sizeof(float4)));
     TMQ_TRY(alloc((void **)&L->u16a, (size_t)8 * vh * sizeof(uint4)));
-    TMQ_TRY(alloc((void **)&L->u16b, (size_t)8 * vh * sizeof(uint2)));
+    TMQ_TRY(alloc((void **)&L->u16b, (size_t)8 * ((vh + 15) & ~15L) * sizeof(uint2)));  // 16-site chunks
     GaugeOut o{L->u64f, L->u64r, L->u32r, L->u16a, L->u16b};
     TMQ_HIP(launch_gauge_ingest(L->g, U, o, L->partial[0], st));
     TMQ_HIP(launch_max(L->partial[0], blas_grid(2 * vh), L->partial[1], st));
