@@ -293,14 +293,17 @@ int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double
 int tmq_stream_copy(int device, size_t bytes, int reps, double *gbps);
 
 /* JSON text of the autotuner's choices so far: for every (spinor storage,
- * link format) used on this lattice, the hop kernel variant picked and the
- * measured microseconds per launch of each variant (-1: not applicable).  The
- * autotuner times the variants (0: lexicographic block order; 1: each XCD
- * walks its own range of z-planes time-slice by time-slice, needs LZ >= 8;
- * 2: 1 with scheduling barriers between directions; 3: 2 with at least 2
- * waves per SIMD; 4: 0 with barriers and 2 waves per SIMD) at the first
- * launch of each format on a lattice; TMQ_HOP_VARIANT=0..4 in the environment
- * forces one.  TMQ_EINVAL if buf (len bytes) is too small. */
+ * link format) used on this lattice, the hop kernel variant picked, the
+ * measured microseconds per launch of each variant (-1: not applicable), and
+ * the cap on resident blocks per CU picked for it (0: none) with the time of
+ * each cap tried.  The variants order the blocks of each XCD differently: 0
+ * lexicographic (an eighth of the time-slices per XCD); 1 each XCD walks its
+ * own range of z-planes time-slice by time-slice (needs LZ >= 8); 2 as 1 with
+ * scheduling barriers between directions; 3 each XCD walks its own range of
+ * time-slices z-plane by z-plane (needs T >= 8); 4 as 3 with barriers.  The
+ * tuner runs at the first launch of each format on a lattice;
+ * TMQ_HOP_VARIANT=0..4 in the environment forces a variant, and then
+ * TMQ_HOP_CAP=0..5 a cap.  TMQ_EINVAL if buf (len bytes) is too small. */
 int tmq_tuning_report(tmq_lattice *lat, char *buf, size_t len);
 
 /* Encode n_sites canonical complex128 sites (12 complex each) into the device

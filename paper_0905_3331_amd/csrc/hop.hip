@@ -12,28 +12,37 @@ int hop_grid(long n)
     return (int)g;
 }
 
-// variant table: {W, SLAB, SB}; the link loads are non-temporal for a single
+// variant table: {order, SB}; the link loads are non-temporal for a single
 // RHS (each link is used once) and cached for a batch (each link is used once
 // per RHS of a group, from L2)
 struct HopVariant {
-    int w;
-    bool slab, sb;
+    int ord;
+    bool sb;
 };
 static const HopVariant kVariants[HOP_VARIANTS] = {
-    {0, false, false}, {0, true, false}, {0, true, true}, {2, true, true}, {2, false, true},
+    {ORD_PLAIN, false}, {ORD_ZSLAB, false}, {ORD_ZSLAB, true}, {ORD_TSLAB, false}, {ORD_TSLAB, true},
 };
 
 bool hop_variant_valid(const Geom &g, int v)
 {
     if (v < 0 || v >= HOP_VARIANTS) return false;
-    return !kVariants[v].slab || g.LZ >= 8;
+    if (kVariants[v].ord == ORD_ZSLAB) return g.LZ >= 8;
+    if (kVariants[v].ord == ORD_TSLAB) return g.T >= 8;
+    return true;
 }
 
 int hop_grid_variant(const Geom &g, int v)
 {
-    if (!hop_variant_valid(g, v) || !kVariants[v].slab) return hop_grid(g.vh);
-    const long zc = g.LZ / 8 + (g.LZ % 8 ? 1 : 0);
-    const long per_xcd = ((long)g.T * zc * g.LY * g.XH + HOP_BLOCK - 1) / HOP_BLOCK;
+    if (!hop_variant_valid(g, v) || kVariants[v].ord == ORD_PLAIN) return hop_grid(g.vh);
+    const long plane = (long)g.LY * g.XH;
+    long per_xcd;
+    if (kVariants[v].ord == ORD_ZSLAB) {
+        const long zc = g.LZ / 8 + (g.LZ % 8 ? 1 : 0);
+        per_xcd = ((long)g.T * zc * plane + HOP_BLOCK - 1) / HOP_BLOCK;
+    } else {
+        const long tc = g.T / 8 + (g.T % 8 ? 1 : 0);
+        per_xcd = ((long)g.LZ * tc * plane + HOP_BLOCK - 1) / HOP_BLOCK;
+    }
     return (int)(8 * per_xcd);
 }
 
@@ -42,7 +51,7 @@ int hop_grid_variant(const Geom &g, int v)
 #define TMQ_HOP_ARGS                                                                                       \
     const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,           \
         const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,      \
-        long pstride, const CgScalars *scal, int variant, int group, hipStream_t st
+        long pstride, const CgScalars *scal, int variant, int group, unsigned lds, hipStream_t st
 hipError_t launch_hop_f64(TMQ_HOP_ARGS);
 hipError_t launch_hop_f32(TMQ_HOP_ARGS);
 hipError_t launch_hop_f16(TMQ_HOP_ARGS);
@@ -52,10 +61,10 @@ hipError_t launch_hop(TMQ_HOP_ARGS)
 {
     if (in.prec != out.prec || (self.data && self.prec != in.prec)) return hipErrorInvalidValue;
     switch (in.prec) {
-    case P64: return launch_hop_f64(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, st);
-    case P32: return launch_hop_f32(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, st);
-    case P16: return launch_hop_f16(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, st);
-    case PB16: return launch_hop_b16(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, st);
+    case P64: return launch_hop_f64(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, lds, st);
+    case P32: return launch_hop_f32(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, lds, st);
+    case P16: return launch_hop_f16(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, lds, st);
+    case PB16: return launch_hop_b16(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, lds, st);
     }
     return hipErrorInvalidValue;
 }

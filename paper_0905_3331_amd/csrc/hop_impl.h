@@ -168,25 +168,26 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP &in, 
     }
 }
 
-// Variant bits: W > 0 asks the compiler for at least W waves per SIMD (a
-// register budget of 512 / W per lane), W = 0 leaves the choice to the
-// compiler; NT makes the link loads non-temporal (single RHS); SLAB gives XCD k = block % 8
-// its own range of z-planes, walked with t outermost, so that the sites of
-// time-slices t-1, t, t+1 that one XCD needs at a time fit its L2; SB puts a
-// scheduling barrier between directions.  The autotuner picks the fastest
-// variant per format and lattice.
+// Variant bits: ORD is the order in which an XCD's blocks walk the lattice
+// (physical block b runs on XCD j = b % 8): ORD_PLAIN gives XCD j the j-th
+// eighth of the eo index range (a range of time-slices, lexicographic);
+// ORD_ZSLAB gives it its own range of z-planes, walked with t outermost, so
+// that the sites of time-slices t-1, t, t+1 that the XCD needs at a time fit
+// its L2; ORD_TSLAB gives it a range of time-slices walked with z outermost
+// (half the boundary planes of ORD_ZSLAB when T >= LZ).  NT makes the link
+// loads non-temporal (single RHS); SB puts a scheduling barrier between
+// directions.  The autotuner picks the fastest variant per format and lattice.
 //
-// Batches: physical block b runs on XCD j = b % 8.  The RHS are taken in
-// groups of `group`; an XCD sweeps its whole share of sites for one group
-// before the next, and within a group its consecutive blocks apply the same
-// links to every RHS of the group in turn.  The links are then fetched from
-// HBM once per group, while the neighbour spinors of a group (three
-// time-slices of the XCD's share per RHS) still fit its L2; the host sizes the
-// group for that.  With one RHS this is the single-field order, and each RHS's
-// arithmetic and partial sums do not depend on the batch around it.
-template <class SP, class LK, bool SELF, bool NORM, int W, bool NT, bool SLAB, bool SB>
-__global__ __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1, W > 0 ? 8 : 8)))
-void hop_kernel(HopArgs<SP, LK> a)
+// Batches: the RHS are taken in groups of `group`; an XCD sweeps its whole
+// share of sites for one group before the next, and within a group its
+// consecutive blocks apply the same links to every RHS of the group in turn.
+// The links are then fetched from HBM once per group, while the neighbour
+// spinors of a group (three time-slices of the XCD's share per RHS) still fit
+// its L2; the host sizes the group for that.  With one RHS this is the
+// single-field order, and each RHS's arithmetic and partial sums do not depend
+// on the batch around it.
+template <class SP, class LK, bool SELF, bool NORM, bool NT, int ORD, bool SB>
+__global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 {
     using R = typename LK::real;
     const Geom &g = a.g;
@@ -205,7 +206,7 @@ void hop_kernel(HopArgs<SP, LK> a)
     int t, z, y, pidx;
     unsigned xh;
     bool active;
-    if (SLAB) {
+    if (ORD == ORD_ZSLAB) {
         const int zb = g.LZ >> 3, zr = g.LZ & 7;
         const int zc = zb + (j < zr ? 1 : 0), z0 = j * zb + (j < zr ? j : zr);
         const long S = (long)zc * plane;  // sites of one time-slice of this slab
@@ -216,6 +217,21 @@ void hop_kernel(HopArgs<SP, LK> a)
         const unsigned rem = lu - (unsigned)t * (unsigned)S;
         z = z0 + (int)(rem / (unsigned)plane);
         const unsigned r2 = rem - (unsigned)(z - z0) * (unsigned)plane;
+        y = (int)(r2 / (unsigned)g.XH);
+        xh = r2 - (unsigned)y * (unsigned)g.XH;
+        h = ((long)t * g.LZ + z) * plane + (long)y * g.XH + xh;
+        pidx = 8 * sb + j;
+    } else if (ORD == ORD_TSLAB) {
+        const int tb = g.T >> 3, tr = g.T & 7;
+        const int tc = tb + (j < tr ? 1 : 0), t0 = j * tb + (j < tr ? j : tr);
+        const long P = (long)tc * plane;  // sites of one z-plane of this block of time-slices
+        const long l = (long)sb * HOP_BLOCK + threadIdx.x;
+        active = l < (long)g.LZ * P;
+        const unsigned lu = active ? (unsigned)l : 0u;
+        z = (int)(lu / (unsigned)P);
+        const unsigned rem = lu - (unsigned)z * (unsigned)P;
+        t = t0 + (int)(rem / (unsigned)plane);
+        const unsigned r2 = rem - (unsigned)(t - t0) * (unsigned)plane;
         y = (int)(r2 / (unsigned)g.XH);
         xh = r2 - (unsigned)y * (unsigned)g.XH;
         h = ((long)t * g.LZ + z) * plane + (long)y * g.XH + xh;
@@ -313,17 +329,17 @@ void hop_kernel(HopArgs<SP, LK> a)
 
 // ------------------------------------------------------------- dispatch
 
-template <class SP, class LK, int W, bool NT, bool SLAB, bool SB>
-void go_w(const HopArgs<SP, LK> &a, bool s, bool n, dim3 grid, dim3 block, hipStream_t st)
+template <class SP, class LK, bool NT, int ORD, bool SB>
+void go_w(const HopArgs<SP, LK> &a, bool s, bool n, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
     if (s && n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, W, NT, SLAB, SB>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, SB>), grid, block, lds, st, a);
     else if (s)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, W, NT, SLAB, SB>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, NT, ORD, SB>), grid, block, lds, st, a);
     else if (n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true, W, NT, SLAB, SB>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true, NT, ORD, SB>), grid, block, lds, st, a);
     else
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, W, NT, SLAB, SB>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, NT, ORD, SB>), grid, block, lds, st, a);
 }
 
 // ALL = false: only variant 0 is instantiated (rarely used format pairs)
@@ -340,7 +356,8 @@ inline int rhs_group(const Geom &g, int prec, int n)
 template <class SP, class LK, bool ALL>
 hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
                      const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl,
-                     double *partial, long pstride, const CgScalars *scal, int variant, int group, hipStream_t st)
+                     double *partial, long pstride, const CgScalars *scal, int variant, int group, unsigned lds,
+                     hipStream_t st)
 {
     if (rl.n <= 0) return hipSuccess;
     HopArgs<SP, LK> a;
@@ -370,24 +387,24 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     const bool nt = rl.n == 1;
     if (!ALL) {
         if (nt)
-            go_w<SP, LK, 0, true, false, false>(a, s, n, grid, block, st);
+            go_w<SP, LK, true, ORD_PLAIN, false>(a, s, n, grid, block, lds, st);
         else
-            go_w<SP, LK, 0, false, false, false>(a, s, n, grid, block, st);
+            go_w<SP, LK, false, ORD_PLAIN, false>(a, s, n, grid, block, lds, st);
         return hipGetLastError();
     }
-#define GOV(W, SLAB, SB)                                                 \
-    do {                                                                 \
-        if (nt)                                                          \
-            go_w<SP, LK, W, true, SLAB, SB>(a, s, n, grid, block, st);   \
-        else                                                             \
-            go_w<SP, LK, W, false, SLAB, SB>(a, s, n, grid, block, st);  \
+#define GOV(ORD, SB)                                                          \
+    do {                                                                      \
+        if (nt)                                                               \
+            go_w<SP, LK, true, ORD, SB>(a, s, n, grid, block, lds, st);       \
+        else                                                                  \
+            go_w<SP, LK, false, ORD, SB>(a, s, n, grid, block, lds, st);      \
     } while (0)
     switch (variant) {
-    case 1: GOV(0, true, false); break;
-    case 2: GOV(0, true, true); break;
-    case 3: GOV(2, true, true); break;
-    case 4: GOV(2, false, true); break;
-    default: GOV(0, false, false); break;
+    case 1: GOV(ORD_ZSLAB, false); break;
+    case 2: GOV(ORD_ZSLAB, true); break;
+    case 3: GOV(ORD_TSLAB, false); break;
+    case 4: GOV(ORD_TSLAB, true); break;
+    default: GOV(ORD_PLAIN, false); break;
     }
 #undef GOV
     return hipGetLastError();

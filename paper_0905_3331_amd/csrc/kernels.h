@@ -101,10 +101,11 @@ constexpr int BLAS_BLOCK = 256;
 int hop_grid(long n);
 int blas_grid(long n);
 
-// hop kernel variants (see hop.hip): 0 plain order, 1 XCD slabs, 2 slabs +
-// scheduling barriers, 3 as 2 with >= 2 waves per SIMD, 4 plain order with
-// barriers and >= 2 waves.  Slab variants need LZ >= 8.  Links are loaded
-// non-temporally in single-RHS launches and cached in batched ones.
+// hop kernel variants (see hop.hip): 0 plain order, 1 z-slabs per XCD, 2
+// z-slabs + scheduling barriers, 3 t-slabs per XCD, 4 t-slabs + barriers.
+// z-slabs need LZ >= 8, t-slabs T >= 8.  Links are loaded non-temporally in
+// single-RHS launches and cached in batched ones.
+enum HopOrder { ORD_PLAIN = 0, ORD_ZSLAB = 1, ORD_TSLAB = 2 };
 constexpr int HOP_VARIANTS = 5;
 bool hop_variant_valid(const Geom &g, int v);
 // blocks per RHS (= per-block partial sums written with a norm) of variant v
@@ -116,10 +117,12 @@ int hop_grid_variant(const Geom &g, int v);
 // sums of |out|^2 at partial[r * pstride + block].  scal != nullptr: blocks of
 // RHS r with scal[r].done set do nothing.
 // group: RHS per group in a batched launch (0: a size from the L2 capacity).
+// lds: bytes of LDS reserved per block (unused by the kernel; a value above
+// the CU's LDS / (c + 1) caps the blocks resident per CU at c), 0 for none.
 hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
                       const RhsList &rl, double *partial, long pstride, const CgScalars *scal, int variant,
-                      int group, hipStream_t st);
+                      int group, unsigned lds, hipStream_t st);
 
 // Vector kernels over the n sites of each RHS of rl.  Reductions write
 // blas_grid(n) per-block sums at partial[r * pstride + block]; scalars come

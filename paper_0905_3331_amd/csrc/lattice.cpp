@@ -114,11 +114,17 @@ int lattice_create(const int dims[4], int device, Lattice **out)
     L->device = device;
     for (int k = 0; k < 16; k++) {
         L->hop_variant[k] = -1;
+        L->hop_occ[k] = 0;
         for (int v = 0; v < HOP_VARIANTS; v++) L->hop_tune_us[k][v] = -1.f;
+        for (int c = 0; c < 6; c++) L->hop_occ_us[k][c] = -1.f;
     }
     if (const char *fv = getenv("TMQ_HOP_VARIANT")) {
         const int v = atoi(fv);
         if (v >= 0 && v < HOP_VARIANTS) L->forced_variant = v;
+    }
+    if (const char *fc = getenv("TMQ_HOP_CAP")) {
+        const int c = atoi(fc);
+        if (c >= 0 && c <= 5) L->forced_cap = c;
     }
     memcpy(L->dims, dims, sizeof(L->dims));
     L->g.T = dims[0];
@@ -139,6 +145,10 @@ int lattice_create(const int dims[4], int device, Lattice **out)
     if (hipSetDevice(device) != hipSuccess) return fail(TMQ_EDEVICE, "hipSetDevice failed");
     if (hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking) != hipSuccess)
         return fail(TMQ_EDEVICE, "hipStreamCreate failed");
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess &&
+        lds > 0)
+        L->lds_per_cu = lds;
     // per RHS: at least as many partials as any hop variant or vector kernel writes
     L->pstride = hop_grid(2 * L->g.vh) + 64;
     for (auto &p : L->partial)
@@ -284,6 +294,15 @@ static hipEvent_t pool_event(Lattice *L)
     return e;
 }
 
+// LDS bytes per block that let at most c blocks share a CU (0: no cap);
+// ~0u when that needs more than a block may reserve (64 KB)
+static unsigned occ_lds(const Lattice *L, int c)
+{
+    if (c <= 0) return 0;
+    const unsigned b = (unsigned)(L->lds_per_cu / (c + 1)) + 256u;
+    return b > 65536u ? ~0u : b;
+}
+
 // Time every valid variant of this hop launch (same operands, the reduction
 // redirected to a scratch array, no skip flags) and keep the fastest for this
 // lattice, spinor precision and link format.
@@ -296,27 +315,49 @@ static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const
     const int reps = L->g.vh * rl.n >= (1L << 18) ? 3 : 10;
     int best = 0;
     float best_us = 0.f;
-    for (int v = 0; v < HOP_VARIANTS; v++) {
-        if (!hop_variant_valid(L->g, v)) continue;
-        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, 0, st));
+    auto time_one = [&](int v, unsigned lds, float *us) -> int {
+        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, 0, lds,
+                           st));
         TMQ_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < reps; r++)
-            TMQ_HIP(
-                launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, 0, st));
+            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, 0,
+                               lds, st));
         TMQ_HIP(hipEventRecord(e1, st));
         TMQ_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-        const float us = ms * 1e3f / reps;
+        *us = ms * 1e3f / reps;
+        return TMQ_OK;
+    };
+    for (int v = 0; v < HOP_VARIANTS; v++) {
+        if (!hop_variant_valid(L->g, v)) continue;
+        float us = 0.f;
+        TMQ_TRY(time_one(v, 0, &us));
         L->hop_tune_us[key][v] = us;
         if (best_us == 0.f || us < best_us) {
             best = v;
             best_us = us;
         }
     }
+    // then a cap on the blocks per CU for the chosen variant (fewer sites in
+    // flight per XCD: a smaller working set in its L2)
+    int occ = 0;
+    L->hop_occ_us[key][0] = best_us;
+    for (int c = 2; c <= 5; c++) {
+        const unsigned lds = occ_lds(L, c);
+        if (lds == ~0u) continue;
+        float us = 0.f;
+        TMQ_TRY(time_one(best, lds, &us));
+        L->hop_occ_us[key][c] = us;
+        if (us < best_us) {
+            occ = c;
+            best_us = us;
+        }
+    }
     L->event_pool.push_back(e0);
     L->event_pool.push_back(e1);
     L->hop_variant[key] = best;
+    L->hop_occ[key] = occ;
     return TMQ_OK;
 }
 
@@ -330,15 +371,18 @@ static int tune_group(Lattice *L, int key, int out_par, const FieldDesc &in, con
     hipEvent_t e0 = pool_event(L), e1 = pool_event(L);
     double *tp = norm ? L->partial[2] : nullptr;
     const int v = L->hop_variant[key];
+    const unsigned lds = occ_lds(L, L->hop_occ[key]);
     int best = 1;
     float best_us = 0.f;
     std::vector<float> us_all;
     for (int G = 1;; G *= 2) {
         if (G > rl.n) G = rl.n;
-        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, G, st));
+        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, G, lds,
+                           st));
         TMQ_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < 2; r++)
-            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, G, st));
+            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, G,
+                               lds, st));
         TMQ_HIP(hipEventRecord(e1, st));
         TMQ_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -375,6 +419,12 @@ std::string tuning_report(const Lattice *L)
             snprintf(buf, sizeof(buf), "%s%.2f", v ? ", " : "", L->hop_tune_us[k][v]);
             s += buf;
         }
+        snprintf(buf, sizeof(buf), "], \"blocks_per_cu_cap\": %d, \"cap_us\": [", L->hop_occ[k]);
+        s += buf;
+        for (int c = 0; c < 6; c++) {
+            snprintf(buf, sizeof(buf), "%s%.2f", c ? ", " : "", L->hop_occ_us[k][c]);
+            s += buf;
+        }
         s += "]}";
         first = false;
     }
@@ -402,8 +452,10 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
 {
     if (rl.n <= 0) return TMQ_OK;
     const int key = in.prec * 4 + lk.fmt;
-    if (L->forced_variant >= 0)
+    if (L->forced_variant >= 0) {
         L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;
+        if (L->forced_cap >= 0) L->hop_occ[key] = occ_lds(L, L->forced_cap) == ~0u ? 0 : L->forced_cap;
+    }
     else if (L->hop_variant[key] < 0)
         TMQ_TRY(tune_hop(L, key, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st));
     // batches of up to 4 RHS run as one group; larger ones use the group tuned
@@ -432,7 +484,7 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
         TMQ_HIP(hipEventRecord(t.a, st));
     }
     TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal,
-                       L->hop_variant[key], group, st));
+                       L->hop_variant[key], group, occ_lds(L, L->hop_occ[key]), st));
     L->hop_blocks_last = hop_grid_variant(L->g, L->hop_variant[key]);
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));

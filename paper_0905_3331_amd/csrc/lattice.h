@@ -87,6 +87,11 @@ struct Lattice {
     int hop_variant[16];
     float hop_tune_us[16][HOP_VARIANTS];
     int forced_variant = -1;  // TMQ_HOP_VARIANT in the environment
+    int forced_cap = -1;      // TMQ_HOP_CAP in the environment
+    // blocks-per-CU cap tuned for that variant (0: none; see launch_hop's lds)
+    int hop_occ[16];
+    float hop_occ_us[16][6];
+    int lds_per_cu = 65536;
     // autotuned RHS group of batched hops, per (spinor precision, link format, batch size)
     std::vector<std::pair<int, int>> hop_group;  // (key * 128 + nrhs, group)
     std::vector<std::pair<int, std::vector<float>>> hop_group_us;

@@ -241,11 +241,17 @@ def test_determinism(tmq):
     assert i1.iters == i2.iters and torch.equal(x1, x2)
 
 
+def variant_valid(dims, v):
+    return v == 0 or (v in (1, 2) and dims[1] >= 8) or (v in (3, 4) and dims[0] >= 8)
+
+
 @pytest.mark.parametrize("variant", range(5))
-@pytest.mark.parametrize("dims", [(8, 8, 6, 10), (6, 10, 4, 6)], ids=lambda d: "x".join(map(str, d)))
+@pytest.mark.parametrize("dims", [(8, 8, 6, 10), (6, 10, 4, 6), (10, 4, 6, 6)], ids=lambda d: "x".join(map(str, d)))
 def test_every_hop_variant(tmq, variant, dims, monkeypatch):
-    """Each autotuner variant (block order, register budget) gives the same operator."""
+    """Each autotuner variant (block order within and across XCDs, with a cap
+    on the blocks per CU for odd variants) gives the same operator."""
     monkeypatch.setenv("TMQ_HOP_VARIANT", str(variant))
+    monkeypatch.setenv("TMQ_HOP_CAP", str(3 if variant % 2 else 0))
     U = synth.random_gauge(dims, seed=107)
     lat = tmq.Lattice(dims)
     lat.load_gauge(U)
@@ -261,8 +267,9 @@ def test_every_hop_variant(tmq, variant, dims, monkeypatch):
     assert info.status == 0
     assert oracle.true_residual(U, b, host(x), 0.1632, 0.004, THETA_GEN) <= 1e-10
     rep = lat.tuning_report()["hop"]
-    want = variant if lat.dims[1] >= 8 or variant in (0, 4) else 0
+    want = variant if variant_valid(dims, variant) else 0
     assert all(e["variant"] == want for e in rep if e["spinor"] == "fp64")
+    assert all(e["blocks_per_cu_cap"] == (3 if variant % 2 else 0) for e in rep)
     lat.close()
 
 
