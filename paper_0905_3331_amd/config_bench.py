@@ -1,0 +1,177 @@
+"""Timings of the other benchmark workloads (one MI355X).
+
+  4^4 full     plain FP64 CG on the full-lattice Q^+Q^- (no even/odd), 4^4,
+               kappa 0.16, 2 kappa mu 0.01, Gaussian source, tol 1e-10
+  24^3x48      even/odd Qhat^+Qhat^-: FP64 CG vs FP32-inner / FP64-outer CG,
+               kappa 0.1632, 2 kappa mu 0.004, 5 Gaussian sources, tol 1e-10;
+               hop half-sweep bandwidth per storage precision
+  24^3x48 x48  48 right-hand sides in one batch: 12 spin-colour point sources
+               at one odd site x 2 kappa mu in {0.002, 0.004, 0.008, 0.016},
+               FP32 inner / FP64 outer, tol 1e-10 each; against the same 48
+               solved one after another
+
+Links are random SU(3) exp(i 0.3 H), reunitarised (seeds 1000 + workload);
+theta = (1, 0, 0, 0).  Prints one JSON object.  The solutions' accuracy
+against the FP64 oracle is checked by the GPU tests at these shapes.
+
+    python -m paper_0905_3331_amd.config_bench
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+THETA = (1.0, 0.0, 0.0, 0.0)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def median_time(fn, reps):
+    import torch
+
+    ts = []
+    out = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), out
+
+
+def full_4444(tmq, torch, synth, reps):
+    dims = (4, 4, 4, 4)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(synth.random_gauge(dims, eps=0.3, seed=1000))
+    b = torch.from_numpy(synth.gaussian_spinor(dims + (4, 3), seed=2000).reshape(-1, 4, 3)).cuda()
+    p = tmq.params(0.16, 0.01, THETA)
+    opts = tmq.solver_opts(tol=1e-10)
+    lat.solve_full(p, b, opts)
+    t, (x, info) = median_time(lambda: lat.solve_full(p, b, opts), reps)
+    lat.close()
+    return {"lattice": "4^4", "operator": "full Q^+Q^-, FP64 CG", "ms_to_1e-10": t * 1e3, "iters": info.iters,
+            "true_rel_residual": info.true_rel_residual}
+
+
+def hop_rates(tmq, torch, synth, lat, dims, reps=20):
+    b = torch.from_numpy(synth.gaussian_odd(dims, seed=3)).cuda()
+    out = torch.empty_like(b)
+    p = tmq.params(0.1632, 0.004, THETA)
+    res = {}
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
+        lat.apply_Qhat(p, +1, b, out, prec=prec)
+        torch.cuda.synchronize()
+        lat.set_kernel_timing(True)
+        for _ in range(reps):
+            lat.apply_Qhat(p, +1, b, out, prec=prec)
+        st = lat.kernel_stats("hop")
+        lat.set_kernel_timing(False)
+        res[prec] = {"avg_us": st["ms"] / st["launches"] * 1e3,
+                     "GBps": st["bytes"] / (st["ms"] * 1e-3) / 1e9,
+                     "GFLOPs": st["flops"] / (st["ms"] * 1e-3) / 1e9}
+    return res
+
+
+def eo_24c48(tmq, torch, synth, reps):
+    dims = (48, 24, 24, 24)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(synth.random_gauge(dims, eps=0.3, seed=1001))
+    p = tmq.params(0.1632, 0.004, THETA)
+    out = {"lattice": "24^3x48", "hop": hop_rates(tmq, torch, synth, lat, dims)}
+    for name, opts in (("fp64", tmq.solver_opts(tol=1e-10)),
+                       ("fp32_inner", tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")),
+                       ("fp16_inner", tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16"))):
+        times, iters, rus, res = [], [], [], []
+        for k in range(5):
+            b = torch.from_numpy(synth.gaussian_odd(dims, seed=2100 + k)).cuda()
+            lat.solve(p, b, opts)
+            t, (x, info) = median_time(lambda: lat.solve(p, b, opts), reps)
+            times.append(t)
+            iters.append(info.iters)
+            rus.append(info.reliable_updates)
+            res.append(info.true_rel_residual)
+        out[name] = {"ms_to_1e-10_median_of_5_sources": float(np.median(times)) * 1e3,
+                     "iters": iters, "reliable_updates": rus, "max_true_rel_residual": max(res)}
+    out["speedup_fp32_inner_vs_fp64"] = out["fp64"]["ms_to_1e-10_median_of_5_sources"] / \
+        out["fp32_inner"]["ms_to_1e-10_median_of_5_sources"]
+    lat.close()
+    return out
+
+
+def batch_24c48(tmq, torch, synth, reps):
+    dims = (48, 24, 24, 24)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(synth.random_gauge(dims, eps=0.3, seed=1003))
+    vh = int(np.prod(dims)) // 2
+    site = int(np.random.default_rng(2300).integers(0, vh))
+    muts = (0.002, 0.004, 0.008, 0.016)
+    ps, bs = [], []
+    for mut in muts:
+        for k in range(12):
+            bs.append(torch.from_numpy(synth.point_source_odd(dims, site, k // 3, k % 3)).cuda())
+            ps.append(tmq.params(0.1632, mut, THETA))
+    opts = tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")
+    xs = [torch.empty_like(b) for b in bs]
+    lat.solve_batch(ps, bs, opts, xs=xs)  # tunes the batched launches
+    t_batch, (_, infos) = median_time(lambda: lat.solve_batch(ps, bs, opts, xs=xs), reps)
+    lat.set_kernel_timing(True)
+    lat.solve_batch(ps, bs, opts, xs=xs)
+    st = lat.kernel_stats("hop")
+    lat.set_kernel_timing(False)
+
+    def alone():
+        inf = []
+        for i in range(len(bs)):
+            _, f = lat.solve(ps[i], bs[i], opts, x=xs[i])
+            inf.append(f)
+        return inf
+
+    t_alone, infos_alone = median_time(alone, 1)
+    report = lat.tuning_report()
+    lat.close()
+    return {"lattice": "24^3x48", "nrhs": len(bs), "point_site": site,
+            "batch_ms": t_batch * 1e3, "per_rhs_ms": t_batch * 1e3 / len(bs),
+            "one_after_another_ms": t_alone * 1e3, "speedup_batch_vs_alone": t_alone / t_batch,
+            "iters": [f.iters for f in infos], "all_converged": all(f.status == 0 for f in infos),
+            "max_true_rel_residual": max(f.true_rel_residual for f in infos),
+            "batch_hop_GBps_links_once": st["bytes"] / (st["ms"] * 1e-3) / 1e9,
+            "batch_hop_launch_us": st["ms"] / st["launches"] * 1e3,
+            "batch_tuning": report.get("batch")}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--only", default="full,eo,batch")
+    args = ap.parse_args(argv)
+    import torch
+
+    import synth
+    from paper_0905_3331_amd import tmq
+
+    if not torch.cuda.is_available():
+        raise SystemExit("config_bench needs a GPU")
+    want = args.only.split(",")
+    res = {}
+    if "full" in want:
+        log("4^4 full-lattice FP64 CG")
+        res["full_4444"] = full_4444(tmq, torch, synth, max(args.reps, 5))
+    if "eo" in want:
+        log("24^3x48 even/odd: FP64 vs mixed")
+        res["eo_24c48"] = eo_24c48(tmq, torch, synth, args.reps)
+    if "batch" in want:
+        log("24^3x48 batch of 48")
+        res["batch_24c48_48rhs"] = batch_24c48(tmq, torch, synth, args.reps)
+    print(json.dumps(res))
+    return res
+
+
+if __name__ == "__main__":
+    main()

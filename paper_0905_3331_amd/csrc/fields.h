@@ -93,6 +93,41 @@ __device__ __forceinline__ uint2 ld(const uint2 *p)
     return *p;
 }
 
+// Stores of data that this kernel does not read again (a hop's output) can
+// be non-temporal too, so that they do not displace the spinors in L2.
+template <bool NT>
+__device__ __forceinline__ void st(double2 *p, double2 v)
+{
+    if (NT)
+        __builtin_nontemporal_store(nv_d2{v.x, v.y}, (nv_d2 *)p);
+    else
+        *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st(float4 *p, float4 v)
+{
+    if (NT)
+        __builtin_nontemporal_store(nv_f4{v.x, v.y, v.z, v.w}, (nv_f4 *)p);
+    else
+        *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st(uint4 *p, uint4 v)
+{
+    if (NT)
+        __builtin_nontemporal_store(nv_u4{v.x, v.y, v.z, v.w}, (nv_u4 *)p);
+    else
+        *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st(float *p, float v)
+{
+    if (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // ------------------------------------------------------------ 16-bit codes
 
 __device__ __forceinline__ float h16_to_f32(uint16_t c) { return __half2float(__ushort_as_half(c)); }
@@ -147,14 +182,14 @@ struct SpF64 {
             s.c[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
         }
     }
-    template <typename R>
+    template <bool NT = false, typename R>
     __device__ __forceinline__ void store(long h, const spinor<R> &s) const
     {
         double2 *q = p + aidx(h, 0, 12);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             cx<R> v = s.c[k / 3][k % 3];
-            q[k * 8] = make_double2((double)v.re, (double)v.im);
+            st<NT>(q + k * 8, make_double2((double)v.re, (double)v.im));
         }
     }
 };
@@ -174,7 +209,7 @@ struct SpF32 {
             s.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = cx<R>{(R)v.z, (R)v.w};
         }
     }
-    template <typename R>
+    template <bool NT = false, typename R>
     __device__ __forceinline__ void store(long h, const spinor<R> &s) const
     {
         float4 *q = p + aidx(h, 0, 6);
@@ -182,7 +217,7 @@ struct SpF32 {
         for (int k = 0; k < 6; k++) {
             cx<R> a = s.c[(2 * k) / 3][(2 * k) % 3];
             cx<R> b = s.c[(2 * k + 1) / 3][(2 * k + 1) % 3];
-            q[k * 8] = make_float4((float)a.re, (float)a.im, (float)b.re, (float)b.im);
+            st<NT>(q + k * 8, make_float4((float)a.re, (float)a.im, (float)b.re, (float)b.im));
         }
     }
 };
@@ -230,7 +265,7 @@ struct Sp16 {
     // A site whose largest part is below the smallest normal FP32 number is
     // stored as zero (its reciprocal would overflow); a non-finite site keeps
     // a NaN scale so that the solver's checks see it.
-    template <typename R>
+    template <bool NT = false, typename R>
     __device__ __forceinline__ void store(long h, const spinor<R> &s) const
     {
         float m = 0.f;
@@ -243,7 +278,7 @@ struct Sp16 {
         }
         const bool tiny = m < 1.17549435e-38f;
         const float inv = tiny ? 0.f : 1.0f / m;
-        scale[h] = bad ? __int_as_float(0x7fc00000) : (tiny ? 0.f : m);
+        st<NT>(scale + h, bad ? __int_as_float(0x7fc00000) : (tiny ? 0.f : m));
         uint4 *q = p + aidx(h, 0, 3);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
@@ -254,7 +289,7 @@ struct Sp16 {
                 cx<R> v = s.c[comp / 3][comp % 3];
                 w[j] = pack16(f32_to_code<BF>((float)v.re * inv), f32_to_code<BF>((float)v.im * inv));
             }
-            q[k * 8] = make_uint4(w[0], w[1], w[2], w[3]);
+            st<NT>(q + k * 8, make_uint4(w[0], w[1], w[2], w[3]));
         }
     }
 };
@@ -278,12 +313,16 @@ struct L64F {
             u.e[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
         }
     }
-    // out = U p or U^+ p for the link of direction mu at site h of parity par
-    template <bool DAG, bool NT, typename R>
-    __device__ __forceinline__ void mul(int par, int mu, long h, const half<R> &p, half<R> &out) const
+    // a link held in registers, and out = U p or U^+ p with it
+    using Loaded = su3<real>;
+    template <bool NT>
+    __device__ __forceinline__ void load_link(int par, int mu, long h, Loaded &u) const
     {
-        su3<R> u;
         load<NT>(par, mu, h, u);
+    }
+    template <bool DAG>
+    __device__ __forceinline__ void apply(const Loaded &u, const half<real> &p, half<real> &out) const
+    {
         link_mul<DAG>(u, p, out);
     }
 };
@@ -303,12 +342,16 @@ struct L64R {
         }
         su3_third_row(u);
     }
-    // out = U p or U^+ p for the link of direction mu at site h of parity par
-    template <bool DAG, bool NT, typename R>
-    __device__ __forceinline__ void mul(int par, int mu, long h, const half<R> &p, half<R> &out) const
+    // a link held in registers, and out = U p or U^+ p with it
+    using Loaded = su3<real>;
+    template <bool NT>
+    __device__ __forceinline__ void load_link(int par, int mu, long h, Loaded &u) const
     {
-        su3<R> u;
         load<NT>(par, mu, h, u);
+    }
+    template <bool DAG>
+    __device__ __forceinline__ void apply(const Loaded &u, const half<real> &p, half<real> &out) const
+    {
         link_mul<DAG>(u, p, out);
     }
 };
@@ -329,12 +372,16 @@ struct L32R {
         }
         su3_third_row(u);
     }
-    // out = U p or U^+ p for the link of direction mu at site h of parity par
-    template <bool DAG, bool NT, typename R>
-    __device__ __forceinline__ void mul(int par, int mu, long h, const half<R> &p, half<R> &out) const
+    // a link held in registers, and out = U p or U^+ p with it
+    using Loaded = su3<real>;
+    template <bool NT>
+    __device__ __forceinline__ void load_link(int par, int mu, long h, Loaded &u) const
     {
-        su3<R> u;
         load<NT>(par, mu, h, u);
+    }
+    template <bool DAG>
+    __device__ __forceinline__ void apply(const Loaded &u, const half<real> &p, half<real> &out) const
+    {
         link_mul<DAG>(u, p, out);
     }
 };
@@ -344,27 +391,42 @@ struct L16R {
     const uint4 *a;  // complex 0..3 of rows 0,1 (row-major)
     const uint2 *b;  // complex 4, 5
     long vh;
-    // out = U p or U^+ p in FP32 with the FP16 entries of rows 0 and 1 read
-    // directly by the FMAs; row 2 = conj(row0 x row1) is formed in FP32
-    template <bool DAG, bool NT>
-    __device__ __forceinline__ void mul(int par, int mu, long h, const half<float> &p, half<float> &out) const
+    // A link held in registers: the words of rows 0 and 1 (entry (i, j) is
+    // word 3 i + j, real part in the low half) and row 2 = conj(row0 x row1)
+    // formed in FP32 from them.  apply() computes U p or U^+ p in FP32 with
+    // the FP16 entries read directly by the FMAs.
+    struct Loaded {
+        uint32_t w[6];
+        cx<float> r2[3];
+    };
+    template <bool NT>
+    __device__ __forceinline__ void load_link(int par, int mu, long h, Loaded &u) const
     {
         const uint4 va = ld<NT>(a + par * 4 * vh + lidx(h, mu, 0, 1));
         const uint2 vb = ld<NT>(b + par * 4 * vh16(vh) + lidx16(h, mu));
-        const uint32_t w[6] = {va.x, va.y, va.z, va.w, vb.x, vb.y};
-        // entry (i, j) of rows 0, 1 is word 3 i + j
-        auto re = [&](int i, int j) { return code_lo<false>(w[3 * i + j]); };
-        auto im = [&](int i, int j) { return code_hi<false>(w[3 * i + j]); };
+        u.w[0] = va.x;
+        u.w[1] = va.y;
+        u.w[2] = va.z;
+        u.w[3] = va.w;
+        u.w[4] = vb.x;
+        u.w[5] = vb.y;
+        auto re = [&](int i, int j) { return code_lo<false>(u.w[3 * i + j]); };
+        auto im = [&](int i, int j) { return code_hi<false>(u.w[3 * i + j]); };
         // row 2, column c: conj(u0a u1b - u0b u1a) with (a, b) the other two columns in cyclic order
-        cx<float> r2[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             const int ca = (c + 1) % 3, cb = (c + 2) % 3;
-            r2[c].re = fmad(re(0, ca), re(1, cb),
-                            fmad(-im(0, ca), im(1, cb), fmad(-re(0, cb), re(1, ca), fmad(im(0, cb), im(1, ca), 0.f))));
-            r2[c].im = fmad(-re(0, ca), im(1, cb),
-                            fmad(-im(0, ca), re(1, cb), fmad(re(0, cb), im(1, ca), fmad(im(0, cb), re(1, ca), 0.f))));
+            u.r2[c].re = fmad(re(0, ca), re(1, cb),
+                              fmad(-im(0, ca), im(1, cb), fmad(-re(0, cb), re(1, ca), fmad(im(0, cb), im(1, ca), 0.f))));
+            u.r2[c].im = fmad(-re(0, ca), im(1, cb),
+                              fmad(-im(0, ca), re(1, cb), fmad(re(0, cb), im(1, ca), fmad(im(0, cb), re(1, ca), 0.f))));
         }
+    }
+    template <bool DAG>
+    __device__ __forceinline__ void apply(const Loaded &u, const half<float> &p, half<float> &out) const
+    {
+        auto re = [&](int i, int j) { return code_lo<false>(u.w[3 * i + j]); };
+        auto im = [&](int i, int j) { return code_hi<false>(u.w[3 * i + j]); };
 #pragma unroll
         for (int k = 0; k < 2; k++)
 #pragma unroll
@@ -378,16 +440,16 @@ struct L16R {
                             sr = fmad(re(r, c), x.re, fmad(-im(r, c), x.im, sr));
                             si = fmad(re(r, c), x.im, fmad(im(r, c), x.re, si));
                         } else {
-                            sr = fmad(r2[c].re, x.re, fmad(-r2[c].im, x.im, sr));
-                            si = fmad(r2[c].re, x.im, fmad(r2[c].im, x.re, si));
+                            sr = fmad(u.r2[c].re, x.re, fmad(-u.r2[c].im, x.im, sr));
+                            si = fmad(u.r2[c].re, x.im, fmad(u.r2[c].im, x.re, si));
                         }
                     } else {  // + conj(U[c][r]) x
                         if (c < 2) {
                             sr = fmad(re(c, r), x.re, fmad(im(c, r), x.im, sr));
                             si = fmad(re(c, r), x.im, fmad(-im(c, r), x.re, si));
                         } else {
-                            sr = fmad(r2[r].re, x.re, fmad(r2[r].im, x.im, sr));
-                            si = fmad(r2[r].re, x.im, fmad(-r2[r].im, x.re, si));
+                            sr = fmad(u.r2[r].re, x.re, fmad(u.r2[r].im, x.im, sr));
+                            si = fmad(u.r2[r].re, x.im, fmad(-u.r2[r].im, x.re, si));
                         }
                     }
                 }

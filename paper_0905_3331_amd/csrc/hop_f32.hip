@@ -5,11 +5,11 @@ namespace tmq {
 
 hipError_t launch_hop_f32(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
                    const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
-                   long pstride, const CgScalars *scal, int variant, int group, unsigned lds, hipStream_t st)
+                   long pstride, const CgScalars *scal, const HopTune &tu, hipStream_t st)
 {
-#define GO(SPT, LKT, ALL) return go<SPT, LKT, ALL>(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, variant, group, lds, st)
-    if (lk.fmt == LK32R) GO(SpF32, L32R, true);
-    if (lk.fmt == LK16R) GO(SpF32, L16R, false);
+#define GO(SPT, LKT, ALL, MULTI) return go<SPT, LKT, ALL, MULTI>(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st)
+    if (lk.fmt == LK32R) GO(SpF32, L32R, true, true);
+    if (lk.fmt == LK16R) GO(SpF32, L16R, false, false);
 #undef GO
     return hipErrorInvalidValue;
 }

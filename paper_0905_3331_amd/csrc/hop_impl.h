@@ -119,52 +119,71 @@ __device__ __forceinline__ void reconstruct_fma(spinor<float> &acc, const half<f
     }
 }
 
-template <int MU, bool NT, class SP, class LK, typename R>
-__device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP &in, spinor<R> &acc, long h, long hf,
-                                        long hb)
+// The contribution of direction MU (forward and backward hop) for the G
+// right-hand sides of a lane: each link is loaded once and applied to the
+// projected neighbour spinor of every RHS in turn; per RHS the operations are
+// those of a lane with one RHS.
+template <int MU, bool NT, int G, class SP, class LK, typename R>
+__device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)[G], const bool (&live)[G],
+                                        spinor<R> (&acc)[G], long h, long hf, long hb)
 {
     const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
     const cx<R> ph = {(R)a.op.ph[MU][0], (R)a.op.ph[MU][1]};
-    half<R> p, w;
-    if constexpr (SP::coded) {
-        // 16-bit spinors: project the codes, multiply by the link, and apply
-        // the site's scale (times the phase) when accumulating
-        uint32_t c[12];
-        float sc;
-        // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu); U at the output site
-        in.load_codes(hf, c, sc);
-        project_codes<MU, +1, SP::bf>(c, a.one, p);
-        a.lk.template mul<false, NT>(a.out_par, MU, h, p, w);
-        if (phase) {
-            half_scale(w, cx<R>{sc * ph.re, sc * ph.im});
-            reconstruct_add<MU, +1>(acc, w);
-        } else {
-            reconstruct_fma<MU, +1>(acc, w, sc);
+    typename LK::Loaded u;
+#pragma unroll
+    for (int dir = 0; dir < 2; dir++) {
+        // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu), U at the output site;
+        // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu), U at the neighbour
+        const long hn = dir == 0 ? hf : hb;
+        a.lk.template load_link<NT>(dir == 0 ? a.out_par : a.out_par ^ 1, MU, dir == 0 ? h : hb, u);
+        const cx<R> phd = dir == 0 ? ph : conj(ph);
+#pragma unroll
+        for (int gi = 0; gi < G; gi++) {
+            if (!live[gi]) continue;
+            half<R> p, w;
+            if constexpr (SP::coded) {
+                // 16-bit spinors: project the codes, multiply by the link, and
+                // apply the site's scale (times the phase) when accumulating
+                uint32_t c[12];
+                float sc;
+                in[gi].load_codes(hn, c, sc);
+                if (dir == 0)
+                    project_codes<MU, +1, SP::bf>(c, a.one, p);
+                else
+                    project_codes<MU, -1, SP::bf>(c, a.one, p);
+                if (dir == 0)
+                    a.lk.template apply<false>(u, p, w);
+                else
+                    a.lk.template apply<true>(u, p, w);
+                if (phase) {
+                    half_scale(w, cx<R>{sc * phd.re, sc * phd.im});
+                    if (dir == 0)
+                        reconstruct_add<MU, +1>(acc[gi], w);
+                    else
+                        reconstruct_add<MU, -1>(acc[gi], w);
+                } else {
+                    if (dir == 0)
+                        reconstruct_fma<MU, +1>(acc[gi], w, sc);
+                    else
+                        reconstruct_fma<MU, -1>(acc[gi], w, sc);
+                }
+            } else {
+                spinor<R> sp;
+                in[gi].load(hn, sp);
+                if (dir == 0) {
+                    project<MU, +1>(sp, p);
+                    a.lk.template apply<false>(u, p, w);
+                } else {
+                    project<MU, -1>(sp, p);
+                    a.lk.template apply<true>(u, p, w);
+                }
+                if (phase) half_scale(w, phd);
+                if (dir == 0)
+                    reconstruct_add<MU, +1>(acc[gi], w);
+                else
+                    reconstruct_add<MU, -1>(acc[gi], w);
+            }
         }
-        // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu); U at the neighbour
-        in.load_codes(hb, c, sc);
-        project_codes<MU, -1, SP::bf>(c, a.one, p);
-        a.lk.template mul<true, NT>(a.out_par ^ 1, MU, hb, p, w);
-        if (phase) {
-            half_scale(w, cx<R>{sc * ph.re, -(sc * ph.im)});
-            reconstruct_add<MU, -1>(acc, w);
-        } else {
-            reconstruct_fma<MU, -1>(acc, w, sc);
-        }
-    } else {
-        spinor<R> s;
-        // forward: e^{i theta pi/L} U(x,mu) (1 + gamma_mu) psi(x+mu); U at the output site
-        in.load(hf, s);
-        project<MU, +1>(s, p);
-        a.lk.template mul<false, NT>(a.out_par, MU, h, p, w);
-        if (phase) half_scale(w, ph);
-        reconstruct_add<MU, +1>(acc, w);
-        // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu); U at the neighbour
-        in.load(hb, s);
-        project<MU, -1>(s, p);
-        a.lk.template mul<true, NT>(a.out_par ^ 1, MU, hb, p, w);
-        if (phase) half_scale(w, conj(ph));
-        reconstruct_add<MU, -1>(acc, w);
     }
 }
 
@@ -186,21 +205,32 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP &in, 
 // its L2; the host sizes the group for that.  With one RHS this is the
 // single-field order, and each RHS's arithmetic and partial sums do not depend
 // on the batch around it.
-template <class SP, class LK, bool SELF, bool NORM, bool NT, int ORD, bool SB>
+template <class SP, class LK, bool SELF, bool NORM, bool NT, int ORD, bool SB, int G>
 __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 {
     using R = typename LK::real;
     const Geom &g = a.g;
     const int j = blockIdx.x & 7;
     const int k = blockIdx.x >> 3;
-    const int nb = a.nblk >> 3;                      // site blocks of this XCD's share
-    const int G = a.group, gi = k / (nb * G);        // group of this block
-    const int gsize = min(G, a.rl.n - gi * G);       // the last group may be smaller
-    const int within = k - gi * nb * G;
-    const int sb = within / gsize;                   // site block within the XCD's share
-    const int ri = gi * G + (within - sb * gsize);
-    const int rhs = a.rl.idx[ri];
-    if (a.scal && a.scal[rhs].done) return;
+    const int nb = a.nblk >> 3;                        // site blocks of this XCD's share
+    const int ntup = (a.rl.n + G - 1) / G;             // tuples of G RHS (one per lane)
+    const int GR = a.group, gr = k / (nb * GR);        // group of tuples of this block
+    const int gsize = min(GR, ntup - gr * GR);         // the last group may be smaller
+    const int within = k - gr * nb * GR;
+    const int sb = within / gsize;                     // site block within the XCD's share
+    const int tup = gr * GR + (within - sb * gsize);
+    int rhs[G];
+    bool live[G];
+    bool any = false;
+#pragma unroll
+    for (int gi = 0; gi < G; gi++) {
+        const int ri = tup * G + gi;
+        live[gi] = ri < a.rl.n;
+        rhs[gi] = live[gi] ? a.rl.idx[ri] : 0;
+        if (live[gi] && a.scal && a.scal[rhs[gi]].done) live[gi] = false;
+        any |= live[gi];
+    }
+    if (!any) return;
     const long plane = (long)g.LY * g.XH;  // sites of one (t, z) plane
     long h;
     int t, z, y, pidx;
@@ -249,97 +279,112 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         t = (int)(r / (unsigned)g.LZ);
         pidx = lb;
     }
-    double nrm = 0.0;
+    double nrm[G];
+#pragma unroll
+    for (int gi = 0; gi < G; gi++) nrm[gi] = 0.0;
     if (active) {
-        const SP in = a.in.at(rhs);
+        SP in[G];
+#pragma unroll
+        for (int gi = 0; gi < G; gi++) in[gi] = a.in.at(rhs[gi]);
         // x parity makes (t+z+y+x) = out_par mod 2
         const int x = 2 * (int)xh + ((a.out_par + t + z + y) & 1);
         const long row = h - xh;  // eo index of (t, z, y, 0)
         const long sy = g.XH, sz = plane, stt = (long)g.LZ * plane;
 
-        spinor<R> acc;
+        spinor<R> acc[G];
 #pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) acc.c[i][c] = cx<R>{R(0), R(0)};
-
-        hop_dir<0, NT>(a, in, acc, h, t + 1 == g.T ? h - (g.T - 1) * stt : h + stt,
-                       t == 0 ? h + (g.T - 1) * stt : h - stt);
-        if (SB) __builtin_amdgcn_sched_barrier(0);
-        hop_dir<1, NT>(a, in, acc, h, row + ((x + 1 == g.LX ? 0 : x + 1) >> 1),
-                       row + ((x == 0 ? g.LX - 1 : x - 1) >> 1));
-        if (SB) __builtin_amdgcn_sched_barrier(0);
-        hop_dir<2, NT>(a, in, acc, h, y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy,
-                       y == 0 ? h + (g.LY - 1) * sy : h - sy);
-        if (SB) __builtin_amdgcn_sched_barrier(0);
-        hop_dir<3, NT>(a, in, acc, h, z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz,
-                       z == 0 ? h + (g.LZ - 1) * sz : h - sz);
-
-        // epilogue coefficients of this RHS (upper spins: gamma_5 = +1, lower: -1)
-        const double kap = a.op.kappa[rhs], m = a.sign * a.op.mut[rhs];
-        cx<R> Au, Ad, Bu, Bd;
-        if (a.epi == EPI_K1) {
-            const double c = kap * kap / (1.0 + m * m);
-            Au = Ad = cx<R>{R(0), R(0)};
-            Bu = cx<R>{(R)c, (R)(-c * m)};
-            Bd = cx<R>{(R)c, (R)(c * m)};
-        } else {
-            const double b = a.epi == EPI_FULL ? kap : 1.0;
-            Au = cx<R>{R(1), (R)m};
-            Ad = cx<R>{R(-1), (R)m};
-            Bu = cx<R>{(R)(-b), R(0)};
-            Bd = cx<R>{(R)b, R(0)};
-        }
-        spinor<R> o;
-        if (SELF) {
-            spinor<R> sf;
-            a.self.at(rhs).load(h, sf);
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                o.c[0][c] = fma(Au, sf.c[0][c], Bu * acc.c[0][c]);
-                o.c[1][c] = fma(Au, sf.c[1][c], Bu * acc.c[1][c]);
-                o.c[2][c] = fma(Ad, sf.c[2][c], Bd * acc.c[2][c]);
-                o.c[3][c] = fma(Ad, sf.c[3][c], Bd * acc.c[3][c]);
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                o.c[0][c] = Bu * acc.c[0][c];
-                o.c[1][c] = Bu * acc.c[1][c];
-                o.c[2][c] = Bd * acc.c[2][c];
-                o.c[3][c] = Bd * acc.c[3][c];
-            }
-        }
-        a.out.at(rhs).store(h, o);
-        if (NORM) {
-            R n2 = R(0);
+        for (int gi = 0; gi < G; gi++)
 #pragma unroll
             for (int i = 0; i < 4; i++)
 #pragma unroll
-                for (int c = 0; c < 3; c++) n2 += norm2(o.c[i][c]);
-            nrm = (double)n2;
+                for (int c = 0; c < 3; c++) acc[gi].c[i][c] = cx<R>{R(0), R(0)};
+
+        hop_dir<0, NT>(a, in, live, acc, h, t + 1 == g.T ? h - (g.T - 1) * stt : h + stt,
+                       t == 0 ? h + (g.T - 1) * stt : h - stt);
+        if (SB) __builtin_amdgcn_sched_barrier(0);
+        hop_dir<1, NT>(a, in, live, acc, h, row + ((x + 1 == g.LX ? 0 : x + 1) >> 1),
+                       row + ((x == 0 ? g.LX - 1 : x - 1) >> 1));
+        if (SB) __builtin_amdgcn_sched_barrier(0);
+        hop_dir<2, NT>(a, in, live, acc, h, y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy,
+                       y == 0 ? h + (g.LY - 1) * sy : h - sy);
+        if (SB) __builtin_amdgcn_sched_barrier(0);
+        hop_dir<3, NT>(a, in, live, acc, h, z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz,
+                       z == 0 ? h + (g.LZ - 1) * sz : h - sz);
+
+#pragma unroll
+        for (int gi = 0; gi < G; gi++) {
+            if (!live[gi]) continue;
+            // epilogue coefficients of this RHS (upper spins: gamma_5 = +1, lower: -1)
+            const double kap = a.op.kappa[rhs[gi]], m = a.sign * a.op.mut[rhs[gi]];
+            cx<R> Au, Ad, Bu, Bd;
+            if (a.epi == EPI_K1) {
+                const double c = kap * kap / (1.0 + m * m);
+                Au = Ad = cx<R>{R(0), R(0)};
+                Bu = cx<R>{(R)c, (R)(-c * m)};
+                Bd = cx<R>{(R)c, (R)(c * m)};
+            } else {
+                const double b = a.epi == EPI_FULL ? kap : 1.0;
+                Au = cx<R>{R(1), (R)m};
+                Ad = cx<R>{R(-1), (R)m};
+                Bu = cx<R>{(R)(-b), R(0)};
+                Bd = cx<R>{(R)b, R(0)};
+            }
+            const spinor<R> &ac = acc[gi];
+            spinor<R> o;
+            if (SELF) {
+                spinor<R> sf;
+                a.self.at(rhs[gi]).load(h, sf);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    o.c[0][c] = fma(Au, sf.c[0][c], Bu * ac.c[0][c]);
+                    o.c[1][c] = fma(Au, sf.c[1][c], Bu * ac.c[1][c]);
+                    o.c[2][c] = fma(Ad, sf.c[2][c], Bd * ac.c[2][c]);
+                    o.c[3][c] = fma(Ad, sf.c[3][c], Bd * ac.c[3][c]);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    o.c[0][c] = Bu * ac.c[0][c];
+                    o.c[1][c] = Bu * ac.c[1][c];
+                    o.c[2][c] = Bd * ac.c[2][c];
+                    o.c[3][c] = Bd * ac.c[3][c];
+                }
+            }
+            a.out.at(rhs[gi]).template store<true>(h, o);
+            if (NORM) {
+                R n2 = R(0);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) n2 += norm2(o.c[i][c]);
+                nrm[gi] = (double)n2;
+            }
         }
     }
     if (NORM) {
-        __shared__ double sh[HOP_BLOCK / 64];
-        const double s = block_sum(nrm, sh);
-        if (threadIdx.x == 0) a.partial[rhs * a.pstride + pidx] = s;
+        __shared__ double sh[G][HOP_BLOCK / 64];
+#pragma unroll
+        for (int gi = 0; gi < G; gi++) {
+            if (!live[gi]) continue;
+            const double s = block_sum(nrm[gi], sh[gi]);
+            if (threadIdx.x == 0) a.partial[rhs[gi] * a.pstride + pidx] = s;
+        }
     }
 }
 
 // ------------------------------------------------------------- dispatch
 
-template <class SP, class LK, bool NT, int ORD, bool SB>
+template <class SP, class LK, bool NT, int ORD, bool SB, int G>
 void go_w(const HopArgs<SP, LK> &a, bool s, bool n, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
     if (s && n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, SB>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, SB, G>), grid, block, lds, st, a);
     else if (s)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, NT, ORD, SB>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, NT, ORD, SB, G>), grid, block, lds, st, a);
     else if (n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true, NT, ORD, SB>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true, NT, ORD, SB, G>), grid, block, lds, st, a);
     else
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, NT, ORD, SB>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, NT, ORD, SB, G>), grid, block, lds, st, a);
 }
 
 // ALL = false: only variant 0 is instantiated (rarely used format pairs)
@@ -353,11 +398,13 @@ inline int rhs_group(const Geom &g, int prec, int n)
     return G < 1 ? 1 : (G > n ? n : G);
 }
 
-template <class SP, class LK, bool ALL>
+// ALL = false: only variant 0 with one RHS per lane is instantiated (rarely
+// used format pairs); MULTI = true adds 2 and 4 RHS per lane for batches (the
+// FP32-arithmetic formats; FP64 lanes already use all 256 registers).
+template <class SP, class LK, bool ALL, bool MULTI>
 hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
-                     const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl,
-                     double *partial, long pstride, const CgScalars *scal, int variant, int group, unsigned lds,
-                     hipStream_t st)
+              const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
+              long pstride, const CgScalars *scal, const HopTune &tu, hipStream_t st)
 {
     if (rl.n <= 0) return hipSuccess;
     HopArgs<SP, LK> a;
@@ -378,26 +425,54 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     a.pstride = pstride;
     a.scal = scal;
     a.one = 1.0f;
+    int variant = tu.variant;
     if (!ALL || !hop_variant_valid(g, variant)) variant = 0;
+    int G = MULTI && ALL && rl.n > 1 ? tu.rpl : 1;
+    if (G != 2 && G != 4) G = 1;
+    const int ntup = (rl.n + G - 1) / G;
     a.nblk = hop_grid_variant(g, variant);
-    a.group = group > 0 ? (group < rl.n ? group : rl.n) : rhs_group(g, in.prec, rl.n);
-    dim3 grid(a.nblk * rl.n), block(HOP_BLOCK);
+    const int grp = tu.group > 0 ? tu.group : rhs_group(g, in.prec, rl.n);  // in RHS
+    a.group = (grp + G - 1) / G;
+    if (a.group > ntup) a.group = ntup;
+    dim3 grid(a.nblk * ntup), block(HOP_BLOCK);
     const bool s = epi != EPI_K1, n = partial != nullptr;
     if (s && !self.data) return hipErrorInvalidValue;
     const bool nt = rl.n == 1;
+    const unsigned lds = tu.lds;
     if (!ALL) {
         if (nt)
-            go_w<SP, LK, true, ORD_PLAIN, false>(a, s, n, grid, block, lds, st);
+            go_w<SP, LK, true, ORD_PLAIN, false, 1>(a, s, n, grid, block, lds, st);
         else
-            go_w<SP, LK, false, ORD_PLAIN, false>(a, s, n, grid, block, lds, st);
+            go_w<SP, LK, false, ORD_PLAIN, false, 1>(a, s, n, grid, block, lds, st);
+        return hipGetLastError();
+    }
+    if (MULTI && G > 1) {
+        // several RHS per lane: no scheduling-barrier flavours (same block order)
+        const int ord = variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB;
+#define GOM(GG)                                                                                \
+    do {                                                                                       \
+        if (ord == ORD_ZSLAB)                                                                  \
+            go_w<SP, LK, false, ORD_ZSLAB, false, GG>(a, s, n, grid, block, lds, st);          \
+        else if (ord == ORD_TSLAB)                                                             \
+            go_w<SP, LK, false, ORD_TSLAB, false, GG>(a, s, n, grid, block, lds, st);          \
+        else                                                                                   \
+            go_w<SP, LK, false, ORD_PLAIN, false, GG>(a, s, n, grid, block, lds, st);          \
+    } while (0)
+        if constexpr (MULTI) {
+            if (G == 2)
+                GOM(2);
+            else
+                GOM(4);
+        }
+#undef GOM
         return hipGetLastError();
     }
 #define GOV(ORD, SB)                                                          \
     do {                                                                      \
         if (nt)                                                               \
-            go_w<SP, LK, true, ORD, SB>(a, s, n, grid, block, lds, st);       \
+            go_w<SP, LK, true, ORD, SB, 1>(a, s, n, grid, block, lds, st);    \
         else                                                                  \
-            go_w<SP, LK, false, ORD, SB>(a, s, n, grid, block, lds, st);      \
+            go_w<SP, LK, false, ORD, SB, 1>(a, s, n, grid, block, lds, st);   \
     } while (0)
     switch (variant) {
     case 1: GOV(ORD_ZSLAB, false); break;
@@ -409,6 +484,5 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
 #undef GOV
     return hipGetLastError();
 }
-
 
 }  // namespace tmq

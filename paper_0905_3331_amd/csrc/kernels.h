@@ -116,13 +116,18 @@ int hop_grid_variant(const Geom &g, int v);
 // the epilogue needs it) holds parity out_par.  partial != nullptr: per-block
 // sums of |out|^2 at partial[r * pstride + block].  scal != nullptr: blocks of
 // RHS r with scal[r].done set do nothing.
-// group: RHS per group in a batched launch (0: a size from the L2 capacity).
-// lds: bytes of LDS reserved per block (unused by the kernel; a value above
-// the CU's LDS / (c + 1) caps the blocks resident per CU at c), 0 for none.
+// Launch shape of a hop half-sweep, chosen by the autotuner.
+struct HopTune {
+    int variant = 0;   // block order (see above)
+    int group = 0;     // RHS per L2 group of a batched launch (0: sized from the L2 capacity)
+    int rpl = 1;       // RHS per lane in a batched launch: 1, 2 or 4 (FP32-arithmetic formats)
+    unsigned lds = 0;  // LDS bytes reserved per block (unused by the kernel; a value above
+                       // the CU's LDS / (c + 1) caps the blocks resident per CU at c)
+};
 hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
-                      const RhsList &rl, double *partial, long pstride, const CgScalars *scal, int variant,
-                      int group, unsigned lds, hipStream_t st);
+                      const RhsList &rl, double *partial, long pstride, const CgScalars *scal, const HopTune &tu,
+                      hipStream_t st);
 
 // Vector kernels over the n sites of each RHS of rl.  Reductions write
 // blas_grid(n) per-block sums at partial[r * pstride + block]; scalars come

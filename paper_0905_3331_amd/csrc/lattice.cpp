@@ -122,6 +122,10 @@ int lattice_create(const int dims[4], int device, Lattice **out)
         const int v = atoi(fv);
         if (v >= 0 && v < HOP_VARIANTS) L->forced_variant = v;
     }
+    if (const char *fr = getenv("TMQ_HOP_RPL")) {
+        const int r = atoi(fr);
+        if (r == 1 || r == 2 || r == 4) L->forced_rpl = r;
+    }
     if (const char *fc = getenv("TMQ_HOP_CAP")) {
         const int c = atoi(fc);
         if (c >= 0 && c <= 5) L->forced_cap = c;
@@ -316,12 +320,13 @@ static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const
     int best = 0;
     float best_us = 0.f;
     auto time_one = [&](int v, unsigned lds, float *us) -> int {
-        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, 0, lds,
-                           st));
+        HopTune tu;
+        tu.variant = v;
+        tu.lds = lds;
+        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
         TMQ_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < reps; r++)
-            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, 0,
-                               lds, st));
+            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
         TMQ_HIP(hipEventRecord(e1, st));
         TMQ_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -361,45 +366,56 @@ static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const
     return TMQ_OK;
 }
 
-// For a batched launch, time RHS groups of 1, 2, 4, ... (the variant fixed)
-// and keep the fastest for this format and batch size.  The group only
-// orders the blocks; it does not change any result.
-static int tune_group(Lattice *L, int key, int out_par, const FieldDesc &in, const FieldDesc &self,
+// formats with kernels that take 2 or 4 RHS per lane (see hop_f32/f16/b16.hip)
+static bool multi_rhs_format(int prec, int link_fmt)
+{
+    return (prec == P32 && link_fmt == LK32R) || ((prec == P16 || prec == PB16) && link_fmt == LK16R);
+}
+
+// For a batched launch, time the RHS per lane (1, 2, 4 where the format has
+// them) and RHS groups (the variant and cap fixed), and keep the fastest for
+// this format and batch size class.  Neither changes any result.
+static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
-                      const RhsList &rl, bool norm, hipStream_t st, int *group)
+                      const RhsList &rl, bool norm, hipStream_t st, HopTune *res)
 {
     hipEvent_t e0 = pool_event(L), e1 = pool_event(L);
     double *tp = norm ? L->partial[2] : nullptr;
-    const int v = L->hop_variant[key];
-    const unsigned lds = occ_lds(L, L->hop_occ[key]);
-    int best = 1;
+    Lattice::BatchTune bt;
+    bt.key = key;
+    bt.cls = cls;
+    HopTune base;
+    base.variant = L->hop_variant[key];
+    base.lds = occ_lds(L, L->hop_occ[key]);
     float best_us = 0.f;
-    std::vector<float> us_all;
-    for (int G = 1;; G *= 2) {
-        if (G > rl.n) G = rl.n;
-        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, G, lds,
-                           st));
-        TMQ_HIP(hipEventRecord(e0, st));
-        for (int r = 0; r < 2; r++)
-            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, v, G,
-                               lds, st));
-        TMQ_HIP(hipEventRecord(e1, st));
-        TMQ_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-        const float us = ms * 1e3f / 2;
-        us_all.push_back(us);
-        if (best_us == 0.f || us < best_us) {
-            best = G;
-            best_us = us;
+    const int max_rpl = multi_rhs_format(in.prec, lk.fmt) ? 4 : 1;
+    for (int rpl = 1; rpl <= max_rpl && rpl <= rl.n; rpl *= 2)
+        for (int G = rpl;; G *= 2) {
+            if (G > rl.n) G = rl.n;
+            HopTune tu = base;
+            tu.rpl = rpl;
+            tu.group = G;
+            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
+            TMQ_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 2; r++)
+                TMQ_HIP(
+                    launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
+            TMQ_HIP(hipEventRecord(e1, st));
+            TMQ_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const float us = ms * 1e3f / 2;
+            bt.tried.push_back({(float)rpl, (float)G, us});
+            if (best_us == 0.f || us < best_us) {
+                bt.tu = tu;
+                best_us = us;
+            }
+            if (G == rl.n) break;
         }
-        if (G == rl.n) break;
-    }
     L->event_pool.push_back(e0);
     L->event_pool.push_back(e1);
-    L->hop_group.emplace_back(key * 128 + rl.n, best);
-    L->hop_group_us.emplace_back(key * 128 + rl.n, us_all);
-    *group = best;
+    *res = bt.tu;
+    L->hop_batch.push_back(bt);
     return TMQ_OK;
 }
 
@@ -428,16 +444,18 @@ std::string tuning_report(const Lattice *L)
         s += "]}";
         first = false;
     }
-    s += "], \"batch_group\": [";
-    for (size_t i = 0; i < L->hop_group.size(); i++) {
-        const int k = L->hop_group[i].first / 128, n = L->hop_group[i].first % 128;
+    s += "], \"batch\": [";
+    for (size_t i = 0; i < L->hop_batch.size(); i++) {
+        const Lattice::BatchTune &b = L->hop_batch[i];
         char buf[256];
-        snprintf(buf, sizeof(buf), "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"nrhs\": %d, \"group\": %d, \"us\": [",
-                 i ? ", " : "", pn[k / 4], ln[k % 4], n, L->hop_group[i].second);
+        snprintf(buf, sizeof(buf),
+                 "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"nrhs_class\": %d, \"rhs_per_lane\": %d, "
+                 "\"group\": %d, \"tried\": [",
+                 i ? ", " : "", pn[b.key / 4], ln[b.key % 4], b.cls, b.tu.rpl, b.tu.group);
         s += buf;
-        const auto &u = L->hop_group_us[i].second;
-        for (size_t j = 0; j < u.size(); j++) {
-            snprintf(buf, sizeof(buf), "%s%.1f", j ? ", " : "", u[j]);
+        for (size_t j = 0; j < b.tried.size(); j++) {
+            snprintf(buf, sizeof(buf), "%s[%d, %d, %.1f]", j ? ", " : "", (int)b.tried[j][0], (int)b.tried[j][1],
+                     b.tried[j][2]);
             s += buf;
         }
         s += "]}";
@@ -458,20 +476,23 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
     }
     else if (L->hop_variant[key] < 0)
         TMQ_TRY(tune_hop(L, key, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st));
-    // batches of up to 4 RHS run as one group; larger ones use the group tuned
-    // for their power-of-two size class
-    int group = rl.n;
-    if (rl.n > 4) {
-        int cls = 8;
+    // batches use the launch shape tuned for their power-of-two size class
+    HopTune tu;
+    tu.variant = L->hop_variant[key];
+    tu.lds = occ_lds(L, L->hop_occ[key]);
+    if (rl.n > 1) {
+        int cls = 2;
         while (cls < rl.n) cls *= 2;
-        group = 0;
-        for (auto &e : L->hop_group)
-            if (e.first == key * 128 + cls) group = e.second;
-        if (!group) {
-            TMQ_TRY(tune_group(L, key, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st, &group));
-            L->hop_group.back().first = key * 128 + cls;
-            L->hop_group_us.back().first = key * 128 + cls;
-        }
+        bool found = false;
+        for (auto &e : L->hop_batch)
+            if (e.key == key && e.cls == cls) {
+                tu = e.tu;
+                found = true;
+            }
+        if (!found)
+            TMQ_TRY(tune_batch(L, key, cls, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st,
+                               &tu));
+        if (L->forced_rpl) tu.rpl = L->forced_rpl;
     }
     TimedLaunch t{};
     if (L->timing) {
@@ -483,8 +504,7 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
         t.nrhs = rl.n;
         TMQ_HIP(hipEventRecord(t.a, st));
     }
-    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal,
-                       L->hop_variant[key], group, occ_lds(L, L->hop_occ[key]), st));
+    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal, tu, st));
     L->hop_blocks_last = hop_grid_variant(L->g, L->hop_variant[key]);
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));

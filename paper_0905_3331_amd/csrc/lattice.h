@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <string>
 #include <vector>
 
@@ -88,13 +89,19 @@ struct Lattice {
     float hop_tune_us[16][HOP_VARIANTS];
     int forced_variant = -1;  // TMQ_HOP_VARIANT in the environment
     int forced_cap = -1;      // TMQ_HOP_CAP in the environment
+    int forced_rpl = 0;       // TMQ_HOP_RPL in the environment (RHS per lane of batched hops)
     // blocks-per-CU cap tuned for that variant (0: none; see launch_hop's lds)
     int hop_occ[16];
     float hop_occ_us[16][6];
     int lds_per_cu = 65536;
-    // autotuned RHS group of batched hops, per (spinor precision, link format, batch size)
-    std::vector<std::pair<int, int>> hop_group;  // (key * 128 + nrhs, group)
-    std::vector<std::pair<int, std::vector<float>>> hop_group_us;
+    // autotuned launch shape of batched hops, per (spinor precision, link
+    // format) key and power-of-two batch size class
+    struct BatchTune {
+        int key, cls;
+        HopTune tu;
+        std::vector<std::array<float, 3>> tried;  // (RHS per lane, group, us per launch)
+    };
+    std::vector<BatchTune> hop_batch;
     int hop_blocks_last = 0;  // blocks (partial sums) of the last hop launch
 
     // kernel timing

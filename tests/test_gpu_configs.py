@@ -1,0 +1,69 @@
+"""GPU checks at the full sizes of the benchmark workloads, in the launch
+configuration the benchmarks time: 24^3x48 FP64 and FP32-inner even/odd CG
+(kappa 0.1632, 2 kappa mu 0.004) and the 48-RHS batch on 24^3x48 (12 point
+sources x 4 twisted masses).  Solutions are judged by the oracle's FP64 true
+residual (the oracle applies Qhat^+Qhat^- once per check), and batched
+solutions against their solves alone, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+THETA = (1.0, 0.0, 0.0, 0.0)
+DIMS = (48, 24, 24, 24)
+
+
+@pytest.fixture(scope="module")
+def tmq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0905_3331_amd import tmq as t
+
+    return t
+
+
+def test_eo_24c48_fp64_and_mixed(tmq):
+    U = synth.random_gauge(DIMS, eps=0.3, seed=1001)
+    lat = tmq.Lattice(DIMS)
+    lat.load_gauge(U)
+    b = synth.gaussian_odd(DIMS, seed=2100)
+    p = tmq.params(0.1632, 0.004, THETA)
+    for opts in (tmq.solver_opts(tol=1e-10), tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32"),
+                 tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")):
+        x, info = lat.solve(p, torch.from_numpy(b).cuda(), opts)
+        res = oracle.true_residual(U, b, x.cpu().numpy(), 0.1632, 0.004, THETA)
+        print(f"24^3x48 sloppy={opts.sloppy}: iters {info.iters} reliable {info.reliable_updates} "
+              f"true res {res:.2e} (gpu {info.true_rel_residual:.2e})")
+        assert info.status == 0 and res <= 1e-10
+        assert abs(res - info.true_rel_residual) <= 1e-3 * res
+    lat.close()
+
+
+def test_batch_24c48_48rhs(tmq):
+    U = synth.random_gauge(DIMS, eps=0.3, seed=1003)
+    lat = tmq.Lattice(DIMS)
+    lat.load_gauge(U)
+    vh = int(np.prod(DIMS)) // 2
+    site = int(np.random.default_rng(2300).integers(0, vh))
+    ps, bs = [], []
+    for mut in (0.002, 0.004, 0.008, 0.016):
+        for k in range(12):
+            bs.append(synth.point_source_odd(DIMS, site, k // 3, k % 3))
+            ps.append(tmq.params(0.1632, mut, THETA))
+    opts = tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    xs, infos = lat.solve_batch(ps, bd, opts)
+    assert all(f.status == 0 for f in infos)
+    for i in (0, 17, 47):
+        x1, i1 = lat.solve(ps[i], bd[i], opts)
+        assert torch.equal(x1, xs[i]), i
+        assert (i1.iters, i1.reliable_updates) == (infos[i].iters, infos[i].reliable_updates)
+    for i in (0, 13, 26, 39, 47):
+        res = oracle.true_residual(U, bs[i], xs[i].cpu().numpy(), 0.1632, ps[i].mu_tilde, THETA)
+        assert res <= 1e-10, (i, res)
+    lat.close()

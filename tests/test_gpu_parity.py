@@ -299,6 +299,33 @@ def test_batch_equals_alone(tmq, sloppy):
         assert infos[i].status == 0 and res <= 1e-10, (i, res)
 
 
+@pytest.mark.parametrize("rpl", [1, 2, 4])
+@pytest.mark.parametrize("sloppy", ["fp32", "fp16", "bf16"])
+def test_batch_rhs_per_lane(tmq, sloppy, rpl, monkeypatch):
+    """Batched hops with 1, 2 or 4 right-hand sides per lane (the link read
+    once per lane for all of them): 7 RHS (a ragged last tuple), each equal bit
+    for bit to its solve alone and converged by the oracle's residual."""
+    monkeypatch.setenv("TMQ_HOP_RPL", str(rpl))
+    dims = (8, 8, 6, 10)
+    U = synth.random_gauge(dims, seed=109)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(U)
+    ps = [tmq.params(0.1632, 0.002 + 0.003 * i, THETA_GEN) for i in range(7)]
+    bs = [synth.gaussian_odd(dims, seed=40 + i) for i in range(7)]
+    opts = tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp32" if sloppy == "fp32" else "fp16")
+    xs, infos = lat.solve_batch(ps, [dev(b) for b in bs], opts)
+    for i in (0, 3, 6):
+        x1, i1 = lat.solve(ps[i], dev(bs[i]), opts)
+        assert torch.equal(x1, xs[i]), f"rhs {i} differs from its solve alone"
+        assert (i1.iters, i1.reliable_updates) == (infos[i].iters, infos[i].reliable_updates)
+    for i in range(7):
+        res = oracle.true_residual(U, bs[i], host(xs[i]), 0.1632, ps[i].mu_tilde, THETA_GEN)
+        assert infos[i].status == 0 and res <= 1e-10, (i, res)
+    rep = lat.tuning_report()["batch"]
+    assert rep, "batched hops were not tuned"
+    lat.close()
+
+
 def test_batch_host_api_and_validation(tmq):
     dims = (4, 4, 4, 4)
     lat, U = lattice(tmq, dims, seed=106)
