@@ -14,7 +14,6 @@ cores on a bounded sample of the same operator.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -43,17 +42,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    h = hashlib.sha256()
-    for f in ("hop.hip", "fields.h", "spin.h", "devutil.h"):
-        with open(os.path.join(ROOT, "paper_0905_3331_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(family, key):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
+    from paper_0905_3331_amd.profile_hop import kernel_hash
+
     path = os.path.join(ROOT, "profiles", "hop_traffic.json")
     try:
         with open(path) as f:
@@ -129,6 +122,10 @@ def main():
     mixed = tmq.solver_opts(tol=w["tol"], sloppy=args.sloppy, sloppy_link=args.link)
     fp64 = tmq.solver_opts(tol=w["tol"], sloppy="fp64")
     vh = b.shape[0]
+
+    # calibration: a plain copy kernel, 1 GiB read + 1 GiB written per launch
+    copy_gbs = tmq.stream_copy_gbps(1 << 30, reps=5)
+    log(f"copy kernel: {copy_gbs:.0f} GB/s")
 
     log(f"warmup: {args.warmup} mixed solves")
     for _ in range(args.warmup):
@@ -242,6 +239,8 @@ def main():
             "algorithmic_bytes_per_launch": round(per_launch_bytes),
             "avg_launch_us": round(dom["ms"] / max(dom["launches"], 1) * 1e3, 2),
             "launches": dom["launches"],
+            "copy_kernel_GBps": round(copy_gbs, 1),
+            "frac_of_copy": round(dom_gbs / copy_gbs, 4),
         },
         "cpu_baseline": cpu,
         "verify": verify,

@@ -1,4 +1,5 @@
-"""Drive the hopping kernels for profiling (rocprofv3 kernel traces and counters).
+"""Drive the hopping kernels for profiling (rocprofv3 kernel traces and counters),
+and summarise what rocprofv3 wrote.
 
 Runs one calibration copy of a known size (kernel ``k_stream_copy``: reads and
 writes --copy-mib MiB once each), then --reps applications of Qhat^+ (two hop
@@ -9,8 +10,23 @@ WRITE_SIZE per dispatch) can be scaled by the copy's and compared.
 
     rocprofv3 --kernel-trace --stats -- python3 -m paper_0905_3331_amd.profile_hop
     rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_0905_3331_amd.profile_hop
+
+Summaries (no GPU needed):
+
+    python -m paper_0905_3331_amd.profile_hop --summarize-trace STATS_CSV --cmd "..." --out FILE.md
+    python -m paper_0905_3331_amd.profile_hop --summarize-pmc FETCH_CSV WRITE_CSV --copy-bytes N \
+        --cmd "..." --out profiles/hop_traffic.json
+
+The traffic summary scales each counter by what it reads for the plain copy
+kernel (k_stream_copy, N bytes read and N written per launch), averages it
+over the dispatches of each hop family (hop16: FP16/BF16 spinors, hop32,
+hop64) and records the hash of the kernel sources, so that a benchmark can
+tell whether the figures belong to the current kernels.
 """
 import argparse
+import collections
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -19,6 +35,114 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# sources that determine the hop kernels' memory traffic
+KERNEL_SOURCES = ("hop_impl.h", "hop.hip", "hop_f64.hip", "hop_f32.hip", "hop_f16.hip", "hop_b16.hip",
+                  "fields.h", "spin.h", "views.h", "kernels.h", "devutil.h")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0905_3331_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def hop_family(name: str):
+    if "hop_kernel" not in name:
+        return None
+    if "Sp16" in name:
+        return "hop16"
+    if "SpF32" in name:
+        return "hop32"
+    if "SpF64" in name:
+        return "hop64"
+    return None
+
+
+def _counter_rows(path, counter):
+    out = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_bytes, cmd, out):
+    f = _counter_rows(fetch_csv, "FETCH_SIZE")
+    w = _counter_rows(write_csv, "WRITE_SIZE")
+    copy = [k for k in f if "k_stream_copy" in k]
+    if not copy or not [k for k in w if "k_stream_copy" in k]:
+        raise SystemExit("no k_stream_copy dispatch in the counter files")
+    fcopy = sum(f[copy[0]]) / len(f[copy[0]]) * 1024.0
+    wk = [k for k in w if "k_stream_copy" in k][0]
+    wcopy = sum(w[wk]) / len(w[wk]) * 1024.0
+    fscale, wscale = copy_bytes / fcopy, copy_bytes / wcopy
+    # instantiations launched only while the autotuner timed its candidates
+    # (a few dispatches each) are left out of the family averages
+    def used(rows):
+        top = collections.Counter()
+        for k, v in rows.items():
+            fa = hop_family(k)
+            if fa:
+                top[fa] = max(top[fa], len(v))
+        return {k for k, v in rows.items() if hop_family(k) and len(v) >= 0.1 * top[hop_family(k)]}
+
+    fam = collections.defaultdict(lambda: {"fetch": [], "write": []})
+    per_kernel = {}
+    fu, wu = used(f), used(w)
+    for k, v in f.items():
+        fa = hop_family(k)
+        if fa:
+            per_kernel.setdefault(k, {})["read_bytes_per_launch"] = sum(v) / len(v) * 1024.0 * fscale
+            per_kernel[k]["dispatches"] = len(v)
+            if k in fu:
+                fam[fa]["fetch"] += [x * 1024.0 * fscale for x in v]
+    for k, v in w.items():
+        fa = hop_family(k)
+        if fa:
+            per_kernel.setdefault(k, {})["write_bytes_per_launch"] = sum(v) / len(v) * 1024.0 * wscale
+            if k in wu:
+                fam[fa]["write"] += [x * 1024.0 * wscale for x in v]
+    res = {"kernel_hash": kernel_hash(), "command": cmd, "copy_bytes": copy_bytes,
+           "fetch_scale": fscale, "write_scale": wscale, "per_kernel": per_kernel}
+    for fa, d in fam.items():
+        if d["fetch"] and d["write"]:
+            res[fa] = {"hbm_bytes_per_launch": sum(d["fetch"]) / len(d["fetch"]) + sum(d["write"]) / len(d["write"]),
+                       "read_bytes_per_launch": sum(d["fetch"]) / len(d["fetch"]),
+                       "write_bytes_per_launch": sum(d["write"]) / len(d["write"]),
+                       "dispatches": [len(d["fetch"]), len(d["write"])]}
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps({k: v for k, v in res.items() if k != "per_kernel"}))
+
+
+def summarize_trace(stats_csv, cmd, out):
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["# Kernel trace: " + os.path.basename(out).replace(".md", ""), "",
+             "Command (repo root, one MI355X, rocprofv3 --kernel-trace --stats):", "", "    " + cmd, "",
+             "| kernel | calls | total ms | share | avg us |", "|---|---|---|---|---|"]
+    fam = collections.defaultdict(lambda: [0, 0.0])
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        n, t = int(r["Calls"]), float(r["TotalDurationNs"])
+        name = r["Name"].replace("tmq::", "")
+        if len(name) > 110:
+            name = name[:107] + "..."
+        if t / tot >= 0.002:
+            lines.append(f"| `{name}` | {n} | {t / 1e6:.2f} | {100 * t / tot:.1f} % | {t / n / 1e3:.2f} |")
+        fa = hop_family(r["Name"])
+        if fa:
+            fam[fa][0] += n
+            fam[fa][1] += t
+    lines += ["", "Hop families (all instantiations together):", "", "| family | launches | avg us |", "|---|---|---|"]
+    for fa, (n, t) in sorted(fam.items()):
+        lines.append(f"| {fa} | {n} | {t / n / 1e3:.2f} |")
+    lines.append("")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -26,7 +150,16 @@ def main():
     ap.add_argument("--prec", default="fp64,fp16", help="comma list of fp64, fp32, fp16, bf16")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--summarize-trace", metavar="STATS_CSV")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--cmd", default="")
+    ap.add_argument("--out")
     args = ap.parse_args()
+    if args.summarize_trace:
+        return summarize_trace(args.summarize_trace, args.cmd, args.out)
+    if args.summarize_pmc:
+        return summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.copy_bytes, args.cmd, args.out)
 
     import torch
 
