@@ -19,10 +19,11 @@ namespace tmq {
 
 size_t engine_slot_bytes(long vh, int sloppy)
 {
-    // FP64: b, x, r, A x, t_e, t_o, p, A p ; mixed: b, x, r, A x, t_e, t_o,
-    // five inner vectors (r, p, A p, t_e, t_o) and the FP32 x_s
-    if (sloppy == P64) return 8 * field_bytes(P64, vh);
-    return 6 * field_bytes(P64, vh) + 5 * field_bytes(sloppy, vh) + field_bytes(P32, vh);
+    // FP64: b, x, r, t_e, t_o, p ; mixed: b, x, r, t_e, t_o in FP64, four inner
+    // vectors (r, p, t_e, t_o) and the FP32 x_s (A p never reaches memory: the
+    // CG update is fused into the half-sweep that forms it)
+    if (sloppy == P64) return 6 * field_bytes(P64, vh);
+    return 5 * field_bytes(P64, vh) + 4 * field_bytes(sloppy, vh) + field_bytes(P32, vh);
 }
 
 size_t engine_bytes(const Lattice *L, int sloppy, int cap)
@@ -76,12 +77,12 @@ int engine_create(Lattice *L, int sloppy, int sloppy_link, int cap, hipStream_t 
         return TMQ_OK;
     };
     int s = TMQ_OK;
-    for (FieldDesc *d : {&E->b, &E->x, &E->r64, &E->ax64, &E->te64, &E->to64})
+    for (FieldDesc *d : {&E->b, &E->x, &E->r64, &E->te64, &E->to64})
         if ((s = field(P64, d)) != TMQ_OK) return fail(s);
     E->lk64 = lattice_links(L, link_fmt_for(L, P64, P64));
     if (E->mixed) {
         E->lks = lattice_links(L, link_fmt_for(L, sloppy, sloppy_link));
-        for (FieldDesc *d : {&E->rs, &E->ps, &E->aps, &E->tes, &E->tos})
+        for (FieldDesc *d : {&E->rs, &E->ps, &E->tes, &E->tos})
             if ((s = field(sloppy, d)) != TMQ_OK) return fail(s);
         if ((s = field(P32, &E->xs)) != TMQ_OK) return fail(s);
     } else {
@@ -91,7 +92,6 @@ int engine_create(Lattice *L, int sloppy, int sloppy_link, int cap, hipStream_t 
         E->tes = E->te64;
         E->tos = E->to64;
         if ((s = field(P64, &E->ps)) != TMQ_OK) return fail(s);
-        if ((s = field(P64, &E->aps)) != TMQ_OK) return fail(s);
     }
     for (auto &p : E->partial)
         if (hipMalloc((void **)&p, sizeof(double) * L->pstride * cap) != hipSuccess) {
@@ -230,10 +230,13 @@ int engine_begin_step(Engine *E)
         TMQ_TRY(apply_Qhat(L, E->op, -1, E->ps, E->tos, E->tes, E->lks, al, E->partial[0], S, st));
         TMQ_HIP(launch_scalar(SC_ALPHA, al, E->partial[0], L->pstride, L->hop_blocks_last, S, 0, 0, true, nullptr,
                               st));
-        TMQ_TRY(apply_Qhat(L, E->op, +1, E->tos, E->aps, E->tes, E->lks, al, nullptr, S, st));
-        // x_s += alpha p ; r -= alpha A p ; |r|^2 ; beta
-        TMQ_HIP(launch_axpy_norm(E->xs, E->ps, E->rs, E->aps, al, S, E->partial[1], L->pstride, true, st));
-        TMQ_HIP(launch_scalar(SC_BETA, al, E->partial[1], L->pstride, blas_grid(L->g.vh), S, 0, 0, true, pub, st));
+        // A p = Qhat^+ t fused with x_s += alpha p ; r -= alpha A p ; |r|^2 ; then beta
+        CgFields cg;
+        cg.r = E->rs;
+        cg.p = E->ps;
+        cg.x = E->xs;
+        TMQ_TRY(apply_Qhat_cg(L, E->op, E->tos, E->tes, E->lks, al, cg, E->partial[1], S, st));
+        TMQ_HIP(launch_scalar(SC_BETA, al, E->partial[1], L->pstride, L->hop_blocks_last, S, 0, 0, true, pub, st));
     }
     E->body_pending = true;
     return TMQ_OK;
@@ -252,9 +255,8 @@ static int reliable_update(Engine *E, const RhsList &rl, CgScalars *publish)
     Lattice *L = E->L;
     hipStream_t st = E->st;
     if (E->mixed) TMQ_HIP(launch_accumulate(E->x, E->xs, rl, st));
-    TMQ_TRY(apply_QhatQhat(L, E->op, E->x, E->ax64, E->te64, E->to64, E->lk64, rl, nullptr, nullptr, st));
-    TMQ_HIP(launch_residual(E->b, E->ax64, E->r64, rl, E->partial[2], L->pstride, st));
-    TMQ_HIP(launch_scalar(SC_RELIABLE, rl, E->partial[2], L->pstride, blas_grid(L->g.vh), E->scal, 0.0, 0, false,
+    TMQ_TRY(residual_QhatQhat(L, E->op, E->x, E->b, E->r64, E->te64, E->to64, E->lk64, rl, E->partial[2], st));
+    TMQ_HIP(launch_scalar(SC_RELIABLE, rl, E->partial[2], L->pstride, L->hop_blocks_last, E->scal, 0.0, 0, false,
                           publish, st));
     if (E->mixed) TMQ_HIP(launch_convert(E->r64, E->rs, rl, st));
     return TMQ_OK;

@@ -39,7 +39,7 @@ struct Engine {
     bool mixed = false;
 
     std::vector<Field> fields;
-    FieldDesc b, x, r64, ax64, te64, to64, rs, ps, aps, tes, tos, xs;
+    FieldDesc b, x, r64, te64, to64, rs, ps, tes, tos, xs;
     LinkDesc lk64{}, lks{};
     OpParams op{};
     double *partial[3] = {nullptr, nullptr, nullptr};  // per slot at + slot * L->pstride

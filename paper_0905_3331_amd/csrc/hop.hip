@@ -51,7 +51,7 @@ int hop_grid_variant(const Geom &g, int v)
 #define TMQ_HOP_ARGS                                                                                       \
     const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,           \
         const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,      \
-        long pstride, const CgScalars *scal, const HopTune &tu, hipStream_t st
+        long pstride, const CgScalars *scal, const HopTune &tu, hipStream_t st, const CgFields *cg
 hipError_t launch_hop_f64(TMQ_HOP_ARGS);
 hipError_t launch_hop_f32(TMQ_HOP_ARGS);
 hipError_t launch_hop_f16(TMQ_HOP_ARGS);
@@ -59,12 +59,13 @@ hipError_t launch_hop_b16(TMQ_HOP_ARGS);
 
 hipError_t launch_hop(TMQ_HOP_ARGS)
 {
-    if (in.prec != out.prec || (self.data && self.prec != in.prec)) return hipErrorInvalidValue;
+    const bool fused = epi == EPI_K2_CG || epi == EPI_K2_RES;  // no output field
+    if ((!fused && in.prec != out.prec) || (self.data && self.prec != in.prec)) return hipErrorInvalidValue;
     switch (in.prec) {
-    case P64: return launch_hop_f64(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st);
-    case P32: return launch_hop_f32(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st);
-    case P16: return launch_hop_f16(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st);
-    case PB16: return launch_hop_b16(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st);
+    case P64: return launch_hop_f64(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st, cg);
+    case P32: return launch_hop_f32(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st, cg);
+    case P16: return launch_hop_f16(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st, cg);
+    case PB16: return launch_hop_b16(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st, cg);
     }
     return hipErrorInvalidValue;
 }

@@ -5,9 +5,9 @@ namespace tmq {
 
 hipError_t launch_hop_f64(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
                    const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
-                   long pstride, const CgScalars *scal, const HopTune &tu, hipStream_t st)
+                   long pstride, const CgScalars *scal, const HopTune &tu, hipStream_t st, const CgFields *cg)
 {
-#define GO(SPT, LKT, ALL, MULTI) return go<SPT, LKT, ALL, MULTI>(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st)
+#define GO(SPT, LKT, ALL, MULTI) return go<SPT, LKT, ALL, MULTI>(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st, cg)
     if (lk.fmt == LK64F) GO(SpF64, L64F, true, false);
     if (lk.fmt == LK64R) GO(SpF64, L64R, true, false);
 #undef GO

@@ -32,6 +32,18 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk)
     return (bid & 7) * (nblk >> 3) + (bid >> 3);
 }
 
+// format of the solution correction updated by the fused CG epilogue
+template <class SP>
+struct XsOf {
+    using type = SpF32;
+};
+template <>
+struct XsOf<SpF64> {
+    using type = SpF64;
+};
+
+enum HopEp { EP_STORE = 0, EP_CG = 1, EP_RES = 2 };
+
 template <class SP, class LK>
 struct HopArgs {
     Geom g;
@@ -48,6 +60,9 @@ struct HopArgs {
     long pstride;
     const CgScalars *scal;
     float one;  // 1.0, opaque to the compiler (see code_lo in fields.h)
+    // fused epilogues (EPI_K2_CG, EPI_K2_RES)
+    BatchView<SP> cg_r, cg_p;
+    BatchView<typename XsOf<SP>::type> cg_x;
 };
 
 // x + C y for C = 1, -1, i, -i (selector 0..3), x and y complex 16-bit codes
@@ -205,7 +220,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)
 // its L2; the host sizes the group for that.  With one RHS this is the
 // single-field order, and each RHS's arithmetic and partial sums do not depend
 // on the batch around it.
-template <class SP, class LK, bool SELF, bool NORM, bool NT, int ORD, bool SB, int G>
+template <class SP, class LK, bool SELF, bool NORM, bool NT, int ORD, bool SB, int G, int EP>
 __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 {
     using R = typename LK::real;
@@ -350,7 +365,42 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
                     o.c[3][c] = Bd * ac.c[3][c];
                 }
             }
-            a.out.at(rhs[gi]).template store<true>(h, o);
+            if (EP == EP_CG) {
+                // CG update: x += alpha p ; r -= alpha (A p) ; |r|^2
+                using XS = typename XsOf<SP>::type;
+                using RX = typename XS::real;
+                const double al = a.scal[rhs[gi]].alpha;
+                const R ar = (R)al;
+                const RX ax = (RX)al;
+                spinor<R> rr, pp;
+                spinor<RX> xx;
+                a.cg_r.at(rhs[gi]).load(h, rr);
+                a.cg_p.at(rhs[gi]).load(h, pp);
+                a.cg_x.at(rhs[gi]).load(h, xx);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        xx.c[i][c].re = fmad(ax, (RX)pp.c[i][c].re, xx.c[i][c].re);
+                        xx.c[i][c].im = fmad(ax, (RX)pp.c[i][c].im, xx.c[i][c].im);
+                        rr.c[i][c].re = fmad(-ar, o.c[i][c].re, rr.c[i][c].re);
+                        rr.c[i][c].im = fmad(-ar, o.c[i][c].im, rr.c[i][c].im);
+                    }
+                a.cg_x.at(rhs[gi]).store(h, xx);
+                a.cg_r.at(rhs[gi]).store(h, rr);
+                o = rr;
+            } else if (EP == EP_RES) {
+                // true residual r = b - A x
+                spinor<R> bb;
+                a.cg_p.at(rhs[gi]).load(h, bb);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) o.c[i][c] = bb.c[i][c] - o.c[i][c];
+                a.cg_r.at(rhs[gi]).store(h, o);
+            } else {
+                a.out.at(rhs[gi]).template store<true>(h, o);
+            }
             if (NORM) {
                 R n2 = R(0);
 #pragma unroll
@@ -375,16 +425,20 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 // ------------------------------------------------------------- dispatch
 
 template <class SP, class LK, bool NT, int ORD, bool SB, int G>
-void go_w(const HopArgs<SP, LK> &a, bool s, bool n, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
+void go_w(const HopArgs<SP, LK> &a, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
-    if (s && n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, SB, G>), grid, block, lds, st, a);
+    if (ep == EP_CG)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, SB, G, EP_CG>), grid, block, lds, st, a);
+    else if (ep == EP_RES)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, SB, G, EP_RES>), grid, block, lds, st, a);
+    else if (s && n)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, SB, G, EP_STORE>), grid, block, lds, st, a);
     else if (s)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, NT, ORD, SB, G>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, NT, ORD, SB, G, EP_STORE>), grid, block, lds, st, a);
     else if (n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true, NT, ORD, SB, G>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, true, NT, ORD, SB, G, EP_STORE>), grid, block, lds, st, a);
     else
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, NT, ORD, SB, G>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, NT, ORD, SB, G, EP_STORE>), grid, block, lds, st, a);
 }
 
 // ALL = false: only variant 0 is instantiated (rarely used format pairs)
@@ -399,14 +453,23 @@ inline int rhs_group(const Geom &g, int prec, int n)
 }
 
 // ALL = false: only variant 0 with one RHS per lane is instantiated (rarely
-// used format pairs); MULTI = true adds 2 and 4 RHS per lane for batches (the
-// FP32-arithmetic formats; FP64 lanes already use all 256 registers).
+// used format pairs); MULTI = true adds 2 RHS per lane for batches (the
+// FP32-arithmetic formats; FP64 lanes already use all 256 registers; 4 per
+// lane measured slower than 1 and 2).
 template <class SP, class LK, bool ALL, bool MULTI>
 hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
               const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
-              long pstride, const CgScalars *scal, const HopTune &tu, hipStream_t st)
+              long pstride, const CgScalars *scal, const HopTune &tu, hipStream_t st, const CgFields *cg)
 {
     if (rl.n <= 0) return hipSuccess;
+    const int ep = epi == EPI_K2_CG ? EP_CG : epi == EPI_K2_RES ? EP_RES : EP_STORE;
+    if (ep != EP_STORE) {
+        // fused epilogues: the vectors must be given, in the right formats, the
+        // norm asked for, and (for CG) the device scalars holding alpha
+        if (!cg || !partial || (ep == EP_CG && !scal)) return hipErrorInvalidValue;
+        if (cg->r.prec != in.prec || cg->p.prec != in.prec) return hipErrorInvalidValue;
+        if (ep == EP_CG && cg->x.prec != (in.prec == P64 ? P64 : P32)) return hipErrorInvalidValue;
+    }
     HopArgs<SP, LK> a;
     a.g = g;
     a.out_par = out_par;
@@ -425,10 +488,15 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     a.pstride = pstride;
     a.scal = scal;
     a.one = 1.0f;
+    if (ep != EP_STORE) {
+        a.cg_r = make_bv<SP>(cg->r);
+        a.cg_p = make_bv<SP>(cg->p);
+        if (ep == EP_CG) a.cg_x = make_bv<typename XsOf<SP>::type>(cg->x);
+    }
     int variant = tu.variant;
     if (!ALL || !hop_variant_valid(g, variant)) variant = 0;
     int G = MULTI && ALL && rl.n > 1 ? tu.rpl : 1;
-    if (G != 2 && G != 4) G = 1;
+    if (G != 2) G = 1;
     const int ntup = (rl.n + G - 1) / G;
     a.nblk = hop_grid_variant(g, variant);
     const int grp = tu.group > 0 ? tu.group : rhs_group(g, in.prec, rl.n);  // in RHS
@@ -437,13 +505,14 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     dim3 grid(a.nblk * ntup), block(HOP_BLOCK);
     const bool s = epi != EPI_K1, n = partial != nullptr;
     if (s && !self.data) return hipErrorInvalidValue;
+    a.epi = ep == EP_STORE ? epi : EPI_K2;
     const bool nt = rl.n == 1;
     const unsigned lds = tu.lds;
     if (!ALL) {
         if (nt)
-            go_w<SP, LK, true, ORD_PLAIN, false, 1>(a, s, n, grid, block, lds, st);
+            go_w<SP, LK, true, ORD_PLAIN, false, 1>(a, s, n, ep, grid, block, lds, st);
         else
-            go_w<SP, LK, false, ORD_PLAIN, false, 1>(a, s, n, grid, block, lds, st);
+            go_w<SP, LK, false, ORD_PLAIN, false, 1>(a, s, n, ep, grid, block, lds, st);
         return hipGetLastError();
     }
     if (MULTI && G > 1) {
@@ -452,27 +521,22 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
 #define GOM(GG)                                                                                \
     do {                                                                                       \
         if (ord == ORD_ZSLAB)                                                                  \
-            go_w<SP, LK, false, ORD_ZSLAB, false, GG>(a, s, n, grid, block, lds, st);          \
+            go_w<SP, LK, false, ORD_ZSLAB, false, GG>(a, s, n, ep, grid, block, lds, st);          \
         else if (ord == ORD_TSLAB)                                                             \
-            go_w<SP, LK, false, ORD_TSLAB, false, GG>(a, s, n, grid, block, lds, st);          \
+            go_w<SP, LK, false, ORD_TSLAB, false, GG>(a, s, n, ep, grid, block, lds, st);          \
         else                                                                                   \
-            go_w<SP, LK, false, ORD_PLAIN, false, GG>(a, s, n, grid, block, lds, st);          \
+            go_w<SP, LK, false, ORD_PLAIN, false, GG>(a, s, n, ep, grid, block, lds, st);          \
     } while (0)
-        if constexpr (MULTI) {
-            if (G == 2)
-                GOM(2);
-            else
-                GOM(4);
-        }
+        if constexpr (MULTI) GOM(2);
 #undef GOM
         return hipGetLastError();
     }
 #define GOV(ORD, SB)                                                          \
     do {                                                                      \
         if (nt)                                                               \
-            go_w<SP, LK, true, ORD, SB, 1>(a, s, n, grid, block, lds, st);    \
+            go_w<SP, LK, true, ORD, SB, 1>(a, s, n, ep, grid, block, lds, st);    \
         else                                                                  \
-            go_w<SP, LK, false, ORD, SB, 1>(a, s, n, grid, block, lds, st);   \
+            go_w<SP, LK, false, ORD, SB, 1>(a, s, n, ep, grid, block, lds, st);   \
     } while (0)
     switch (variant) {
     case 1: GOV(ORD_ZSLAB, false); break;

@@ -77,7 +77,18 @@ struct OpParams {
 //   EPI_K1   out = kappa^2/(1+mut^2) (1 - sigma i mut g5) acc              (eq. (eo3))
 //   EPI_K2   out = g5 [(1 + sigma i mut g5) self - acc]                    (eq. (eo4))
 //   EPI_FULL out = g5 [(1 + sigma i mut g5) self - kappa acc]              (eq. (eo1))
-enum HopEpi { EPI_K1 = 0, EPI_K2 = 1, EPI_FULL = 2 };
+//   EPI_K2_CG  as EPI_K2, then the CG update with the RHS's alpha (device
+//              scalars): r -= alpha out ; x += alpha p ; norm of the new r; out is
+//              not stored
+//   EPI_K2_RES as EPI_K2, then r = b - out (the true residual) with its norm;
+//              out is not stored
+enum HopEpi { EPI_K1 = 0, EPI_K2 = 1, EPI_FULL = 2, EPI_K2_CG = 3, EPI_K2_RES = 4 };
+
+// Vectors of the fused epilogues: r and p in the hop's spinor format (p is b
+// for EPI_K2_RES), x in FP32 (FP64 for an FP64 hop).
+struct CgFields {
+    FieldDesc r, p, x;
+};
 
 // Device scalars of a CG solve (one struct per right-hand side).
 struct CgScalars {
@@ -120,14 +131,14 @@ int hop_grid_variant(const Geom &g, int v);
 struct HopTune {
     int variant = 0;   // block order (see above)
     int group = 0;     // RHS per L2 group of a batched launch (0: sized from the L2 capacity)
-    int rpl = 1;       // RHS per lane in a batched launch: 1, 2 or 4 (FP32-arithmetic formats)
+    int rpl = 1;       // RHS per lane in a batched launch: 1 or 2 (FP32-arithmetic formats)
     unsigned lds = 0;  // LDS bytes reserved per block (unused by the kernel; a value above
                        // the CU's LDS / (c + 1) caps the blocks resident per CU at c)
 };
 hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
                       const RhsList &rl, double *partial, long pstride, const CgScalars *scal, const HopTune &tu,
-                      hipStream_t st);
+                      hipStream_t st, const CgFields *cg = nullptr);
 
 // Vector kernels over the n sites of each RHS of rl.  Reductions write
 // blas_grid(n) per-block sums at partial[r * pstride + block]; scalars come

@@ -124,7 +124,7 @@ int lattice_create(const int dims[4], int device, Lattice **out)
     }
     if (const char *fr = getenv("TMQ_HOP_RPL")) {
         const int r = atoi(fr);
-        if (r == 1 || r == 2 || r == 4) L->forced_rpl = r;
+        if (r == 1 || r == 2) L->forced_rpl = r;
     }
     if (const char *fc = getenv("TMQ_HOP_CAP")) {
         const int c = atoi(fc);
@@ -372,7 +372,7 @@ static bool multi_rhs_format(int prec, int link_fmt)
     return (prec == P32 && link_fmt == LK32R) || ((prec == P16 || prec == PB16) && link_fmt == LK16R);
 }
 
-// For a batched launch, time the RHS per lane (1, 2, 4 where the format has
+// For a batched launch, time the RHS per lane (1, or 2 where the format has
 // them) and RHS groups (the variant and cap fixed), and keep the fastest for
 // this format and batch size class.  Neither changes any result.
 static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc &in, const FieldDesc &self,
@@ -388,7 +388,7 @@ static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc
     base.variant = L->hop_variant[key];
     base.lds = occ_lds(L, L->hop_occ[key]);
     float best_us = 0.f;
-    const int max_rpl = multi_rhs_format(in.prec, lk.fmt) ? 4 : 1;
+    const int max_rpl = multi_rhs_format(in.prec, lk.fmt) ? 2 : 1;
     for (int rpl = 1; rpl <= max_rpl && rpl <= rl.n; rpl *= 2)
         for (int G = rpl;; G *= 2) {
             if (G > rl.n) G = rl.n;
@@ -466,10 +466,17 @@ std::string tuning_report(const Lattice *L)
 
 int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
         const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
-        const CgScalars *scal, hipStream_t st)
+        const CgScalars *scal, hipStream_t st, const CgFields *cg)
 {
     if (rl.n <= 0) return TMQ_OK;
     const int key = in.prec * 4 + lk.fmt;
+    const bool fused = epi == EPI_K2_CG || epi == EPI_K2_RES;
+    if (fused && L->forced_variant < 0 && L->hop_variant[key] < 0) {
+        // the tuner re-runs its launch, which a fused epilogue must not (it
+        // updates vectors in place); the plain half-sweeps before it tune the format
+        set_error("internal: fused hop epilogue before the format was tuned");
+        return TMQ_ESTATE;
+    }
     if (L->forced_variant >= 0) {
         L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;
         if (L->forced_cap >= 0) L->hop_occ[key] = occ_lds(L, L->forced_cap) == ~0u ? 0 : L->forced_cap;
@@ -489,6 +496,10 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
                 tu = e.tu;
                 found = true;
             }
+        if (!found && fused) {
+            set_error("internal: fused hop epilogue before the batch shape was tuned");
+            return TMQ_ESTATE;
+        }
         if (!found)
             TMQ_TRY(tune_batch(L, key, cls, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st,
                                &tu));
@@ -499,12 +510,19 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
         t.a = pool_event(L);
         t.b = pool_event(L);
         t.bytes = hop_bytes_per_site(in.prec, lk.fmt, epi != EPI_K1, rl.n) * (double)L->g.vh;
+        if (fused) {
+            // the epilogue's own vectors instead of the output: CG reads r, p, x and writes r, x
+            // (the output is not stored); the residual reads b and writes r
+            const double sp = in.prec == P64 ? 192.0 : in.prec == P32 ? 96.0 : 52.0;
+            const double xsp = in.prec == P64 ? 192.0 : 96.0;
+            t.bytes += (epi == EPI_K2_CG ? (sp + 2 * xsp) : sp) * (double)L->g.vh * rl.n;
+        }
         t.flops = 1320.0 * (double)L->g.vh * rl.n;
         t.prec = in.prec;
         t.nrhs = rl.n;
         TMQ_HIP(hipEventRecord(t.a, st));
     }
-    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal, tu, st));
+    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal, tu, st, cg));
     L->hop_blocks_last = hop_grid_variant(L->g, L->hop_variant[key]);
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));
@@ -520,6 +538,29 @@ int apply_Qhat(Lattice *L, const OpParams &op, int sign, const FieldDesc &in, co
     const FieldDesc none{};
     TMQ_TRY(hop(L, 0, in, none, tmp_e, lk, op, EPI_K1, sign, rl, nullptr, scal, st));
     TMQ_TRY(hop(L, 1, tmp_e, in, out, lk, op, EPI_K2, sign, rl, partial, scal, st));
+    return TMQ_OK;
+}
+
+int apply_Qhat_cg(Lattice *L, const OpParams &op, const FieldDesc &in, const FieldDesc &tmp_e, const LinkDesc &lk,
+                  const RhsList &rl, const CgFields &cg, double *partial, const CgScalars *scal, hipStream_t st)
+{
+    const FieldDesc none{};
+    TMQ_TRY(hop(L, 0, in, none, tmp_e, lk, op, EPI_K1, +1, rl, nullptr, scal, st));
+    TMQ_TRY(hop(L, 1, tmp_e, in, none, lk, op, EPI_K2_CG, +1, rl, partial, scal, st, &cg));
+    return TMQ_OK;
+}
+
+int residual_QhatQhat(Lattice *L, const OpParams &op, const FieldDesc &x, const FieldDesc &b, const FieldDesc &r,
+                      const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, const RhsList &rl,
+                      double *partial, hipStream_t st)
+{
+    const FieldDesc none{};
+    CgFields cg;
+    cg.r = r;
+    cg.p = b;
+    TMQ_TRY(apply_Qhat(L, op, -1, x, tmp_o, tmp_e, lk, rl, nullptr, nullptr, st));
+    TMQ_TRY(hop(L, 0, tmp_o, none, tmp_e, lk, op, EPI_K1, +1, rl, nullptr, nullptr, st));
+    TMQ_TRY(hop(L, 1, tmp_e, tmp_o, none, lk, op, EPI_K2_RES, +1, rl, partial, nullptr, st, &cg));
     return TMQ_OK;
 }
 

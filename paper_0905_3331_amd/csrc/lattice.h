@@ -128,12 +128,20 @@ OpParams make_op(const Lattice *L, const tmq_params *p, int n);
 // one hop half-sweep through the autotuner and the timing hook
 int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
         const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
-        const CgScalars *scal, hipStream_t st);
+        const CgScalars *scal, hipStream_t st, const CgFields *cg = nullptr);
 
 // Qhat^{sign} in -> out (odd fields), tmp_e an even work field; partial: |out|^2 per block
 int apply_Qhat(Lattice *L, const OpParams &op, int sign, const FieldDesc &in, const FieldDesc &out,
                const FieldDesc &tmp_e, const LinkDesc &lk, const RhsList &rl, double *partial,
                const CgScalars *scal, hipStream_t st);
+// Qhat^+ applied to in (odd), fused with the CG update of the vectors of cg
+// (r -= alpha Qhat^+ in ; x += alpha p, alpha from scal); partial: |r|^2 per block
+int apply_Qhat_cg(Lattice *L, const OpParams &op, const FieldDesc &in, const FieldDesc &tmp_e, const LinkDesc &lk,
+                  const RhsList &rl, const CgFields &cg, double *partial, const CgScalars *scal, hipStream_t st);
+// r = b - Qhat^+ Qhat^- x (FP64 or any one format) with |r|^2 per block in partial
+int residual_QhatQhat(Lattice *L, const OpParams &op, const FieldDesc &x, const FieldDesc &b, const FieldDesc &r,
+                      const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, const RhsList &rl,
+                      double *partial, hipStream_t st);
 // Qhat^+ Qhat^- in -> out; partial receives |Qhat^- in|^2 per block
 int apply_QhatQhat(Lattice *L, const OpParams &op, const FieldDesc &in, const FieldDesc &out,
                    const FieldDesc &tmp_e, const FieldDesc &tmp_o, const LinkDesc &lk, const RhsList &rl,

@@ -299,10 +299,10 @@ def test_batch_equals_alone(tmq, sloppy):
         assert infos[i].status == 0 and res <= 1e-10, (i, res)
 
 
-@pytest.mark.parametrize("rpl", [1, 2, 4])
+@pytest.mark.parametrize("rpl", [1, 2])
 @pytest.mark.parametrize("sloppy", ["fp32", "fp16", "bf16"])
 def test_batch_rhs_per_lane(tmq, sloppy, rpl, monkeypatch):
-    """Batched hops with 1, 2 or 4 right-hand sides per lane (the link read
+    """Batched hops with 1 or 2 right-hand sides per lane (the link read
     once per lane for all of them): 7 RHS (a ragged last tuple), each equal bit
     for bit to its solve alone and converged by the oracle's residual."""
     monkeypatch.setenv("TMQ_HOP_RPL", str(rpl))
