@@ -186,6 +186,25 @@ int tmq_solve_batch_dev(tmq_lattice *lat, int nrhs, const tmq_params *p, const t
 int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts,
                        const double *b, double *x, void *stream, tmq_solve_info *info);
 
+/* Solve M^{sign} psi = phi on the full lattice (eq. (eo0), sign = +1 or -1)
+ * with the even/odd factorisation of App. B ("Inversion"):
+ *   phi'_e = (M_ee)^-1 phi_e,  phi'_o = phi_o - M_oe (M_ee)^-1 phi_e,
+ *   psi_o = (M_oo - M_oe (M_ee)^-1 M_eo)^-1 phi'_o,
+ *   psi_e = phi'_e - (M_ee)^-1 M_eo psi_o,
+ * where the odd-site operator is gamma_5 Qhat^{sign}, inverted by the CG of
+ * tmq_solve on Qhat^+ Qhat^- (options as there, mixed precision included):
+ * psi_o = Qhat^- A^-1 g5 phi'_o (sign +1) or A^-1 Qhat^+ g5 phi'_o (sign -1).
+ * The residual phi - M psi is then recomputed in FP64 on the full lattice and,
+ * while it is above opts->tol (relative to |phi| or absolute), the same steps
+ * solve for the correction (at most 4 rounds).  info->true_rel_residual is that
+ * full-lattice residual, info->iters the CG iterations of all rounds.
+ * Full-lattice canonical spinors; phi and psi must not overlap.  TMQ_ENOCONV if
+ * the tolerance is not reached. */
+int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts,
+                const double *phi, double *psi, tmq_solve_info *info);
+int tmq_solve_M_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts,
+                    const double *phi, double *psi, void *stream, tmq_solve_info *info);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A solve server: a stream of independent even/odd solves (each a request

@@ -14,6 +14,8 @@ int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o
                 double *const *x, hipStream_t st, tmq_solve_info *info);
 int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
                hipStream_t st, tmq_solve_info *info);
+int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const double2 *phi, double2 *psi,
+            hipStream_t st, tmq_solve_info *info);
 }  // namespace tmq
 
 using namespace tmq;
@@ -342,6 +344,45 @@ int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_o
     if (s == TMQ_OK || s == TMQ_ENOCONV) {
         TMQ_HIP(launch_full_to_canonical(L->g, fx, (double2 *)x, st));
         TMQ_HIP(hipStreamSynchronize(st));
+    }
+    return s;
+}
+
+int tmq_solve_M_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts, const double *phi,
+                    double *psi, void *stream, tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_sign(sign));
+    TMQ_TRY(check_opts(opts));
+    TMQ_TRY(check_ptrs(phi, psi));
+    if (phi == psi) {
+        set_error("tmq_solve_M: phi and psi must not overlap");
+        return TMQ_EINVAL;
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    return solve_M(L, *p, sign, *opts, (const double2 *)phi, (double2 *)psi, (hipStream_t)stream, info);
+}
+
+int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts, const double *phi,
+                double *psi, tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_ptrs(phi, psi));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const size_t bytes = (size_t)2 * L->g.vh * 12 * sizeof(double2);
+    void *dphi = nullptr, *dpsi = nullptr;
+    TMQ_TRY(stage_buffer(L, 0, bytes, &dphi));
+    TMQ_TRY(stage_buffer(L, 1, bytes, &dpsi));
+    TMQ_HIP(hipMemcpyAsync(dphi, phi, bytes, hipMemcpyHostToDevice, L->own));
+    const int s = tmq_solve_M_dev(lat, p, sign, opts, (const double *)dphi, (double *)dpsi, L->own, info);
+    if (s == TMQ_OK || s == TMQ_ENOCONV) {
+        TMQ_HIP(hipMemcpyAsync(psi, dpsi, bytes, hipMemcpyDeviceToHost, L->own));
+        TMQ_HIP(hipStreamSynchronize(L->own));
     }
     return s;
 }

@@ -127,6 +127,28 @@ __global__ __launch_bounds__(BLAS_BLOCK) void k_axpy_norm(BatchView<FX> x, Batch
     WRITE_PARTIAL(partial, pstride, part)
 }
 
+// out = cu * in on spins 0, 1 and cd * in on spins 2, 3 (a site-local
+// a + i b gamma_5, FP64)
+__global__ __launch_bounds__(BLAS_BLOCK) void k_twist(BatchView<SpF64> in, BatchView<SpF64> out, long n, RhsList rl,
+                                                      double2 cu, double2 cd)
+{
+    BLOCK_RHS(rl);
+    const long h = (long)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (h < n) {
+        spinor<double> s;
+        in.at(rhs).load(h, s);
+        const cx<double> u = {cu.x, cu.y}, d = {cd.x, cd.y};
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            s.c[0][c] = u * s.c[0][c];
+            s.c[1][c] = u * s.c[1][c];
+            s.c[2][c] = d * s.c[2][c];
+            s.c[3][c] = d * s.c[3][c];
+        }
+        out.at(rhs).store(h, s);
+    }
+}
+
 // p = r + beta p
 template <class F>
 __global__ __launch_bounds__(BLAS_BLOCK) void k_xpay(BatchView<F> r, BatchView<F> p, long n, RhsList rl,
@@ -302,6 +324,14 @@ hipError_t launch_norm2(const FieldDesc &v, const RhsList &rl, double *partial, 
 hipError_t launch_zero(const FieldDesc &v, const RhsList &rl, hipStream_t st)
 {
     DISPATCH_SP(v.prec, F, LAUNCH(k_zero<F>, v.n, rl, st, make_bv<F>(v), v.n, rl));
+    return hipGetLastError();
+}
+
+hipError_t launch_twist(const FieldDesc &in, const FieldDesc &out, const RhsList &rl, double2 cu, double2 cd,
+                        hipStream_t st)
+{
+    if (in.prec != P64 || out.prec != P64 || in.n != out.n) return hipErrorInvalidValue;
+    LAUNCH(k_twist, in.n, rl, st, make_bv<SpF64>(in), make_bv<SpF64>(out), in.n, rl, cu, cd);
     return hipGetLastError();
 }
 

@@ -337,6 +337,15 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
                 Au = Ad = cx<R>{R(0), R(0)};
                 Bu = cx<R>{(R)c, (R)(-c * m)};
                 Bd = cx<R>{(R)c, (R)(c * m)};
+            } else if (a.epi == EPI_SRC) {
+                Au = Ad = cx<R>{R(1), R(0)};
+                Bu = Bd = cx<R>{(R)kap, R(0)};
+            } else if (a.epi == EPI_REC) {
+                const double c = 1.0 / (1.0 + m * m);
+                Au = cx<R>{(R)c, (R)(-c * m)};
+                Ad = cx<R>{(R)c, (R)(c * m)};
+                Bu = cx<R>{(R)(kap * c), (R)(-kap * c * m)};
+                Bd = cx<R>{(R)(kap * c), (R)(kap * c * m)};
             } else {
                 const double b = a.epi == EPI_FULL ? kap : 1.0;
                 Au = cx<R>{R(1), (R)m};

@@ -77,12 +77,14 @@ struct OpParams {
 //   EPI_K1   out = kappa^2/(1+mut^2) (1 - sigma i mut g5) acc              (eq. (eo3))
 //   EPI_K2   out = g5 [(1 + sigma i mut g5) self - acc]                    (eq. (eo4))
 //   EPI_FULL out = g5 [(1 + sigma i mut g5) self - kappa acc]              (eq. (eo1))
+//   EPI_SRC  out = self + kappa acc                                       (even/odd source, App. B)
+//   EPI_REC  out = (1 - sigma i mut g5)/(1+mut^2) (self + kappa acc)      (even-site solution, App. B)
 //   EPI_K2_CG  as EPI_K2, then the CG update with the RHS's alpha (device
 //              scalars): r -= alpha out ; x += alpha p ; norm of the new r; out is
 //              not stored
 //   EPI_K2_RES as EPI_K2, then r = b - out (the true residual) with its norm;
 //              out is not stored
-enum HopEpi { EPI_K1 = 0, EPI_K2 = 1, EPI_FULL = 2, EPI_K2_CG = 3, EPI_K2_RES = 4 };
+enum HopEpi { EPI_K1 = 0, EPI_K2 = 1, EPI_FULL = 2, EPI_K2_CG = 3, EPI_K2_RES = 4, EPI_SRC = 5, EPI_REC = 6 };
 
 // Vectors of the fused epilogues: r and p in the hop's spinor format (p is b
 // for EPI_K2_RES), x in FP32 (FP64 for an FP64 hop).
@@ -156,6 +158,9 @@ hipError_t launch_xpay(const FieldDesc &r, const FieldDesc &p, const RhsList &rl
 // r = b - ax (FP64), partial |r|^2
 hipError_t launch_residual(const FieldDesc &b, const FieldDesc &ax, const FieldDesc &r, const RhsList &rl,
                            double *partial, long pstride, hipStream_t st);
+// out = cu in (spins 0, 1), cd in (spins 2, 3); FP64 fields
+hipError_t launch_twist(const FieldDesc &in, const FieldDesc &out, const RhsList &rl, double2 cu, double2 cd,
+                        hipStream_t st);
 // x64 += xs ; xs = 0
 hipError_t launch_accumulate(const FieldDesc &x64, const FieldDesc &xs, const RhsList &rl, hipStream_t st);
 

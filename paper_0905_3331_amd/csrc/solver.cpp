@@ -79,6 +79,125 @@ int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o
     return status;
 }
 
+// ------------------------------------------- M psi = phi through even/odd
+
+// |v|^2 of a one-RHS FP64 field, summed on the host in a fixed order
+static int field_norm2(Lattice *L, const FieldDesc &v, hipStream_t st, double *out)
+{
+    const int nb = blas_grid(v.n);
+    TMQ_HIP(launch_norm2(v, rhs_all(1), L->partial[2], L->pstride, st));
+    std::vector<double> part(nb);
+    TMQ_HIP(hipMemcpyAsync(part.data(), L->partial[2], sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    TMQ_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double x : part) s += x;
+    *out = s;
+    return TMQ_OK;
+}
+
+// Solve M^{sign} psi = phi (full lattice, canonical device buffers) with the
+// even/odd factorisation of the inversion in App. B:
+//   phi'_e = (M_ee)^-1 phi_e,  phi'_o = phi_o - M_oe (M_ee)^-1 phi_e,
+//   psi_o  = (M_oo - M_oe (M_ee)^-1 M_eo)^-1 phi'_o,
+//   psi_e  = phi'_e - (M_ee)^-1 M_eo psi_o = (M_ee)^-1 (phi_e + kappa H_eo psi_o),
+// with M_ee = 1 + sign i mut g5, M_eo = -kappa H_eo, M_oe = -kappa H_oe.  The
+// Schur complement is g5 Qhat^{sign} (eq. (eo4)), so psi_o solves
+// Qhat^{sign} psi_o = g5 phi'_o: psi_o = Qhat^- A^-1 g5 phi'_o for sign +1
+// and psi_o = A^-1 Qhat^+ g5 phi'_o for sign -1, A = Qhat^+ Qhat^- by CG.
+// The residual phi - M psi is recomputed in FP64 on the full lattice; while
+// it is above the tolerance the same steps solve for the correction.
+int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const double2 *phi, double2 *psi,
+            hipStream_t st, tmq_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const long vh = L->g.vh, n = 2 * vh;
+    FieldDesc fphi, fpsi, fr, fd, fq, fg, te, to, wo, yo, bc, yc;
+    TMQ_TRY(work_field(L, "m_phi", P64, n, &fphi));  // g5 phi
+    TMQ_TRY(work_field(L, "m_psi", P64, n, &fpsi));
+    TMQ_TRY(work_field(L, "m_r", P64, n, &fr));      // source of the round (the residual)
+    TMQ_TRY(work_field(L, "m_d", P64, n, &fd));      // solution of the round
+    TMQ_TRY(work_field(L, "m_q", P64, n, &fq));
+    TMQ_TRY(work_field(L, "m_g", P64, n, &fg));
+    TMQ_TRY(work_field(L, "m_te", P64, vh, &te));
+    TMQ_TRY(work_field(L, "m_to", P64, vh, &to));
+    TMQ_TRY(work_field(L, "m_wo", P64, vh, &wo));
+    TMQ_TRY(work_field(L, "m_yo", P64, vh, &yo));
+    TMQ_TRY(work_field(L, "m_bc", P64, vh, &bc));  // canonical odd buffers (same size)
+    TMQ_TRY(work_field(L, "m_yc", P64, vh, &yc));
+    const OpParams op = make_op(L, &p, 1);
+    const RhsList one = rhs_all(1);
+    const LinkDesc lk = lattice_links(L, link_fmt_for(L, P64, P64));
+    const double m = sign * p.mu_tilde, c = 1.0 / (1.0 + m * m);
+    const double2 mee_u = make_double2(c, -c * m), mee_d = make_double2(c, c * m);  // (M_ee)^-1
+    const double2 g5_u = make_double2(1.0, 0.0), g5_d = make_double2(-1.0, 0.0);
+    const int max_rounds = 4;
+
+    TMQ_HIP(launch_full_from_canonical(L->g, phi, fr, st));
+    TMQ_HIP(launch_twist(fr, fphi, one, g5_u, g5_d, st));
+    TMQ_HIP(launch_zero(fpsi, one, st));
+    double bb = 0.0, rr = 0.0;
+    TMQ_TRY(field_norm2(L, fr, st, &bb));
+    const double target = o.relative ? o.tol * o.tol * bb : o.tol * o.tol;
+    int status = TMQ_OK, iters = 0, rus = 0, rounds = 0;
+    rr = bb;
+    while (rr > target && bb > 0.0 && rounds < max_rounds) {
+        rounds++;
+        const FieldDesc re = field_sub(fr, 0, vh), ro = field_sub(fr, vh, vh);
+        const FieldDesc de = field_sub(fd, 0, vh), dd = field_sub(fd, vh, vh);
+        // phi'_o = r_o + kappa H_oe (M_ee)^-1 r_e
+        TMQ_HIP(launch_twist(re, te, one, mee_u, mee_d, st));
+        TMQ_TRY(hop(L, 1, te, ro, wo, lk, op, EPI_SRC, sign, one, nullptr, nullptr, st));
+        // odd system: Qhat^{sign} d_o = g5 phi'_o
+        TMQ_HIP(launch_twist(wo, to, one, g5_u, g5_d, st));
+        if (sign < 0) {
+            TMQ_TRY(apply_Qhat(L, op, +1, to, wo, te, lk, one, nullptr, nullptr, st));
+            TMQ_HIP(launch_to_canonical(wo, (double2 *)bc.data, st));
+        } else {
+            TMQ_HIP(launch_to_canonical(to, (double2 *)bc.data, st));
+        }
+        tmq_solve_info ci{};
+        const double *bp = (const double *)bc.data;
+        double *yp = (double *)yc.data;
+        const int cs = solve_batch(L, 1, &p, o, &bp, &yp, st, &ci);
+        iters += ci.iters;
+        rus += ci.reliable_updates;
+        if (cs == TMQ_ENAN) {
+            status = TMQ_ENAN;
+            break;
+        }
+        if (cs != TMQ_OK && cs != TMQ_ENOCONV) return cs;
+        if (cs == TMQ_ENOCONV) status = TMQ_ENOCONV;
+        TMQ_HIP(launch_from_canonical((const double2 *)yc.data, yo, st));
+        if (sign > 0)
+            TMQ_TRY(apply_Qhat(L, op, -1, yo, dd, te, lk, one, nullptr, nullptr, st));
+        else
+            TMQ_HIP(launch_convert(yo, dd, one, st));
+        // d_e = (M_ee)^-1 (r_e + kappa H_eo d_o) ; psi += d
+        TMQ_TRY(hop(L, 0, dd, re, de, lk, op, EPI_REC, sign, one, nullptr, nullptr, st));
+        TMQ_HIP(launch_accumulate(fpsi, fd, one, st));
+        // r = phi - M psi = g5 (g5 phi - Q psi)
+        TMQ_TRY(apply_Q_full(L, op, sign, fpsi, fq, lk, one, st));
+        TMQ_HIP(launch_residual(fphi, fq, fg, one, L->partial[2], L->pstride, st));
+        TMQ_HIP(launch_twist(fg, fr, one, g5_u, g5_d, st));
+        TMQ_TRY(field_norm2(L, fr, st, &rr));
+        if (status == TMQ_ENOCONV) break;
+    }
+    if (!std::isfinite(rr)) status = TMQ_ENAN;
+    if (status == TMQ_OK && rr > target) status = TMQ_ENOCONV;
+    TMQ_HIP(launch_full_to_canonical(L->g, fpsi, psi, st));
+    TMQ_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->status = status;
+        info->iters = iters;
+        info->reliable_updates = rus;
+        info->true_rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status == TMQ_ENAN) set_error("tmq_solve_M: non-finite value");
+    if (status == TMQ_ENOCONV) set_error("tmq_solve_M: tolerance not reached");
+    return status;
+}
+
 // ------------------------------------------------------ full lattice CG
 
 static int read_scalars(Lattice *L, int n, hipStream_t st, std::vector<CgScalars> &out)

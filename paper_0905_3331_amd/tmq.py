@@ -85,6 +85,8 @@ _SIGS = {
     "tmq_solve_batch_dev": (_ip, [_vp, _ip, _P(tmq_params), _P(tmq_solver_opts), _P(_vp), _P(_vp), _vp,
                                   _P(tmq_solve_info)]),
     "tmq_solve_full_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_solve_M": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_solve_M_dev": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
     "tmq_set_kernel_timing": (_ip, [_vp, _ip]),
     "tmq_kernel_stats": (_ip, [_vp, ctypes.c_char_p, _P(ctypes.c_int), _P(ctypes.c_double),
                                _P(ctypes.c_double), _P(ctypes.c_double)]),
@@ -349,6 +351,25 @@ class Lattice:
         if check:
             _check(code, "tmq_solve_full")
         return x, _info(info)
+
+    def solve_M(self, p: tmq_params, sign: int, phi, opts: tmq_solver_opts, psi=None, stream=None, check=True):
+        """Solve M^{sign} psi = phi on the full lattice through the even/odd
+        factorisation; phi: (V, 4, 3) device tensor or host array; returns (psi, SolveInfo)."""
+        n = self.V * 12
+        info = tmq_solve_info()
+        if isinstance(phi, np.ndarray):
+            psi = np.empty_like(phi) if psi is None else psi
+            code = _lib.tmq_solve_M(self._h, ctypes.byref(p), sign, ctypes.byref(opts), _hptr(phi, n, "phi"),
+                                    _hptr(psi, n, "psi"), ctypes.byref(info))
+        else:
+            import torch
+
+            psi = torch.empty_like(phi) if psi is None else psi
+            code = _lib.tmq_solve_M_dev(self._h, ctypes.byref(p), sign, ctypes.byref(opts), _dptr(phi, n, "phi"),
+                                        _dptr(psi, n, "psi"), _stream(stream), ctypes.byref(info))
+        if check:
+            _check(code, "tmq_solve_M")
+        return psi, _info(info)
 
     # ---------------------------------------------------------- diagnostics
     def set_kernel_timing(self, on: bool):

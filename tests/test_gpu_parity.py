@@ -350,3 +350,50 @@ def test_point_source_16bit_far_decay(tmq, sloppy):
     x, info = lat.solve(p, dev(b), tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp16"))
     assert info.status == 0, info
     assert oracle.true_residual(U, b, host(x), 0.1632, 0.004, THETA) <= 1e-10
+
+
+# ------------------------------------------ full-lattice M through even/odd
+
+@pytest.mark.parametrize("sign", [+1, -1])
+@pytest.mark.parametrize("sloppy", ["fp64", "fp32"])
+def test_solve_M_against_dense(tmq, sign, sloppy):
+    """M^{sign} psi = phi by the even/odd inversion of App. B on 4x2^3 equals
+    the dense solve of the matrix assembled from eq. (eo0) (tests/dense.py)."""
+    import dense
+
+    dims = (4, 2, 2, 2)
+    U = synth.random_gauge(dims, seed=110)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(U)
+    phi = synth.gaussian_spinor(dims + (4, 3), seed=50)
+    p = tmq.params(0.16, 0.03, THETA_GEN)
+    psi, info = lat.solve_M(p, sign, dev(phi.reshape(-1, 4, 3)),
+                            tmq.solver_opts(tol=1e-12, sloppy=sloppy, sloppy_link="fp32"))
+    Md = dense.M_hopping(U, 0.16, 0.03, sign, THETA_GEN)
+    want = np.linalg.solve(Md, phi.reshape(-1))
+    assert info.status == 0, info
+    assert rel(host(psi).reshape(-1), want) < 1e-9
+    lat.close()
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+@pytest.mark.parametrize("sloppy", ["fp64", "fp16"])
+def test_solve_M_oracle_residual(tmq, sign, sloppy):
+    """Full-lattice residual |phi - M psi| / |phi| by the oracle's M meets the
+    tolerance and agrees with the residual the library reports."""
+    dims = (8, 4, 4, 6)
+    lat, U = lattice(tmq, dims, seed=111)
+    phi = synth.gaussian_spinor(dims + (4, 3), seed=51)
+    p = tmq.params(0.1632, 0.004, THETA)
+    psi, info = lat.solve_M(p, sign, dev(phi.reshape(-1, 4, 3)),
+                            tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp16"))
+    r = phi - oracle.M(U, host(psi).reshape(phi.shape), 0.1632, 0.004, sign, THETA)
+    res = float(np.linalg.norm(r) / np.linalg.norm(phi))
+    print(f"solve_M sign {sign} {sloppy}: iters {info.iters} res {res:.2e} (gpu {info.true_rel_residual:.2e})")
+    assert info.status == 0 and res <= 1e-10
+    assert abs(res - info.true_rel_residual) <= 1e-3 * res + 1e-16
+    # host-pointer form gives the same solution
+    psi_h, info_h = lat.solve_M(p, sign, phi.reshape(-1, 4, 3).copy(),
+                                tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp16"))
+    assert np.array_equal(psi_h, host(psi))
+
