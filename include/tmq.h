@@ -92,7 +92,17 @@ typedef struct {
     double delta;        /* mixed precision: recompute the FP64 true residual whenever the
                             iterated residual fell by this factor (0 < delta < 1); <= 0: default
                             (1e-4 for FP32, 0.02 for FP16, 0.05 for BF16 storage) */
+    int mode;            /* TMQ_MODE_RELIABLE (0, default): the inner CG runs entirely in the
+                            reduced precision with FP64 reliable updates (above).
+                            TMQ_MODE_SWITCH (1): the paper's reduced-precision CG (Sec. 4.4):
+                            FP64 vectors throughout, the FP64 operator until the relative
+                            residual is below sqrt(tol), the reduced-precision operator (storage
+                            `sloppy`, links `sloppy_link`) after that; convergence is still
+                            declared on the FP64 true residual */
 } tmq_solver_opts;
+
+#define TMQ_MODE_RELIABLE 0
+#define TMQ_MODE_SWITCH 1
 
 typedef struct {
     int status;               /* same value the call returned */

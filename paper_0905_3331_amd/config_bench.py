@@ -87,7 +87,9 @@ def eo_24c48(tmq, torch, synth, reps):
     out = {"lattice": "24^3x48", "hop": hop_rates(tmq, torch, synth, lat, dims)}
     for name, opts in (("fp64", tmq.solver_opts(tol=1e-10)),
                        ("fp32_inner", tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")),
-                       ("fp16_inner", tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16"))):
+                       ("fp16_inner", tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")),
+                       ("fp32_switch_paper", tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32",
+                                                             mode="switch"))):
         times, iters, rus, res = [], [], [], []
         for k in range(5):
             b = torch.from_numpy(synth.gaussian_odd(dims, seed=2100 + k)).cuda()

@@ -533,7 +533,7 @@ int tmq_footprint_bytes(const int dims[4], const tmq_solver_opts *opts, int nrhs
     // gauge copies: FP64 full + FP64, FP32, FP16 two-row, both parities, 4 directions
     size_t g = (size_t)8 * vh * (9 * 16 + 6 * 16 + 3 * 16 + 24);
     // work fields of one right-hand side in a CG engine
-    const size_t per = engine_slot_bytes(vh, opts ? opts->sloppy : TMQ_FP64);
+    const size_t per = engine_slot_bytes(vh, opts ? opts->sloppy : TMQ_FP64, opts ? opts->mode : 0);
     *out = g + per * (size_t)nrhs;
     return TMQ_OK;
 }

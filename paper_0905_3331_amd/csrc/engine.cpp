@@ -17,8 +17,11 @@
 
 namespace tmq {
 
-size_t engine_slot_bytes(long vh, int sloppy)
+size_t engine_slot_bytes(long vh, int sloppy, int mode)
 {
+    // switch mode: b, x, r, t_e, t_o, p, A p in FP64 and p, A p, t_e, t_o reduced
+    if (mode == TMQ_MODE_SWITCH)
+        return 7 * field_bytes(P64, vh) + (sloppy == P64 ? 0 : 4 * field_bytes(sloppy, vh));
     // FP64: b, x, r, t_e, t_o, p ; mixed: b, x, r, t_e, t_o in FP64, four inner
     // vectors (r, p, t_e, t_o) and the FP32 x_s (A p never reaches memory: the
     // CG update is fused into the half-sweep that forms it)
@@ -26,9 +29,9 @@ size_t engine_slot_bytes(long vh, int sloppy)
     return 5 * field_bytes(P64, vh) + 4 * field_bytes(sloppy, vh) + field_bytes(P32, vh);
 }
 
-size_t engine_bytes(const Lattice *L, int sloppy, int cap)
+size_t engine_bytes(const Lattice *L, int sloppy, int cap, int mode)
 {
-    return (size_t)cap * engine_slot_bytes(L->g.vh, sloppy) + (size_t)cap * 3 * L->pstride * sizeof(double) +
+    return (size_t)cap * engine_slot_bytes(L->g.vh, sloppy, mode) + (size_t)cap * 3 * L->pstride * sizeof(double) +
            (size_t)cap * sizeof(CgScalars);
 }
 
@@ -51,7 +54,7 @@ Engine::~Engine()
     if (ring) hipHostFree(ring);
 }
 
-int engine_create(Lattice *L, int sloppy, int sloppy_link, int cap, hipStream_t st, Engine **out)
+int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hipStream_t st, Engine **out)
 {
     if (cap < 1 || cap > MAX_RHS) {
         set_error("engine: capacity must be 1..64");
@@ -67,7 +70,9 @@ int engine_create(Lattice *L, int sloppy, int sloppy_link, int cap, hipStream_t 
     E->sloppy_link = sloppy_link;
     E->st = st;
     E->cap = cap;
-    E->mixed = sloppy != P64;
+    E->mode = mode;
+    E->mixed = sloppy != P64 && mode == TMQ_MODE_RELIABLE;
+    E->switching = sloppy != P64 && mode == TMQ_MODE_SWITCH;
     const long vh = L->g.vh;
     E->fields.reserve(16);
     auto field = [&](int prec, FieldDesc *d) -> int {
@@ -92,6 +97,12 @@ int engine_create(Lattice *L, int sloppy, int sloppy_link, int cap, hipStream_t 
         E->tes = E->te64;
         E->tos = E->to64;
         if ((s = field(P64, &E->ps)) != TMQ_OK) return fail(s);
+        if (E->switching) {
+            E->lks = lattice_links(L, link_fmt_for(L, sloppy, sloppy_link));
+            if ((s = field(P64, &E->ap64)) != TMQ_OK) return fail(s);
+            for (FieldDesc *d : {&E->pss, &E->apss, &E->tes, &E->tos})
+                if ((s = field(sloppy, d)) != TMQ_OK) return fail(s);
+        }
     }
     for (auto &p : E->partial)
         if (hipMalloc((void **)&p, sizeof(double) * L->pstride * cap) != hipSuccess) {
@@ -126,7 +137,7 @@ int engine_create(Lattice *L, int sloppy, int sloppy_link, int cap, hipStream_t 
             return fail(TMQ_EDEVICE);
         }
     E->slots.assign(cap, Engine::Slot{});
-    E->bytes = engine_bytes(L, sloppy, cap);
+    E->bytes = engine_bytes(L, sloppy, cap, mode);
     *out = E;
     return TMQ_OK;
 }
@@ -217,15 +228,51 @@ static std::vector<int> body_slots(const Engine *E)
     return r;
 }
 
+// switch mode, slots on the reduced-precision operator: the FP64 p is
+// converted down, A p = Qhat^+ Qhat^- p applied in reduced precision and
+// converted back, then the CG update in FP64
+static int body_switched(Engine *E, const RhsList &al, CgScalars *pub)
+{
+    Lattice *L = E->L;
+    hipStream_t st = E->st;
+    CgScalars *S = E->scal;
+    TMQ_HIP(launch_convert(E->ps, E->pss, al, st));
+    TMQ_TRY(apply_Qhat(L, E->op, -1, E->pss, E->tos, E->tes, E->lks, al, E->partial[0], S, st));
+    TMQ_HIP(launch_scalar(SC_ALPHA, al, E->partial[0], L->pstride, L->hop_blocks_last, S, 0, 0, true, nullptr, st));
+    TMQ_TRY(apply_Qhat(L, E->op, +1, E->tos, E->apss, E->tes, E->lks, al, nullptr, S, st));
+    TMQ_HIP(launch_convert(E->apss, E->ap64, al, st));
+    TMQ_HIP(launch_axpy_norm(E->x, E->ps, E->r64, E->ap64, al, S, E->partial[1], L->pstride, true, st));
+    TMQ_HIP(launch_scalar(SC_BETA, al, E->partial[1], L->pstride, blas_grid(L->g.vh), S, 0, 0, true, pub, st));
+    return TMQ_OK;
+}
+
 int engine_begin_step(Engine *E)
 {
     if (E->body_pending) return TMQ_OK;
     Lattice *L = E->L;
-    const RhsList al = list_of(body_slots(E));
+    std::vector<int> all = body_slots(E), sw;
+    if (E->switching) {
+        std::vector<int> keep;
+        for (int r : all) (E->slots[r].switched ? sw : keep).push_back(r);
+        all.swap(keep);
+    }
+    const RhsList al = list_of(all);
     hipStream_t st = E->st;
     CgScalars *S = E->scal;
     CgScalars *pub = E->ring_dev + (size_t)(E->step_no % Lattice::RING) * E->cap;
-    if (al.n > 0) {
+    if (!sw.empty()) TMQ_TRY(body_switched(E, list_of(sw), pub));
+    if (al.n > 0 && E->switching) {
+        // switch mode, slots still on the FP64 operator
+        TMQ_TRY(apply_Qhat(L, E->op, -1, E->ps, E->to64, E->te64, E->lk64, al, E->partial[0], S, st));
+        TMQ_HIP(launch_scalar(SC_ALPHA, al, E->partial[0], L->pstride, L->hop_blocks_last, S, 0, 0, true, nullptr,
+                              st));
+        CgFields cg;
+        cg.r = E->r64;
+        cg.p = E->ps;
+        cg.x = E->x;
+        TMQ_TRY(apply_Qhat_cg(L, E->op, E->to64, E->te64, E->lk64, al, cg, E->partial[1], S, st));
+        TMQ_HIP(launch_scalar(SC_BETA, al, E->partial[1], L->pstride, L->hop_blocks_last, S, 0, 0, true, pub, st));
+    } else if (al.n > 0) {
         // t = Qhat^- p, <p, A p> = |t|^2 ; A p = Qhat^+ t
         TMQ_TRY(apply_Qhat(L, E->op, -1, E->ps, E->tos, E->tes, E->lks, al, E->partial[0], S, st));
         TMQ_HIP(launch_scalar(SC_ALPHA, al, E->partial[0], L->pstride, L->hop_blocks_last, S, 0, 0, true, nullptr,
@@ -306,6 +353,8 @@ int engine_end_step(Engine *E, std::vector<int> *finished)
             }
             if (pv.last_true || pv.rr > sl.maxr2) sl.maxr2 = pv.rr;
             if (E->mixed && pv.rr < sl.delta * sl.delta * sl.maxr2) ru.push_back(r);
+            // switch mode: the reduced-precision operator once |r| / |b| < sqrt(tol)
+            if (E->switching && !sl.switched && pv.rr < sl.tol * (sl.relative ? pv.bb : 1.0)) sl.switched = true;
         }
     }
     // reliable updates after this step's body publish to the same ring entry

@@ -23,6 +23,13 @@
 //   below delta^2 times the largest since the last true one -> reliable
 //   update.  At k = max_iter a solution that has no true residual yet gets
 //   one, and the slot finishes one step later (ENOCONV unless converged).
+//
+// Switch mode (the paper's reduced-precision CG, Sec. 4.4): the vectors stay
+// in FP64 and a slot's operator is FP64 until its iterated residual is below
+// sqrt(tol) relative (rr < tol * bb), then the reduced-precision operator
+// (its input converted down, its output converted back); the switch decided at
+// step k takes effect at step k+1.  No delta updates; the true-residual check
+// at convergence is the same.
 #pragma once
 #include <vector>
 
@@ -34,12 +41,15 @@ struct Engine {
     Lattice *L = nullptr;
     int sloppy = P64;       // inner spinor precision (P64: plain FP64 CG)
     int sloppy_link = P32;  // inner link precision (mixed only)
+    int mode = 0;           // TMQ_MODE_RELIABLE or TMQ_MODE_SWITCH
     hipStream_t st = nullptr;
     int cap = 0;
-    bool mixed = false;
+    bool mixed = false;     // reliable-update mode with a reduced inner precision
+    bool switching = false; // switch mode with a reduced operator precision
 
     std::vector<Field> fields;
     FieldDesc b, x, r64, te64, to64, rs, ps, tes, tos, xs;
+    FieldDesc ap64, pss, apss;  // switch mode: FP64 A p, reduced-precision p and A p
     LinkDesc lk64{}, lks{};
     OpParams op{};
     double *partial[3] = {nullptr, nullptr, nullptr};  // per slot at + slot * L->pstride
@@ -55,6 +65,7 @@ struct Engine {
         double maxr2 = 0.0;    // largest |r|^2 since the last true residual
         double tol = 0.0, delta = 0.0;
         int relative = 1, max_iter = 0;
+        bool switched = false;  // switch mode: reduced-precision operator in use
         CgScalars last{};      // scalars at finish
         int status = TMQ_OK;
     };
@@ -70,13 +81,14 @@ struct Engine {
 };
 
 // Bytes of device memory one slot holds (work fields of one right-hand side).
-size_t engine_slot_bytes(long vh, int sloppy);
+size_t engine_slot_bytes(long vh, int sloppy, int mode = 0);
 // Bytes an engine of cap slots holds in total.
-size_t engine_bytes(const Lattice *L, int sloppy, int cap);
+size_t engine_bytes(const Lattice *L, int sloppy, int cap, int mode = 0);
 
 // Allocate an engine with cap slots (1..MAX_RHS) on L for the inner
-// precision of o (sloppy, sloppy_link); commands go to stream st.
-int engine_create(Lattice *L, int sloppy, int sloppy_link, int cap, hipStream_t st, Engine **out);
+// precision (sloppy, sloppy_link) and mode of the options; commands go to
+// stream st.
+int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hipStream_t st, Engine **out);
 // Default delta of reliable updates for an inner precision.
 double engine_default_delta(int sloppy);
 

@@ -608,6 +608,10 @@ int check_opts(const tmq_solver_opts *o)
         set_error("sloppy_link must be TMQ_FP32 or TMQ_FP16");
         return TMQ_EINVAL;
     }
+    if (o->mode != TMQ_MODE_RELIABLE && o->mode != TMQ_MODE_SWITCH) {
+        set_error("mode must be TMQ_MODE_RELIABLE or TMQ_MODE_SWITCH");
+        return TMQ_EINVAL;
+    }
     return TMQ_OK;
 }
 

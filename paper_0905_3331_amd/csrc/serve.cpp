@@ -52,7 +52,7 @@ struct Request {
 struct EngineRec {
     std::unique_ptr<Engine> E;
     hipStream_t st = nullptr;
-    int lat = 0, sloppy = 0, link_fmt = 0;
+    int lat = 0, sloppy = 0, link_fmt = 0, mode = 0;
     double theta[4] = {0, 0, 0, 0};
     std::vector<Request *> slot_req;  // request in each slot (nullptr: free)
     bool broken = false;
@@ -156,7 +156,7 @@ EngineRec *Server::engine_for(Request *r, bool may_create)
     const int sp = r->o.sloppy;
     const int lkf = sp == P64 ? link_fmt_for(L, P64, P64) : link_fmt_for(L, sp, r->o.sloppy_link);
     auto same_key = [&](const EngineRec *er) {
-        return er->lat == r->lat && er->sloppy == sp && er->link_fmt == lkf;
+        return er->lat == r->lat && er->sloppy == sp && er->link_fmt == lkf && er->mode == r->o.mode;
     };
     for (auto &er : engines) {
         if (er->broken || !same_key(er.get()) || er->E->body_pending) continue;
@@ -167,7 +167,7 @@ EngineRec *Server::engine_for(Request *r, bool may_create)
     }
     if (!may_create) return nullptr;
     // a new engine: as many slots as the budget allows, up to max_batch
-    const size_t one = engine_bytes(L, sp, 1);
+    const size_t one = engine_bytes(L, sp, 1, r->o.mode);
     size_t in_use;
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -196,11 +196,11 @@ EngineRec *Server::engine_for(Request *r, bool may_create)
         if (in_use + one > budget) return nullptr;
     }
     int cap = max_batch;
-    while (cap > 1 && in_use + engine_bytes(L, sp, cap) > budget) cap--;
+    while (cap > 1 && in_use + engine_bytes(L, sp, cap, r->o.mode) > budget) cap--;
     auto er = std::make_unique<EngineRec>();
     if (hipStreamCreateWithFlags(&er->st, hipStreamNonBlocking) != hipSuccess) return nullptr;
     Engine *E = nullptr;
-    if (engine_create(L, sp, r->o.sloppy_link, cap, er->st, &E) != TMQ_OK) {
+    if (engine_create(L, sp, r->o.sloppy_link, r->o.mode, cap, er->st, &E) != TMQ_OK) {
         hipStreamDestroy(er->st);
         return nullptr;
     }
@@ -208,6 +208,7 @@ EngineRec *Server::engine_for(Request *r, bool may_create)
     er->lat = r->lat;
     er->sloppy = sp;
     er->link_fmt = lkf;
+    er->mode = r->o.mode;
     memcpy(er->theta, r->p.theta, sizeof(er->theta));
     er->slot_req.assign(cap, nullptr);
     {
@@ -234,7 +235,7 @@ void Server::admit(std::vector<Request *> &pending, std::vector<Request *> &fail
             bool has_engine = false;
             for (auto &e : engines)
                 has_engine |= !e->broken && e->lat == r->lat && e->sloppy == r->o.sloppy &&
-                              memcmp(e->theta, r->p.theta, sizeof(e->theta)) == 0;
+                              e->mode == r->o.mode && memcmp(e->theta, r->p.theta, sizeof(e->theta)) == 0;
             if (!has_engine) {
                 er = engine_for(r, true);
                 if (!er) blocked = true;
@@ -499,7 +500,7 @@ int tmq_server_submit(tmq_server *srv, int lattice_id, const tmq_params *p, cons
         return TMQ_EINVAL;
     }
     const Lattice *L = S.lats[lattice_id]->L.get();
-    const size_t one = engine_bytes(L, opts->sloppy, 1);
+    const size_t one = engine_bytes(L, opts->sloppy, 1, opts->mode);
     if (one > S.budget) {
         S.rejected++;
         set_error("tmq_server_submit: one solve on this lattice needs more device memory than the budget");

@@ -22,7 +22,7 @@ static int lattice_engine(Lattice *L, const tmq_solver_opts &o, int n, Engine **
     const int lk = sp == P64 ? link_fmt_for(L, P64, P64) : link_fmt_for(L, sp, o.sloppy_link);
     for (size_t i = 0; i < L->engines.size(); i++) {
         Engine *E = L->engines[i];
-        if (E->sloppy != sp || E->lks.fmt != lk) continue;
+        if (E->sloppy != sp || E->lks.fmt != lk || E->mode != o.mode) continue;
         if (E->cap >= n) {
             *out = E;
             return TMQ_OK;
@@ -32,7 +32,7 @@ static int lattice_engine(Lattice *L, const tmq_solver_opts &o, int n, Engine **
         break;
     }
     Engine *E = nullptr;
-    TMQ_TRY(engine_create(L, sp, o.sloppy_link, n, nullptr, &E));
+    TMQ_TRY(engine_create(L, sp, o.sloppy_link, o.mode, n, nullptr, &E));
     L->engines.push_back(E);
     *out = E;
     return TMQ_OK;

@@ -41,7 +41,8 @@ class tmq_params(ctypes.Structure):
 
 class tmq_solver_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("relative", ctypes.c_int), ("max_iter", ctypes.c_int),
-                ("sloppy", ctypes.c_int), ("sloppy_link", ctypes.c_int), ("delta", ctypes.c_double)]
+                ("sloppy", ctypes.c_int), ("sloppy_link", ctypes.c_int), ("delta", ctypes.c_double),
+                ("mode", ctypes.c_int)]
 
 
 class tmq_solve_info(ctypes.Structure):
@@ -141,8 +142,11 @@ def params(kappa: float, mu_tilde: float, theta=(1.0, 0.0, 0.0, 0.0)) -> tmq_par
     return p
 
 
+MODE_RELIABLE, MODE_SWITCH = 0, 1
+
+
 def solver_opts(tol=1e-10, relative=True, max_iter=10000, sloppy="fp64", sloppy_link="fp16",
-                delta=0.0) -> tmq_solver_opts:
+                delta=0.0, mode="reliable") -> tmq_solver_opts:
     o = tmq_solver_opts()
     o.tol = float(tol)
     o.relative = 1 if relative else 0
@@ -150,6 +154,7 @@ def solver_opts(tol=1e-10, relative=True, max_iter=10000, sloppy="fp64", sloppy_
     o.sloppy = PREC[sloppy] if isinstance(sloppy, str) else int(sloppy)
     o.sloppy_link = PREC[sloppy_link] if isinstance(sloppy_link, str) else int(sloppy_link)
     o.delta = float(delta)
+    o.mode = {"reliable": MODE_RELIABLE, "switch": MODE_SWITCH}[mode] if isinstance(mode, str) else int(mode)
     return o
 
 

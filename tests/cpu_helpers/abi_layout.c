@@ -16,6 +16,7 @@ int main(void)
     Z(tmq_solver_opts);
     F(tmq_solver_opts, tol); F(tmq_solver_opts, relative); F(tmq_solver_opts, max_iter);
     F(tmq_solver_opts, sloppy); F(tmq_solver_opts, sloppy_link); F(tmq_solver_opts, delta);
+    F(tmq_solver_opts, mode);
     Z(tmq_solve_info);
     F(tmq_solve_info, status); F(tmq_solve_info, iters); F(tmq_solve_info, reliable_updates);
     F(tmq_solve_info, true_rel_residual); F(tmq_solve_info, seconds);

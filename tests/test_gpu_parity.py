@@ -194,6 +194,26 @@ def test_cg_mixed(tmq, sloppy, link):
     assert info.reliable_updates >= 1
 
 
+@pytest.mark.parametrize("sloppy,link", [("fp32", "fp32"), ("fp16", "fp16")])
+def test_cg_switch_mode(tmq, sloppy, link):
+    """The paper's reduced-precision CG (FP64 operator until sqrt(tol), then the
+    reduced one, FP64 vectors): converges to the tolerance by the oracle's
+    true residual, and a batch equals its solves alone."""
+    dims = (12, 8, 6, 10)
+    lat, U = lattice(tmq, dims, seed=106)
+    opts = tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link=link, mode="switch")
+    bs = [synth.gaussian_odd(dims, seed=60 + i) for i in range(3)]
+    ps = [tmq.params(0.1632, m, THETA) for m in (0.004, 0.01, 0.02)]
+    xs, infos = lat.solve_batch(ps, [dev(b) for b in bs], opts)
+    for i in range(3):
+        res = oracle.true_residual(U, bs[i], host(xs[i]), 0.1632, ps[i].mu_tilde, THETA)
+        print(f"switch {sloppy}/{link} rhs {i}: iters {infos[i].iters} true checks {infos[i].reliable_updates} "
+              f"res {res:.2e}")
+        assert infos[i].status == 0 and res <= 1e-10
+    x1, i1 = lat.solve(ps[1], dev(bs[1]), opts)
+    assert torch.equal(x1, xs[1]) and i1.iters == infos[1].iters
+
+
 def test_cg_full_lattice_4444(tmq):
     """Full-lattice Q^+Q^- CG on 4^4, kappa 0.16, 2 kappa mu 0.01, tol 1e-10."""
     dims = (4, 4, 4, 4)
