@@ -91,7 +91,8 @@ typedef struct {
     tmq_prec sloppy_link;/* inner link storage, TMQ_FP32 or TMQ_FP16 (two-row); ignored for FP64 */
     double delta;        /* mixed precision: recompute the FP64 true residual whenever the
                             iterated residual fell by this factor (0 < delta < 1); <= 0: default
-                            (1e-4 for FP32, 0.02 for FP16, 0.05 for BF16 storage) */
+                            (1e-4 for FP32 spinors and links, 0.01 for FP32 spinors with FP16
+                            links, 0.005 for FP16 and 0.05 for BF16 spinors) */
     int mode;            /* TMQ_MODE_RELIABLE (0, default): the inner CG runs entirely in the
                             reduced precision with FP64 reliable updates (above).
                             TMQ_MODE_SWITCH (1): the paper's reduced-precision CG (Sec. 4.4):

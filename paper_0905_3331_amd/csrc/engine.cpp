@@ -35,11 +35,16 @@ size_t engine_bytes(const Lattice *L, int sloppy, int cap, int mode)
            (size_t)cap * sizeof(CgScalars);
 }
 
-double engine_default_delta(int sloppy)
+double engine_default_delta(int sloppy, int sloppy_link)
 {
-    // the FP32 recursion stays faithful over 4 decades, FP16 over about 2,
-    // BF16 (8-bit mantissa) over a little more than 1
-    return sloppy == P32 ? 1e-4 : sloppy == PB16 ? 0.05 : 0.02;
+    // How far the reduced-precision recursion stays faithful to the true
+    // residual, set by the coarser of spinor and link storage (measured on the
+    // 32^3x64 workload): FP32 with FP32 links over 4 decades; with FP16 links
+    // about 2; FP16 spinors a little over 2; BF16 (8-bit mantissa) a little
+    // over 1.  A delta below that reach stalls the recursion (FP32 spinors
+    // with FP16 links at 1e-4 took 765 iterations instead of 35).
+    if (sloppy == P32) return sloppy_link == P32 ? 1e-4 : 0.01;
+    return sloppy == PB16 ? 0.05 : 0.005;
 }
 
 Engine::~Engine()
@@ -196,7 +201,7 @@ int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts 
     s.tol = o.tol;
     s.relative = o.relative;
     s.max_iter = o.max_iter > 0 ? o.max_iter : 10000;
-    s.delta = o.delta > 0.0 && o.delta < 1.0 ? o.delta : engine_default_delta(E->sloppy);
+    s.delta = o.delta > 0.0 && o.delta < 1.0 ? o.delta : engine_default_delta(E->sloppy, E->sloppy_link);
 
     // x = 0 ; r = b ; p = r ; bb = |b|^2
     const RhsList one = list_of({slot});

@@ -89,8 +89,8 @@ size_t engine_bytes(const Lattice *L, int sloppy, int cap, int mode = 0);
 // precision (sloppy, sloppy_link) and mode of the options; commands go to
 // stream st.
 int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hipStream_t st, Engine **out);
-// Default delta of reliable updates for an inner precision.
-double engine_default_delta(int sloppy);
+// Default delta of reliable updates for an inner spinor and link precision.
+double engine_default_delta(int sloppy, int sloppy_link);
 
 // Put right-hand side b (device, canonical odd-site complex128 [V/2][12])
 // into free slot `slot` and enqueue its initialisation.  Boundary phases are

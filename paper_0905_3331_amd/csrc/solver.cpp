@@ -6,6 +6,7 @@
 // goes through exactly the same arithmetic whatever shares the batch, so a
 // batched solution equals its solve alone bit for bit.
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -208,6 +209,15 @@ static int read_scalars(Lattice *L, int n, hipStream_t st, std::vector<CgScalars
     return TMQ_OK;
 }
 
+// Small lattices are launch-latency bound (a 4^4 iteration is nine kernels
+// of a few microseconds): there the iterations run as HIP graphs of CHUNK
+// iterations each, captured once per solve, two graphs publishing their
+// scalars to the two halves of the ring so that the host reads one chunk
+// while the next runs.  Right-hand sides already converged skip their work
+// inside a chunk, so the result equals that of single iterations.
+constexpr int GRAPH_CHUNK = 4;
+constexpr long GRAPH_MAX_SITES = 1L << 16;
+
 int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
                hipStream_t st, tmq_solve_info *info)
 {
@@ -225,12 +235,55 @@ int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const 
     CgScalars *S = L->scal;
     const double tol2 = o.tol * o.tol;
     const long ps = L->pstride;
+    const bool graphs = n <= GRAPH_MAX_SITES && !L->timing && !getenv("TMQ_NO_GRAPH");
+    if (graphs) {
+        // graphs are captured on the lattice's own stream (never the null stream)
+        TMQ_HIP(hipStreamSynchronize(st));
+        st = L->own;
+    }
 
     // t = Q^- in ; out = Q^+ t ; partial = |t|^2
     auto apply_A = [&](const FieldDesc &in, const FieldDesc &out, double *partial) -> int {
         TMQ_TRY(apply_Q_full(L, op, -1, in, t, lk, one, st));
         if (partial) TMQ_HIP(launch_norm2(t, one, partial, ps, st));
         TMQ_TRY(apply_Q_full(L, op, +1, t, out, lk, one, st));
+        return TMQ_OK;
+    };
+    // one CG iteration publishing its scalars to ring slot `slot`
+    auto iterate = [&](int slot) -> int {
+        TMQ_TRY(apply_A(pp, ap, L->partial[0]));
+        TMQ_HIP(launch_scalar(SC_ALPHA, one, L->partial[0], ps, blas_grid(n), S, 0, 0, true, nullptr, st));
+        TMQ_HIP(launch_axpy_norm(x, pp, r, ap, one, S, L->partial[1], ps, true, st));
+        TMQ_HIP(launch_scalar(SC_BETA, one, L->partial[1], ps, blas_grid(n), S, 0, 0, true,
+                              L->ring_dev + (size_t)slot * MAX_RHS, st));
+        TMQ_HIP(launch_xpay(r, pp, one, S, true, st));
+        return TMQ_OK;
+    };
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    struct GraphScope {
+        hipGraph_t *g;
+        hipGraphExec_t *e;
+        ~GraphScope()
+        {
+            for (int i = 0; i < 2; i++) {
+                if (e[i]) hipGraphExecDestroy(e[i]);
+                if (g[i]) hipGraphDestroy(g[i]);
+            }
+        }
+    } gscope{graph, exec};
+    auto capture = [&]() -> int {
+        for (int h = 0; h < 2; h++) {
+            TMQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            int rc = TMQ_OK;
+            for (int k = 0; k < GRAPH_CHUNK && rc == TMQ_OK; k++) rc = iterate(h * GRAPH_CHUNK + k);
+            hipGraph_t gr = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &gr);
+            graph[h] = gr;
+            if (rc != TMQ_OK) return rc;
+            TMQ_HIP(ec);
+            TMQ_HIP(hipGraphInstantiate(&exec[h], graph[h], nullptr, nullptr, 0));
+        }
         return TMQ_OK;
     };
 
@@ -243,21 +296,46 @@ int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const 
     TMQ_TRY(read_scalars(L, 1, st, cur));
     int enq = 0;
     while (!(cur[0].done && cur[0].last_true) && !cur[0].nan && enq < max_iter) {
-        while (enq < max_iter) {
-            const int slot = enq % Lattice::RING;
-            TMQ_TRY(apply_A(pp, ap, L->partial[0]));
-            TMQ_HIP(launch_scalar(SC_ALPHA, one, L->partial[0], ps, blas_grid(n), S, 0, 0, true, nullptr, st));
-            TMQ_HIP(launch_axpy_norm(x, pp, r, ap, one, S, L->partial[1], ps, true, st));
-            TMQ_HIP(launch_scalar(SC_BETA, one, L->partial[1], ps, blas_grid(n), S, 0, 0, true,
-                                  L->ring_dev + (size_t)slot * MAX_RHS, st));
-            TMQ_HIP(launch_xpay(r, pp, one, S, true, st));
-            TMQ_HIP(hipEventRecord(L->ring_ev[slot], st));
-            enq++;
-            if (enq > 1) {
-                const int pslot = (enq - 2) % Lattice::RING;
-                TMQ_HIP(hipEventSynchronize(L->ring_ev[pslot]));
-                const CgScalars pv = L->ring[(size_t)pslot * MAX_RHS];
-                if (pv.done || pv.nan) break;
+        if (graphs) {
+            // one plain iteration first (it tunes the kernels), then chunks of
+            // GRAPH_CHUNK; the host checks chunk c - 1 while chunk c runs
+            if (enq == 0) {
+                TMQ_TRY(iterate(0));
+                enq++;
+            }
+            if (!exec[0]) TMQ_TRY(capture());
+            int c = 0;
+            while (enq + GRAPH_CHUNK <= max_iter) {
+                TMQ_HIP(hipGraphLaunch(exec[c & 1], st));
+                TMQ_HIP(hipEventRecord(L->ring_ev[c & 1], st));
+                enq += GRAPH_CHUNK;
+                if (c > 0) {
+                    const int h = (c - 1) & 1;
+                    TMQ_HIP(hipEventSynchronize(L->ring_ev[h]));
+                    const CgScalars pv = L->ring[(size_t)(h * GRAPH_CHUNK + GRAPH_CHUNK - 1) * MAX_RHS];
+                    if (pv.done || pv.nan) break;
+                }
+                c++;
+            }
+            // the last iterations before max_iter, one at a time
+            TMQ_TRY(read_scalars(L, 1, st, cur));
+            while (!cur[0].done && !cur[0].nan && enq < max_iter) {
+                TMQ_TRY(iterate(0));
+                enq++;
+                TMQ_TRY(read_scalars(L, 1, st, cur));
+            }
+        } else {
+            while (enq < max_iter) {
+                const int slot = enq % Lattice::RING;
+                TMQ_TRY(iterate(slot));
+                TMQ_HIP(hipEventRecord(L->ring_ev[slot], st));
+                enq++;
+                if (enq > 1) {
+                    const int pslot = (enq - 2) % Lattice::RING;
+                    TMQ_HIP(hipEventSynchronize(L->ring_ev[pslot]));
+                    const CgScalars pv = L->ring[(size_t)pslot * MAX_RHS];
+                    if (pv.done || pv.nan) break;
+                }
             }
         }
         TMQ_TRY(read_scalars(L, 1, st, cur));

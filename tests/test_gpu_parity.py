@@ -227,6 +227,31 @@ def test_cg_full_lattice_4444(tmq):
     assert abs(info.iters - io["iters"]) <= 2
 
 
+def test_cg_full_lattice_graphs_equal_plain(tmq, monkeypatch):
+    """The full-lattice CG of a small lattice runs its iterations as HIP graph
+    replays (two graphs of four iterations, replayed many times with host
+    reads and synchronisations between them); the solution and the iteration
+    count equal those of plain launches bit for bit, for several solves in a
+    row, and a max_iter that ends inside a chunk is honoured."""
+    dims = (4, 4, 4, 4)
+    lat, U = lattice(tmq, dims, seed=1000)
+    p = tmq.params(0.16, 0.01, THETA)
+    opts = tmq.solver_opts(tol=1e-10)
+    got = []
+    for seed in (2000, 2001, 2002):
+        b = dev(synth.gaussian_spinor(dims + (4, 3), seed=seed).reshape(-1, 4, 3))
+        got.append(lat.solve_full(p, b, opts))
+    monkeypatch.setenv("TMQ_NO_GRAPH", "1")
+    for k, seed in enumerate((2000, 2001, 2002)):
+        b = dev(synth.gaussian_spinor(dims + (4, 3), seed=seed).reshape(-1, 4, 3))
+        x, info = lat.solve_full(p, b, opts)
+        assert torch.equal(x, got[k][0]) and info.iters == got[k][1].iters, seed
+    monkeypatch.delenv("TMQ_NO_GRAPH")
+    b = dev(synth.gaussian_spinor(dims + (4, 3), seed=2003).reshape(-1, 4, 3))
+    x, info = lat.solve_full(p, b, tmq.solver_opts(tol=1e-10, max_iter=10), check=False)
+    assert info.status == tmq.TMQ_ENOCONV and info.iters == 10
+
+
 def test_cg_edge_cases(tmq):
     dims = (4, 4, 4, 4)
     lat, U = lattice(tmq, dims, seed=106)
