@@ -242,7 +242,9 @@ int tmq_solve_M_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_s
  * queue until a slot of its engine is free or memory for one can be found
  * (idle engines of other keys are released for it); requests of other keys
  * may pass a waiting one.  A request whose single slot exceeds the whole
- * budget is rejected at submission with TMQ_ENOMEM.
+ * budget is rejected at submission with TMQ_ENOMEM; one whose engine the
+ * device cannot allocate while no other engine exists finishes with
+ * TMQ_ENOMEM.
  *
  * Threads: the server runs one worker thread that drives every engine; all
  * tmq_server_* calls are thread-safe.  Fields are DEVICE pointers on the

@@ -97,7 +97,7 @@ struct Server {
     void run();
     bool pass();
     void admit(std::vector<Request *> &pending, std::vector<Request *> &failed_join);
-    EngineRec *engine_for(Request *r, bool may_create);
+    EngineRec *engine_for(Request *r, bool may_create, int *err = nullptr);
     void fail_engine(EngineRec *er, const std::string &msg);
     void complete(Request *r, int status);
     hipEvent_t get_event();
@@ -146,8 +146,9 @@ void Server::fail_engine(EngineRec *er, const std::string &msg)
 
 // An engine with a free slot for r; may create one within the budget,
 // releasing idle engines of other keys for it.  Called without mu.
-EngineRec *Server::engine_for(Request *r, bool may_create)
+EngineRec *Server::engine_for(Request *r, bool may_create, int *err)
 {
+    if (err) *err = TMQ_OK;
     Lattice *L = nullptr;
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -198,10 +199,15 @@ EngineRec *Server::engine_for(Request *r, bool may_create)
     int cap = max_batch;
     while (cap > 1 && in_use + engine_bytes(L, sp, cap, r->o.mode) > budget) cap--;
     auto er = std::make_unique<EngineRec>();
-    if (hipStreamCreateWithFlags(&er->st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipStreamCreateWithFlags(&er->st, hipStreamNonBlocking) != hipSuccess) {
+        if (err) *err = TMQ_EDEVICE;
+        return nullptr;
+    }
     Engine *E = nullptr;
-    if (engine_create(L, sp, r->o.sloppy_link, r->o.mode, cap, er->st, &E) != TMQ_OK) {
+    const int cs = engine_create(L, sp, r->o.sloppy_link, r->o.mode, cap, er->st, &E);
+    if (cs != TMQ_OK) {
         hipStreamDestroy(er->st);
+        if (err) *err = cs;
         return nullptr;
     }
     er->E.reset(E);
@@ -237,7 +243,16 @@ void Server::admit(std::vector<Request *> &pending, std::vector<Request *> &fail
                 has_engine |= !e->broken && e->lat == r->lat && e->sloppy == r->o.sloppy &&
                               e->mode == r->o.mode && memcmp(e->theta, r->p.theta, sizeof(e->theta)) == 0;
             if (!has_engine) {
-                er = engine_for(r, true);
+                int err = TMQ_OK;
+                er = engine_for(r, true, &err);
+                if (!er && err != TMQ_OK && engines.empty()) {
+                    // the device refused memory that the budget allowed, and no
+                    // engine will ever release any: fail rather than wait
+                    r->t_admit = Clock::now();
+                    r->info.status = err;
+                    failed_join.push_back(r);
+                    continue;
+                }
                 if (!er) blocked = true;
             }
         }
@@ -343,7 +358,7 @@ bool Server::pass()
             queue.swap(q);
             for (Request *r : failed_join) {
                 r->t_admit = Clock::now();
-                complete(r, TMQ_EDEVICE);
+                complete(r, r->info.status == TMQ_ENOMEM ? TMQ_ENOMEM : TMQ_EDEVICE);
             }
         }
     }

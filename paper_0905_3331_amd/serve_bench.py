@@ -152,7 +152,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--requests", type=int, default=2000, help="requests per Poisson run")
     ap.add_argument("--burst", type=int, default=400, help="requests of the saturation run")
-    ap.add_argument("--loads", default="0.5,0.8", help="Poisson rates as fractions of saturation throughput")
+    ap.add_argument("--loads", default="0.5,0.8,0.95", help="Poisson rates as fractions of saturation throughput")
     ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=0.0, help="0: 60%% of free device memory")
     ap.add_argument("--sloppy", default="fp32")

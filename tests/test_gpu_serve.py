@@ -187,3 +187,47 @@ def test_serve_edge_requests(tmq):
     assert ig.status == 0
     assert oracle.true_residual(U, good, host(xg), KAPPA, 0.01, THETA) <= 1e-10
     assert st["failed"] == 2
+
+
+def test_serve_threads_poll_and_destroy(tmq):
+    """Requests submitted from several host threads at once all finish and
+    converge; poll reports a pending request as pending; destroying the server
+    with requests in flight waits for them and returns."""
+    import threading
+
+    dims = (8, 4, 4, 6)
+    U = gauge(dims, 3106)
+    o = tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")
+    srv = tmq.Server(max_batch=4)
+    lid = srv.add_lattice(dims, dev(U))
+    bs = [synth.gaussian_odd(dims, seed=8000 + i) for i in range(12)]
+    bd = [dev(b) for b in bs]
+    torch.cuda.synchronize()
+    tickets = [None] * 12
+
+    def worker(k):
+        for i in range(k, 12, 3):
+            tickets[i] = srv.submit(lid, tmq.params(KAPPA, 0.002 + 0.001 * i, THETA), bd[i], o, sync=False)
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(3)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    first = srv.poll(tickets[11])  # most likely still queued or running
+    assert first is None or first[1].status == 0
+    for i, t in enumerate(tickets):
+        if i == 11 and first is not None:
+            x, info = first
+        else:
+            x, info = srv.wait(t, timeout=60)
+        assert info.status == 0
+        res = oracle.true_residual(U, bs[i], host(x), KAPPA, 0.002 + 0.001 * i, THETA)
+        assert res <= 1e-10, (i, res)
+    st = srv.stats()
+    assert st["completed"] == 12 and st["peak_running"] <= 4
+    # in flight at destruction: destroy waits for them
+    for i in range(4):
+        srv.submit(lid, tmq.params(KAPPA, 0.01, THETA), bd[i], o)
+    srv.close()
+
