@@ -255,3 +255,107 @@ def decode_site_scaled(codes: np.ndarray, scale: np.ndarray, kind: str) -> np.nd
         y = _bf16_bits_to_f32(codes)
     v = (y * scale.astype(np.float32)[:, None]).astype(np.float64)
     return v.view(np.complex128).reshape(-1, 4, 3)
+
+
+# ------------------------------------------------------ flavour doublet
+#
+# The mass non-degenerate doublet of eq. (Dh), D_h = D_W 1_f + i mubar g5 tau^3
+# + epsbar tau^1, in the hopping normalisation of eq. (eo0): with A the site
+# term 1 + i mubar g5 tau^3 + epsbar tau^1 (mubar and epsbar standing for
+# 2 kappa mubar and 2 kappa epsbar),
+#     M_h psi = A psi - kappa H psi      (H flavour-diagonal),
+# and Q_h = g5 M_h.  Its even/odd reduction follows the factorisation of
+# App. B for the doublet: Qhat_h = g5 (A_oo - kappa^2 H_oe A_ee^-1 H_eo) on
+# the odd sites, A_ee^-1 the inverse of the 8x8 site matrix (flavour x spin).
+# sign = -1 flips the sign of mubar (Qhat_h^- is the adjoint of Qhat_h^+).
+# Doublet fields are (2, ...) arrays: flavour index first (upper, lower).
+
+_TAU = np.array([[[0, 1], [1, 0]], [[0, -1j], [1j, 0]], [[1, 0], [0, -1]]], dtype=np.complex128)
+
+
+def doublet_site_matrix(mubar, epsbar):
+    """The 8x8 site term A = 1 + i mubar g5 tau^3 + epsbar tau^1 of eq. (Dh),
+    indexed (flavour, spin), built from the dense gamma_5 of App. A."""
+    g5 = gammas()[4]
+    return (np.eye(8) + 1j * mubar * np.kron(_TAU[2], g5) + epsbar * np.kron(_TAU[0], np.eye(4)))
+
+
+def _site_apply(A8, psi2):
+    """(A8 psi)(x) for a doublet field (2, n, 4, 3): A8 acts on (flavour, spin)."""
+    n = psi2.shape[1]
+    v = np.transpose(psi2, (1, 0, 2, 3)).reshape(n, 8, 3)
+    w = np.einsum("ab,nbc->nac", A8, v)
+    return np.transpose(w.reshape(n, 2, 4, 3), (1, 0, 2, 3))
+
+
+def _gamma5(psi):
+    return np.einsum("st,...tc->...sc", gammas()[4], psi)
+
+
+def Mh(U, psi2, kappa, mubar, epsbar, theta):
+    """M_h psi on the full lattice for a doublet psi2 (2, T, LZ, LY, LX, 4, 3)."""
+    dims = tuple(U.shape[:4])
+    V = volume(dims)
+    psi2 = np.asarray(psi2, dtype=np.complex128).reshape((2,) + dims + (4, 3))
+    loc = _site_apply(doublet_site_matrix(mubar, epsbar), psi2.reshape(2, V, 4, 3))
+    out = np.empty_like(psi2)
+    for f in range(2):
+        out[f] = loc[f].reshape(dims + (4, 3)) - kappa * hop(U, psi2[f], theta)
+    return out
+
+
+def _hop_parity(U, part, theta, src_sites, dst_sites):
+    """H restricted to parity blocks: the field `part` on src_sites, H applied, read on dst_sites."""
+    dims = tuple(U.shape[:4])
+    full = np.zeros((volume(dims), 4, 3), dtype=np.complex128)
+    full[src_sites] = part
+    return hop(U, full.reshape(dims + (4, 3)), theta).reshape(volume(dims), 4, 3)[dst_sites]
+
+
+def Qhat_nd(U, psi2_odd, kappa, mubar, epsbar, sign, theta):
+    """Qhat_h^{sign} psi on the odd sites of a doublet (2, V/2, 4, 3)."""
+    dims = tuple(U.shape[:4])
+    V = volume(dims)
+    odd = odd_sites(dims)
+    even = np.setdiff1d(np.arange(V), odd)
+    psi2 = np.asarray(psi2_odd, dtype=np.complex128).reshape(2, V // 2, 4, 3)
+    A8 = doublet_site_matrix(sign * mubar, epsbar)
+    Ainv = np.linalg.inv(A8)
+    t_e = np.stack([_hop_parity(U, psi2[f], theta, odd, even) for f in range(2)])
+    s_e = _site_apply(Ainv, t_e)
+    w_o = np.stack([_hop_parity(U, s_e[f], theta, even, odd) for f in range(2)])
+    return _gamma5(_site_apply(A8, psi2) - kappa * kappa * w_o)
+
+
+def QhatQhat_nd(U, psi2_odd, kappa, mubar, epsbar, theta):
+    """Qhat_h^+ Qhat_h^- psi (Qhat_h^- first) on a doublet of odd-site fields."""
+    return Qhat_nd(U, Qhat_nd(U, psi2_odd, kappa, mubar, epsbar, -1, theta), kappa, mubar, epsbar, +1, theta)
+
+
+def cg_nd(U, b2, kappa, mubar, epsbar, theta, tol=1e-10, max_iter=10000):
+    """Textbook CG (Sec. 4.4) on Qhat_h^+ Qhat_h^- for a doublet source, x_0 = 0,
+    inner products over both flavours; stops when |r|^2 <= tol^2 |b|^2."""
+    b = np.asarray(b2, dtype=np.complex128)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = float(np.vdot(r, r).real)
+    target = tol * tol * rr
+    k = 0
+    while rr > target and k < max_iter:
+        ap = QhatQhat_nd(U, p, kappa, mubar, epsbar, theta)
+        alpha = rr / float(np.vdot(p, ap).real)
+        x += alpha * p
+        r -= alpha * ap
+        rr_new = float(np.vdot(r, r).real)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        k += 1
+    return x, {"converged": rr <= target, "iters": k}
+
+
+def true_residual_nd(U, b2, x2, kappa, mubar, epsbar, theta) -> float:
+    """||b - Qhat_h^+ Qhat_h^- x|| / ||b|| in FP64 for doublet fields."""
+    b = np.asarray(b2, dtype=np.complex128)
+    r = b - QhatQhat_nd(U, x2, kappa, mubar, epsbar, theta)
+    return float(np.linalg.norm(r.ravel()) / np.linalg.norm(b.ravel()))

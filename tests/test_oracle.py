@@ -377,3 +377,109 @@ def test_codec_reference(kind):
     err = np.abs(back.reshape(-1, 12).view(np.float64).reshape(-1, 24) - re)
     assert np.all(err <= bound * scale[:, None] * (1 + 1e-6))
     assert scale[3] == 0 and np.all(back[3] == 0)
+
+
+# ---------------------------------------------------------- flavour doublet
+# eq. (Dh) in the hopping normalisation; mubar, epsbar stand for 2 kappa mubar
+# and 2 kappa epsbar (the doublet run of the paper's test-run table: kappa
+# 0.17, 2 kappa mubar 0.1105, 2 kappa epsbar 0.0935).
+ND_KAPPA, ND_MUBAR, ND_EPSBAR = 0.17, 0.1105, 0.0935
+TAU = [np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]], complex)]
+
+
+def _dense_Mh(U, kappa, mubar, epsbar, theta):
+    """Dense doublet operator [[M(+mubar), epsbar], [epsbar, M(-mubar)]] assembled from
+    the one-flavour eq. (eo0) matrices (flavour-major index)."""
+    Mu = dense.M_hopping(U, kappa, mubar, +1, theta)
+    Md = dense.M_hopping(U, kappa, mubar, -1, theta)
+    one = np.eye(Mu.shape[0])
+    return np.block([[Mu, epsbar * one], [epsbar * one, Md]])
+
+
+def test_doublet_site_term_flavour_rotation():
+    """eq. (altDh): the site term of eq. (Dh) rotated in flavour space is the
+    (mu_sigma, mu_delta) = (mubar, -epsbar) form.  The rotation that does it
+    is (1 - i tau^2) . (1 + i tau^2) / 2 (the paper prints the factors in the
+    other order, which gives the same form with both masses negated)."""
+    g5 = dense.G5
+    for mb, eb in ((ND_MUBAR, ND_EPSBAR), (0.3, -0.2)):
+        A = oracle.doublet_site_matrix(mb, eb)
+        Ap = np.eye(8) + 1j * mb * np.kron(TAU[0], g5) + (-eb) * np.kron(TAU[2], np.eye(4))
+        Rm = np.kron(np.eye(2) - 1j * TAU[1], np.eye(4))
+        Rp = np.kron(np.eye(2) + 1j * TAU[1], np.eye(4))
+        assert np.abs(Rm @ A @ Rp / 2 - Ap).max() < 1e-15
+        # and the inverse the even/odd reduction needs: (1 - i mubar g5 tau^3 - epsbar tau^1) / (1 + mubar^2 - epsbar^2)
+        inv = (np.eye(8) - 1j * mb * np.kron(TAU[2], g5) - eb * np.kron(TAU[0], np.eye(4))) / (1 + mb * mb - eb * eb)
+        assert np.abs(A @ inv - np.eye(8)).max() < 1e-15
+
+
+def test_doublet_Mh_matches_dense(small_case):
+    dims, U = small_case
+    V = int(np.prod(dims))
+    A = dense.dense_of(lambda v: oracle.Mh(U, v, ND_KAPPA, ND_MUBAR, ND_EPSBAR, THETA_GEN), 24 * V,
+                       (2,) + tuple(dims) + (4, 3))
+    B = _dense_Mh(U, ND_KAPPA, ND_MUBAR, ND_EPSBAR, THETA_GEN)
+    assert rel(A, B) < 1e-14
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_Qhat_nd_matches_dense_schur_complement(small_case, sign):
+    """Qhat_h = g5 (M_oo - M_oe M_ee^-1 M_eo) of the dense doublet operator,
+    the even/odd factorisation of App. B applied to eq. (Dh)."""
+    dims, U = small_case
+    V = int(np.prod(dims))
+    A = dense.dense_of(lambda v: oracle.Qhat_nd(U, v, ND_KAPPA, ND_MUBAR, ND_EPSBAR, sign, THETA_GEN), 12 * V,
+                       (2, V // 2, 4, 3))
+    M = _dense_Mh(U, ND_KAPPA, sign * ND_MUBAR, ND_EPSBAR, THETA_GEN)
+    e, o = dense.eo_blocks(dims)
+    e2 = np.concatenate([e, 12 * V + e])
+    o2 = np.concatenate([o, 12 * V + o])
+    S = M[np.ix_(o2, o2)] - M[np.ix_(o2, e2)] @ np.linalg.solve(M[np.ix_(e2, e2)], M[np.ix_(e2, o2)])
+    g5 = np.kron(np.eye(V), np.kron(dense.G5, dense.I3))  # 2 flavours x V/2 odd sites
+    assert rel(A, g5 @ S) < 1e-13
+
+
+def test_Qhat_nd_reduces_to_degenerate():
+    """epsbar = 0: the doublet decouples into Qhat^{+-} of eq. (eo4) for the two flavours."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_gauge(dims, seed=71)
+    psi = np.stack([synth.gaussian_odd(dims, seed=72), synth.gaussian_odd(dims, seed=73)])
+    for sign in (+1, -1):
+        a = oracle.Qhat_nd(U, psi, ND_KAPPA, ND_MUBAR, 0.0, sign, THETA_AP)
+        assert rel(a[0], oracle.Qhat(U, psi[0], ND_KAPPA, ND_MUBAR, sign, THETA_AP)) < 1e-14
+        assert rel(a[1], oracle.Qhat(U, psi[1], ND_KAPPA, ND_MUBAR, -sign, THETA_AP)) < 1e-14
+
+
+def test_Qhat_nd_adjoint_and_tau3():
+    """(Qhat_h^+)^dagger = Qhat_h^- ; flipping the sign of epsbar (the convention of
+    eq. (Dheo) against eq. (Dh)) is the flavour rotation tau^3 on both sides."""
+    dims = (4, 4, 2, 6)
+    U = synth.random_gauge(dims, seed=74)
+    x = np.stack([synth.gaussian_odd(dims, seed=75), synth.gaussian_odd(dims, seed=76)])
+    y = np.stack([synth.gaussian_odd(dims, seed=77), synth.gaussian_odd(dims, seed=78)])
+    args = (ND_KAPPA, ND_MUBAR, ND_EPSBAR)
+    lhs = np.vdot(y, oracle.Qhat_nd(U, x, *args, +1, THETA_GEN))
+    rhs = np.vdot(oracle.Qhat_nd(U, y, *args, -1, THETA_GEN), x)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-13
+    assert abs(lhs - np.vdot(y, oracle.Qhat_nd(U, x, *args, -1, THETA_GEN))) / abs(lhs) > 1e-6
+    t3 = np.array([1.0, -1.0])[:, None, None, None]
+    a = oracle.Qhat_nd(U, x, ND_KAPPA, ND_MUBAR, -ND_EPSBAR, +1, THETA_GEN)
+    b = t3 * oracle.Qhat_nd(U, t3 * x, *args, +1, THETA_GEN)
+    assert rel(a, b) < 1e-15
+
+
+def test_cg_nd_matches_dense_solve():
+    dims = (2, 2, 2, 2)
+    U = synth.random_gauge(dims, seed=79)
+    args = (ND_KAPPA, ND_MUBAR, ND_EPSBAR)
+    n = 2 * 6 * 16
+    A = dense.dense_of(lambda v: oracle.QhatQhat_nd(U, v, *args, THETA_AP), n, (2, 8, 4, 3))
+    assert rel(A, A.conj().T) < 1e-14
+    ev = np.linalg.eigvalsh(A)
+    assert ev[0] > 0
+    b = np.stack([synth.gaussian_odd(dims, seed=80), synth.gaussian_odd(dims, seed=81)])
+    xs = np.linalg.solve(A, b.ravel())
+    x, info = oracle.cg_nd(U, b, *args, THETA_AP, tol=1e-10)
+    assert info["converged"]
+    assert rel(x.ravel(), xs) <= (ev[-1] / ev[0]) * 1e-10
+    assert oracle.true_residual_nd(U, b, x, *args, THETA_AP) <= 1e-10
