@@ -216,6 +216,19 @@ int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solve
 int tmq_solve_M_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts,
                     const double *phi, double *psi, void *stream, tmq_solve_info *info);
 
+/* Even/odd split and merge of canonical spinor fields (App. B: the even/odd
+ * decomposition of a field): full = complex128 [V][4][3] over lexicographic
+ * sites, even/odd = complex128 [V/2][4][3] over the sites of that parity in
+ * the same order (eo index = site >> 1), the layout of every odd-site call
+ * above.  A copy: no arithmetic.  Split: either output may be NULL (not
+ * written).  Merge: a NULL parity is taken as zero.  The buffers must not
+ * overlap.  The gauge field need not be loaded.  *_dev: device pointers,
+ * ordered on the stream. */
+int tmq_split_eo(tmq_lattice *lat, const double *full, double *even, double *odd);
+int tmq_merge_eo(tmq_lattice *lat, const double *even, const double *odd, double *full);
+int tmq_split_eo_dev(tmq_lattice *lat, const double *full, double *even, double *odd, void *stream);
+int tmq_merge_eo_dev(tmq_lattice *lat, const double *even, const double *odd, double *full, void *stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A solve server: a stream of independent even/odd solves (each a request

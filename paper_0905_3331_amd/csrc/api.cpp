@@ -387,6 +387,79 @@ int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solve
     return s;
 }
 
+int tmq_split_eo_dev(tmq_lattice *lat, const double *full, double *even, double *odd, void *stream)
+{
+    TMQ_TRY(check_lat(lat, false));
+    if (!full || (!even && !odd)) {
+        set_error("tmq_split_eo: NULL full field, or both outputs NULL");
+        return TMQ_EINVAL;
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    TMQ_HIP(launch_split_eo(L->g, (const double2 *)full, (double2 *)even, (double2 *)odd, (hipStream_t)stream));
+    return TMQ_OK;
+}
+
+int tmq_merge_eo_dev(tmq_lattice *lat, const double *even, const double *odd, double *full, void *stream)
+{
+    TMQ_TRY(check_lat(lat, false));
+    if (!full) {
+        set_error("tmq_merge_eo: NULL full field");
+        return TMQ_EINVAL;
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    TMQ_HIP(launch_merge_eo(L->g, (const double2 *)even, (const double2 *)odd, (double2 *)full, (hipStream_t)stream));
+    return TMQ_OK;
+}
+
+static int split_merge_host(tmq_lattice *lat, bool merge, const double *full_in, double *full_out, const double *ev_in,
+                            const double *od_in, double *ev_out, double *od_out)
+{
+    TMQ_TRY(check_lat(lat, false));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const size_t half = (size_t)L->g.vh * 12 * sizeof(double2);
+    void *df = nullptr, *dh = nullptr;
+    TMQ_TRY(stage_buffer(L, 0, 2 * half, &df));
+    TMQ_TRY(stage_buffer(L, 1, 2 * half, &dh));
+    double2 *de = (double2 *)dh, *dodd = (double2 *)((char *)dh + half);
+    hipStream_t st = L->own;
+    if (merge) {
+        if (ev_in) TMQ_HIP(hipMemcpyAsync(de, ev_in, half, hipMemcpyHostToDevice, st));
+        if (od_in) TMQ_HIP(hipMemcpyAsync(dodd, od_in, half, hipMemcpyHostToDevice, st));
+        TMQ_TRY(tmq_merge_eo_dev(lat, ev_in ? (double *)de : nullptr, od_in ? (double *)dodd : nullptr, (double *)df,
+                                 st));
+        TMQ_HIP(hipMemcpyAsync(full_out, df, 2 * half, hipMemcpyDeviceToHost, st));
+    } else {
+        TMQ_HIP(hipMemcpyAsync(df, full_in, 2 * half, hipMemcpyHostToDevice, st));
+        TMQ_TRY(tmq_split_eo_dev(lat, (double *)df, ev_out ? (double *)de : nullptr, od_out ? (double *)dodd : nullptr,
+                                 st));
+        if (ev_out) TMQ_HIP(hipMemcpyAsync(ev_out, de, half, hipMemcpyDeviceToHost, st));
+        if (od_out) TMQ_HIP(hipMemcpyAsync(od_out, dodd, half, hipMemcpyDeviceToHost, st));
+    }
+    TMQ_HIP(hipStreamSynchronize(st));
+    return TMQ_OK;
+}
+
+int tmq_split_eo(tmq_lattice *lat, const double *full, double *even, double *odd)
+{
+    if (!full || (!even && !odd)) {
+        set_error("tmq_split_eo: NULL full field, or both outputs NULL");
+        return TMQ_EINVAL;
+    }
+    return split_merge_host(lat, false, full, nullptr, nullptr, nullptr, even, odd);
+}
+
+int tmq_merge_eo(tmq_lattice *lat, const double *even, const double *odd, double *full)
+{
+    if (!full) {
+        set_error("tmq_merge_eo: NULL full field");
+        return TMQ_EINVAL;
+    }
+    return split_merge_host(lat, true, nullptr, full, even, odd, nullptr, nullptr);
+}
+
 static void recycle_timed(Lattice *L)
 {
     for (auto &t : L->timed) {

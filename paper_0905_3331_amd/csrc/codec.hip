@@ -150,6 +150,26 @@ __global__ __launch_bounds__(BLAS_BLOCK) void k_export_codes(SP in, uint16_t *co
     }
 }
 
+// ------------------------------------------------------- even/odd split
+
+// Canonical full field <-> canonical even and odd fields, one thread per
+// complex component (reads or writes of the full field coalesced).  A null
+// parity pointer: split skips it, merge writes zeros there.
+template <bool MERGE>
+__global__ __launch_bounds__(BLAS_BLOCK) void k_split_eo(Geom g, double2 *full, double2 *even, double2 *odd)
+{
+    const long i = (long)blockIdx.x * BLAS_BLOCK + threadIdx.x;
+    if (i >= 2 * g.vh * 12) return;
+    const long s = i / 12;
+    const int c = (int)(i - s * 12);
+    double2 *part = site_parity(g, s) ? odd : even;
+    const long j = (s >> 1) * 12 + c;
+    if (MERGE)
+        full[i] = part ? part[j] : make_double2(0.0, 0.0);
+    else if (part)
+        part[j] = full[i];
+}
+
 // ------------------------------------------------------------------ gauge
 
 __global__ __launch_bounds__(BLAS_BLOCK) void k_gauge_ingest(Geom g, const double2 *U, GaugeOut o, double *partial)
@@ -248,6 +268,20 @@ hipError_t launch_full_to_canonical(const Geom &g, const FieldDesc &in, double2 
     DISPATCH_SPC(in.prec, F,
                  hipLaunchKernelGGL((k_full_canonical<F, true>), dim3(blas_grid(in.n)), dim3(BLAS_BLOCK), 0, st,
                                     g, out, make_sp<F>(in)));
+    return hipGetLastError();
+}
+
+hipError_t launch_split_eo(const Geom &g, const double2 *full, double2 *even, double2 *odd, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_split_eo<false>, dim3(blas_grid(2 * g.vh * 12)), dim3(BLAS_BLOCK), 0, st, g, (double2 *)full,
+                       even, odd);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_eo(const Geom &g, const double2 *even, const double2 *odd, double2 *full, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_split_eo<true>, dim3(blas_grid(2 * g.vh * 12)), dim3(BLAS_BLOCK), 0, st, g, full,
+                       (double2 *)even, (double2 *)odd);
     return hipGetLastError();
 }
 

@@ -187,6 +187,11 @@ hipError_t launch_to_canonical(const FieldDesc &in, double2 *out, hipStream_t st
 // full-lattice fields: canonical site s of parity p -> stacked view site p * V/2 + (s >> 1)
 hipError_t launch_full_from_canonical(const Geom &g, const double2 *in, const FieldDesc &out, hipStream_t st);
 hipError_t launch_full_to_canonical(const Geom &g, const FieldDesc &in, double2 *out, hipStream_t st);
+// canonical full field (complex128 [V][12], lexicographic sites) <-> canonical
+// even and odd fields ([V/2][12], eo index = site >> 1); split skips a null
+// parity, merge writes zeros for one
+hipError_t launch_split_eo(const Geom &g, const double2 *full, double2 *even, double2 *odd, hipStream_t st);
+hipError_t launch_merge_eo(const Geom &g, const double2 *even, const double2 *odd, double2 *full, hipStream_t st);
 // export 16-bit codes of a field in canonical [site][24] order plus scales
 hipError_t launch_export_codes(const FieldDesc &in, uint16_t *codes, float *scale, hipStream_t st);
 

@@ -88,6 +88,10 @@ _SIGS = {
     "tmq_solve_full_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
     "tmq_solve_M": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _P(tmq_solve_info)]),
     "tmq_solve_M_dev": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_split_eo": (_ip, [_vp, _vp, _vp, _vp]),
+    "tmq_merge_eo": (_ip, [_vp, _vp, _vp, _vp]),
+    "tmq_split_eo_dev": (_ip, [_vp, _vp, _vp, _vp, _vp]),
+    "tmq_merge_eo_dev": (_ip, [_vp, _vp, _vp, _vp, _vp]),
     "tmq_set_kernel_timing": (_ip, [_vp, _ip]),
     "tmq_kernel_stats": (_ip, [_vp, ctypes.c_char_p, _P(ctypes.c_int), _P(ctypes.c_double),
                                _P(ctypes.c_double), _P(ctypes.c_double)]),
@@ -375,6 +379,42 @@ class Lattice:
         if check:
             _check(code, "tmq_solve_M")
         return psi, _info(info)
+
+    def split_eo(self, full, stream=None):
+        """Split a full (V, 4, 3) complex128 field (device tensor or host array)
+        into its (even, odd) parts, each (V/2, 4, 3)."""
+        n, nh = self.V * 12, self.V // 2 * 12
+        if isinstance(full, np.ndarray):
+            ev = np.empty((self.V // 2, 4, 3), np.complex128)
+            od = np.empty_like(ev)
+            _check(_lib.tmq_split_eo(self._h, _hptr(full, n, "full"), _hptr(ev, nh, "even"), _hptr(od, nh, "odd")),
+                   "tmq_split_eo")
+        else:
+            import torch
+
+            ev = torch.empty((self.V // 2, 4, 3), dtype=torch.complex128, device=full.device)
+            od = torch.empty_like(ev)
+            _check(_lib.tmq_split_eo_dev(self._h, _dptr(full, n, "full"), _dptr(ev, nh, "even"), _dptr(od, nh, "odd"),
+                                         _stream(stream)), "tmq_split_eo")
+        return ev, od
+
+    def merge_eo(self, even, odd, stream=None):
+        """Merge (even, odd) parts (either may be None: zero) into a full (V, 4, 3) field."""
+        n, nh = self.V * 12, self.V // 2 * 12
+        ref = even if even is not None else odd
+        if isinstance(ref, np.ndarray):
+            full = np.empty((self.V, 4, 3), np.complex128)
+            e = _hptr(even, nh, "even") if even is not None else None
+            o = _hptr(odd, nh, "odd") if odd is not None else None
+            _check(_lib.tmq_merge_eo(self._h, e, o, _hptr(full, n, "full")), "tmq_merge_eo")
+        else:
+            import torch
+
+            full = torch.empty((self.V, 4, 3), dtype=torch.complex128, device=ref.device)
+            e = _dptr(even, nh, "even") if even is not None else None
+            o = _dptr(odd, nh, "odd") if odd is not None else None
+            _check(_lib.tmq_merge_eo_dev(self._h, e, o, _dptr(full, n, "full"), _stream(stream)), "tmq_merge_eo")
+        return full
 
     # ---------------------------------------------------------- diagnostics
     def set_kernel_timing(self, on: bool):

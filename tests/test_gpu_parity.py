@@ -442,3 +442,22 @@ def test_solve_M_oracle_residual(tmq, sign, sloppy):
                                 tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp16"))
     assert np.array_equal(psi_h, host(psi))
 
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (6, 4, 2, 10)], ids=lambda d: "x".join(map(str, d)))
+def test_split_merge_eo(tmq, dims):
+    """Split of a full field into its parities and the merge back are exact
+    copies onto the oracle's odd-site order (and its complement for even)."""
+    lat, _ = lattice(tmq, dims, 91)
+    V = int(np.prod(dims))
+    full = synth.gaussian_spinor(tuple(dims) + (4, 3), seed=92).reshape(V, 4, 3)
+    odd = oracle.odd_sites(dims)
+    even = np.setdiff1d(np.arange(V), odd)
+    ev, od = lat.split_eo(dev(full))
+    assert np.array_equal(host(ev), full[even]) and np.array_equal(host(od), full[odd])
+    assert np.array_equal(host(lat.merge_eo(ev, od)), full)
+    z = host(lat.merge_eo(None, od))
+    assert np.array_equal(z[odd], full[odd]) and not np.any(z[even])
+    hev, hod = lat.split_eo(full)  # host-pointer calls
+    assert np.array_equal(hev, full[even]) and np.array_equal(hod, full[odd])
+    assert np.array_equal(lat.merge_eo(hev, hod), full)
