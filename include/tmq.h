@@ -216,6 +216,46 @@ int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solve
 int tmq_solve_M_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts,
                     const double *phi, double *psi, void *stream, tmq_solve_info *info);
 
+/* ------------------------------------------------- flavour doublet */
+
+/* The mass non-degenerate doublet of eq. (Dh), D_h = D_W 1_f + i mubar g5 tau^3
+ * + epsbar tau^1, in the hopping normalisation of eq. (eo0):
+ *   M_h = A - kappa H 1_f,   A = 1 + i mubar g5 tau^3 + epsbar tau^1,
+ *   Q_h = g5 M_h,
+ * and its even/odd reduction on the odd sites (App. B, the doublet's Q^h_oo)
+ *   Qhat_h^{+-} = g5 [ A_oo - kappa^2 H_oe A_ee^-1 H_eo ],
+ *   A^-1 = (1 - i mubar g5 tau^3 - epsbar tau^1) / (1 + mubar^2 - epsbar^2),
+ * with mubar -> -mubar for the minus sign, so that (Qhat_h^+)^dagger =
+ * Qhat_h^-.  The printed eq. (Dheo) carries epsbar with the opposite sign,
+ * which is the flavour rotation tau^3 of this operator (same spectrum).
+ * Solves are CG on Qhat_h^+ Qhat_h^- x = b (Qhat_h^- first), with the options
+ * of tmq_solve (mixed precision and modes included).
+ * Doublet fields are complex128 [2][V/2][4][3]: the upper flavour's odd-site
+ * field, then the lower's, each in the odd-site order above. */
+typedef struct {
+    double kappa;        /* hopping parameter */
+    double mubar_tilde;  /* 2 kappa mubar */
+    double epsbar_tilde; /* 2 kappa epsbar; 1 + mubar_tilde^2 - epsbar_tilde^2 must be > 0 */
+    double theta[4];     /* boundary phases along t, x, y, z (1 = antiperiodic) */
+} tmq_nd_params;
+
+/* out = Qhat_h^{sign} in, storage precision prec as for tmq_apply_Qhat. */
+int tmq_apply_Qhat_nd(tmq_lattice *lat, const tmq_nd_params *p, int sign, tmq_prec prec, const double *in,
+                      double *out);
+int tmq_apply_Qhat_nd_dev(tmq_lattice *lat, const tmq_nd_params *p, int sign, tmq_prec prec, const double *in,
+                          double *out, void *stream);
+/* Solve Qhat_h^+ Qhat_h^- x = b; x_0 = 0; info as for tmq_solve (the
+ * residual is over both flavours). */
+int tmq_solve_nd(tmq_lattice *lat, const tmq_nd_params *p, const tmq_solver_opts *opts, const double *b, double *x,
+                 tmq_solve_info *info);
+int tmq_solve_nd_dev(tmq_lattice *lat, const tmq_nd_params *p, const tmq_solver_opts *opts, const double *b,
+                     double *x, void *stream, tmq_solve_info *info);
+/* n doublets (1 <= n <= TMQ_MAX_RHS / 2) solved together, each with its own
+ * kappa, mubar and epsbar (common theta), links read once per half-sweep for
+ * all of them; each result equals its solve alone bit for bit. */
+int tmq_solve_nd_batch_dev(tmq_lattice *lat, int n, const tmq_nd_params *p, const tmq_solver_opts *opts,
+                           const double *const *b, double *const *x, void *stream, tmq_solve_info *info);
+
 /* Even/odd split and merge of canonical spinor fields (App. B: the even/odd
  * decomposition of a field): full = complex128 [V][4][3] over lexicographic
  * sites, even/odd = complex128 [V/2][4][3] over the sites of that parity in

@@ -11,7 +11,7 @@
 
 namespace tmq {
 int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o, const double *const *b,
-                double *const *x, hipStream_t st, tmq_solve_info *info);
+                double *const *x, hipStream_t st, tmq_solve_info *info, const double *eps = nullptr);
 int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const FieldDesc &b, const FieldDesc &x,
                hipStream_t st, tmq_solve_info *info);
 int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const double2 *phi, double2 *psi,
@@ -79,6 +79,55 @@ int qhat_dev(Lattice *L, const tmq_params *p, int sign, int prec, const double *
     const LinkDesc lk = lattice_links(L, link_fmt_for(L, prec, prec == TMQ_FP32 ? P32 : P16));
     TMQ_HIP(launch_from_canonical((const double2 *)in, fi, st));
     TMQ_TRY(apply_Qhat(L, make_op(L, p, 1), sign, fi, fo, te, lk, rhs_all(1), nullptr, nullptr, st));
+    TMQ_HIP(launch_to_canonical(fo, (double2 *)out, st));
+    return TMQ_OK;
+}
+
+int check_nd(const tmq_nd_params *p)
+{
+    if (!p) {
+        set_error("NULL tmq_nd_params");
+        return TMQ_EINVAL;
+    }
+    const double d = 1.0 + p->mubar_tilde * p->mubar_tilde - p->epsbar_tilde * p->epsbar_tilde;
+    if (!std::isfinite(p->kappa) || !std::isfinite(p->mubar_tilde) || !std::isfinite(p->epsbar_tilde) ||
+        !(d > 0.0)) {
+        set_error("doublet parameters must be finite with 1 + mubar^2 - epsbar^2 > 0");
+        return TMQ_EINVAL;
+    }
+    for (int mu = 0; mu < 4; mu++)
+        if (!std::isfinite(p->theta[mu])) {
+            set_error("theta must be finite");
+            return TMQ_EINVAL;
+        }
+    return TMQ_OK;
+}
+
+// the one-flavour parameter record of a doublet (mu_tilde carries 2 kappa mubar)
+tmq_params nd_base(const tmq_nd_params &p)
+{
+    tmq_params q{};
+    q.kappa = p.kappa;
+    q.mu_tilde = p.mubar_tilde;
+    for (int mu = 0; mu < 4; mu++) q.theta[mu] = p.theta[mu];
+    return q;
+}
+
+// doublet Qhat_h on device canonical buffers [2][V/2][12]
+int qhat_nd_dev(Lattice *L, const tmq_nd_params &p, int sign, int prec, const double *in, double *out, hipStream_t st)
+{
+    const long n = 2 * L->g.vh;
+    FieldDesc fi, fo, te;
+    TMQ_TRY(work_field(L, "nd_in", prec, n, &fi));
+    TMQ_TRY(work_field(L, "nd_out", prec, n, &fo));
+    TMQ_TRY(work_field(L, "nd_te", prec, n, &te));
+    const LinkDesc lk = lattice_links(L, link_fmt_for(L, prec, prec == TMQ_FP32 ? P32 : P16));
+    const tmq_params q = nd_base(p);
+    OpParams op = make_op(L, &q, 1);
+    op.eps[0] = p.epsbar_tilde;
+    op.nd = 1;
+    TMQ_HIP(launch_from_canonical((const double2 *)in, fi, st));
+    TMQ_TRY(apply_Qhat(L, op, sign, fi, fo, te, lk, rhs_all(1), nullptr, nullptr, st));
     TMQ_HIP(launch_to_canonical(fo, (double2 *)out, st));
     return TMQ_OK;
 }
@@ -382,6 +431,92 @@ int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solve
     const int s = tmq_solve_M_dev(lat, p, sign, opts, (const double *)dphi, (double *)dpsi, L->own, info);
     if (s == TMQ_OK || s == TMQ_ENOCONV) {
         TMQ_HIP(hipMemcpyAsync(psi, dpsi, bytes, hipMemcpyDeviceToHost, L->own));
+        TMQ_HIP(hipStreamSynchronize(L->own));
+    }
+    return s;
+}
+
+int tmq_apply_Qhat_nd_dev(tmq_lattice *lat, const tmq_nd_params *p, int sign, tmq_prec prec, const double *in,
+                          double *out, void *stream)
+{
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_nd(p));
+    TMQ_TRY(check_sign(sign));
+    TMQ_TRY(check_prec(prec));
+    TMQ_TRY(check_ptrs(in, out));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    return qhat_nd_dev(L, *p, sign, prec, in, out, (hipStream_t)stream);
+}
+
+int tmq_apply_Qhat_nd(tmq_lattice *lat, const tmq_nd_params *p, int sign, tmq_prec prec, const double *in,
+                      double *out)
+{
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_ptrs(in, out));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const size_t bytes = (size_t)2 * L->g.vh * 12 * sizeof(double2);
+    double *din = nullptr;
+    TMQ_TRY(copy_in(L, 0, in, bytes, &din));
+    void *d = nullptr;
+    TMQ_TRY(stage_buffer(L, 1, bytes, &d));
+    TMQ_TRY(tmq_apply_Qhat_nd_dev(lat, p, sign, prec, din, (double *)d, L->own));
+    TMQ_HIP(hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, L->own));
+    TMQ_HIP(hipStreamSynchronize(L->own));
+    return TMQ_OK;
+}
+
+int tmq_solve_nd_batch_dev(tmq_lattice *lat, int n, const tmq_nd_params *p, const tmq_solver_opts *opts,
+                           const double *const *b, double *const *x, void *stream, tmq_solve_info *info)
+{
+    if (info && n > 0) memset(info, 0, sizeof(*info) * (size_t)n);
+    TMQ_TRY(check_lat(lat, true));
+    if (n < 1 || n > TMQ_MAX_RHS / 2 || !p || !b || !x) {
+        set_error("tmq_solve_nd_batch: need 1 <= n <= TMQ_MAX_RHS / 2 and non-NULL arrays");
+        return TMQ_EINVAL;
+    }
+    std::vector<tmq_params> q((size_t)n);
+    std::vector<double> eps((size_t)n);
+    for (int r = 0; r < n; r++) {
+        TMQ_TRY(check_nd(&p[r]));
+        TMQ_TRY(check_ptrs(b[r], x[r]));
+        for (int mu = 0; mu < 4; mu++)
+            if (p[r].theta[mu] != p[0].theta[mu]) {
+                set_error("tmq_solve_nd_batch: every doublet must have the same boundary phases");
+                return TMQ_EINVAL;
+            }
+        q[r] = nd_base(p[r]);
+        eps[r] = p[r].epsbar_tilde;
+    }
+    TMQ_TRY(check_opts(opts));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    return solve_batch(L, n, q.data(), *opts, b, x, (hipStream_t)stream, info, eps.data());
+}
+
+int tmq_solve_nd_dev(tmq_lattice *lat, const tmq_nd_params *p, const tmq_solver_opts *opts, const double *b,
+                     double *x, void *stream, tmq_solve_info *info)
+{
+    return tmq_solve_nd_batch_dev(lat, 1, p, opts, &b, &x, stream, info);
+}
+
+int tmq_solve_nd(tmq_lattice *lat, const tmq_nd_params *p, const tmq_solver_opts *opts, const double *b, double *x,
+                 tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_ptrs(b, x));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const size_t bytes = (size_t)2 * L->g.vh * 12 * sizeof(double2);
+    double *db = nullptr;
+    TMQ_TRY(copy_in(L, 0, b, bytes, &db));
+    void *dx = nullptr;
+    TMQ_TRY(stage_buffer(L, 1, bytes, &dx));
+    const int s = tmq_solve_nd_dev(lat, p, opts, db, (double *)dx, L->own, info);
+    if (s == TMQ_OK || s == TMQ_ENOCONV) {
+        TMQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, L->own));
         TMQ_HIP(hipStreamSynchronize(L->own));
     }
     return s;

@@ -17,8 +17,9 @@
 
 namespace tmq {
 
-size_t engine_slot_bytes(long vh, int sloppy, int mode)
+size_t engine_slot_bytes(long vh, int sloppy, int mode, bool nd)
 {
+    if (nd) return engine_slot_bytes(2 * vh, sloppy, mode, false);
     // switch mode: b, x, r, t_e, t_o, p, A p in FP64 and p, A p, t_e, t_o reduced
     if (mode == TMQ_MODE_SWITCH)
         return 7 * field_bytes(P64, vh) + (sloppy == P64 ? 0 : 4 * field_bytes(sloppy, vh));
@@ -29,9 +30,9 @@ size_t engine_slot_bytes(long vh, int sloppy, int mode)
     return 5 * field_bytes(P64, vh) + 4 * field_bytes(sloppy, vh) + field_bytes(P32, vh);
 }
 
-size_t engine_bytes(const Lattice *L, int sloppy, int cap, int mode)
+size_t engine_bytes(const Lattice *L, int sloppy, int cap, int mode, bool nd)
 {
-    return (size_t)cap * engine_slot_bytes(L->g.vh, sloppy, mode) + (size_t)cap * 3 * L->pstride * sizeof(double) +
+    return (size_t)cap * engine_slot_bytes(L->g.vh, sloppy, mode, nd) + (size_t)cap * 3 * L->pstride * sizeof(double) +
            (size_t)cap * sizeof(CgScalars);
 }
 
@@ -59,10 +60,11 @@ Engine::~Engine()
     if (ring) hipHostFree(ring);
 }
 
-int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hipStream_t st, Engine **out)
+int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hipStream_t st, Engine **out,
+                  bool nd)
 {
-    if (cap < 1 || cap > MAX_RHS) {
-        set_error("engine: capacity must be 1..64");
+    if (cap < 1 || cap > (nd ? MAX_RHS / 2 : MAX_RHS)) {
+        set_error(nd ? "engine: capacity must be 1..32 doublets" : "engine: capacity must be 1..64");
         return TMQ_EINVAL;
     }
     Engine *E = new Engine();
@@ -78,7 +80,10 @@ int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hi
     E->mode = mode;
     E->mixed = sloppy != P64 && mode == TMQ_MODE_RELIABLE;
     E->switching = sloppy != P64 && mode == TMQ_MODE_SWITCH;
-    const long vh = L->g.vh;
+    E->nd = nd;
+    E->op.nd = nd ? 1 : 0;
+    const long vh = nd ? 2 * L->g.vh : L->g.vh;
+    E->n = vh;
     E->fields.reserve(16);
     auto field = [&](int prec, FieldDesc *d) -> int {
         E->fields.emplace_back();
@@ -142,7 +147,7 @@ int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hi
             return fail(TMQ_EDEVICE);
         }
     E->slots.assign(cap, Engine::Slot{});
-    E->bytes = engine_bytes(L, sloppy, cap, mode);
+    E->bytes = engine_bytes(L, sloppy, cap, mode, nd);
     *out = E;
     return TMQ_OK;
 }
@@ -176,7 +181,7 @@ int engine_occupied(const Engine *E)
     return n;
 }
 
-int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts &o, const double2 *b)
+int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts &o, const double2 *b, double epsbar)
 {
     if (slot < 0 || slot >= E->cap || E->slots[slot].state != Engine::FREE) {
         set_error("engine: slot is not free");
@@ -196,6 +201,7 @@ int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts 
     }
     E->op.kappa[slot] = p.kappa;
     E->op.mut[slot] = p.mu_tilde;
+    E->op.eps[slot] = E->nd ? epsbar : 0.0;
     Engine::Slot &s = E->slots[slot];
     s = Engine::Slot{};
     s.tol = o.tol;
@@ -210,7 +216,7 @@ int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts 
     TMQ_HIP(launch_zero(E->x, one, st));
     TMQ_HIP(launch_convert(E->b, E->r64, one, st));
     TMQ_HIP(launch_norm2(E->r64, one, E->partial[1], L->pstride, st));
-    TMQ_HIP(launch_scalar(SC_INIT, one, E->partial[1], L->pstride, blas_grid(L->g.vh), E->scal, o.tol * o.tol,
+    TMQ_HIP(launch_scalar(SC_INIT, one, E->partial[1], L->pstride, blas_grid(E->n), E->scal, o.tol * o.tol,
                           o.relative, false, nullptr, st));
     if (E->mixed) {
         TMQ_HIP(launch_convert(E->r64, E->rs, one, st));
@@ -247,7 +253,7 @@ static int body_switched(Engine *E, const RhsList &al, CgScalars *pub)
     TMQ_TRY(apply_Qhat(L, E->op, +1, E->tos, E->apss, E->tes, E->lks, al, nullptr, S, st));
     TMQ_HIP(launch_convert(E->apss, E->ap64, al, st));
     TMQ_HIP(launch_axpy_norm(E->x, E->ps, E->r64, E->ap64, al, S, E->partial[1], L->pstride, true, st));
-    TMQ_HIP(launch_scalar(SC_BETA, al, E->partial[1], L->pstride, blas_grid(L->g.vh), S, 0, 0, true, pub, st));
+    TMQ_HIP(launch_scalar(SC_BETA, al, E->partial[1], L->pstride, blas_grid(E->n), S, 0, 0, true, pub, st));
     return TMQ_OK;
 }
 

@@ -46,6 +46,8 @@ struct Engine {
     int cap = 0;
     bool mixed = false;     // reliable-update mode with a reduced inner precision
     bool switching = false; // switch mode with a reduced operator precision
+    bool nd = false;        // slots hold flavour doublets (eq. (Dh)), op.nd set
+    long n = 0;             // sites of a slot's fields: V/2, or 2 V/2 for doublets
 
     std::vector<Field> fields;
     FieldDesc b, x, r64, te64, to64, rs, ps, tes, tos, xs;
@@ -81,22 +83,27 @@ struct Engine {
 };
 
 // Bytes of device memory one slot holds (work fields of one right-hand side).
-size_t engine_slot_bytes(long vh, int sloppy, int mode = 0);
+size_t engine_slot_bytes(long vh, int sloppy, int mode = 0, bool nd = false);
 // Bytes an engine of cap slots holds in total.
-size_t engine_bytes(const Lattice *L, int sloppy, int cap, int mode = 0);
+size_t engine_bytes(const Lattice *L, int sloppy, int cap, int mode = 0, bool nd = false);
 
-// Allocate an engine with cap slots (1..MAX_RHS) on L for the inner
-// precision (sloppy, sloppy_link) and mode of the options; commands go to
-// stream st.
-int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hipStream_t st, Engine **out);
+// Allocate an engine with cap slots (1..MAX_RHS, 1..MAX_RHS/2 for doublets)
+// on L for the inner precision (sloppy, sloppy_link) and mode of the options;
+// commands go to stream st.  nd: every slot is a flavour doublet (fields of
+// 2 V/2 sites, upper flavour first) and the operator that of eq. (Dh).
+int engine_create(Lattice *L, int sloppy, int sloppy_link, int mode, int cap, hipStream_t st, Engine **out,
+                  bool nd = false);
 // Default delta of reliable updates for an inner spinor and link precision.
 double engine_default_delta(int sloppy, int sloppy_link);
 
-// Put right-hand side b (device, canonical odd-site complex128 [V/2][12])
-// into free slot `slot` and enqueue its initialisation.  Boundary phases are
-// common to the engine: theta must equal that of the slots already running.
-// tol, relative, max_iter and delta of o apply to this slot.
-int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts &o, const double2 *b);
+// Put right-hand side b (device, canonical odd-site complex128 [V/2][12];
+// [2][V/2][12] for doublets) into free slot `slot` and enqueue its
+// initialisation.  Boundary phases are common to the engine: theta must equal
+// that of the slots already running.  tol, relative, max_iter and delta of o
+// apply to this slot; epsbar (2 kappa epsbar) only to doublets, whose p.mu_tilde
+// is 2 kappa mubar.
+int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts &o, const double2 *b,
+                double epsbar = 0.0);
 int engine_free_slot(const Engine *E);  // a free slot, or -1
 int engine_begin_step(Engine *E);
 // True when the scalars end_step() reads are on the host (never blocks).

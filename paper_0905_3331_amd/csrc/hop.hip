@@ -47,6 +47,16 @@ int hop_grid_variant(const Geom &g, int v)
 }
 
 
+bool hop_all_variants(int prec, int link_fmt)
+{
+    // the pairings of a solve's inner iteration and of FP64; the others
+    // (FP32 spinors on FP16 links, 16-bit spinors on FP32 links) are
+    // instantiated with the plain order only
+    if (prec == P64) return true;
+    if (prec == P32) return link_fmt == LK32R;
+    return link_fmt == LK16R;
+}
+
 // per-format entry points (hop_f64.hip, hop_f32.hip, hop_f16.hip)
 #define TMQ_HOP_ARGS                                                                                       \
     const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,           \

@@ -202,6 +202,49 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)
     }
 }
 
+// The site terms of the flavour doublet (eq. (Dh)) for the two flavours of a
+// lane, in place of their hop sums acc[0] (upper flavour) and acc[1] (lower):
+// K1 multiplies by kappa^2 A^-1, A^-1 = (1 - i m g5 tau^3 - e tau^1) / d with
+// m = sigma mubar, e = epsbar, d = 1 + m^2 - e^2; K2 forms g5 (A self - acc).
+// Upper spins have g5 = +1, lower g5 = -1.
+template <class SP, class LK, typename R>
+__device__ __forceinline__ void nd_mix(const HopArgs<SP, LK> &a, spinor<R> (&acc)[2], const int (&rhs)[2], long h)
+{
+    const int d = rhs[0] >> 1;
+    const double kap = a.op.kappa[d], m = a.sign * a.op.mut[d], e = a.op.eps[d];
+    if (a.epi == EPI_K1) {
+        const double c = kap * kap / (1.0 + m * m - e * e);
+        const cx<R> pm = {(R)c, (R)(-c * m)}, pp = {(R)c, (R)(c * m)};  // c (1 - i m), c (1 + i m)
+        const R ce = (R)(-c * e);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c3 = 0; c3 < 3; c3++) {
+                const cx<R> u = acc[0].c[i][c3], w = acc[1].c[i][c3];
+                // upper flavour: c (1 - i m g5) u - c e w ; lower: - c e u + c (1 + i m g5) w
+                acc[0].c[i][c3] = fma(i < 2 ? pm : pp, u, ce * w);
+                acc[1].c[i][c3] = fma(i < 2 ? pp : pm, w, ce * u);
+            }
+    } else {
+        spinor<R> su, sd;
+        a.self.at(rhs[0]).load(h, su);
+        a.self.at(rhs[1]).load(h, sd);
+        const cx<R> one_pm = {R(1), (R)m}, one_mm = {R(1), (R)(-m)};  // 1 + i m, 1 - i m
+        const R ee = (R)e;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c3 = 0; c3 < 3; c3++) {
+                // A self: upper flavour (1 + i m g5) su + e sd ; lower e su + (1 - i m g5) sd
+                const cx<R> au = fma(i < 2 ? one_pm : one_mm, su.c[i][c3], ee * sd.c[i][c3]);
+                const cx<R> ad = fma(i < 2 ? one_mm : one_pm, sd.c[i][c3], ee * su.c[i][c3]);
+                const cx<R> ou = au - acc[0].c[i][c3], od = ad - acc[1].c[i][c3];
+                acc[0].c[i][c3] = i < 2 ? ou : -ou;
+                acc[1].c[i][c3] = i < 2 ? od : -od;
+            }
+    }
+}
+
 // Variant bits: ORD is the order in which an XCD's blocks walk the lattice
 // (physical block b runs on XCD j = b % 8): ORD_PLAIN gives XCD j the j-th
 // eighth of the eo index range (a range of time-slices, lexicographic);
@@ -220,9 +263,10 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)
 // its L2; the host sizes the group for that.  With one RHS this is the
 // single-field order, and each RHS's arithmetic and partial sums do not depend
 // on the batch around it.
-template <class SP, class LK, bool SELF, bool NORM, bool NT, int ORD, bool SB, int G, int EP>
+template <class SP, class LK, bool SELF, bool NORM, bool NT, int ORD, bool SB, int G, int EP, bool ND = false>
 __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 {
+    static_assert(!ND || G == 2, "a doublet lane holds both flavours");
     using R = typename LK::real;
     const Geom &g = a.g;
     const int j = blockIdx.x & 7;
@@ -242,7 +286,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         const int ri = tup * G + gi;
         live[gi] = ri < a.rl.n;
         rhs[gi] = live[gi] ? a.rl.idx[ri] : 0;
-        if (live[gi] && a.scal && a.scal[rhs[gi]].done) live[gi] = false;
+        if (live[gi] && a.scal && a.scal[ND ? rhs[gi] >> 1 : rhs[gi]].done) live[gi] = false;
         any |= live[gi];
     }
     if (!any) return;
@@ -326,9 +370,13 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         hop_dir<3, NT>(a, in, live, acc, h, z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz,
                        z == 0 ? h + (g.LZ - 1) * sz : h - sz);
 
+        if constexpr (ND) {
+            if (live[0]) nd_mix(a, acc, rhs, h);
+        }
 #pragma unroll
         for (int gi = 0; gi < G; gi++) {
             if (!live[gi]) continue;
+            const int si = ND ? rhs[gi] >> 1 : rhs[gi];  // index of the scalars
             // epilogue coefficients of this RHS (upper spins: gamma_5 = +1, lower: -1)
             const double kap = a.op.kappa[rhs[gi]], m = a.sign * a.op.mut[rhs[gi]];
             cx<R> Au, Ad, Bu, Bd;
@@ -355,7 +403,9 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
             }
             const spinor<R> &ac = acc[gi];
             spinor<R> o;
-            if (SELF) {
+            if (ND) {
+                o = ac;  // the doublet's site terms are applied already
+            } else if (SELF) {
                 spinor<R> sf;
                 a.self.at(rhs[gi]).load(h, sf);
 #pragma unroll
@@ -378,7 +428,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
                 // CG update: x += alpha p ; r -= alpha (A p) ; |r|^2
                 using XS = typename XsOf<SP>::type;
                 using RX = typename XS::real;
-                const double al = a.scal[rhs[gi]].alpha;
+                const double al = a.scal[si].alpha;
                 const R ar = (R)al;
                 const RX ax = (RX)al;
                 spinor<R> rr, pp;
@@ -420,7 +470,12 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
             }
         }
     }
-    if (NORM) {
+    if (NORM && ND) {
+        // one sum over both flavours per doublet
+        __shared__ double sh[HOP_BLOCK / 64];
+        const double s = block_sum(nrm[0] + nrm[1], sh);
+        if (threadIdx.x == 0) a.partial[(rhs[0] >> 1) * a.pstride + pidx] = s;
+    } else if (NORM) {
         __shared__ double sh[G][HOP_BLOCK / 64];
 #pragma unroll
         for (int gi = 0; gi < G; gi++) {
@@ -432,6 +487,27 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 }
 
 // ------------------------------------------------------------- dispatch
+
+// doublet launches: two flavours per lane, K1 (no self, no norm), K2 with
+// or without the norm, and the fused CG and residual epilogues
+template <class SP, class LK, int ORD>
+void go_nd(const HopArgs<SP, LK> &a, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
+{
+    if (ep == EP_CG)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, false, ORD, false, 2, EP_CG, true>), grid, block, lds, st, a);
+    else if (ep == EP_RES)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, false, ORD, false, 2, EP_RES, true>), grid, block, lds, st,
+                           a);
+    else if (s && n)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, false, ORD, false, 2, EP_STORE, true>), grid, block, lds,
+                           st, a);
+    else if (s)
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, false, ORD, false, 2, EP_STORE, true>), grid, block, lds,
+                           st, a);
+    else
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, false, ORD, false, 2, EP_STORE, true>), grid, block, lds,
+                           st, a);
+}
 
 template <class SP, class LK, bool NT, int ORD, bool SB, int G>
 void go_w(const HopArgs<SP, LK> &a, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
@@ -502,8 +578,38 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         a.cg_p = make_bv<SP>(cg->p);
         if (ep == EP_CG) a.cg_x = make_bv<typename XsOf<SP>::type>(cg->x);
     }
+    if (ALL != hop_all_variants(in.prec, lk.fmt)) return hipErrorInvalidValue;  // tables out of step
     int variant = tu.variant;
     if (!ALL || !hop_variant_valid(g, variant)) variant = 0;
+    if (op.nd) {
+        // doublets: both flavours of a site in one lane (pairs 2d, 2d + 1 of rl)
+        if (rl.n % 2) return hipErrorInvalidValue;
+        for (int i = 0; i < rl.n; i += 2)
+            if (rl.idx[i] % 2 || rl.idx[i + 1] != rl.idx[i] + 1) return hipErrorInvalidValue;
+        if (epi != EPI_K1 && epi != EPI_K2 && ep == EP_STORE) return hipErrorInvalidValue;
+        const bool s = epi != EPI_K1, n = partial != nullptr;
+        if (s && !self.data) return hipErrorInvalidValue;
+        if (!s && n) return hipErrorInvalidValue;
+        a.nblk = hop_grid_variant(g, variant);
+        const int ntup = rl.n / 2;
+        const int grp = tu.group > 0 ? tu.group : rhs_group(g, in.prec, rl.n);
+        a.group = (grp + 1) / 2;
+        if (a.group > ntup) a.group = ntup;
+        a.epi = ep == EP_STORE ? epi : EPI_K2;
+        const dim3 grid(a.nblk * ntup), block(HOP_BLOCK);
+        const int ord = variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB;
+        if constexpr (ALL) {
+            if (ord == ORD_ZSLAB)
+                go_nd<SP, LK, ORD_ZSLAB>(a, s, n, ep, grid, block, tu.lds, st);
+            else if (ord == ORD_TSLAB)
+                go_nd<SP, LK, ORD_TSLAB>(a, s, n, ep, grid, block, tu.lds, st);
+            else
+                go_nd<SP, LK, ORD_PLAIN>(a, s, n, ep, grid, block, tu.lds, st);
+        } else {
+            go_nd<SP, LK, ORD_PLAIN>(a, s, n, ep, grid, block, tu.lds, st);
+        }
+        return hipGetLastError();
+    }
     int G = MULTI && ALL && rl.n > 1 ? tu.rpl : 1;
     if (G != 2) G = 1;
     const int ntup = (rl.n + G - 1) / G;

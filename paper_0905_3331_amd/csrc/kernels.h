@@ -66,10 +66,18 @@ struct LinkDesc {
 
 // Operator parameters of a launch: boundary phases common to the batch,
 // kappa and mut = 2 kappa mu per RHS (indexed by the batch index).
+//
+// nd = 1: the flavour doublet of eq. (Dh) (mut is 2 kappa mubar, eps is
+// 2 kappa epsbar).  A doublet field is one field of twice the sites, the
+// upper flavour's sites first; doublet d of a batch has its parameters at
+// index d.  Host wrappers present the launch to the kernel as a batch of
+// single-flavour fields in which doublet d is the pair 2d, 2d + 1.
 struct OpParams {
     double ph[4][2];  // e^{i theta_mu pi / L_mu} (re, im), mu = t, x, y, z
     double kappa[MAX_RHS];
     double mut[MAX_RHS];
+    double eps[MAX_RHS];
+    int nd = 0;
 };
 
 // Epilogue of a hop half-sweep at output site h (spin s; upper = spins 0,1
@@ -84,6 +92,13 @@ struct OpParams {
 //              not stored
 //   EPI_K2_RES as EPI_K2, then r = b - out (the true residual) with its norm;
 //              out is not stored
+// For a doublet (OpParams::nd) the lane holds both flavours (f, f') of its
+// site and, with A = 1 + sigma i mubar g5 tau^3 + epsbar tau^1 the site term
+// and d = 1 + mubar^2 - epsbar^2,
+//   EPI_K1   out = kappa^2 / d (1 - sigma i mubar g5 tau^3 - epsbar tau^1) acc
+//   EPI_K2   out = g5 [A self - acc]
+// and the fused epilogues as above, per flavour, with the doublet's scalars;
+// the norm is over both flavours.  Other epilogues are refused.
 enum HopEpi { EPI_K1 = 0, EPI_K2 = 1, EPI_FULL = 2, EPI_K2_CG = 3, EPI_K2_RES = 4, EPI_SRC = 5, EPI_REC = 6 };
 
 // Vectors of the fused epilogues: r and p in the hop's spinor format (p is b
@@ -121,6 +136,9 @@ int blas_grid(long n);
 enum HopOrder { ORD_PLAIN = 0, ORD_ZSLAB = 1, ORD_TSLAB = 2 };
 constexpr int HOP_VARIANTS = 5;
 bool hop_variant_valid(const Geom &g, int v);
+// whether the (spinor precision, link format) pairing has every variant; the
+// others always run variant 0 whatever HopTune asks for
+bool hop_all_variants(int prec, int link_fmt);
 // blocks per RHS (= per-block partial sums written with a norm) of variant v
 int hop_grid_variant(const Geom &g, int v);
 

@@ -334,7 +334,8 @@ static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const
         *us = ms * 1e3f / reps;
         return TMQ_OK;
     };
-    for (int v = 0; v < HOP_VARIANTS; v++) {
+    const int nv = hop_all_variants(in.prec, lk.fmt) ? HOP_VARIANTS : 1;
+    for (int v = 0; v < nv; v++) {
         if (!hop_variant_valid(L->g, v)) continue;
         float us = 0.f;
         TMQ_TRY(time_one(v, 0, &us));
@@ -464,11 +465,103 @@ std::string tuning_report(const Lattice *L)
     return s;
 }
 
+// A doublet field (2 V/2 sites, upper flavour first) seen as a batch of two
+// single-flavour fields per doublet: doublet d becomes the pair 2d, 2d + 1.
+static FieldDesc flavour_view(const FieldDesc &f)
+{
+    FieldDesc o = f;
+    if (!f.data) return o;
+    o.n = f.n / 2;
+    o.nrhs = 2 * f.nrhs;
+    o.rhs_elems = f.rhs_elems / 2;
+    o.rhs_sites = f.rhs_sites / 2;
+    return o;
+}
+
+static double fused_extra_bytes(int prec, int epi)
+{
+    // the epilogue's own vectors instead of the output: CG reads r, p, x and writes r, x
+    // (the output is not stored); the residual reads b and writes r
+    const double sp = prec == P64 ? 192.0 : prec == P32 ? 96.0 : 52.0;
+    const double xsp = prec == P64 ? 192.0 : 96.0;
+    return epi == EPI_K2_CG ? (sp + 2 * xsp) : epi == EPI_K2_RES ? sp : 0.0;
+}
+
+// hop half-sweep of a batch of doublets (op.nd): both flavours of a site in
+// one lane, the launch shape of the format's single-field tuning
+static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
+                  const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
+                  const CgScalars *scal, hipStream_t st, const CgFields *cg)
+{
+    const long n2 = 2 * L->g.vh;
+    const bool fused = epi == EPI_K2_CG || epi == EPI_K2_RES;
+    if (2 * rl.n > MAX_RHS || in.n != n2 || (!fused && out.n != n2) || (self.data && self.n != n2) ||
+        (in.rhs_elems != n2 * field_blocks(in.prec))) {
+        set_error("internal: doublet fields must hold 2 V/2 sites per doublet, at most 32 doublets");
+        return TMQ_EINVAL;
+    }
+    const FieldDesc fi = flavour_view(in), fs = flavour_view(self), fo = flavour_view(out);
+    CgFields c2;
+    if (cg) {
+        c2.r = flavour_view(cg->r);
+        c2.p = flavour_view(cg->p);
+        c2.x = flavour_view(cg->x);
+    }
+    RhsList fl;
+    fl.n = 2 * rl.n;
+    for (int i = 0; i < rl.n; i++) {
+        fl.idx[2 * i] = (unsigned char)(2 * rl.idx[i]);
+        fl.idx[2 * i + 1] = (unsigned char)(2 * rl.idx[i] + 1);
+    }
+    const int key = in.prec * 4 + lk.fmt;
+    if (L->forced_variant >= 0) {
+        L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;
+        if (L->forced_cap >= 0) L->hop_occ[key] = occ_lds(L, L->forced_cap) == ~0u ? 0 : L->forced_cap;
+    } else if (L->hop_variant[key] < 0) {
+        if (fused) {
+            set_error("internal: fused hop epilogue before the format was tuned");
+            return TMQ_ESTATE;
+        }
+        // tune the format on single-field launches of the first upper flavour
+        OpParams o1 = op;
+        o1.nd = 0;
+        RhsList one;
+        one.n = 1;
+        one.idx[0] = fl.idx[0];
+        TMQ_TRY(tune_hop(L, key, out_par, fi, fs, fo, lk, o1, epi, sign, one, false, st));
+    }
+    HopTune tu;
+    tu.variant = L->hop_variant[key];
+    tu.lds = occ_lds(L, L->hop_occ[key]);
+    tu.rpl = 2;
+    TimedLaunch t{};
+    if (L->timing) {
+        t.a = pool_event(L);
+        t.b = pool_event(L);
+        t.bytes = (hop_bytes_per_site(in.prec, lk.fmt, epi != EPI_K1, fl.n) + fused_extra_bytes(in.prec, epi) * fl.n) *
+                  (double)L->g.vh;
+        t.flops = 1320.0 * (double)L->g.vh * fl.n;
+        t.prec = in.prec;
+        t.nrhs = fl.n;
+        TMQ_HIP(hipEventRecord(t.a, st));
+    }
+    TMQ_HIP(launch_hop(L->g, out_par, fi, fs, fo, lk, op, epi, sign, fl, partial, L->pstride, scal, tu, st,
+                       cg ? &c2 : nullptr));
+    // partial sums of the launch: its blocks per field, from the variant it ran
+    L->hop_blocks_last = hop_grid_variant(L->g, hop_all_variants(in.prec, lk.fmt) ? L->hop_variant[key] : 0);
+    if (L->timing) {
+        TMQ_HIP(hipEventRecord(t.b, st));
+        L->timed.push_back(t);
+    }
+    return TMQ_OK;
+}
+
 int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
         const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
         const CgScalars *scal, hipStream_t st, const CgFields *cg)
 {
     if (rl.n <= 0) return TMQ_OK;
+    if (op.nd) return hop_nd(L, out_par, in, self, out, lk, op, epi, sign, rl, partial, scal, st, cg);
     const int key = in.prec * 4 + lk.fmt;
     const bool fused = epi == EPI_K2_CG || epi == EPI_K2_RES;
     if (fused && L->forced_variant < 0 && L->hop_variant[key] < 0) {
@@ -509,21 +602,16 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
     if (L->timing) {
         t.a = pool_event(L);
         t.b = pool_event(L);
-        t.bytes = hop_bytes_per_site(in.prec, lk.fmt, epi != EPI_K1, rl.n) * (double)L->g.vh;
-        if (fused) {
-            // the epilogue's own vectors instead of the output: CG reads r, p, x and writes r, x
-            // (the output is not stored); the residual reads b and writes r
-            const double sp = in.prec == P64 ? 192.0 : in.prec == P32 ? 96.0 : 52.0;
-            const double xsp = in.prec == P64 ? 192.0 : 96.0;
-            t.bytes += (epi == EPI_K2_CG ? (sp + 2 * xsp) : sp) * (double)L->g.vh * rl.n;
-        }
+        t.bytes = (hop_bytes_per_site(in.prec, lk.fmt, epi != EPI_K1, rl.n) + fused_extra_bytes(in.prec, epi) * rl.n) *
+                  (double)L->g.vh;
         t.flops = 1320.0 * (double)L->g.vh * rl.n;
         t.prec = in.prec;
         t.nrhs = rl.n;
         TMQ_HIP(hipEventRecord(t.a, st));
     }
     TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal, tu, st, cg));
-    L->hop_blocks_last = hop_grid_variant(L->g, L->hop_variant[key]);
+    // partial sums of the launch: its blocks per field, from the variant it ran
+    L->hop_blocks_last = hop_grid_variant(L->g, hop_all_variants(in.prec, lk.fmt) ? L->hop_variant[key] : 0);
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));
         L->timed.push_back(t);

@@ -17,13 +17,13 @@ namespace tmq {
 
 // the lattice's engine for this inner precision and link format with at
 // least n slots (grown by reallocation when a larger batch comes)
-static int lattice_engine(Lattice *L, const tmq_solver_opts &o, int n, Engine **out)
+static int lattice_engine(Lattice *L, const tmq_solver_opts &o, int n, bool nd, Engine **out)
 {
     const int sp = o.sloppy;
     const int lk = sp == P64 ? link_fmt_for(L, P64, P64) : link_fmt_for(L, sp, o.sloppy_link);
     for (size_t i = 0; i < L->engines.size(); i++) {
         Engine *E = L->engines[i];
-        if (E->sloppy != sp || E->lks.fmt != lk || E->mode != o.mode) continue;
+        if (E->sloppy != sp || E->lks.fmt != lk || E->mode != o.mode || E->nd != nd) continue;
         if (E->cap >= n) {
             *out = E;
             return TMQ_OK;
@@ -33,7 +33,7 @@ static int lattice_engine(Lattice *L, const tmq_solver_opts &o, int n, Engine **
         break;
     }
     Engine *E = nullptr;
-    TMQ_TRY(engine_create(L, sp, o.sloppy_link, o.mode, n, nullptr, &E));
+    TMQ_TRY(engine_create(L, sp, o.sloppy_link, o.mode, n, nullptr, &E, nd));
     L->engines.push_back(E);
     *out = E;
     return TMQ_OK;
@@ -51,15 +51,17 @@ struct EngineScope {
     }
 };
 
+// eps != nullptr: the right-hand sides are flavour doublets with 2 kappa
+// epsbar = eps[r] (and 2 kappa mubar = p[r].mu_tilde)
 int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o, const double *const *b,
-                double *const *x, hipStream_t st, tmq_solve_info *info)
+                double *const *x, hipStream_t st, tmq_solve_info *info, const double *eps)
 {
     const auto t0 = std::chrono::steady_clock::now();
     Engine *E = nullptr;
-    TMQ_TRY(lattice_engine(L, o, n, &E));
+    TMQ_TRY(lattice_engine(L, o, n, eps != nullptr, &E));
     E->st = st;
     EngineScope scope{E};
-    for (int r = 0; r < n; r++) TMQ_TRY(engine_join(E, r, p[r], o, (const double2 *)b[r]));
+    for (int r = 0; r < n; r++) TMQ_TRY(engine_join(E, r, p[r], o, (const double2 *)b[r], eps ? eps[r] : 0.0));
     while (engine_running(E) > 0) {
         TMQ_TRY(engine_begin_step(E));
         TMQ_TRY(engine_end_step(E, nullptr));
@@ -159,7 +161,7 @@ int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o,
         tmq_solve_info ci{};
         const double *bp = (const double *)bc.data;
         double *yp = (double *)yc.data;
-        const int cs = solve_batch(L, 1, &p, o, &bp, &yp, st, &ci);
+        const int cs = solve_batch(L, 1, &p, o, &bp, &yp, st, &ci, nullptr);
         iters += ci.iters;
         rus += ci.reliable_updates;
         if (cs == TMQ_ENAN) {

@@ -39,6 +39,11 @@ class tmq_params(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_double), ("mu_tilde", ctypes.c_double), ("theta", ctypes.c_double * 4)]
 
 
+class tmq_nd_params(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("mubar_tilde", ctypes.c_double), ("epsbar_tilde", ctypes.c_double),
+                ("theta", ctypes.c_double * 4)]
+
+
 class tmq_solver_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("relative", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("sloppy", ctypes.c_int), ("sloppy_link", ctypes.c_int), ("delta", ctypes.c_double),
@@ -88,6 +93,12 @@ _SIGS = {
     "tmq_solve_full_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
     "tmq_solve_M": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _P(tmq_solve_info)]),
     "tmq_solve_M_dev": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_apply_Qhat_nd": (_ip, [_vp, _P(tmq_nd_params), _ip, _ip, _vp, _vp]),
+    "tmq_apply_Qhat_nd_dev": (_ip, [_vp, _P(tmq_nd_params), _ip, _ip, _vp, _vp, _vp]),
+    "tmq_solve_nd": (_ip, [_vp, _P(tmq_nd_params), _P(tmq_solver_opts), _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_solve_nd_dev": (_ip, [_vp, _P(tmq_nd_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_solve_nd_batch_dev": (_ip, [_vp, _ip, _P(tmq_nd_params), _P(tmq_solver_opts), _P(_vp), _P(_vp), _vp,
+                                     _P(tmq_solve_info)]),
     "tmq_split_eo": (_ip, [_vp, _vp, _vp, _vp]),
     "tmq_merge_eo": (_ip, [_vp, _vp, _vp, _vp]),
     "tmq_split_eo_dev": (_ip, [_vp, _vp, _vp, _vp, _vp]),
@@ -141,6 +152,17 @@ def params(kappa: float, mu_tilde: float, theta=(1.0, 0.0, 0.0, 0.0)) -> tmq_par
     p = tmq_params()
     p.kappa = float(kappa)
     p.mu_tilde = float(mu_tilde)
+    for i in range(4):
+        p.theta[i] = float(theta[i])
+    return p
+
+
+def nd_params(kappa: float, mubar_tilde: float, epsbar_tilde: float, theta=(1.0, 0.0, 0.0, 0.0)) -> tmq_nd_params:
+    """Parameters of the flavour doublet of eq. (Dh): 2 kappa mubar and 2 kappa epsbar."""
+    p = tmq_nd_params()
+    p.kappa = float(kappa)
+    p.mubar_tilde = float(mubar_tilde)
+    p.epsbar_tilde = float(epsbar_tilde)
     for i in range(4):
         p.theta[i] = float(theta[i])
     return p
@@ -346,6 +368,59 @@ class Lattice:
             code = _lib.tmq_solve_batch_dev(self._h, n, parr, ctypes.byref(opts), bp, xp, _stream(stream), infos)
         if check:
             _check(code, "tmq_solve_batch")
+        return xs, [_info(i) for i in infos]
+
+    # ------------------------------------------------------ flavour doublet
+    def apply_Qhat_nd(self, p: tmq_nd_params, sign: int, src, out=None, prec="fp64", stream=None):
+        """Qhat_h^{sign} on a doublet of odd-site fields (2, V/2, 4, 3); device tensor or host array."""
+        pr = PREC[prec] if isinstance(prec, str) else int(prec)
+        n = self.V * 12
+        if isinstance(src, np.ndarray):
+            out = np.empty_like(src) if out is None else out
+            _check(_lib.tmq_apply_Qhat_nd(self._h, ctypes.byref(p), sign, pr, _hptr(src, n, "in"),
+                                          _hptr(out, n, "out")), "tmq_apply_Qhat_nd")
+            return out
+        import torch
+
+        out = torch.empty_like(src) if out is None else out
+        _check(_lib.tmq_apply_Qhat_nd_dev(self._h, ctypes.byref(p), sign, pr, _dptr(src, n, "in"),
+                                          _dptr(out, n, "out"), _stream(stream)), "tmq_apply_Qhat_nd_dev")
+        return out
+
+    def solve_nd(self, p: tmq_nd_params, b, opts: tmq_solver_opts, x=None, stream=None, check=True):
+        """Solve Qhat_h^+ Qhat_h^- x = b for a doublet (2, V/2, 4, 3); returns (x, SolveInfo)."""
+        n = self.V * 12
+        info = tmq_solve_info()
+        if isinstance(b, np.ndarray):
+            x = np.empty_like(b) if x is None else x
+            code = _lib.tmq_solve_nd(self._h, ctypes.byref(p), ctypes.byref(opts), _hptr(b, n, "b"),
+                                     _hptr(x, n, "x"), ctypes.byref(info))
+        else:
+            import torch
+
+            x = torch.empty_like(b) if x is None else x
+            code = _lib.tmq_solve_nd_dev(self._h, ctypes.byref(p), ctypes.byref(opts), _dptr(b, n, "b"),
+                                         _dptr(x, n, "x"), _stream(stream), ctypes.byref(info))
+        if check:
+            _check(code, "tmq_solve_nd")
+        return x, _info(info)
+
+    def solve_nd_batch(self, ps, bs, opts: tmq_solver_opts, xs=None, stream=None, check=True):
+        """Solve a batch of doublets (device tensors (2, V/2, 4, 3)); returns (list of x, list of SolveInfo)."""
+        import torch
+
+        n = len(bs)
+        if len(ps) != n or not 1 <= n <= MAX_RHS // 2:
+            raise ValueError(f"need 1..{MAX_RHS // 2} doublets and one params per doublet")
+        nc = self.V * 12
+        parr = (tmq_nd_params * n)(*ps)
+        infos = (tmq_solve_info * n)()
+        xs = [torch.empty_like(b) for b in bs] if xs is None else xs
+        bp = (ctypes.c_void_p * n)(*[_dptr(b, nc, "b").value for b in bs])
+        xp = (ctypes.c_void_p * n)(*[_dptr(x, nc, "x").value for x in xs])
+        code = _lib.tmq_solve_nd_batch_dev(self._h, n, parr, ctypes.byref(opts), bp, xp, _stream(stream), infos)
+        if check:
+            _check(code, "tmq_solve_nd_batch")
         return xs, [_info(i) for i in infos]
 
     def solve_full(self, p: tmq_params, b, opts: tmq_solver_opts, x=None, stream=None, check=True):

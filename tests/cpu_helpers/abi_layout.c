@@ -13,6 +13,9 @@ int main(void)
 {
     Z(tmq_params);
     F(tmq_params, kappa); F(tmq_params, mu_tilde); F(tmq_params, theta);
+    Z(tmq_nd_params);
+    F(tmq_nd_params, kappa); F(tmq_nd_params, mubar_tilde); F(tmq_nd_params, epsbar_tilde);
+    F(tmq_nd_params, theta);
     Z(tmq_solver_opts);
     F(tmq_solver_opts, tol); F(tmq_solver_opts, relative); F(tmq_solver_opts, max_iter);
     F(tmq_solver_opts, sloppy); F(tmq_solver_opts, sloppy_link); F(tmq_solver_opts, delta);

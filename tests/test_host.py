@@ -71,7 +71,7 @@ def test_struct_layouts_match_header(tmp_path):
     for line in subprocess.check_output([str(exe)], text=True).splitlines():
         k, v = line.split()
         want[k] = int(v)
-    for cls in (tmq.tmq_params, tmq.tmq_solver_opts, tmq.tmq_solve_info, tmq.tmq_server_config,
+    for cls in (tmq.tmq_params, tmq.tmq_nd_params, tmq.tmq_solver_opts, tmq.tmq_solve_info, tmq.tmq_server_config,
                 tmq.tmq_server_stats):
         name = cls.__name__
         assert ctypes.sizeof(cls) == want[name], name
