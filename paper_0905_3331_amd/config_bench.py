@@ -10,6 +10,13 @@
                FP32 inner / FP64 outer, tol 1e-10 each; against the same 48
                solved one after another
 
+  doublet      the mass non-degenerate doublet of eq. (Dh) at 32^3x64 with the
+               paper's doublet run parameters (kappa 0.17, 2 kappa mubar 0.1105,
+               2 kappa epsbar 0.0935): doublet hop half-sweep bandwidth per
+               storage precision (links read once for both flavours), and CG on
+               Qhat_h^+ Qhat_h^- to 1e-10, FP64 vs FP32-inner vs FP16-inner,
+               3 Gaussian doublet sources, median
+
 Links are random SU(3) exp(i 0.3 H), reunitarised (seeds 1000 + workload);
 theta = (1, 0, 0, 0).  Prints one JSON object.  The solutions' accuracy
 against the FP64 oracle is checked by the GPU tests at these shapes.
@@ -148,10 +155,54 @@ def batch_24c48(tmq, torch, synth, reps):
             "batch_tuning": report.get("batch")}
 
 
+def nd_32c64(tmq, torch, synth, reps):
+    dims = (64, 32, 32, 32)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(synth.random_gauge(dims, eps=0.3, seed=1002))
+    p = tmq.nd_params(0.17, 0.1105, 0.0935, THETA)
+
+    def src(seed):
+        return torch.from_numpy(np.stack([synth.gaussian_odd(dims, seed=seed),
+                                          synth.gaussian_odd(dims, seed=seed + 1)])).cuda()
+
+    out = {"lattice": "32^3x64", "kappa": 0.17, "mubar_tilde": 0.1105, "epsbar_tilde": 0.0935, "hop": {}}
+    b = src(2400)
+    o = torch.empty_like(b)
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
+        lat.apply_Qhat_nd(p, +1, b, o, prec=prec)
+        torch.cuda.synchronize()
+        lat.set_kernel_timing(True)
+        for _ in range(20):
+            lat.apply_Qhat_nd(p, +1, b, o, prec=prec)
+        st = lat.kernel_stats("hop")
+        lat.set_kernel_timing(False)
+        out["hop"][prec] = {"avg_us": st["ms"] / st["launches"] * 1e3,
+                            "GBps": st["bytes"] / (st["ms"] * 1e-3) / 1e9,
+                            "GFLOPs": st["flops"] / (st["ms"] * 1e-3) / 1e9}
+    for name, opts in (("fp64", tmq.solver_opts(tol=1e-10)),
+                       ("fp32_inner", tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")),
+                       ("fp16_inner", tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16"))):
+        times, iters, rus, res = [], [], [], []
+        for k in range(3):
+            bk = src(2410 + 2 * k)
+            lat.solve_nd(p, bk, opts)
+            t, (x, info) = median_time(lambda: lat.solve_nd(p, bk, opts), reps)
+            times.append(t)
+            iters.append(info.iters)
+            rus.append(info.reliable_updates)
+            res.append(info.true_rel_residual)
+        out[name] = {"ms_to_1e-10_median_of_3_sources": float(np.median(times)) * 1e3,
+                     "iters": iters, "reliable_updates": rus, "max_true_rel_residual": max(res)}
+    out["speedup_fp16_inner_vs_fp64"] = out["fp64"]["ms_to_1e-10_median_of_3_sources"] / \
+        out["fp16_inner"]["ms_to_1e-10_median_of_3_sources"]
+    lat.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--only", default="full,eo,batch")
+    ap.add_argument("--only", default="full,eo,batch,nd")
     args = ap.parse_args(argv)
     import torch
 
@@ -171,6 +222,9 @@ def main(argv=None):
     if "batch" in want:
         log("24^3x48 batch of 48")
         res["batch_24c48_48rhs"] = batch_24c48(tmq, torch, synth, args.reps)
+    if "nd" in want:
+        log("32^3x64 flavour doublet")
+        res["doublet_32c64"] = nd_32c64(tmq, torch, synth, args.reps)
     print(json.dumps(res))
     return res
 

@@ -31,17 +31,18 @@ bool hop_variant_valid(const Geom &g, int v)
     return true;
 }
 
-int hop_grid_variant(const Geom &g, int v)
+int hop_grid_variant(const Geom &g, int v, int lanes_per_site)
 {
-    if (!hop_variant_valid(g, v) || kVariants[v].ord == ORD_PLAIN) return hop_grid(g.vh);
+    const long L = lanes_per_site;
+    if (!hop_variant_valid(g, v) || kVariants[v].ord == ORD_PLAIN) return hop_grid(L * g.vh);
     const long plane = (long)g.LY * g.XH;
     long per_xcd;
     if (kVariants[v].ord == ORD_ZSLAB) {
         const long zc = g.LZ / 8 + (g.LZ % 8 ? 1 : 0);
-        per_xcd = ((long)g.T * zc * plane + HOP_BLOCK - 1) / HOP_BLOCK;
+        per_xcd = (L * g.T * zc * plane + HOP_BLOCK - 1) / HOP_BLOCK;
     } else {
         const long tc = g.T / 8 + (g.T % 8 ? 1 : 0);
-        per_xcd = ((long)g.LZ * tc * plane + HOP_BLOCK - 1) / HOP_BLOCK;
+        per_xcd = (L * g.LZ * tc * plane + HOP_BLOCK - 1) / HOP_BLOCK;
     }
     return (int)(8 * per_xcd);
 }

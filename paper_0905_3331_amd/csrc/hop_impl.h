@@ -202,15 +202,31 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)
     }
 }
 
-// The site terms of the flavour doublet (eq. (Dh)) for the two flavours of a
-// lane, in place of their hop sums acc[0] (upper flavour) and acc[1] (lower):
+// The partner lane's value (lanes 2i and 2i+1 swap: DPP quad permutation
+// [1, 0, 3, 2]).  Both lanes of a pair are active or inactive together.
+__device__ __forceinline__ float pair_swap(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// The site terms of the flavour doublet (eq. (Dh)).  A doublet's two
+// flavours at one site sit in a lane pair (flavour f = lane & 1, f = 0 the
+// upper); acc is this lane's hop sum, the partner's comes by pair_swap.
 // K1 multiplies by kappa^2 A^-1, A^-1 = (1 - i m g5 tau^3 - e tau^1) / d with
 // m = sigma mubar, e = epsbar, d = 1 + m^2 - e^2; K2 forms g5 (A self - acc).
-// Upper spins have g5 = +1, lower g5 = -1.
+// Upper spins have g5 = +1, lower g5 = -1; tau^3 is +1 on the upper flavour.
 template <class SP, class LK, typename R>
-__device__ __forceinline__ void nd_mix(const HopArgs<SP, LK> &a, spinor<R> (&acc)[2], const int (&rhs)[2], long h)
+__device__ __forceinline__ void nd_mix(const HopArgs<SP, LK> &a, spinor<R> &acc, int rhs, long h)
 {
-    const int d = rhs[0] >> 1;
+    const int d = rhs >> 1;
+    const bool up = (rhs & 1) == 0;
     const double kap = a.op.kappa[d], m = a.sign * a.op.mut[d], e = a.op.eps[d];
     if (a.epi == EPI_K1) {
         const double c = kap * kap / (1.0 + m * m - e * e);
@@ -220,27 +236,25 @@ __device__ __forceinline__ void nd_mix(const HopArgs<SP, LK> &a, spinor<R> (&acc
         for (int i = 0; i < 4; i++)
 #pragma unroll
             for (int c3 = 0; c3 < 3; c3++) {
-                const cx<R> u = acc[0].c[i][c3], w = acc[1].c[i][c3];
-                // upper flavour: c (1 - i m g5) u - c e w ; lower: - c e u + c (1 + i m g5) w
-                acc[0].c[i][c3] = fma(i < 2 ? pm : pp, u, ce * w);
-                acc[1].c[i][c3] = fma(i < 2 ? pp : pm, w, ce * u);
+                const cx<R> own = acc.c[i][c3];
+                const cx<R> other = {pair_swap(own.re), pair_swap(own.im)};
+                // c (1 -+ i m g5) own - c e other (upper / lower flavour)
+                acc.c[i][c3] = fma((i < 2) == up ? pm : pp, own, ce * other);
             }
     } else {
-        spinor<R> su, sd;
-        a.self.at(rhs[0]).load(h, su);
-        a.self.at(rhs[1]).load(h, sd);
+        spinor<R> so, sx;
+        a.self.at(rhs).load(h, so);
+        a.self.at(rhs ^ 1).load(h, sx);
         const cx<R> one_pm = {R(1), (R)m}, one_mm = {R(1), (R)(-m)};  // 1 + i m, 1 - i m
         const R ee = (R)e;
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
             for (int c3 = 0; c3 < 3; c3++) {
-                // A self: upper flavour (1 + i m g5) su + e sd ; lower e su + (1 - i m g5) sd
-                const cx<R> au = fma(i < 2 ? one_pm : one_mm, su.c[i][c3], ee * sd.c[i][c3]);
-                const cx<R> ad = fma(i < 2 ? one_mm : one_pm, sd.c[i][c3], ee * su.c[i][c3]);
-                const cx<R> ou = au - acc[0].c[i][c3], od = ad - acc[1].c[i][c3];
-                acc[0].c[i][c3] = i < 2 ? ou : -ou;
-                acc[1].c[i][c3] = i < 2 ? od : -od;
+                // A self = (1 +- i m g5) own + e other
+                const cx<R> as = fma((i < 2) == up ? one_pm : one_mm, so.c[i][c3], ee * sx.c[i][c3]);
+                const cx<R> o = as - acc.c[i][c3];
+                acc.c[i][c3] = i < 2 ? o : -o;
             }
     }
 }
@@ -263,16 +277,22 @@ __device__ __forceinline__ void nd_mix(const HopArgs<SP, LK> &a, spinor<R> (&acc
 // its L2; the host sizes the group for that.  With one RHS this is the
 // single-field order, and each RHS's arithmetic and partial sums do not depend
 // on the batch around it.
+//
+// Doublets (ND): a block covers HOP_BLOCK / 2 sites, each in a lane pair
+// holding the doublet's two flavours (tuple = doublet = RHS pair 2d, 2d + 1
+// of the list); both lanes load the same link at once, so it is fetched once.
 template <class SP, class LK, bool SELF, bool NORM, bool NT, int ORD, bool SB, int G, int EP, bool ND = false>
 __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 {
-    static_assert(!ND || G == 2, "a doublet lane holds both flavours");
+    static_assert(!ND || G == 1, "a doublet lane holds one flavour, its partner lane the other");
+    constexpr int SPB = ND ? HOP_BLOCK / 2 : HOP_BLOCK;   // sites per block
+    const int ls = ND ? (int)(threadIdx.x >> 1) : (int)threadIdx.x;  // site of the lane within the block
     using R = typename LK::real;
     const Geom &g = a.g;
     const int j = blockIdx.x & 7;
     const int k = blockIdx.x >> 3;
     const int nb = a.nblk >> 3;                        // site blocks of this XCD's share
-    const int ntup = (a.rl.n + G - 1) / G;             // tuples of G RHS (one per lane)
+    const int ntup = ND ? a.rl.n / 2 : (a.rl.n + G - 1) / G;  // tuples of G RHS (one per lane), or doublets
     const int GR = a.group, gr = k / (nb * GR);        // group of tuples of this block
     const int gsize = min(GR, ntup - gr * GR);         // the last group may be smaller
     const int within = k - gr * nb * GR;
@@ -283,7 +303,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
     bool any = false;
 #pragma unroll
     for (int gi = 0; gi < G; gi++) {
-        const int ri = tup * G + gi;
+        const int ri = ND ? 2 * tup + (int)(threadIdx.x & 1) : tup * G + gi;
         live[gi] = ri < a.rl.n;
         rhs[gi] = live[gi] ? a.rl.idx[ri] : 0;
         if (live[gi] && a.scal && a.scal[ND ? rhs[gi] >> 1 : rhs[gi]].done) live[gi] = false;
@@ -299,7 +319,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         const int zb = g.LZ >> 3, zr = g.LZ & 7;
         const int zc = zb + (j < zr ? 1 : 0), z0 = j * zb + (j < zr ? j : zr);
         const long S = (long)zc * plane;  // sites of one time-slice of this slab
-        const long l = (long)sb * HOP_BLOCK + threadIdx.x;
+        const long l = (long)sb * SPB + ls;
         active = l < (long)g.T * S;
         const unsigned lu = active ? (unsigned)l : 0u;
         t = (int)(lu / (unsigned)S);
@@ -314,7 +334,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         const int tb = g.T >> 3, tr = g.T & 7;
         const int tc = tb + (j < tr ? 1 : 0), t0 = j * tb + (j < tr ? j : tr);
         const long P = (long)tc * plane;  // sites of one z-plane of this block of time-slices
-        const long l = (long)sb * HOP_BLOCK + threadIdx.x;
+        const long l = (long)sb * SPB + ls;
         active = l < (long)g.LZ * P;
         const unsigned lu = active ? (unsigned)l : 0u;
         z = (int)(lu / (unsigned)P);
@@ -327,7 +347,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         pidx = 8 * sb + j;
     } else {
         const int lb = j * (a.nblk >> 3) + sb;
-        h = (long)lb * HOP_BLOCK + threadIdx.x;
+        h = (long)lb * SPB + ls;
         active = h < g.vh;
         const unsigned hu = active ? (unsigned)h : 0u;
         xh = hu % (unsigned)g.XH;
@@ -371,7 +391,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
                        z == 0 ? h + (g.LZ - 1) * sz : h - sz);
 
         if constexpr (ND) {
-            if (live[0]) nd_mix(a, acc, rhs, h);
+            if (live[0]) nd_mix(a, acc[0], rhs[0], h);
         }
 #pragma unroll
         for (int gi = 0; gi < G; gi++) {
@@ -470,42 +490,37 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
             }
         }
     }
-    if (NORM && ND) {
-        // one sum over both flavours per doublet
-        __shared__ double sh[HOP_BLOCK / 64];
-        const double s = block_sum(nrm[0] + nrm[1], sh);
-        if (threadIdx.x == 0) a.partial[(rhs[0] >> 1) * a.pstride + pidx] = s;
-    } else if (NORM) {
+    if (NORM) {
+        // (doublets: the block's lanes hold both flavours, so the sum is over the doublet)
         __shared__ double sh[G][HOP_BLOCK / 64];
 #pragma unroll
         for (int gi = 0; gi < G; gi++) {
             if (!live[gi]) continue;
             const double s = block_sum(nrm[gi], sh[gi]);
-            if (threadIdx.x == 0) a.partial[rhs[gi] * a.pstride + pidx] = s;
+            if (threadIdx.x == 0) a.partial[(ND ? rhs[gi] >> 1 : rhs[gi]) * a.pstride + pidx] = s;
         }
     }
 }
 
 // ------------------------------------------------------------- dispatch
 
-// doublet launches: two flavours per lane, K1 (no self, no norm), K2 with
+// doublet launches: a lane pair per site, K1 (no self, no norm), K2 with
 // or without the norm, and the fused CG and residual epilogues
-template <class SP, class LK, int ORD>
+template <class SP, class LK, bool NT, int ORD>
 void go_nd(const HopArgs<SP, LK> &a, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
     if (ep == EP_CG)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, false, ORD, false, 2, EP_CG, true>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, false, 1, EP_CG, true>), grid, block, lds, st, a);
     else if (ep == EP_RES)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, false, ORD, false, 2, EP_RES, true>), grid, block, lds, st,
-                           a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, false, 1, EP_RES, true>), grid, block, lds, st, a);
     else if (s && n)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, false, ORD, false, 2, EP_STORE, true>), grid, block, lds,
-                           st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, true, NT, ORD, false, 1, EP_STORE, true>), grid, block, lds, st,
+                           a);
     else if (s)
-        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, false, ORD, false, 2, EP_STORE, true>), grid, block, lds,
-                           st, a);
+        hipLaunchKernelGGL((hop_kernel<SP, LK, true, false, NT, ORD, false, 1, EP_STORE, true>), grid, block, lds, st,
+                           a);
     else
-        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, false, ORD, false, 2, EP_STORE, true>), grid, block, lds,
+        hipLaunchKernelGGL((hop_kernel<SP, LK, false, false, NT, ORD, false, 1, EP_STORE, true>), grid, block, lds,
                            st, a);
 }
 
@@ -582,7 +597,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     int variant = tu.variant;
     if (!ALL || !hop_variant_valid(g, variant)) variant = 0;
     if (op.nd) {
-        // doublets: both flavours of a site in one lane (pairs 2d, 2d + 1 of rl)
+        // doublets: the two flavours of a site in a lane pair (RHS pairs 2d, 2d + 1 of rl)
         if (rl.n % 2) return hipErrorInvalidValue;
         for (int i = 0; i < rl.n; i += 2)
             if (rl.idx[i] % 2 || rl.idx[i + 1] != rl.idx[i] + 1) return hipErrorInvalidValue;
@@ -590,7 +605,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         const bool s = epi != EPI_K1, n = partial != nullptr;
         if (s && !self.data) return hipErrorInvalidValue;
         if (!s && n) return hipErrorInvalidValue;
-        a.nblk = hop_grid_variant(g, variant);
+        a.nblk = hop_grid_variant(g, variant, 2);  // blocks of HOP_BLOCK / 2 sites
         const int ntup = rl.n / 2;
         const int grp = tu.group > 0 ? tu.group : rhs_group(g, in.prec, rl.n);
         a.group = (grp + 1) / 2;
@@ -598,16 +613,25 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         a.epi = ep == EP_STORE ? epi : EPI_K2;
         const dim3 grid(a.nblk * ntup), block(HOP_BLOCK);
         const int ord = variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB;
+        const bool nt = ntup == 1;
+#define GON(ORD)                                                                \
+    do {                                                                        \
+        if (nt)                                                                 \
+            go_nd<SP, LK, true, ORD>(a, s, n, ep, grid, block, tu.lds, st);     \
+        else                                                                    \
+            go_nd<SP, LK, false, ORD>(a, s, n, ep, grid, block, tu.lds, st);    \
+    } while (0)
         if constexpr (ALL) {
             if (ord == ORD_ZSLAB)
-                go_nd<SP, LK, ORD_ZSLAB>(a, s, n, ep, grid, block, tu.lds, st);
+                GON(ORD_ZSLAB);
             else if (ord == ORD_TSLAB)
-                go_nd<SP, LK, ORD_TSLAB>(a, s, n, ep, grid, block, tu.lds, st);
+                GON(ORD_TSLAB);
             else
-                go_nd<SP, LK, ORD_PLAIN>(a, s, n, ep, grid, block, tu.lds, st);
+                GON(ORD_PLAIN);
         } else {
-            go_nd<SP, LK, ORD_PLAIN>(a, s, n, ep, grid, block, tu.lds, st);
+            GON(ORD_PLAIN);
         }
+#undef GON
         return hipGetLastError();
     }
     int G = MULTI && ALL && rl.n > 1 ? tu.rpl : 1;

@@ -92,8 +92,8 @@ struct OpParams {
 //              not stored
 //   EPI_K2_RES as EPI_K2, then r = b - out (the true residual) with its norm;
 //              out is not stored
-// For a doublet (OpParams::nd) the lane holds both flavours (f, f') of its
-// site and, with A = 1 + sigma i mubar g5 tau^3 + epsbar tau^1 the site term
+// For a doublet (OpParams::nd) a lane pair holds the two flavours (f, f') of
+// a site and, with A = 1 + sigma i mubar g5 tau^3 + epsbar tau^1 the site term
 // and d = 1 + mubar^2 - epsbar^2,
 //   EPI_K1   out = kappa^2 / d (1 - sigma i mubar g5 tau^3 - epsbar tau^1) acc
 //   EPI_K2   out = g5 [A self - acc]
@@ -139,8 +139,9 @@ bool hop_variant_valid(const Geom &g, int v);
 // whether the (spinor precision, link format) pairing has every variant; the
 // others always run variant 0 whatever HopTune asks for
 bool hop_all_variants(int prec, int link_fmt);
-// blocks per RHS (= per-block partial sums written with a norm) of variant v
-int hop_grid_variant(const Geom &g, int v);
+// blocks per RHS (= per-block partial sums written with a norm) of variant v;
+// lanes_per_site = 2 for doublets (a lane pair per site)
+int hop_grid_variant(const Geom &g, int v, int lanes_per_site = 1);
 
 // Hop half-sweep: out(h) over the V/2 sites of parity out_par for every RHS
 // of rl; `in` holds parity 1 - out_par; `self` (data may be nullptr unless

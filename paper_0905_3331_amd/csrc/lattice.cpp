@@ -487,8 +487,8 @@ static double fused_extra_bytes(int prec, int epi)
     return epi == EPI_K2_CG ? (sp + 2 * xsp) : epi == EPI_K2_RES ? sp : 0.0;
 }
 
-// hop half-sweep of a batch of doublets (op.nd): both flavours of a site in
-// one lane, the launch shape of the format's single-field tuning
+// hop half-sweep of a batch of doublets (op.nd): the two flavours of a site
+// in a lane pair, the block order of the format's single-field tuning
 static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, const FieldDesc &out,
                   const LinkDesc &lk, const OpParams &op, int epi, int sign, const RhsList &rl, double *partial,
                   const CgScalars *scal, hipStream_t st, const CgFields *cg)
@@ -533,7 +533,6 @@ static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc 
     HopTune tu;
     tu.variant = L->hop_variant[key];
     tu.lds = occ_lds(L, L->hop_occ[key]);
-    tu.rpl = 2;
     TimedLaunch t{};
     if (L->timing) {
         t.a = pool_event(L);
@@ -548,7 +547,7 @@ static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc 
     TMQ_HIP(launch_hop(L->g, out_par, fi, fs, fo, lk, op, epi, sign, fl, partial, L->pstride, scal, tu, st,
                        cg ? &c2 : nullptr));
     // partial sums of the launch: its blocks per field, from the variant it ran
-    L->hop_blocks_last = hop_grid_variant(L->g, hop_all_variants(in.prec, lk.fmt) ? L->hop_variant[key] : 0);
+    L->hop_blocks_last = hop_grid_variant(L->g, hop_all_variants(in.prec, lk.fmt) ? L->hop_variant[key] : 0, 2);
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));
         L->timed.push_back(t);

@@ -67,3 +67,20 @@ def test_batch_24c48_48rhs(tmq):
         res = oracle.true_residual(U, bs[i], xs[i].cpu().numpy(), 0.1632, ps[i].mu_tilde, THETA)
         assert res <= 1e-10, (i, res)
     lat.close()
+
+
+def test_doublet_24c48_mixed(tmq):
+    """The flavour doublet (eq. (Dh), the paper's doublet run parameters) at
+    24^3x48, FP16-inner CG, judged by the oracle's FP64 true residual."""
+    U = synth.random_gauge(DIMS, eps=0.3, seed=1001)
+    lat = tmq.Lattice(DIMS)
+    lat.load_gauge(U)
+    b = np.stack([synth.gaussian_odd(DIMS, seed=2500), synth.gaussian_odd(DIMS, seed=2501)])
+    p = tmq.nd_params(0.17, 0.1105, 0.0935, THETA)
+    x, info = lat.solve_nd(p, torch.from_numpy(b).cuda(), tmq.solver_opts(tol=1e-10, sloppy="fp16",
+                                                                           sloppy_link="fp16"))
+    res = oracle.true_residual_nd(U, b, x.cpu().numpy(), 0.17, 0.1105, 0.0935, THETA)
+    print(f"doublet 24^3x48 fp16 inner: iters {info.iters} reliable {info.reliable_updates} true res {res:.2e}")
+    assert info.status == 0 and res <= 1e-10
+    assert abs(res - info.true_rel_residual) <= 1e-3 * res
+    lat.close()
