@@ -359,3 +359,45 @@ def true_residual_nd(U, b2, x2, kappa, mubar, epsbar, theta) -> float:
     b = np.asarray(b2, dtype=np.complex128)
     r = b - QhatQhat_nd(U, x2, kappa, mubar, epsbar, theta)
     return float(np.linalg.norm(r.ravel()) / np.linalg.norm(b.ravel()))
+
+
+# ------------------------------------------------------------ BiCGstab
+#
+# The stabilised bi-conjugate gradient method (one of the solvers the paper
+# lists for D chi = phi, Sec. 4.4; van der Vorst's algorithm as given in the
+# textbooks the paper cites), applied to the odd-site operator Qhat^{sign}
+# itself rather than to the normal equations.  Shadow residual = the initial
+# residual; x_0 = 0; stops when |r|^2 <= tol^2 |b|^2 on the iterated
+# residual; complex inner products <a, b> = sum conj(a) b.
+
+def bicgstab(U, b, kappa, mut, sign, theta, tol=1e-10, max_iter=10000):
+    """Solve Qhat^{sign} x = b; returns (x, {converged, iters, breakdown})."""
+    b = np.asarray(b, dtype=np.complex128)
+    x = np.zeros_like(b)
+    r = b.copy()
+    rhat = r.copy()
+    bb = float(np.vdot(b, b).real)
+    target = tol * tol * bb
+    rho = alpha = omega = 1.0 + 0j
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    k = 0
+    rr = bb
+    while rr > target and k < max_iter:
+        rho_new = np.vdot(rhat, r)
+        if rho_new == 0 or omega == 0:
+            return x, {"converged": False, "iters": k, "breakdown": True}
+        beta = (rho_new / rho) * (alpha / omega)
+        rho = rho_new
+        p = r + beta * (p - omega * v)
+        v = Qhat(U, p, kappa, mut, sign, theta)
+        alpha = rho / np.vdot(rhat, v)
+        s = r - alpha * v
+        t = Qhat(U, s, kappa, mut, sign, theta)
+        tt = float(np.vdot(t, t).real)
+        omega = np.vdot(t, s) / tt if tt > 0 else 0.0
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rr = float(np.vdot(r, r).real)
+        k += 1
+    return x, {"converged": rr <= target, "iters": k, "breakdown": False}

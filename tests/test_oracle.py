@@ -483,3 +483,53 @@ def test_cg_nd_matches_dense_solve():
     assert info["converged"]
     assert rel(x.ravel(), xs) <= (ev[-1] / ev[0]) * 1e-10
     assert oracle.true_residual_nd(U, b, x, *args, THETA_AP) <= 1e-10
+
+
+# -------------------------------------------------------------- BiCGstab
+
+
+def test_bicgstab_matches_dense_solve():
+    """BiCGstab on Qhat^{+-} itself against a dense solve of the dense Qhat (2^4 and 4x2^3)."""
+    for dims in [(2, 2, 2, 2), (4, 2, 2, 2)]:
+        U = synth.random_gauge(dims, seed=91)
+        V = int(np.prod(dims))
+        b = synth.gaussian_odd(dims, seed=92)
+        for sign in (+1, -1):
+            A = dense.schur_Qhat(dense.M_hopping(U, 0.1632, 0.004, sign, THETA_AP), dims)
+            xs = np.linalg.solve(A, b.ravel())
+            sv = np.linalg.svd(A, compute_uv=False)
+            x, info = oracle.bicgstab(U, b, 0.1632, 0.004, sign, THETA_AP, tol=1e-11)
+            assert info["converged"], info
+            assert rel(x.ravel(), xs) <= (sv[0] / sv[-1]) * 1e-11
+            assert rel(oracle.Qhat(U, x, 0.1632, 0.004, sign, THETA_AP), b) <= 2e-11
+            assert x.shape == (V // 2, 4, 3)
+
+
+def test_bicgstab_kappa_zero_closed_form():
+    """kappa = 0: Qhat^{+-} = g5 (1 +- i mut g5) = g5 +- i mut has the two eigenvalues
+    +-1 +- i mut, so the BiCG polynomial of degree 2 annihilates any residual and
+    BiCGstab ends within two steps, with x = (g5 -+ i mut) b / (1 + mut^2)."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_gauge(dims, seed=93)
+    b = synth.gaussian_odd(dims, seed=94)
+    mut = 0.3
+    for sign in (+1, -1):
+        x, info = oracle.bicgstab(U, b, 0.0, mut, sign, THETA_AP, tol=1e-12)
+        assert info["converged"] and info["iters"] <= 2
+        g5b = b.copy()
+        g5b[:, 2:, :] *= -1
+        want = (g5b - sign * 1j * mut * b) / (1 + mut ** 2)
+        assert rel(x, want) < 1e-14
+
+
+def test_bicgstab_solves_the_cg_system_consistently():
+    """Solving Qhat^+ y = b by BiCGstab, then Qhat^- x = y, gives the CG solution of
+    Qhat^+ Qhat^- x = b (4^4, random links)."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_gauge(dims, seed=95)
+    b = synth.gaussian_odd(dims, seed=96)
+    y, i1 = oracle.bicgstab(U, b, 0.1632, 0.004, +1, THETA_AP, tol=1e-12)
+    x, i2 = oracle.bicgstab(U, y, 0.1632, 0.004, -1, THETA_AP, tol=1e-12)
+    xc, ic = oracle.cg(U, b, 0.1632, 0.004, THETA_AP, tol=1e-12)
+    assert i1["converged"] and i2["converged"] and ic["converged"]
+    assert rel(x, xc) < 1e-9
