@@ -104,6 +104,9 @@ typedef struct {
 
 #define TMQ_MODE_RELIABLE 0
 #define TMQ_MODE_SWITCH 1
+#define TMQ_MODE_BICGSTAB 2 /* tmq_solve_M only: the odd-site system Qhat^{sign} psi_o = g5 phi'_o by
+                               BiCGstab on Qhat itself (FP64, sloppy = TMQ_FP64) instead of CG on
+                               the normal equations; the CG calls refuse it */
 
 typedef struct {
     int status;               /* same value the call returned */
@@ -197,6 +200,22 @@ int tmq_solve_batch_dev(tmq_lattice *lat, int nrhs, const tmq_params *p, const t
 int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts,
                        const double *b, double *x, void *stream, tmq_solve_info *info);
 
+/* Solve Qhat^{sign} x = b on the odd sites by BiCGstab (one of the solvers the
+ * paper lists for D chi = phi, Sec. 4.4) applied to the non-Hermitian
+ * operator itself: two applications of Qhat per iteration, against four (one
+ * Qhat^+ Qhat^-) for a CG iteration on the normal equations.  FP64 only
+ * (opts->sloppy must be TMQ_FP64; opts->mode is ignored).  x_0 = 0; the
+ * iteration stops on the iterated residual, then the FP64 true residual
+ * b - Qhat x is recomputed: the solve ends if it meets opts->tol, otherwise
+ * BiCGstab restarts from it (also after a breakdown, rho or omega = 0).
+ * info->iters = BiCGstab iterations, info->reliable_updates = true-residual
+ * recomputations, info->true_rel_residual = |b - Qhat x| / |b|.  Odd-site
+ * canonical fields; TMQ_ENOCONV if max_iter is reached. */
+int tmq_solve_Qhat(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts, const double *b,
+                   double *x, tmq_solve_info *info);
+int tmq_solve_Qhat_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts,
+                       const double *b, double *x, void *stream, tmq_solve_info *info);
+
 /* Solve M^{sign} psi = phi on the full lattice (eq. (eo0), sign = +1 or -1)
  * with the even/odd factorisation of App. B ("Inversion"):
  *   phi'_e = (M_ee)^-1 phi_e,  phi'_o = phi_o - M_oe (M_ee)^-1 phi_e,
@@ -209,6 +228,8 @@ int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_o
  * while it is above opts->tol (relative to |phi| or absolute), the same steps
  * solve for the correction (at most 4 rounds).  info->true_rel_residual is that
  * full-lattice residual, info->iters the CG iterations of all rounds.
+ * With opts->mode = TMQ_MODE_BICGSTAB the odd-site system is solved by
+ * BiCGstab on Qhat^{sign} directly (as tmq_solve_Qhat), FP64.
  * Full-lattice canonical spinors; phi and psi must not overlap.  TMQ_ENOCONV if
  * the tolerance is not reached. */
 int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts,

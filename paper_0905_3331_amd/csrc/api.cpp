@@ -16,6 +16,8 @@ int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const 
                hipStream_t st, tmq_solve_info *info);
 int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const double2 *phi, double2 *psi,
             hipStream_t st, tmq_solve_info *info);
+int solve_qhat_bicgstab(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const FieldDesc &fb,
+                        const FieldDesc &fx, hipStream_t st, tmq_solve_info *info);
 }  // namespace tmq
 
 using namespace tmq;
@@ -393,6 +395,56 @@ int tmq_solve_full_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_o
     if (s == TMQ_OK || s == TMQ_ENOCONV) {
         TMQ_HIP(launch_full_to_canonical(L->g, fx, (double2 *)x, st));
         TMQ_HIP(hipStreamSynchronize(st));
+    }
+    return s;
+}
+
+int tmq_solve_Qhat_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts, const double *b,
+                       double *x, void *stream, tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_sign(sign));
+    TMQ_TRY(check_opts(opts));
+    TMQ_TRY(check_ptrs(b, x));
+    if (opts->sloppy != TMQ_FP64) {
+        set_error("tmq_solve_Qhat: BiCGstab runs in FP64 only (sloppy = TMQ_FP64)");
+        return TMQ_EINVAL;
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    hipStream_t st = (hipStream_t)stream;
+    const long vh = L->g.vh;
+    FieldDesc fb, fx;
+    TMQ_TRY(work_field(L, "bq_b", P64, vh, &fb));
+    TMQ_TRY(work_field(L, "bq_x", P64, vh, &fx));
+    TMQ_HIP(launch_from_canonical((const double2 *)b, fb, st));
+    const int s = solve_qhat_bicgstab(L, *p, sign, *opts, fb, fx, st, info);
+    if (s == TMQ_OK || s == TMQ_ENOCONV) {
+        TMQ_HIP(launch_to_canonical(fx, (double2 *)x, st));
+        TMQ_HIP(hipStreamSynchronize(st));
+    }
+    return s;
+}
+
+int tmq_solve_Qhat(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts, const double *b,
+                   double *x, tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_ptrs(b, x));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    const size_t bytes = (size_t)L->g.vh * 12 * sizeof(double2);
+    double *db = nullptr;
+    TMQ_TRY(copy_in(L, 0, b, bytes, &db));
+    void *dx = nullptr;
+    TMQ_TRY(stage_buffer(L, 1, bytes, &dx));
+    const int s = tmq_solve_Qhat_dev(lat, p, sign, opts, db, (double *)dx, L->own, info);
+    if (s == TMQ_OK || s == TMQ_ENOCONV) {
+        TMQ_HIP(hipMemcpyAsync(x, dx, bytes, hipMemcpyDeviceToHost, L->own));
+        TMQ_HIP(hipStreamSynchronize(L->own));
     }
     return s;
 }

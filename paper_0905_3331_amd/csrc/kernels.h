@@ -200,6 +200,37 @@ hipError_t launch_max(const double *partial, int n, double *out, hipStream_t st)
 // b = a, bytes / 16 lanes of 16 bytes (bandwidth calibration)
 hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 
+// BiCGstab on one odd-site system (FP64, RHS 0 of each field), scalars on
+// the device; every kernel does nothing once `done` is set (see bicgstab.hip)
+struct BicgScalars {
+    double rho[2], alpha[2], omega[2], beta[2];  // complex (re, im)
+    double rr, bb, target;
+    int iter, restarts, done, nan, breakdown;
+    int max_iter;  // done once iter reaches it (set by the host before the start)
+};
+enum BicgOp {
+    BI_START = 0,  // r = rhat: sums <rhat, r>, |r|^2 ; alpha = omega = 1, beta = 0
+    BI_ALPHA = 1,  // sum <rhat, v> ; alpha = rho / <rhat, v>
+    BI_OMEGA = 2,  // sums <t, s>, |t|^2 ; omega = <t, s> / |t|^2
+    BI_UPDATE = 3  // sums <rhat, r>, |r|^2 of the new r ; beta = (rho' / rho)(alpha / omega) ; done
+};
+// <a, b> -> p0 (re), p1 (im); |a|^2 -> p2, one partial per block (blas_grid(n))
+hipError_t launch_bi_dot(const FieldDesc &a, const FieldDesc &b, const BicgScalars *sc, double *p0, double *p1,
+                         double *p2, hipStream_t st);
+// p = r + beta (p - omega v)
+hipError_t launch_bi_p(const FieldDesc &r, const FieldDesc &p, const FieldDesc &v, const BicgScalars *sc,
+                       hipStream_t st);
+// s = r - alpha v
+hipError_t launch_bi_s(const FieldDesc &r, const FieldDesc &v, const FieldDesc &s, const BicgScalars *sc,
+                       hipStream_t st);
+// x += alpha p + omega s ; r = s - omega t ; <rhat, r> -> p0, p1 ; |r|^2 -> p2
+hipError_t launch_bi_xr(const FieldDesc &x, const FieldDesc &p, const FieldDesc &s, const FieldDesc &t,
+                        const FieldDesc &r, const FieldDesc &rhat, const BicgScalars *sc, double *p0, double *p1,
+                        double *p2, hipStream_t st);
+// one scalar step (BicgOp) from nparts partials of p0, p1, p2; publish: copy of the scalars
+hipError_t launch_bi_scalar(int op, const double *p0, const double *p1, const double *p2, int nparts,
+                            BicgScalars *s, double tol2, int relative, BicgScalars *publish, hipStream_t st);
+
 // codec: canonical complex128 [site][12] <-> one device field (RHS 0 of the view)
 hipError_t launch_from_canonical(const double2 *in, const FieldDesc &out, hipStream_t st);
 hipError_t launch_to_canonical(const FieldDesc &in, double2 *out, hipStream_t st);

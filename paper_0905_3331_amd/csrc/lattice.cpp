@@ -76,6 +76,10 @@ Lattice::~Lattice()
         if (p) hipFree(p);
     if (scal) hipFree(scal);
     if (ring) hipHostFree(ring);
+    if (bicg) hipFree(bicg);
+    if (bicg_ring) hipHostFree(bicg_ring);
+    for (auto &e : bicg_ev)
+        if (e) hipEventDestroy(e);
     for (auto &e : ring_ev)
         if (e) hipEventDestroy(e);
     for (void *s : stage)
@@ -695,8 +699,12 @@ int check_opts(const tmq_solver_opts *o)
         set_error("sloppy_link must be TMQ_FP32 or TMQ_FP16");
         return TMQ_EINVAL;
     }
-    if (o->mode != TMQ_MODE_RELIABLE && o->mode != TMQ_MODE_SWITCH) {
-        set_error("mode must be TMQ_MODE_RELIABLE or TMQ_MODE_SWITCH");
+    if (o->mode != TMQ_MODE_RELIABLE && o->mode != TMQ_MODE_SWITCH && o->mode != TMQ_MODE_BICGSTAB) {
+        set_error("mode must be TMQ_MODE_RELIABLE, TMQ_MODE_SWITCH or TMQ_MODE_BICGSTAB");
+        return TMQ_EINVAL;
+    }
+    if (o->mode == TMQ_MODE_BICGSTAB && o->sloppy != TMQ_FP64) {
+        set_error("TMQ_MODE_BICGSTAB runs in FP64 only (sloppy = TMQ_FP64)");
         return TMQ_EINVAL;
     }
     return TMQ_OK;

@@ -77,6 +77,11 @@ struct Lattice {
     // CG engines of the even/odd solves, one per inner precision and link format
     std::vector<Engine *> engines;
 
+    // BiCGstab scalars (device) and their published copies (pinned, 2 entries)
+    BicgScalars *bicg = nullptr;
+    BicgScalars *bicg_ring = nullptr, *bicg_ring_dev = nullptr;
+    hipEvent_t bicg_ev[2] = {};
+
     // named work fields, grown on demand
     std::vector<std::pair<std::string, Field>> work;
 

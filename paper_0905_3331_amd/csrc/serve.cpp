@@ -504,6 +504,10 @@ int tmq_server_submit(tmq_server *srv, int lattice_id, const tmq_params *p, cons
     }
     TMQ_TRY(check_params(p));
     TMQ_TRY(check_opts(opts));
+    if (opts->mode == TMQ_MODE_BICGSTAB) {
+        set_error("tmq_server_submit: the server solves the normal equations by CG (mode 0 or 1)");
+        return TMQ_EINVAL;
+    }
     Server &S = srv->S;
     std::unique_lock<std::mutex> lk(S.mu);
     if (S.failed) {

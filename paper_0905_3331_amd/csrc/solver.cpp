@@ -57,6 +57,11 @@ int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o
                 double *const *x, hipStream_t st, tmq_solve_info *info, const double *eps)
 {
     const auto t0 = std::chrono::steady_clock::now();
+    if (o.mode == TMQ_MODE_BICGSTAB) {
+        set_error("TMQ_MODE_BICGSTAB solves Qhat x = b (tmq_solve_Qhat) or M psi = phi (tmq_solve_M), "
+                  "not the normal equations");
+        return TMQ_EINVAL;
+    }
     Engine *E = nullptr;
     TMQ_TRY(lattice_engine(L, o, n, eps != nullptr, &E));
     E->st = st;
@@ -82,21 +87,150 @@ int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o
     return status;
 }
 
-// ------------------------------------------- M psi = phi through even/odd
-
-// |v|^2 of a one-RHS FP64 field, summed on the host in a fixed order
-static int field_norm2(Lattice *L, const FieldDesc &v, hipStream_t st, double *out)
+// the sum of nb per-block partials (device), on the host in a fixed order
+static int field_norm2_partials(Lattice *, const double *partial, int nb, hipStream_t st, double *out)
 {
-    const int nb = blas_grid(v.n);
-    TMQ_HIP(launch_norm2(v, rhs_all(1), L->partial[2], L->pstride, st));
     std::vector<double> part(nb);
-    TMQ_HIP(hipMemcpyAsync(part.data(), L->partial[2], sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    TMQ_HIP(hipMemcpyAsync(part.data(), partial, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
     TMQ_HIP(hipStreamSynchronize(st));
     double s = 0.0;
     for (double x : part) s += x;
     *out = s;
     return TMQ_OK;
 }
+
+// |v|^2 of a one-RHS FP64 field, summed on the host in a fixed order
+static int field_norm2(Lattice *L, const FieldDesc &v, hipStream_t st, double *out)
+{
+    TMQ_HIP(launch_norm2(v, rhs_all(1), L->partial[2], L->pstride, st));
+    return field_norm2_partials(L, L->partial[2], blas_grid(v.n), st, out);
+}
+
+// ------------------------------------------------- BiCGstab on Qhat^{+-}
+
+static int bicg_state(Lattice *L)
+{
+    if (L->bicg) return TMQ_OK;
+    if (hipMalloc((void **)&L->bicg, sizeof(BicgScalars)) != hipSuccess) {
+        L->bicg = nullptr;
+        set_error("BiCGstab: device allocation of scalars failed");
+        return TMQ_ENOMEM;
+    }
+    if (hipHostMalloc((void **)&L->bicg_ring, 2 * sizeof(BicgScalars), hipHostMallocMapped) != hipSuccess) {
+        L->bicg_ring = nullptr;
+        set_error("BiCGstab: pinned scalar allocation failed");
+        return TMQ_ENOMEM;
+    }
+    TMQ_HIP(hipHostGetDevicePointer((void **)&L->bicg_ring_dev, L->bicg_ring, 0));
+    for (auto &e : L->bicg_ev) TMQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return TMQ_OK;
+}
+
+// Solve Qhat^{sign} x = b (odd-site FP64 fields) by BiCGstab, x_0 = 0.  The
+// host enqueues iteration k, then reads the scalars of iteration k - 1 (the
+// device skips the work of an iteration once it has flagged the solve done).
+// When the iterated residual meets the target, or the recursion breaks down
+// (rho or omega zero), the FP64 true residual b - Qhat x is recomputed: the
+// solve ends if it meets the target, else BiCGstab restarts from it.
+int solve_qhat_bicgstab(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const FieldDesc &fb,
+                        const FieldDesc &fx, hipStream_t st, tmq_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const long vh = L->g.vh;
+    TMQ_TRY(bicg_state(L));
+    FieldDesc r, rh, pp, v, s, t, te;
+    TMQ_TRY(work_field(L, "bi_r", P64, vh, &r));
+    TMQ_TRY(work_field(L, "bi_rh", P64, vh, &rh));
+    TMQ_TRY(work_field(L, "bi_p", P64, vh, &pp));
+    TMQ_TRY(work_field(L, "bi_v", P64, vh, &v));
+    TMQ_TRY(work_field(L, "bi_s", P64, vh, &s));
+    TMQ_TRY(work_field(L, "bi_t", P64, vh, &t));
+    TMQ_TRY(work_field(L, "bi_te", P64, vh, &te));
+    const OpParams op = make_op(L, &p, 1);
+    const RhsList one = rhs_all(1);
+    const LinkDesc lk = lattice_links(L, link_fmt_for(L, P64, P64));
+    double *P0 = L->partial[0], *P1 = L->partial[1], *P2 = L->partial[2];
+    const int nparts = blas_grid(vh);
+    const int max_iter = o.max_iter > 0 ? o.max_iter : 10000;
+    const double tol2 = o.tol * o.tol;
+    BicgScalars *S = L->bicg;
+
+    BicgScalars init{};
+    init.max_iter = max_iter;
+    TMQ_HIP(hipStreamSynchronize(st));
+    TMQ_HIP(hipMemcpy(S, &init, sizeof(BicgScalars), hipMemcpyHostToDevice));
+    TMQ_HIP(launch_zero(fx, one, st));
+    TMQ_HIP(launch_convert(fb, r, one, st));
+    int status = TMQ_OK, truths = 0;
+    double rr_true = 0.0;
+    BicgScalars last{};
+    for (int restart = 0;; restart++) {
+        // rhat = r ; p = v = 0 ; rho = <rhat, r>
+        TMQ_HIP(launch_convert(r, rh, one, st));
+        TMQ_HIP(launch_zero(pp, one, st));
+        TMQ_HIP(launch_zero(v, one, st));
+        TMQ_HIP(launch_bi_dot(rh, r, nullptr, P0, P1, P2, st));
+        TMQ_HIP(launch_bi_scalar(BI_START, P0, P1, P2, nparts, S, tol2, o.relative, nullptr, st));
+        for (long k = 0;; k++) {
+            TMQ_HIP(launch_bi_p(r, pp, v, S, st));
+            TMQ_TRY(apply_Qhat(L, op, sign, pp, v, te, lk, one, nullptr, nullptr, st));
+            TMQ_HIP(launch_bi_dot(rh, v, S, P0, P1, P2, st));
+            TMQ_HIP(launch_bi_scalar(BI_ALPHA, P0, P1, P2, nparts, S, 0.0, 0, nullptr, st));
+            TMQ_HIP(launch_bi_s(r, v, s, S, st));
+            TMQ_TRY(apply_Qhat(L, op, sign, s, t, te, lk, one, nullptr, nullptr, st));
+            TMQ_HIP(launch_bi_dot(t, s, S, P0, P1, P2, st));
+            TMQ_HIP(launch_bi_scalar(BI_OMEGA, P0, P1, P2, nparts, S, 0.0, 0, nullptr, st));
+            TMQ_HIP(launch_bi_xr(fx, pp, s, t, r, rh, S, P0, P1, P2, st));
+            TMQ_HIP(launch_bi_scalar(BI_UPDATE, P0, P1, P2, nparts, S, 0.0, 0, L->bicg_ring_dev + (k & 1), st));
+            TMQ_HIP(hipEventRecord(L->bicg_ev[k & 1], st));
+            if (k == 0) continue;
+            TMQ_HIP(hipEventSynchronize(L->bicg_ev[(k - 1) & 1]));
+            const BicgScalars prev = L->bicg_ring[(k - 1) & 1];
+            if (prev.done) break;
+        }
+        TMQ_HIP(hipStreamSynchronize(st));
+        TMQ_HIP(hipMemcpy(&last, S, sizeof(BicgScalars), hipMemcpyDeviceToHost));
+        if (last.nan) {
+            status = TMQ_ENAN;
+            break;
+        }
+        // the true residual r = b - Qhat x
+        TMQ_TRY(apply_Qhat(L, op, sign, fx, t, te, lk, one, nullptr, nullptr, st));
+        TMQ_HIP(launch_residual(fb, t, r, one, P2, L->pstride, st));
+        TMQ_TRY(field_norm2_partials(L, P2, nparts, st, &rr_true));
+        truths++;
+        if (!std::isfinite(rr_true)) {
+            status = TMQ_ENAN;
+            break;
+        }
+        if (rr_true <= last.target) break;
+        if (last.iter >= max_iter || restart >= 50) {
+            status = TMQ_ENOCONV;
+            break;
+        }
+        // restart from the true residual (S keeps |b|^2, the target and the count)
+        BicgScalars keep = last;
+        keep.restarts = restart + 1;
+        keep.done = 0;
+        TMQ_HIP(hipStreamSynchronize(st));
+        TMQ_HIP(hipMemcpy(S, &keep, sizeof(BicgScalars), hipMemcpyHostToDevice));
+    }
+    TMQ_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->status = status;
+        info->iters = last.iter;
+        info->reliable_updates = truths;
+        info->true_rel_residual = last.bb > 0 ? std::sqrt(rr_true / last.bb) : std::sqrt(rr_true);
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status == TMQ_ENAN) set_error("BiCGstab: non-finite value");
+    if (status == TMQ_ENOCONV) set_error("BiCGstab: tolerance not reached within max_iter");
+    return status;
+}
+
+// ------------------------------------------- M psi = phi through even/odd
+
+
 
 // Solve M^{sign} psi = phi (full lattice, canonical device buffers) with the
 // even/odd factorisation of the inversion in App. B:
@@ -152,29 +286,43 @@ int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o,
         TMQ_TRY(hop(L, 1, te, ro, wo, lk, op, EPI_SRC, sign, one, nullptr, nullptr, st));
         // odd system: Qhat^{sign} d_o = g5 phi'_o
         TMQ_HIP(launch_twist(wo, to, one, g5_u, g5_d, st));
-        if (sign < 0) {
-            TMQ_TRY(apply_Qhat(L, op, +1, to, wo, te, lk, one, nullptr, nullptr, st));
-            TMQ_HIP(launch_to_canonical(wo, (double2 *)bc.data, st));
+        if (o.mode == TMQ_MODE_BICGSTAB) {
+            // BiCGstab on Qhat^{sign} itself
+            tmq_solve_info ci{};
+            const int cs = solve_qhat_bicgstab(L, p, sign, o, to, dd, st, &ci);
+            iters += ci.iters;
+            rus += ci.reliable_updates;
+            if (cs == TMQ_ENAN) {
+                status = TMQ_ENAN;
+                break;
+            }
+            if (cs != TMQ_OK && cs != TMQ_ENOCONV) return cs;
+            if (cs == TMQ_ENOCONV) status = TMQ_ENOCONV;
         } else {
-            TMQ_HIP(launch_to_canonical(to, (double2 *)bc.data, st));
+            if (sign < 0) {
+                TMQ_TRY(apply_Qhat(L, op, +1, to, wo, te, lk, one, nullptr, nullptr, st));
+                TMQ_HIP(launch_to_canonical(wo, (double2 *)bc.data, st));
+            } else {
+                TMQ_HIP(launch_to_canonical(to, (double2 *)bc.data, st));
+            }
+            tmq_solve_info ci{};
+            const double *bp = (const double *)bc.data;
+            double *yp = (double *)yc.data;
+            const int cs = solve_batch(L, 1, &p, o, &bp, &yp, st, &ci, nullptr);
+            iters += ci.iters;
+            rus += ci.reliable_updates;
+            if (cs == TMQ_ENAN) {
+                status = TMQ_ENAN;
+                break;
+            }
+            if (cs != TMQ_OK && cs != TMQ_ENOCONV) return cs;
+            if (cs == TMQ_ENOCONV) status = TMQ_ENOCONV;
+            TMQ_HIP(launch_from_canonical((const double2 *)yc.data, yo, st));
+            if (sign > 0)
+                TMQ_TRY(apply_Qhat(L, op, -1, yo, dd, te, lk, one, nullptr, nullptr, st));
+            else
+                TMQ_HIP(launch_convert(yo, dd, one, st));
         }
-        tmq_solve_info ci{};
-        const double *bp = (const double *)bc.data;
-        double *yp = (double *)yc.data;
-        const int cs = solve_batch(L, 1, &p, o, &bp, &yp, st, &ci, nullptr);
-        iters += ci.iters;
-        rus += ci.reliable_updates;
-        if (cs == TMQ_ENAN) {
-            status = TMQ_ENAN;
-            break;
-        }
-        if (cs != TMQ_OK && cs != TMQ_ENOCONV) return cs;
-        if (cs == TMQ_ENOCONV) status = TMQ_ENOCONV;
-        TMQ_HIP(launch_from_canonical((const double2 *)yc.data, yo, st));
-        if (sign > 0)
-            TMQ_TRY(apply_Qhat(L, op, -1, yo, dd, te, lk, one, nullptr, nullptr, st));
-        else
-            TMQ_HIP(launch_convert(yo, dd, one, st));
         // d_e = (M_ee)^-1 (r_e + kappa H_eo d_o) ; psi += d
         TMQ_TRY(hop(L, 0, dd, re, de, lk, op, EPI_REC, sign, one, nullptr, nullptr, st));
         TMQ_HIP(launch_accumulate(fpsi, fd, one, st));

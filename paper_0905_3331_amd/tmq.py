@@ -99,6 +99,9 @@ _SIGS = {
     "tmq_solve_nd_dev": (_ip, [_vp, _P(tmq_nd_params), _P(tmq_solver_opts), _vp, _vp, _vp, _P(tmq_solve_info)]),
     "tmq_solve_nd_batch_dev": (_ip, [_vp, _ip, _P(tmq_nd_params), _P(tmq_solver_opts), _P(_vp), _P(_vp), _vp,
                                      _P(tmq_solve_info)]),
+    "tmq_solve_Qhat": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _P(tmq_solve_info)]),
+    "tmq_solve_Qhat_dev": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _vp,
+                                 _P(tmq_solve_info)]),
     "tmq_split_eo": (_ip, [_vp, _vp, _vp, _vp]),
     "tmq_merge_eo": (_ip, [_vp, _vp, _vp, _vp]),
     "tmq_split_eo_dev": (_ip, [_vp, _vp, _vp, _vp, _vp]),
@@ -168,7 +171,7 @@ def nd_params(kappa: float, mubar_tilde: float, epsbar_tilde: float, theta=(1.0,
     return p
 
 
-MODE_RELIABLE, MODE_SWITCH = 0, 1
+MODE_RELIABLE, MODE_SWITCH, MODE_BICGSTAB = 0, 1, 2
 
 
 def solver_opts(tol=1e-10, relative=True, max_iter=10000, sloppy="fp64", sloppy_link="fp16",
@@ -180,7 +183,8 @@ def solver_opts(tol=1e-10, relative=True, max_iter=10000, sloppy="fp64", sloppy_
     o.sloppy = PREC[sloppy] if isinstance(sloppy, str) else int(sloppy)
     o.sloppy_link = PREC[sloppy_link] if isinstance(sloppy_link, str) else int(sloppy_link)
     o.delta = float(delta)
-    o.mode = {"reliable": MODE_RELIABLE, "switch": MODE_SWITCH}[mode] if isinstance(mode, str) else int(mode)
+    o.mode = ({"reliable": MODE_RELIABLE, "switch": MODE_SWITCH, "bicgstab": MODE_BICGSTAB}[mode]
+              if isinstance(mode, str) else int(mode))
     return o
 
 
@@ -369,6 +373,24 @@ class Lattice:
         if check:
             _check(code, "tmq_solve_batch")
         return xs, [_info(i) for i in infos]
+
+    def solve_Qhat(self, p: tmq_params, sign: int, b, opts: tmq_solver_opts, x=None, stream=None, check=True):
+        """Solve Qhat^{sign} x = b by BiCGstab (FP64); device tensor or host array (V/2, 4, 3)."""
+        n = self.V // 2 * 12
+        info = tmq_solve_info()
+        if isinstance(b, np.ndarray):
+            x = np.empty_like(b) if x is None else x
+            code = _lib.tmq_solve_Qhat(self._h, ctypes.byref(p), sign, ctypes.byref(opts), _hptr(b, n, "b"),
+                                       _hptr(x, n, "x"), ctypes.byref(info))
+        else:
+            import torch
+
+            x = torch.empty_like(b) if x is None else x
+            code = _lib.tmq_solve_Qhat_dev(self._h, ctypes.byref(p), sign, ctypes.byref(opts), _dptr(b, n, "b"),
+                                           _dptr(x, n, "x"), _stream(stream), ctypes.byref(info))
+        if check:
+            _check(code, "tmq_solve_Qhat")
+        return x, _info(info)
 
     # ------------------------------------------------------ flavour doublet
     def apply_Qhat_nd(self, p: tmq_nd_params, sign: int, src, out=None, prec="fp64", stream=None):
