@@ -401,3 +401,37 @@ def bicgstab(U, b, kappa, mut, sign, theta, tol=1e-10, max_iter=10000):
         rr = float(np.vdot(r, r).real)
         k += 1
     return x, {"converged": rr <= target, "iters": k, "breakdown": False}
+
+
+# ------------------------------------------------- consumers of the solver
+#
+# The HMC force solves of eq. (eo6) and the one-end-trick correlator of the
+# online measurements (eqs. (source), (oneend)).
+
+def solve_M(U, phi, kappa, mut, sign, theta, tol=1e-12):
+    """psi = (M^{sign})^-1 phi on the full lattice by the plain route
+    Q^{sign} = g5 M^{sign}: psi = (Q^{sign})^-1 g5 phi = Q^{-sign} (Q^+ Q^-)^-1 g5 phi
+    (Q^+ Q^- = Q^- Q^+ on the full lattice), with the oracle's CG."""
+    dims = tuple(U.shape[:4])
+    phi = np.asarray(phi, dtype=np.complex128).reshape(dims + (4, 3))
+    g5phi = _gamma5(phi)
+    y, info = cg(U, g5phi.reshape(-1, 4, 3), kappa, mut, theta, eo=False, tol=tol)
+    assert info["converged"], info
+    return Q(U, y.reshape(dims + (4, 3)), kappa, mut, -sign, theta)
+
+
+def timeslice_bilinear(psi, gamma, t0=0):
+    """C(t) = sum over the sites of time slice (t0 + t) mod T of psi^+ Gamma psi
+    (spin matrix Gamma, colour summed); psi a full field (T, LZ, LY, LX, 4, 3)."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    per_t = np.einsum("tzyxsc,su,tzyxuc->t", psi.conj(), np.asarray(gamma, dtype=np.complex128), psi)
+    return np.roll(per_t, -t0)
+
+
+def pion_correlator(U, xi, kappa, mut, theta, t0=0, tol=1e-12):
+    """One-end-trick estimator of the pseudoscalar correlator for one noise
+    sample xi (a full field, non-zero on time slice t0): phi = (M^+)^-1 xi and
+    C(t) = sum over the spatial sites at time t0 + t of |phi|^2, for M in the
+    hopping normalisation of eq. (eo0)."""
+    phi = solve_M(U, xi, kappa, mut, +1, theta, tol=tol)
+    return timeslice_bilinear(phi, np.eye(4), t0).real, phi

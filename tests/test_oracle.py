@@ -533,3 +533,56 @@ def test_bicgstab_solves_the_cg_system_consistently():
     xc, ic = oracle.cg(U, b, 0.1632, 0.004, THETA_AP, tol=1e-12)
     assert i1["converged"] and i2["converged"] and ic["converged"]
     assert rel(x, xc) < 1e-9
+
+
+# ------------------------------------------------ consumers of the solver
+
+
+@pytest.mark.parametrize("sign", [+1, -1])
+def test_oracle_solve_M_matches_dense(sign):
+    dims = (4, 2, 2, 2)
+    U = synth.random_gauge(dims, seed=97)
+    phi = synth.gaussian_spinor(dims + (4, 3), seed=98)
+    psi = oracle.solve_M(U, phi, 0.16, 0.03, sign, THETA_GEN, tol=1e-13)
+    want = np.linalg.solve(dense.M_hopping(U, 0.16, 0.03, sign, THETA_GEN), phi.ravel())
+    assert rel(psi.ravel(), want) < 1e-10
+
+
+@pytest.mark.parametrize("t0", [0, 1])
+def test_pion_correlator_point_sources_match_dense_propagator(t0):
+    """The one-end estimator summed over the 12 unit sources at one site is the
+    point-to-all correlator sum_x tr[G(x, y) G(x, y)^+] of the dense propagator
+    G = (M^+)^-1 (so the solve, the time-slice sums and the shift by t0 are right)."""
+    dims = (4, 2, 2, 2)
+    U = synth.random_gauge(dims, seed=99)
+    kappa, mut = 0.16, 0.05
+    V = int(np.prod(dims))
+    G = np.linalg.inv(dense.M_hopping(U, kappa, mut, +1, THETA_AP)).reshape(V, 12, V, 12)
+    y = t0 * (V // dims[0])  # site (t0, 0, 0, 0)
+    want = np.zeros(dims[0])
+    for x in range(V):
+        want[(x // (V // dims[0]) - t0) % dims[0]] += float(np.sum(np.abs(G[x, :, y, :]) ** 2))
+    got = np.zeros(dims[0])
+    total = 0.0
+    for k in range(12):
+        xi = np.zeros((V, 12), dtype=np.complex128)
+        xi[y, k] = 1.0
+        c, phi = oracle.pion_correlator(U, xi.reshape(dims + (4, 3)), kappa, mut, THETA_AP, t0=t0)
+        got += c
+        total += float(np.vdot(phi, phi).real)
+    assert rel(got, want) < 1e-10
+    assert abs(got.sum() - total) <= 1e-12 * total
+
+
+def test_heatbath_and_force_solves():
+    """eqs. (eo10), (eo6): with phi_o = Qhat^+ r_o, X_o = (Qhat^+ Qhat^-)^-1 phi_o and
+    Y_o = Qhat^- X_o give back Y_o = r_o, and S_PF = phi_o^+ X_o = |r_o|^2."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_gauge(dims, seed=100)
+    r = synth.gaussian_odd(dims, seed=101)
+    phi = oracle.Qhat(U, r, 0.1632, 0.004, +1, THETA_AP)
+    X, info = oracle.cg(U, phi, 0.1632, 0.004, THETA_AP, tol=1e-12)
+    Y = oracle.Qhat(U, X, 0.1632, 0.004, -1, THETA_AP)
+    assert info["converged"]
+    assert rel(Y, r) < 1e-9
+    assert abs(np.vdot(phi, X).real - np.vdot(r, r).real) < 1e-9 * np.vdot(r, r).real
