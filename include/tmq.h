@@ -277,6 +277,43 @@ int tmq_solve_nd_dev(tmq_lattice *lat, const tmq_nd_params *p, const tmq_solver_
 int tmq_solve_nd_batch_dev(tmq_lattice *lat, int n, const tmq_nd_params *p, const tmq_solver_opts *opts,
                            const double *const *b, double *const *x, void *stream, tmq_solve_info *info);
 
+/* ---------------------------------------------- consumers of the solver */
+
+/* The solves of the HMC fermion force (eq. (eo6)): X_o = (Qhat^+ Qhat^-)^-1 phi_o
+ * (tmq_solve with opts) and Y_o = Qhat^- X_o (FP64), whose combination
+ * -[X_o^+ dQhat^+ Y_o + Y_o^+ dQhat^- X_o] is the variation of the pseudo-fermion
+ * action (eq. (eo5)).  Y may be NULL (not computed); action != NULL (host)
+ * receives S_PF = Re phi_o^+ X_o.  With phi_o = Qhat^+ r_o (the heatbath of
+ * eq. (eo10)), Y_o = r_o and S_PF = |r_o|^2 up to the tolerance.  Odd-site
+ * canonical device fields that must not overlap; info as for tmq_solve.
+ * Returns when the action is on the host (else when enqueued). */
+int tmq_solve_force_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *phi,
+                        double *X, double *Y, double *action, void *stream, tmq_solve_info *info);
+
+/* Time-slice sums of a spin bilinear of a full-lattice field:
+ *   out[t] = sum over the sites x of time slice (t0 + t) mod T of
+ *            sum_colour psi(x)^+ Gamma psi(x),
+ * gamma = the 4x4 complex spin matrix Gamma, row-major (host, 16 complex),
+ * psi = full-lattice canonical field (device), out = T complex (host; the call
+ * returns when it is written).  The contraction of the one-end-trick
+ * correlators (eq. (oneend)): for phi = M^-1 xi, Gamma = 1 gives the
+ * pseudoscalar correlator, other Gamma the source-side insertions. */
+int tmq_timeslice_bilinear_dev(tmq_lattice *lat, const double *gamma, const double *psi, int t0, double *out,
+                               void *stream);
+
+/* One-end-trick estimator of the pseudoscalar correlator for one noise
+ * sample (eqs. (source), (oneend)): phi = (M^+)^-1 xi by tmq_solve_M with
+ * opts, then corr[t] = sum over the spatial sites at time (t0 + t) mod T of
+ * |phi|^2 (spin and colour summed), t = 0 .. T-1 (host, T doubles).  xi is a
+ * full-lattice canonical device field, normally a noise source on time slice
+ * t0 whose components satisfy [xi_i^* xi_j] = delta_ij over samples (drawn by
+ * the caller); the average over samples estimates tr[G G^+] for G = M^-1 in
+ * the hopping normalisation of eq. (eo0) (the conventionally normalised
+ * propagator is 2 kappa G).  phi (device, full canonical) receives the
+ * solution if not NULL.  info as for tmq_solve_M. */
+int tmq_pion_correlator_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *xi,
+                            int t0, double *corr, double *phi, void *stream, tmq_solve_info *info);
+
 /* Even/odd split and merge of canonical spinor fields (App. B: the even/odd
  * decomposition of a field): full = complex128 [V][4][3] over lexicographic
  * sites, even/odd = complex128 [V/2][4][3] over the sites of that parity in

@@ -574,6 +574,112 @@ int tmq_solve_nd(tmq_lattice *lat, const tmq_nd_params *p, const tmq_solver_opts
     return s;
 }
 
+// ---------------------------------------------------- solver consumers
+
+namespace {
+
+// sums of the bilinear partials per time slice, in a fixed order, shifted by t0
+int ts_bilinear_host(Lattice *L, const double *psi, const SpinMat &m, int t0, double *out, hipStream_t st)
+{
+    const int nb = ts_bilinear_blocks(L->g), T = L->g.T;
+    if ((long)nb * T > L->pstride * MAX_RHS) {
+        set_error("internal: too many time-slice partial sums");
+        return TMQ_EINVAL;
+    }
+    TMQ_HIP(launch_ts_bilinear(L->g, (const double2 *)psi, m, L->partial[0], L->partial[1], st));
+    std::vector<double> re((size_t)nb * T), im((size_t)nb * T);
+    TMQ_HIP(hipMemcpyAsync(re.data(), L->partial[0], sizeof(double) * re.size(), hipMemcpyDeviceToHost, st));
+    TMQ_HIP(hipMemcpyAsync(im.data(), L->partial[1], sizeof(double) * im.size(), hipMemcpyDeviceToHost, st));
+    TMQ_HIP(hipStreamSynchronize(st));
+    for (int t = 0; t < T; t++) {
+        const int ts = ((t0 + t) % T + T) % T;
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < nb; k++) a += re[(size_t)ts * nb + k], b += im[(size_t)ts * nb + k];
+        out[2 * t] = a;
+        out[2 * t + 1] = b;
+    }
+    return TMQ_OK;
+}
+
+}  // namespace
+
+int tmq_timeslice_bilinear_dev(tmq_lattice *lat, const double *gamma, const double *psi, int t0, double *out,
+                               void *stream)
+{
+    TMQ_TRY(check_lat(lat, false));
+    if (!gamma || !psi || !out) {
+        set_error("tmq_timeslice_bilinear: NULL argument");
+        return TMQ_EINVAL;
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    SpinMat m;
+    for (int i = 0; i < 16; i++) m.m[i / 4][i % 4] = make_double2(gamma[2 * i], gamma[2 * i + 1]);
+    return ts_bilinear_host(L, psi, m, t0, out, (hipStream_t)stream);
+}
+
+int tmq_pion_correlator_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *xi,
+                            int t0, double *corr, double *phi, void *stream, tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_ptrs(xi, corr));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    hipStream_t st = (hipStream_t)stream;
+    double *ph = phi;
+    if (!ph) {
+        void *w = nullptr;
+        TMQ_TRY(stage_buffer(L, 1, (size_t)2 * L->g.vh * 12 * sizeof(double2), &w));
+        ph = (double *)w;
+    }
+    const int s = tmq_solve_M_dev(lat, p, +1, opts, xi, ph, stream, info);
+    if (s != TMQ_OK && s != TMQ_ENOCONV) return s;
+    SpinMat one{};
+    for (int i = 0; i < 4; i++) one.m[i][i] = make_double2(1.0, 0.0);
+    std::vector<double> c((size_t)2 * L->g.T);
+    TMQ_TRY(ts_bilinear_host(L, ph, one, t0, c.data(), st));
+    for (int t = 0; t < L->g.T; t++) corr[t] = c[2 * t];
+    return s;
+}
+
+int tmq_solve_force_dev(tmq_lattice *lat, const tmq_params *p, const tmq_solver_opts *opts, const double *phi,
+                        double *X, double *Y, double *action, void *stream, tmq_solve_info *info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_opts(opts));
+    TMQ_TRY(check_ptrs(phi, X));
+    if (X == phi || (Y && (Y == phi || Y == X))) {
+        set_error("tmq_solve_force: phi, X and Y must not overlap");
+        return TMQ_EINVAL;
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int s = solve_batch(L, 1, p, *opts, &phi, &X, st, info);
+    if (s != TMQ_OK && s != TMQ_ENOCONV) return s;
+    if (Y) TMQ_TRY(qhat_dev(L, p, -1, P64, X, Y, st));
+    if (action) {
+        const long vh = L->g.vh;
+        FieldDesc fp, fx;
+        TMQ_TRY(work_field(L, "force_phi", P64, vh, &fp));
+        TMQ_TRY(work_field(L, "force_x", P64, vh, &fx));
+        TMQ_HIP(launch_from_canonical((const double2 *)phi, fp, st));
+        TMQ_HIP(launch_from_canonical((const double2 *)X, fx, st));
+        TMQ_HIP(launch_bi_dot(fp, fx, nullptr, L->partial[0], L->partial[1], L->partial[2], st));
+        const int nb = blas_grid(vh);
+        std::vector<double> re((size_t)nb);
+        TMQ_HIP(hipMemcpyAsync(re.data(), L->partial[0], sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+        TMQ_HIP(hipStreamSynchronize(st));
+        double a = 0.0;
+        for (double v : re) a += v;
+        *action = a;
+    }
+    return s;
+}
+
 int tmq_split_eo_dev(tmq_lattice *lat, const double *full, double *even, double *odd, void *stream)
 {
     TMQ_TRY(check_lat(lat, false));

@@ -231,6 +231,17 @@ hipError_t launch_bi_xr(const FieldDesc &x, const FieldDesc &p, const FieldDesc 
 hipError_t launch_bi_scalar(int op, const double *p0, const double *p1, const double *p2, int nparts,
                             BicgScalars *s, double tol2, int relative, BicgScalars *publish, hipStream_t st);
 
+// a 4x4 complex spin matrix (row-major)
+struct SpinMat {
+    double2 m[4][4];
+};
+// per time slice t and block b of it: partial sums of psi^+ Gamma psi over the
+// slice's sites (psi canonical full-lattice complex128 [V][12]) at
+// pre / pim[t * ts_bilinear_blocks(g) + b]
+int ts_bilinear_blocks(const Geom &g);
+hipError_t launch_ts_bilinear(const Geom &g, const double2 *psi, const SpinMat &m, double *pre, double *pim,
+                              hipStream_t st);
+
 // codec: canonical complex128 [site][12] <-> one device field (RHS 0 of the view)
 hipError_t launch_from_canonical(const double2 *in, const FieldDesc &out, hipStream_t st);
 hipError_t launch_to_canonical(const FieldDesc &in, double2 *out, hipStream_t st);

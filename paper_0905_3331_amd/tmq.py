@@ -102,6 +102,11 @@ _SIGS = {
     "tmq_solve_Qhat": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _P(tmq_solve_info)]),
     "tmq_solve_Qhat_dev": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _vp, _vp, _vp,
                                  _P(tmq_solve_info)]),
+    "tmq_solve_force_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _vp, _vp,
+                                  _P(ctypes.c_double), _vp, _P(tmq_solve_info)]),
+    "tmq_timeslice_bilinear_dev": (_ip, [_vp, _vp, _vp, _ip, _vp, _vp]),
+    "tmq_pion_correlator_dev": (_ip, [_vp, _P(tmq_params), _P(tmq_solver_opts), _vp, _ip, _vp, _vp, _vp,
+                                      _P(tmq_solve_info)]),
     "tmq_split_eo": (_ip, [_vp, _vp, _vp, _vp]),
     "tmq_merge_eo": (_ip, [_vp, _vp, _vp, _vp]),
     "tmq_split_eo_dev": (_ip, [_vp, _vp, _vp, _vp, _vp]),
@@ -391,6 +396,49 @@ class Lattice:
         if check:
             _check(code, "tmq_solve_Qhat")
         return x, _info(info)
+
+    # ------------------------------------------------- consumers of the solver
+    def solve_force(self, p: tmq_params, phi, opts: tmq_solver_opts, stream=None, check=True, with_y=True):
+        """X = (Qhat^+ Qhat^-)^-1 phi, Y = Qhat^- X (eq. (eo6)) and S_PF = Re phi^+ X;
+        device tensors (V/2, 4, 3); returns (X, Y or None, S_PF, SolveInfo)."""
+        import torch
+
+        n = self.V // 2 * 12
+        X = torch.empty_like(phi)
+        Y = torch.empty_like(phi) if with_y else None
+        act = ctypes.c_double(0.0)
+        info = tmq_solve_info()
+        code = _lib.tmq_solve_force_dev(self._h, ctypes.byref(p), ctypes.byref(opts), _dptr(phi, n, "phi"),
+                                        _dptr(X, n, "X"), _dptr(Y, n, "Y") if with_y else None,
+                                        ctypes.byref(act), _stream(stream), ctypes.byref(info))
+        if check:
+            _check(code, "tmq_solve_force")
+        return X, Y, act.value, _info(info)
+
+    def timeslice_bilinear(self, gamma, psi, t0=0, stream=None):
+        """Per time slice sum of psi^+ Gamma psi (Gamma 4x4 complex) of a full field; returns complex (T,)."""
+        n = self.V * 12
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.complex128).reshape(4, 4))
+        out = np.zeros(self.dims[0], dtype=np.complex128)
+        _check(_lib.tmq_timeslice_bilinear_dev(self._h, g.ctypes.data, _dptr(psi, n, "psi"), int(t0),
+                                               out.ctypes.data, _stream(stream)), "tmq_timeslice_bilinear")
+        return out
+
+    def pion_correlator(self, p: tmq_params, xi, opts: tmq_solver_opts, t0=0, stream=None, check=True):
+        """One-end-trick pseudoscalar correlator of one noise sample xi (full field, device);
+        returns (C (T,), phi, SolveInfo)."""
+        import torch
+
+        n = self.V * 12
+        phi = torch.empty_like(xi)
+        corr = np.zeros(self.dims[0], dtype=np.float64)
+        info = tmq_solve_info()
+        code = _lib.tmq_pion_correlator_dev(self._h, ctypes.byref(p), ctypes.byref(opts), _dptr(xi, n, "xi"),
+                                            int(t0), corr.ctypes.data, _dptr(phi, n, "phi"), _stream(stream),
+                                            ctypes.byref(info))
+        if check:
+            _check(code, "tmq_pion_correlator")
+        return corr, phi, _info(info)
 
     # ------------------------------------------------------ flavour doublet
     def apply_Qhat_nd(self, p: tmq_nd_params, sign: int, src, out=None, prec="fp64", stream=None):

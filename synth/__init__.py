@@ -41,6 +41,7 @@ __all__ = [
     "gaussian_spinor",
     "gaussian_odd",
     "point_source_odd",
+    "z2_timeslice_source",
     "volume",
     "check_dims",
 ]
@@ -157,3 +158,15 @@ def point_source_odd(dims, site_odd: int, spin: int, colour: int) -> np.ndarray:
     b = np.zeros((volume(dims) // 2, 4, 3), dtype=np.complex128)
     b[site_odd, spin, colour] = 1.0
     return b
+
+
+def z2_timeslice_source(dims, t0: int, seed: int = 0) -> np.ndarray:
+    """Complex Z2 noise (each component (+-1 +- i)/sqrt(2), so that E[xi_i^* xi_j] =
+    delta_ij and E[xi_i xi_j] = 0) on every spin-colour component of time slice t0,
+    zero elsewhere; full field (T, LZ, LY, LX, 4, 3)."""
+    dims = check_dims(dims)
+    rng = np.random.default_rng(seed)
+    xi = np.zeros(dims + (4, 3), dtype=np.complex128)
+    sgn = rng.integers(0, 2, size=dims[1:] + (4, 3, 2)) * 2 - 1
+    xi[t0] = (sgn[..., 0] + 1j * sgn[..., 1]) / np.sqrt(2.0)
+    return xi
