@@ -17,6 +17,13 @@
                Qhat_h^+ Qhat_h^- to 1e-10, FP64 vs FP32-inner vs FP16-inner,
                3 Gaussian doublet sources, median
 
+  minv         24^3x48 (kappa 0.1632, 2 kappa mu 0.004, tol 1e-10): the full-lattice
+               M^+ psi = phi by the even/odd factorisation with CG on the normal
+               equations (FP64 and FP16-inner) against BiCGstab on Qhat^+ itself
+               (FP64); the odd-site system Qhat^+ x = b by BiCGstab against CG on
+               Qhat^+ Qhat^- followed by Qhat^-; the one-end-trick pion
+               correlator of one complex Z2 time-slice source (FP16-inner)
+
 Links are random SU(3) exp(i 0.3 H), reunitarised (seeds 1000 + workload);
 theta = (1, 0, 0, 0).  Prints one JSON object.  The solutions' accuracy
 against the FP64 oracle is checked by the GPU tests at these shapes.
@@ -199,10 +206,46 @@ def nd_32c64(tmq, torch, synth, reps):
     return out
 
 
+def minv_24c48(tmq, torch, synth, reps):
+    dims = (48, 24, 24, 24)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(synth.random_gauge(dims, eps=0.3, seed=1001))
+    p = tmq.params(0.1632, 0.004, THETA)
+    out = {"lattice": "24^3x48"}
+    phi = torch.from_numpy(synth.gaussian_spinor(dims + (4, 3), seed=2600).reshape(-1, 4, 3)).cuda()
+    for name, opts in (("cg_fp64", tmq.solver_opts(tol=1e-10)),
+                       ("cg_fp16_inner", tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")),
+                       ("bicgstab_fp64", tmq.solver_opts(tol=1e-10, mode="bicgstab"))):
+        lat.solve_M(p, +1, phi, opts)
+        t, (psi, info) = median_time(lambda: lat.solve_M(p, +1, phi, opts), reps)
+        out["M_inverse_" + name] = {"ms": t * 1e3, "iters": info.iters, "true_rel_residual": info.true_rel_residual}
+    b = torch.from_numpy(synth.gaussian_odd(dims, seed=2601)).cuda()
+    o64 = tmq.solver_opts(tol=1e-10)
+    lat.solve_Qhat(p, +1, b, o64)
+    t, (x, info) = median_time(lambda: lat.solve_Qhat(p, +1, b, o64), reps)
+    out["Qhat_plus_bicgstab_fp64"] = {"ms": t * 1e3, "iters": info.iters, "true_rel_residual": info.true_rel_residual}
+
+    def cg_route():
+        y, inf = lat.solve(p, b, o64)
+        return lat.apply_Qhat(p, -1, y), inf
+
+    cg_route()
+    t, (x, info) = median_time(cg_route, reps)
+    out["Qhat_plus_cg_normal_fp64"] = {"ms": t * 1e3, "iters": info.iters}
+    xi = torch.from_numpy(synth.z2_timeslice_source(dims, 0, seed=2602).reshape(-1, 4, 3)).cuda()
+    o16 = tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")
+    lat.pion_correlator(p, xi, o16)
+    t, (c, ph, info) = median_time(lambda: lat.pion_correlator(p, xi, o16), reps)
+    out["pion_correlator_fp16_inner"] = {"ms": t * 1e3, "iters": info.iters,
+                                         "C_0_to_4": [float(v) for v in c[:5]]}
+    lat.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--only", default="full,eo,batch,nd")
+    ap.add_argument("--only", default="full,eo,batch,nd,minv")
     args = ap.parse_args(argv)
     import torch
 
@@ -225,6 +268,9 @@ def main(argv=None):
     if "nd" in want:
         log("32^3x64 flavour doublet")
         res["doublet_32c64"] = nd_32c64(tmq, torch, synth, args.reps)
+    if "minv" in want:
+        log("24^3x48 full-lattice inversion, BiCGstab, correlator")
+        res["minv_24c48"] = minv_24c48(tmq, torch, synth, args.reps)
     print(json.dumps(res))
     return res
 
