@@ -231,6 +231,14 @@ hipError_t launch_bi_xr(const FieldDesc &x, const FieldDesc &p, const FieldDesc 
 hipError_t launch_bi_scalar(int op, const double *p0, const double *p1, const double *p2, int nparts,
                             BicgScalars *s, double tol2, int relative, BicgScalars *publish, hipStream_t st);
 
+// the whole full-lattice FP64 CG on Q^+ Q^- of a tiny lattice in one
+// workgroup (small_cg.hip): f = {b, x, r, p, t, ap}, stacked full fields;
+// continues from x and the counters in *sc (zeroed before the first call),
+// ends with the true residual in sc->rr and sc->done set if it met the target
+constexpr long SMALL_CG_MAX_SITES = 1024;
+hipError_t launch_small_cg(const Geom &g, const FieldDesc *f, const LinkDesc &lk, const OpParams &op, double tol2,
+                           int relative, int max_iter, CgScalars *sc, hipStream_t st);
+
 // a 4x4 complex spin matrix (row-major)
 struct SpinMat {
     double2 m[4][4];

@@ -360,7 +360,9 @@ static int read_scalars(Lattice *L, int n, hipStream_t st, std::vector<CgScalars
 }
 
 // Small lattices are launch-latency bound (a 4^4 iteration is nine kernels
-// of a few microseconds): there the iterations run as HIP graphs of CHUNK
+// of a few microseconds).  Tiny ones (at most SMALL_CG_MAX_SITES sites) run
+// the whole CG in one workgroup (small_cg.hip); on the others up to
+// GRAPH_MAX_SITES sites the iterations run as HIP graphs of CHUNK
 // iterations each, captured once per solve, two graphs publishing their
 // scalars to the two halves of the ring so that the host reads one chunk
 // while the next runs.  Right-hand sides already converged skip their work
@@ -385,6 +387,35 @@ int solve_full(Lattice *L, const tmq_params &p, const tmq_solver_opts &o, const 
     CgScalars *S = L->scal;
     const double tol2 = o.tol * o.tol;
     const long ps = L->pstride;
+    if (n <= SMALL_CG_MAX_SITES && !L->timing && !getenv("TMQ_NO_SMALL_CG")) {
+        // the whole CG in one workgroup (small_cg.hip); called again from its
+        // true residual if that has not met the target
+        const FieldDesc f[6] = {b, x, r, pp, t, ap};
+        TMQ_HIP(launch_zero(x, one, st));
+        TMQ_HIP(hipMemsetAsync(S, 0, sizeof(CgScalars), st));
+        std::vector<CgScalars> cur;
+        for (int call = 0;; call++) {
+            TMQ_HIP(launch_small_cg(L->g, f, lk, op, tol2, o.relative, max_iter, S, st));
+            TMQ_TRY(read_scalars(L, 1, st, cur));
+            if (cur[0].done || cur[0].nan || cur[0].iter >= max_iter || call >= 20) break;
+        }
+        int status = TMQ_OK;
+        if (cur[0].nan) {
+            status = TMQ_ENAN;
+            set_error("tmq_solve_full: non-finite value in CG");
+        } else if (!cur[0].done) {
+            status = TMQ_ENOCONV;
+            set_error("tmq_solve_full: max_iter reached before the tolerance");
+        }
+        if (info) {
+            info->status = status;
+            info->iters = cur[0].iter;
+            info->reliable_updates = cur[0].reliable;
+            info->true_rel_residual = cur[0].bb > 0 ? std::sqrt(cur[0].rr / cur[0].bb) : std::sqrt(cur[0].rr);
+            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return status;
+    }
     const bool graphs = n <= GRAPH_MAX_SITES && !L->timing && !getenv("TMQ_NO_GRAPH");
     if (graphs) {
         // graphs are captured on the lattice's own stream (never the null stream)

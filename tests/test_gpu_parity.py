@@ -232,7 +232,9 @@ def test_cg_full_lattice_graphs_equal_plain(tmq, monkeypatch):
     replays (two graphs of four iterations, replayed many times with host
     reads and synchronisations between them); the solution and the iteration
     count equal those of plain launches bit for bit, for several solves in a
-    row, and a max_iter that ends inside a chunk is honoured."""
+    row, and a max_iter that ends inside a chunk is honoured.  (The one-
+    workgroup CG that tiny lattices use otherwise is switched off here.)"""
+    monkeypatch.setenv("TMQ_NO_SMALL_CG", "1")
     dims = (4, 4, 4, 4)
     lat, U = lattice(tmq, dims, seed=1000)
     p = tmq.params(0.16, 0.01, THETA)
@@ -250,6 +252,44 @@ def test_cg_full_lattice_graphs_equal_plain(tmq, monkeypatch):
     b = dev(synth.gaussian_spinor(dims + (4, 3), seed=2003).reshape(-1, 4, 3))
     x, info = lat.solve_full(p, b, tmq.solver_opts(tol=1e-10, max_iter=10), check=False)
     assert info.status == tmq.TMQ_ENOCONV and info.iters == 10
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 2, 10)], ids=lambda d: "x".join(map(str, d)))
+def test_cg_full_lattice_one_workgroup(tmq, dims, monkeypatch):
+    """Tiny lattices run the whole full-lattice CG in one workgroup: the
+    oracle's true residual meets the tolerance, the solution agrees with the
+    multi-kernel CG (reductions summed in another order), iteration counts
+    agree with the oracle's, repeated solves give the same bits, and max_iter
+    is honoured with the true residual reported."""
+    lat, U = lattice(tmq, dims, seed=1010)
+    V = int(np.prod(dims))
+    b = synth.gaussian_spinor(dims + (4, 3), seed=2010).reshape(-1, 4, 3)
+    p = tmq.params(0.16, 0.01, THETA_GEN)
+    x, info = lat.solve_full(p, dev(b), tmq.solver_opts(tol=1e-10))
+    x2, info2 = lat.solve_full(p, dev(b), tmq.solver_opts(tol=1e-10))
+    assert torch.equal(x, x2) and info.iters == info2.iters
+    res = oracle.true_residual(U, b, host(x), 0.16, 0.01, THETA_GEN, eo=False)
+    _, io = oracle.cg(U, b, 0.16, 0.01, THETA_GEN, eo=False, tol=1e-10)
+    print(f"one-workgroup CG {dims}: iters {info.iters} (oracle {io['iters']}) res {res:.2e} "
+          f"({info.seconds * 1e3:.2f} ms)")
+    assert info.status == 0 and res <= 1e-10
+    assert abs(res - info.true_rel_residual) <= 1e-3 * res
+    assert abs(info.iters - io["iters"]) <= 2
+    monkeypatch.setenv("TMQ_NO_SMALL_CG", "1")
+    xm, im = lat.solve_full(p, dev(b), tmq.solver_opts(tol=1e-10))
+    monkeypatch.delenv("TMQ_NO_SMALL_CG")
+    assert rel(host(x), host(xm)) < 1e-8 and abs(im.iters - info.iters) <= 1
+    x3, i3 = lat.solve_full(p, dev(b), tmq.solver_opts(tol=1e-12, max_iter=7), check=False)
+    assert i3.status == tmq.TMQ_ENOCONV and i3.iters == 7
+    r3 = oracle.true_residual(U, b, host(x3), 0.16, 0.01, THETA_GEN, eo=False)
+    assert abs(r3 - i3.true_rel_residual) <= 1e-6 * r3
+    assert V <= 1024
+    xz, iz = lat.solve_full(p, dev(np.zeros_like(b)), tmq.solver_opts(tol=1e-10))
+    assert iz.status == 0 and iz.iters == 0 and not torch.any(xz != 0)
+    bn = b.copy()
+    bn[V // 3, 2, 1] = np.nan
+    _, i_n = lat.solve_full(p, dev(bn), tmq.solver_opts(tol=1e-10), check=False)
+    assert i_n.status == tmq.TMQ_ENAN
 
 
 def test_cg_edge_cases(tmq):
