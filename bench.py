@@ -74,6 +74,16 @@ def cpu_baseline(U, b, w, budget_s):
         if el >= budget_s or n >= 50:
             break
         log(f"cpu oracle Qhat^+Qhat^- #{n}: {el:.1f}s")
+    # the oracle's own CG to 1e-10 on the small full-lattice workload (4^4, kappa 0.16,
+    # 2 kappa mu 0.01), timed whole
+    import synth
+
+    d4 = (4, 4, 4, 4)
+    U4 = synth.random_gauge(d4, eps=0.3, seed=1000)
+    b4 = synth.gaussian_spinor(d4 + (4, 3), seed=2000).reshape(-1, 4, 3)
+    t1 = time.perf_counter()
+    _, i4 = oracle.cg(U4, b4, 0.16, 0.01, w["theta"], eo=False, tol=1e-10)
+    cg4 = time.perf_counter() - t1
     return {
         "value": round(bytes_qq * n / el / 1e9, 3),
         "unit": "GB/s",
@@ -82,6 +92,8 @@ def cpu_baseline(U, b, w, budget_s):
         "sample": f"{n} applications of the FP64 oracle's Qhat^+Qhat^- (4 hopping half-sweeps) on the "
                   f"32^3x64 workload, {el:.1f} s; bytes counted with the same algorithmic model",
         "seconds_per_QhatQhat": round(el / n, 3),
+        "cg_4444_full_ms_to_1e-10": round(cg4 * 1e3, 2),
+        "cg_4444_full_iters": i4["iters"],
     }
 
 
