@@ -236,6 +236,16 @@ int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solve
                 const double *phi, double *psi, tmq_solve_info *info);
 int tmq_solve_M_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts,
                     const double *phi, double *psi, void *stream, tmq_solve_info *info);
+/* n full-lattice sources with common parameters (1 <= n <= TMQ_MAX_RHS), e.g.
+ * the 12 spin-colour point sources of a propagator (Sec. 3.2, the inversion
+ * program): the steps above run on all of them together, the odd-site CG as one
+ * batch (links read once per half-sweep for the batch); each source keeps its
+ * own correction rounds, status and info[r], and psi[r] equals what
+ * tmq_solve_M_dev gives for phi[r] alone.  Device pointers; no psi[r] may
+ * overlap another psi or any phi.  Returns the worst status (TMQ_ENAN before
+ * TMQ_ENOCONV). */
+int tmq_solve_M_batch_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts, int n,
+                          const double *const *phi, double *const *psi, void *stream, tmq_solve_info *info);
 
 /* ------------------------------------------------- flavour doublet */
 

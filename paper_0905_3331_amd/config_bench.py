@@ -21,7 +21,9 @@
                M^+ psi = phi by the even/odd factorisation with CG on the normal
                equations (FP64 and FP16-inner) against BiCGstab on Qhat^+ itself
                (FP64); the odd-site system Qhat^+ x = b by BiCGstab against CG on
-               Qhat^+ Qhat^- followed by Qhat^-; the one-end-trick pion
+               Qhat^+ Qhat^- followed by Qhat^-; a propagator (the 12
+               spin-colour point sources of one site) batched against one
+               after another; the one-end-trick pion
                correlator of one complex Z2 time-slice source (FP16-inner)
 
 Links are random SU(3) exp(i 0.3 H), reunitarised (seeds 1000 + workload);
@@ -232,6 +234,22 @@ def minv_24c48(tmq, torch, synth, reps):
     cg_route()
     t, (x, info) = median_time(cg_route, reps)
     out["Qhat_plus_cg_normal_fp64"] = {"ms": t * 1e3, "iters": info.iters}
+    # a propagator: the 12 spin-colour point sources at one site, batched and one after another
+    V = int(np.prod(dims))
+    site = int(np.random.default_rng(2603).integers(0, V))
+    srcs = []
+    for k in range(12):
+        e = torch.zeros((V, 4, 3), dtype=torch.complex128, device="cuda")
+        e[site, k // 3, k % 3] = 1.0
+        srcs.append(e)
+    for name, opts in (("fp64", tmq.solver_opts(tol=1e-10)),
+                       ("fp16_inner", tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16"))):
+        lat.solve_M_batch(p, +1, srcs, opts)
+        tb, (_, infos) = median_time(lambda: lat.solve_M_batch(p, +1, srcs, opts), reps)
+        ta, _ = median_time(lambda: [lat.solve_M(p, +1, e, opts) for e in srcs], 1)
+        out["propagator_12_point_sources_" + name] = {
+            "batch_ms": tb * 1e3, "one_after_another_ms": ta * 1e3, "speedup": ta / tb,
+            "iters": [i.iters for i in infos], "max_true_rel_residual": max(i.true_rel_residual for i in infos)}
     xi = torch.from_numpy(synth.z2_timeslice_source(dims, 0, seed=2602).reshape(-1, 4, 3)).cuda()
     o16 = tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")
     lat.pion_correlator(p, xi, o16)

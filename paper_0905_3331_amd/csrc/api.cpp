@@ -18,6 +18,8 @@ int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o,
             hipStream_t st, tmq_solve_info *info);
 int solve_qhat_bicgstab(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const FieldDesc &fb,
                         const FieldDesc &fx, hipStream_t st, tmq_solve_info *info);
+int solve_M_batch(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, int nb, const double2 *const *phi,
+                  double2 *const *psi, hipStream_t st, tmq_solve_info *info);
 }  // namespace tmq
 
 using namespace tmq;
@@ -465,6 +467,32 @@ int tmq_solve_M_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_s
     Lattice *L = lat->L;
     DeviceGuard dg(L->device);
     return solve_M(L, *p, sign, *opts, (const double2 *)phi, (double2 *)psi, (hipStream_t)stream, info);
+}
+
+int tmq_solve_M_batch_dev(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts, int n,
+                          const double *const *phi, double *const *psi, void *stream, tmq_solve_info *info)
+{
+    if (info && n > 0) memset(info, 0, sizeof(*info) * (size_t)n);
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_sign(sign));
+    TMQ_TRY(check_opts(opts));
+    if (n < 1 || n > TMQ_MAX_RHS || !phi || !psi) {
+        set_error("tmq_solve_M_batch: need 1 <= n <= TMQ_MAX_RHS and non-NULL arrays");
+        return TMQ_EINVAL;
+    }
+    for (int r = 0; r < n; r++) {
+        TMQ_TRY(check_ptrs(phi[r], psi[r]));
+        for (int q = 0; q < n; q++)
+            if (psi[r] == phi[q] || (q != r && psi[r] == psi[q])) {
+                set_error("tmq_solve_M_batch: the psi buffers must not overlap one another or any phi");
+                return TMQ_EINVAL;
+            }
+    }
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    return solve_M_batch(L, *p, sign, *opts, n, (const double2 *const *)phi, (double2 *const *)psi,
+                         (hipStream_t)stream, info);
 }
 
 int tmq_solve_M(tmq_lattice *lat, const tmq_params *p, int sign, const tmq_solver_opts *opts, const double *phi,

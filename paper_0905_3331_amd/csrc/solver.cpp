@@ -243,110 +243,157 @@ int solve_qhat_bicgstab(Lattice *L, const tmq_params &p, int sign, const tmq_sol
 // and psi_o = A^-1 Qhat^+ g5 phi'_o for sign -1, A = Qhat^+ Qhat^- by CG.
 // The residual phi - M psi is recomputed in FP64 on the full lattice; while
 // it is above the tolerance the same steps solve for the correction.
-int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const double2 *phi, double2 *psi,
-            hipStream_t st, tmq_solve_info *info)
+// per-RHS |v|^2 of the RHS in rl of a batched FP64 field, summed on the host in a fixed order
+static int field_norms(Lattice *L, const FieldDesc &v, const RhsList &rl, hipStream_t st, std::vector<double> &out)
+{
+    const int nb = blas_grid(v.n);
+    TMQ_HIP(launch_norm2(v, rl, L->partial[2], L->pstride, st));
+    std::vector<double> part((size_t)L->pstride * MAX_RHS);
+    TMQ_HIP(hipMemcpyAsync(part.data(), L->partial[2], sizeof(double) * part.size(), hipMemcpyDeviceToHost, st));
+    TMQ_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < rl.n; i++) {
+        const int r = rl.idx[i];
+        double s = 0.0;
+        for (int k = 0; k < nb; k++) s += part[(size_t)r * L->pstride + k];
+        out[r] = s;
+    }
+    return TMQ_OK;
+}
+
+static RhsList rhs_list(const std::vector<int> &idx)
+{
+    RhsList l;
+    l.n = (int)idx.size();
+    for (int i = 0; i < l.n; i++) l.idx[i] = (unsigned char)idx[i];
+    return l;
+}
+
+int solve_M_batch(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, int nb, const double2 *const *phi,
+                  double2 *const *psi, hipStream_t st, tmq_solve_info *info)
 {
     const auto t0 = std::chrono::steady_clock::now();
     const long vh = L->g.vh, n = 2 * vh;
     FieldDesc fphi, fpsi, fr, fd, fq, fg, te, to, wo, yo, bc, yc;
-    TMQ_TRY(work_field(L, "m_phi", P64, n, &fphi));  // g5 phi
-    TMQ_TRY(work_field(L, "m_psi", P64, n, &fpsi));
-    TMQ_TRY(work_field(L, "m_r", P64, n, &fr));      // source of the round (the residual)
-    TMQ_TRY(work_field(L, "m_d", P64, n, &fd));      // solution of the round
-    TMQ_TRY(work_field(L, "m_q", P64, n, &fq));
-    TMQ_TRY(work_field(L, "m_g", P64, n, &fg));
-    TMQ_TRY(work_field(L, "m_te", P64, vh, &te));
-    TMQ_TRY(work_field(L, "m_to", P64, vh, &to));
-    TMQ_TRY(work_field(L, "m_wo", P64, vh, &wo));
-    TMQ_TRY(work_field(L, "m_yo", P64, vh, &yo));
-    TMQ_TRY(work_field(L, "m_bc", P64, vh, &bc));  // canonical odd buffers (same size)
-    TMQ_TRY(work_field(L, "m_yc", P64, vh, &yc));
-    const OpParams op = make_op(L, &p, 1);
-    const RhsList one = rhs_all(1);
+    TMQ_TRY(work_field(L, "m_phi", P64, n, &fphi, nb));  // g5 phi
+    TMQ_TRY(work_field(L, "m_psi", P64, n, &fpsi, nb));
+    TMQ_TRY(work_field(L, "m_r", P64, n, &fr, nb));      // source of the round (the residual)
+    TMQ_TRY(work_field(L, "m_d", P64, n, &fd, nb));      // solution of the round
+    TMQ_TRY(work_field(L, "m_q", P64, n, &fq, nb));
+    TMQ_TRY(work_field(L, "m_g", P64, n, &fg, nb));
+    TMQ_TRY(work_field(L, "m_te", P64, vh, &te, nb));
+    TMQ_TRY(work_field(L, "m_to", P64, vh, &to, nb));
+    TMQ_TRY(work_field(L, "m_wo", P64, vh, &wo, nb));
+    TMQ_TRY(work_field(L, "m_yo", P64, vh, &yo, nb));
+    TMQ_TRY(work_field(L, "m_bc", P64, vh, &bc, nb));  // canonical odd buffers (same size)
+    TMQ_TRY(work_field(L, "m_yc", P64, vh, &yc, nb));
+    const std::vector<tmq_params> pv((size_t)nb, p);
+    const OpParams op = make_op(L, pv.data(), nb);
+    const RhsList all = rhs_all(nb);
     const LinkDesc lk = lattice_links(L, link_fmt_for(L, P64, P64));
     const double m = sign * p.mu_tilde, c = 1.0 / (1.0 + m * m);
     const double2 mee_u = make_double2(c, -c * m), mee_d = make_double2(c, c * m);  // (M_ee)^-1
     const double2 g5_u = make_double2(1.0, 0.0), g5_d = make_double2(-1.0, 0.0);
     const int max_rounds = 4;
 
-    TMQ_HIP(launch_full_from_canonical(L->g, phi, fr, st));
-    TMQ_HIP(launch_twist(fr, fphi, one, g5_u, g5_d, st));
-    TMQ_HIP(launch_zero(fpsi, one, st));
-    double bb = 0.0, rr = 0.0;
-    TMQ_TRY(field_norm2(L, fr, st, &bb));
-    const double target = o.relative ? o.tol * o.tol * bb : o.tol * o.tol;
-    int status = TMQ_OK, iters = 0, rus = 0, rounds = 0;
-    rr = bb;
-    while (rr > target && bb > 0.0 && rounds < max_rounds) {
-        rounds++;
+    for (int r = 0; r < nb; r++) TMQ_HIP(launch_full_from_canonical(L->g, phi[r], field_rhs(fr, r), st));
+    TMQ_HIP(launch_twist(fr, fphi, all, g5_u, g5_d, st));
+    TMQ_HIP(launch_zero(fpsi, all, st));
+    std::vector<double> bb((size_t)nb), rr((size_t)nb), target((size_t)nb);
+    std::vector<int> status((size_t)nb, TMQ_OK), iters((size_t)nb, 0), rus((size_t)nb, 0);
+    TMQ_TRY(field_norms(L, fr, all, st, bb));
+    std::vector<int> active;
+    for (int r = 0; r < nb; r++) {
+        target[r] = o.relative ? o.tol * o.tol * bb[r] : o.tol * o.tol;
+        rr[r] = bb[r];
+        if (rr[r] > target[r] && bb[r] > 0.0) active.push_back(r);
+    }
+    for (int round = 0; !active.empty() && round < max_rounds; round++) {
+        const RhsList al = rhs_list(active);
         const FieldDesc re = field_sub(fr, 0, vh), ro = field_sub(fr, vh, vh);
         const FieldDesc de = field_sub(fd, 0, vh), dd = field_sub(fd, vh, vh);
         // phi'_o = r_o + kappa H_oe (M_ee)^-1 r_e
-        TMQ_HIP(launch_twist(re, te, one, mee_u, mee_d, st));
-        TMQ_TRY(hop(L, 1, te, ro, wo, lk, op, EPI_SRC, sign, one, nullptr, nullptr, st));
+        TMQ_HIP(launch_twist(re, te, al, mee_u, mee_d, st));
+        TMQ_TRY(hop(L, 1, te, ro, wo, lk, op, EPI_SRC, sign, al, nullptr, nullptr, st));
         // odd system: Qhat^{sign} d_o = g5 phi'_o
-        TMQ_HIP(launch_twist(wo, to, one, g5_u, g5_d, st));
+        TMQ_HIP(launch_twist(wo, to, al, g5_u, g5_d, st));
         if (o.mode == TMQ_MODE_BICGSTAB) {
-            // BiCGstab on Qhat^{sign} itself
-            tmq_solve_info ci{};
-            const int cs = solve_qhat_bicgstab(L, p, sign, o, to, dd, st, &ci);
-            iters += ci.iters;
-            rus += ci.reliable_updates;
-            if (cs == TMQ_ENAN) {
-                status = TMQ_ENAN;
-                break;
+            // BiCGstab on Qhat^{sign} itself, one right-hand side at a time
+            for (int r : active) {
+                tmq_solve_info ci{};
+                const int cs = solve_qhat_bicgstab(L, p, sign, o, field_rhs(to, r), field_rhs(dd, r), st, &ci);
+                iters[r] += ci.iters;
+                rus[r] += ci.reliable_updates;
+                if (cs != TMQ_OK && cs != TMQ_ENOCONV && cs != TMQ_ENAN) return cs;
+                if (cs != TMQ_OK) status[r] = cs;
             }
-            if (cs != TMQ_OK && cs != TMQ_ENOCONV) return cs;
-            if (cs == TMQ_ENOCONV) status = TMQ_ENOCONV;
         } else {
-            if (sign < 0) {
-                TMQ_TRY(apply_Qhat(L, op, +1, to, wo, te, lk, one, nullptr, nullptr, st));
-                TMQ_HIP(launch_to_canonical(wo, (double2 *)bc.data, st));
-            } else {
-                TMQ_HIP(launch_to_canonical(to, (double2 *)bc.data, st));
+            // CG on Qhat^+ Qhat^- for all of them together
+            if (sign < 0) TMQ_TRY(apply_Qhat(L, op, +1, to, wo, te, lk, al, nullptr, nullptr, st));
+            const FieldDesc &src = sign < 0 ? wo : to;
+            std::vector<const double *> bp;
+            std::vector<double *> yp;
+            std::vector<tmq_params> pa;
+            for (int r : active) {
+                TMQ_HIP(launch_to_canonical(field_rhs(src, r), (double2 *)field_rhs(bc, r).data, st));
+                bp.push_back((const double *)field_rhs(bc, r).data);
+                yp.push_back((double *)field_rhs(yc, r).data);
+                pa.push_back(p);
             }
-            tmq_solve_info ci{};
-            const double *bp = (const double *)bc.data;
-            double *yp = (double *)yc.data;
-            const int cs = solve_batch(L, 1, &p, o, &bp, &yp, st, &ci, nullptr);
-            iters += ci.iters;
-            rus += ci.reliable_updates;
-            if (cs == TMQ_ENAN) {
-                status = TMQ_ENAN;
-                break;
+            std::vector<tmq_solve_info> ci(active.size());
+            const int cs = solve_batch(L, (int)active.size(), pa.data(), o, bp.data(), yp.data(), st, ci.data(),
+                                       nullptr);
+            if (cs != TMQ_OK && cs != TMQ_ENOCONV && cs != TMQ_ENAN) return cs;
+            for (size_t i = 0; i < active.size(); i++) {
+                const int r = active[i];
+                iters[r] += ci[i].iters;
+                rus[r] += ci[i].reliable_updates;
+                if (ci[i].status != TMQ_OK) status[r] = ci[i].status;
+                TMQ_HIP(launch_from_canonical((const double2 *)field_rhs(yc, r).data, field_rhs(yo, r), st));
             }
-            if (cs != TMQ_OK && cs != TMQ_ENOCONV) return cs;
-            if (cs == TMQ_ENOCONV) status = TMQ_ENOCONV;
-            TMQ_HIP(launch_from_canonical((const double2 *)yc.data, yo, st));
             if (sign > 0)
-                TMQ_TRY(apply_Qhat(L, op, -1, yo, dd, te, lk, one, nullptr, nullptr, st));
+                TMQ_TRY(apply_Qhat(L, op, -1, yo, dd, te, lk, al, nullptr, nullptr, st));
             else
-                TMQ_HIP(launch_convert(yo, dd, one, st));
+                TMQ_HIP(launch_convert(yo, dd, al, st));
         }
         // d_e = (M_ee)^-1 (r_e + kappa H_eo d_o) ; psi += d
-        TMQ_TRY(hop(L, 0, dd, re, de, lk, op, EPI_REC, sign, one, nullptr, nullptr, st));
-        TMQ_HIP(launch_accumulate(fpsi, fd, one, st));
+        TMQ_TRY(hop(L, 0, dd, re, de, lk, op, EPI_REC, sign, al, nullptr, nullptr, st));
+        TMQ_HIP(launch_accumulate(fpsi, fd, al, st));
         // r = phi - M psi = g5 (g5 phi - Q psi)
-        TMQ_TRY(apply_Q_full(L, op, sign, fpsi, fq, lk, one, st));
-        TMQ_HIP(launch_residual(fphi, fq, fg, one, L->partial[2], L->pstride, st));
-        TMQ_HIP(launch_twist(fg, fr, one, g5_u, g5_d, st));
-        TMQ_TRY(field_norm2(L, fr, st, &rr));
-        if (status == TMQ_ENOCONV) break;
+        TMQ_TRY(apply_Q_full(L, op, sign, fpsi, fq, lk, al, st));
+        TMQ_HIP(launch_residual(fphi, fq, fg, al, L->partial[2], L->pstride, st));
+        TMQ_HIP(launch_twist(fg, fr, al, g5_u, g5_d, st));
+        TMQ_TRY(field_norms(L, fr, al, st, rr));
+        std::vector<int> next;
+        for (int r : active)
+            if (status[r] == TMQ_OK && rr[r] > target[r]) next.push_back(r);
+        active.swap(next);
     }
-    if (!std::isfinite(rr)) status = TMQ_ENAN;
-    if (status == TMQ_OK && rr > target) status = TMQ_ENOCONV;
-    TMQ_HIP(launch_full_to_canonical(L->g, fpsi, psi, st));
+    int worst = TMQ_OK;
+    for (int r = 0; r < nb; r++) {
+        if (!std::isfinite(rr[r])) status[r] = TMQ_ENAN;
+        if (status[r] == TMQ_OK && rr[r] > target[r]) status[r] = TMQ_ENOCONV;
+        if (status[r] == TMQ_ENAN || (status[r] == TMQ_ENOCONV && worst == TMQ_OK)) worst = status[r];
+        TMQ_HIP(launch_full_to_canonical(L->g, field_rhs(fpsi, r), psi[r], st));
+    }
     TMQ_HIP(hipStreamSynchronize(st));
-    if (info) {
-        info->status = status;
-        info->iters = iters;
-        info->reliable_updates = rus;
-        info->true_rel_residual = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
-        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
-    if (status == TMQ_ENAN) set_error("tmq_solve_M: non-finite value");
-    if (status == TMQ_ENOCONV) set_error("tmq_solve_M: tolerance not reached");
-    return status;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        for (int r = 0; r < nb; r++) {
+            info[r].status = status[r];
+            info[r].iters = iters[r];
+            info[r].reliable_updates = rus[r];
+            info[r].true_rel_residual = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : std::sqrt(rr[r]);
+            info[r].seconds = secs;
+        }
+    if (worst == TMQ_ENAN) set_error("tmq_solve_M: non-finite value");
+    if (worst == TMQ_ENOCONV) set_error("tmq_solve_M: tolerance not reached");
+    return worst;
+}
+
+int solve_M(Lattice *L, const tmq_params &p, int sign, const tmq_solver_opts &o, const double2 *phi, double2 *psi,
+            hipStream_t st, tmq_solve_info *info)
+{
+    return solve_M_batch(L, p, sign, o, 1, &phi, &psi, st, info);
 }
 
 // ------------------------------------------------------ full lattice CG

@@ -111,6 +111,8 @@ _SIGS = {
     "tmq_merge_eo": (_ip, [_vp, _vp, _vp, _vp]),
     "tmq_split_eo_dev": (_ip, [_vp, _vp, _vp, _vp, _vp]),
     "tmq_merge_eo_dev": (_ip, [_vp, _vp, _vp, _vp, _vp]),
+    "tmq_solve_M_batch_dev": (_ip, [_vp, _P(tmq_params), _ip, _P(tmq_solver_opts), _ip, _P(_vp), _P(_vp), _vp,
+                                    _P(tmq_solve_info)]),
     "tmq_set_kernel_timing": (_ip, [_vp, _ip]),
     "tmq_kernel_stats": (_ip, [_vp, ctypes.c_char_p, _P(ctypes.c_int), _P(ctypes.c_double),
                                _P(ctypes.c_double), _P(ctypes.c_double)]),
@@ -560,6 +562,26 @@ class Lattice:
             o = _dptr(odd, nh, "odd") if odd is not None else None
             _check(_lib.tmq_merge_eo_dev(self._h, e, o, _dptr(full, n, "full"), _stream(stream)), "tmq_merge_eo")
         return full
+
+    def solve_M_batch(self, p: tmq_params, sign: int, phis, opts: tmq_solver_opts, psis=None, stream=None,
+                      check=True):
+        """M^{sign} psi_r = phi_r for a batch of full-lattice sources (device tensors (V, 4, 3)) with common
+        parameters; returns (list of psi, list of SolveInfo)."""
+        import torch
+
+        n = len(phis)
+        if not 1 <= n <= MAX_RHS:
+            raise ValueError(f"need 1..{MAX_RHS} sources")
+        nc = self.V * 12
+        psis = [torch.empty_like(f) for f in phis] if psis is None else psis
+        infos = (tmq_solve_info * n)()
+        pp = (ctypes.c_void_p * n)(*[_dptr(f, nc, "phi").value for f in phis])
+        qp = (ctypes.c_void_p * n)(*[_dptr(f, nc, "psi").value for f in psis])
+        code = _lib.tmq_solve_M_batch_dev(self._h, ctypes.byref(p), sign, ctypes.byref(opts), n, pp, qp,
+                                          _stream(stream), infos)
+        if check:
+            _check(code, "tmq_solve_M_batch")
+        return psis, [_info(i) for i in infos]
 
     # ---------------------------------------------------------- diagnostics
     def set_kernel_timing(self, on: bool):

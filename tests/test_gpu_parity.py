@@ -546,3 +546,31 @@ def test_bicgstab_edges_and_validation(tmq):
     with pytest.raises(tmq.TmqError) as e:
         lat.solve(p, dev(b), tmq.solver_opts(mode="bicgstab"))
     assert e.value.code == tmq.TMQ_EINVAL
+
+
+@pytest.mark.parametrize("sloppy", ["fp64", "fp16"])
+def test_solve_M_batch_point_sources(tmq, sloppy):
+    """The 12 spin-colour point sources of a propagator through the batched
+    full-lattice inversion: every solution meets the tolerance by the oracle's
+    M and equals the inversion of its source alone bit for bit."""
+    dims = (8, 4, 4, 6)
+    lat, U = lattice(tmq, dims, seed=111)
+    V = int(np.prod(dims))
+    site = 37
+    srcs = []
+    for k in range(12):
+        e = np.zeros((V, 4, 3), np.complex128)
+        e[site, k // 3, k % 3] = 1.0
+        srcs.append(e)
+    p = tmq.params(0.1632, 0.004, THETA)
+    o = tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp16")
+    psis, infos = lat.solve_M_batch(p, +1, [dev(e) for e in srcs], o)
+    for k in (0, 5, 11):
+        x1, i1 = lat.solve_M(p, +1, dev(srcs[k]), o)
+        assert torch.equal(x1, psis[k]), k
+        assert (i1.iters, i1.true_rel_residual) == (infos[k].iters, infos[k].true_rel_residual)
+    for k in range(12):
+        phi = srcs[k].reshape(dims + (4, 3))
+        r = phi - oracle.M(U, host(psis[k]).reshape(phi.shape), 0.1632, 0.004, +1, THETA)
+        res = float(np.linalg.norm(r) / np.linalg.norm(phi))
+        assert infos[k].status == 0 and res <= 1e-10, (k, res)
