@@ -116,3 +116,81 @@ def test_su3_two_row_reconstruction(spinlib):
         third = np.zeros(3, np.complex128)
         spinlib.su3_reconstruct(rows.ctypes.data_as(dp), third.ctypes.data_as(dp))
         assert np.max(np.abs(third - u[2])) < 1e-15
+
+
+# ------------------------------------------------ hop block orders (host replay)
+# A replay of the hop kernel's map from (block, lane) to output site for each
+# block order, as written in hop_impl.h / hop.hip: every site of the parity is
+# computed exactly once per field (per flavour for doublet lane pairs), and no
+# active lane addresses a site outside the field.
+
+HOP_BLOCK = 256
+
+
+def _hop_grid(n):
+    g = (n + HOP_BLOCK - 1) // HOP_BLOCK
+    return (g + 7) // 8 * 8
+
+
+def _grid_variant(dims, order, lps):
+    T, LZ, LY, LX = dims
+    plane, vh = LY * (LX // 2), T * LZ * LY * (LX // 2)
+    if order == "plain":
+        return _hop_grid(lps * vh)
+    if order == "zslab":
+        zc = LZ // 8 + (1 if LZ % 8 else 0)
+        return 8 * ((lps * T * zc * plane + HOP_BLOCK - 1) // HOP_BLOCK)
+    tc = T // 8 + (1 if T % 8 else 0)
+    return 8 * ((lps * LZ * tc * plane + HOP_BLOCK - 1) // HOP_BLOCK)
+
+
+def _replay(dims, order, lps):
+    T, LZ, LY, LX = dims
+    XH = LX // 2
+    plane, vh = LY * XH, T * LZ * LY * XH
+    nblk = _grid_variant(dims, order, lps)
+    spb = HOP_BLOCK // lps
+    hits = np.zeros((lps, vh), dtype=np.int64)
+    tid = np.arange(HOP_BLOCK)
+    ls, fl = (tid >> 1, tid & 1) if lps == 2 else (tid, np.zeros_like(tid))
+    for b in range(nblk):
+        j, sb = b & 7, b >> 3
+        if order == "plain":
+            h = (j * (nblk >> 3) + sb) * spb + ls
+            active = h < vh
+        elif order == "zslab":
+            zb, zr = LZ >> 3, LZ & 7
+            zc, z0 = zb + (1 if j < zr else 0), j * zb + min(j, zr)
+            S = zc * plane
+            l = sb * spb + ls
+            active = l < T * S
+            t, rem = l // S, l % S
+            z = z0 + rem // plane
+            r2 = rem - (z - z0) * plane
+            y, xh = r2 // XH, r2 % XH
+            h = ((t * LZ + z) * plane) + y * XH + xh
+        else:
+            tb, tr = T >> 3, T & 7
+            tc, t0 = tb + (1 if j < tr else 0), j * tb + min(j, tr)
+            P = tc * plane
+            l = sb * spb + ls
+            active = l < LZ * P
+            z, rem = l // P, l % P
+            t = t0 + rem // plane
+            r2 = rem - (t - t0) * plane
+            y, xh = r2 // XH, r2 % XH
+            h = ((t * LZ + z) * plane) + y * XH + xh
+        assert np.all(h[active] >= 0) and np.all(h[active] < vh), (dims, order, b)
+        np.add.at(hits, (fl[active], h[active]), 1)
+    return hits
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 6, 10), (10, 4, 6, 6), (48, 24, 24, 24), (12, 10, 2, 4), (2, 2, 2, 2)],
+                         ids=lambda d: "x".join(map(str, d)))
+@pytest.mark.parametrize("lps", [1, 2])
+def test_hop_block_orders_cover_every_site_once(dims, lps):
+    T, LZ = dims[0], dims[1]
+    orders = ["plain"] + (["zslab"] if LZ >= 8 else []) + (["tslab"] if T >= 8 else [])
+    for order in orders:
+        hits = _replay(dims, order, lps)
+        assert np.all(hits == 1), (dims, order, lps, hits.min(), hits.max())
