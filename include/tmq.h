@@ -14,6 +14,12 @@
  *                on the odd sites                                 eqs. (eo3), (eo4)
  *   solve         Qhat^+ Qhat^- x = b  (Qhat^- applied first) by CG, Sec. 4.4
  *
+ * Around that path: batches of right-hand sides and a solve server (many
+ * inversions per gauge field, Sec. 3.2), the full-lattice M^{+-} inversion
+ * through the even/odd factorisation (App. B), BiCGstab on Qhat^{+-} (Sec. 4.4),
+ * the mass non-degenerate flavour doublet (eq. (Dh)), the HMC force solves
+ * (eq. (eo6)) and the one-end-trick correlators of the online measurements.
+ *
  * Gamma matrices are those of Appendix A (gamma_5 = diag(1,1,-1,-1)); mu = 0:t,
  * 1:x, 2:y, 3:z.  theta_mu = 1 is antiperiodic, psi(x + L_mu) = e^{i theta_mu pi} psi(x)
  * (Sec. 2.4).
