@@ -1,7 +1,8 @@
 """GPU checks at the full sizes of the benchmark workloads, in the launch
-configuration the benchmarks time: 24^3x48 FP64 and FP32-inner even/odd CG
-(kappa 0.1632, 2 kappa mu 0.004) and the 48-RHS batch on 24^3x48 (12 point
-sources x 4 twisted masses).  Solutions are judged by the oracle's FP64 true
+configuration the benchmarks time: the 32^3x64 headline (FP64 and FP16 Qhat^+
+over the whole lattice, the mixed FP16 solve), 24^3x48 FP64 and FP32-inner
+even/odd CG (kappa 0.1632, 2 kappa mu 0.004), BiCGstab and the doublet at
+24^3x48, and the 48-RHS batch on 24^3x48 (12 point sources x 4 twisted masses).  Solutions are judged by the oracle's FP64 true
 residual (the oracle applies Qhat^+Qhat^- once per check), and batched
 solutions against their solves alone, bit for bit."""
 import numpy as np
@@ -83,4 +84,45 @@ def test_doublet_24c48_mixed(tmq):
     print(f"doublet 24^3x48 fp16 inner: iters {info.iters} reliable {info.reliable_updates} true res {res:.2e}")
     assert info.status == 0 and res <= 1e-10
     assert abs(res - info.true_rel_residual) <= 1e-3 * res
+    lat.close()
+
+
+def test_headline_32c64_operator_and_mixed_solve(tmq):
+    """The 32^3x64 workload of the benchmark, in its launch configuration
+    (autotuned FP16 half-sweeps): the FP16 Qhat^+ against the oracle on the
+    whole lattice (bounded by the FP16 storage), the FP64 Qhat^+ to 1e-13, and
+    the mixed FP16 solve to 1e-10 by the oracle's FP64 true residual."""
+    dims = (64, 32, 32, 32)
+    U = synth.random_gauge(dims, eps=0.3, seed=1002)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(U)
+    b = synth.gaussian_odd(dims, seed=2200)
+    p = tmq.params(0.1632, 0.004, THETA)
+    want = oracle.Qhat(U, b, 0.1632, 0.004, +1, THETA)
+    bd = torch.from_numpy(b).cuda()
+    for prec, bound in (("fp64", 1e-13), ("fp16", 3e-3)):
+        got = lat.apply_Qhat(p, +1, bd, prec=prec).cpu().numpy()
+        err = float(np.linalg.norm((got - want).ravel()) / np.linalg.norm(want.ravel()))
+        print(f"32^3x64 Qhat^+ {prec}: relative error {err:.2e}")
+        assert err < bound
+    x, info = lat.solve(p, bd, tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16"))
+    res = oracle.true_residual(U, b, x.cpu().numpy(), 0.1632, 0.004, THETA)
+    print(f"32^3x64 mixed fp16: iters {info.iters} reliable {info.reliable_updates} true res {res:.2e}")
+    assert info.status == 0 and res <= 1e-10
+    assert abs(res - info.true_rel_residual) <= 1e-3 * res
+    lat.close()
+
+
+def test_bicgstab_24c48(tmq):
+    """BiCGstab on Qhat^+ at 24^3x48: the oracle's Qhat of the solution gives b back to 1e-10."""
+    U = synth.random_gauge(DIMS, eps=0.3, seed=1001)
+    lat = tmq.Lattice(DIMS)
+    lat.load_gauge(U)
+    b = synth.gaussian_odd(DIMS, seed=2601)
+    p = tmq.params(0.1632, 0.004, THETA)
+    x, info = lat.solve_Qhat(p, +1, torch.from_numpy(b).cuda(), tmq.solver_opts(tol=1e-10))
+    r = b - oracle.Qhat(U, x.cpu().numpy(), 0.1632, 0.004, +1, THETA)
+    res = float(np.linalg.norm(r.ravel()) / np.linalg.norm(b.ravel()))
+    print(f"24^3x48 BiCGstab: iters {info.iters} true res {res:.2e}")
+    assert info.status == 0 and res <= 1e-10
     lat.close()
