@@ -1,9 +1,5 @@
 // hop.hip -- dispatch of the hopping half-sweep to the per-format translation
 // units, the variant table and grid sizes.
-#include <algorithm>
-#include <utility>
-#include <vector>
-
 #include "devutil.h"
 #include "views.h"
 
@@ -51,37 +47,6 @@ int hop_grid_variant(const Geom &g, int v, int lanes_per_site)
     return (int)(8 * per_xcd);
 }
 
-
-void hop_block_order(const Geom &g, int v, int lanes_per_site, int chunks, int *order)
-{
-    const int nblk = hop_grid_variant(g, v, lanes_per_site), nb = nblk / 8;
-    const long spb = HOP_BLOCK / lanes_per_site, plane = (long)g.LY * g.XH;
-    const int ord = hop_variant_valid(g, v) ? kVariants[v].ord : ORD_PLAIN;
-    std::vector<std::pair<int, int>> key((size_t)nb);
-    for (int j = 0; j < 8; j++) {
-        for (int sb = 0; sb < nb; sb++) {
-            // y of the block's first site in the variant's enumeration of XCD j's share
-            long pos = -1;
-            if (ord == ORD_ZSLAB) {
-                const int zb = g.LZ >> 3, zr = g.LZ & 7, zc = zb + (j < zr ? 1 : 0);
-                const long S = (long)zc * plane, l = (long)sb * spb;
-                if (l < (long)g.T * S) pos = l % S;
-            } else if (ord == ORD_TSLAB) {
-                const int tb = g.T >> 3, tr = g.T & 7, tc = tb + (j < tr ? 1 : 0);
-                const long P = (long)tc * plane, l = (long)sb * spb;
-                if (l < (long)g.LZ * P) pos = l % P;
-            } else {
-                const long h = ((long)j * nb + sb) * spb;
-                if (h < g.vh) pos = h;
-            }
-            const int chunk = pos < 0 ? chunks : (int)(((pos % plane) / g.XH) * chunks / g.LY);
-            key[(size_t)sb] = {chunk, sb};
-        }
-        std::stable_sort(key.begin(), key.end(),
-                         [](const std::pair<int, int> &a, const std::pair<int, int> &b) { return a.first < b.first; });
-        for (int i = 0; i < nb; i++) order[(size_t)j * nb + i] = key[(size_t)i].second;
-    }
-}
 
 bool hop_all_variants(int prec, int link_fmt)
 {

@@ -52,7 +52,6 @@ struct HopArgs {
     int phase_mask;  // bit mu set when the boundary phase of direction mu is not 1
     int nblk;        // blocks per RHS
     int group;       // RHS processed together per site block (see the kernel)
-    const int *border;  // XCD block order (HopTune::border) or nullptr: the variant's own
     BatchView<SP> in, self, out;
     LK lk;
     OpParams op;
@@ -297,9 +296,8 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
     const int GR = a.group, gr = k / (nb * GR);        // group of tuples of this block
     const int gsize = min(GR, ntup - gr * GR);         // the last group may be smaller
     const int within = k - gr * nb * GR;
-    int sb = within / gsize;                           // site block within the XCD's share
-    const int tup = gr * GR + (within - sb * gsize);   // tuple of the group (from the position)
-    if (a.border) sb = a.border[j * nb + sb];          // same blocks, another order
+    const int sb = within / gsize;                     // site block within the XCD's share
+    const int tup = gr * GR + (within - sb * gsize);
     int rhs[G];
     bool live[G];
     bool any = false;
@@ -590,7 +588,6 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     a.pstride = pstride;
     a.scal = scal;
     a.one = 1.0f;
-    a.border = tu.border;
     if (ep != EP_STORE) {
         a.cg_r = make_bv<SP>(cg->r);
         a.cg_p = make_bv<SP>(cg->p);
@@ -599,7 +596,6 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     if (ALL != hop_all_variants(in.prec, lk.fmt)) return hipErrorInvalidValue;  // tables out of step
     int variant = tu.variant;
     if (!ALL || !hop_variant_valid(g, variant)) variant = 0;
-    if (variant != tu.variant || op.nd) a.border = nullptr;  // a table belongs to its variant, one lane per site
     if (op.nd) {
         // doublets: the two flavours of a site in a lane pair (RHS pairs 2d, 2d + 1 of rl)
         if (rl.n % 2) return hipErrorInvalidValue;

@@ -155,17 +155,7 @@ struct HopTune {
     int rpl = 1;       // RHS per lane in a batched launch: 1 or 2 (FP32-arithmetic formats)
     unsigned lds = 0;  // LDS bytes reserved per block (unused by the kernel; a value above
                        // the CU's LDS / (c + 1) caps the blocks resident per CU at c)
-    // Order in which an XCD runs its site blocks (batched launches): with
-    // chunks > 1, border (device, hop_grid_variant entries) lists each XCD's
-    // blocks y-chunk by y-chunk (hop_block_order), which shortens the window of
-    // neighbour spinors a group of RHS needs in L2.  The blocks themselves, and
-    // so every partial sum, are those of the variant: results do not change.
-    int chunks = 1;
-    const int *border = nullptr;
 };
-// the block order table of variant v with the given number of y-chunks:
-// order[j * nb + i] = the i-th site block XCD j runs (nb = blocks per XCD)
-void hop_block_order(const Geom &g, int v, int lanes_per_site, int chunks, int *order);
 hipError_t launch_hop(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
                       const RhsList &rl, double *partial, long pstride, const CgScalars *scal, const HopTune &tu,

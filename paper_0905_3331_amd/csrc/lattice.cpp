@@ -76,8 +76,6 @@ Lattice::~Lattice()
         if (p) hipFree(p);
     if (scal) hipFree(scal);
     if (ring) hipHostFree(ring);
-    for (auto &t : border_tables)
-        if (t.second) hipFree(t.second);
     if (bicg) hipFree(bicg);
     if (bicg_ring) hipHostFree(bicg_ring);
     for (auto &e : bicg_ev)
@@ -131,10 +129,6 @@ int lattice_create(const int dims[4], int device, Lattice **out)
     if (const char *fr = getenv("TMQ_HOP_RPL")) {
         const int r = atoi(fr);
         if (r == 1 || r == 2) L->forced_rpl = r;
-    }
-    if (const char *e = getenv("TMQ_HOP_CHUNKS")) {
-        const int c = atoi(e);
-        if (c >= 1 && c <= 8) L->forced_chunks = c;
     }
     if (const char *fc = getenv("TMQ_HOP_CAP")) {
         const int c = atoi(fc);
@@ -386,47 +380,6 @@ static bool multi_rhs_format(int prec, int link_fmt)
 // For a batched launch, time the RHS per lane (1, or 2 where the format has
 // them) and RHS groups (the variant and cap fixed), and keep the fastest for
 // this format and batch size class.  Neither changes any result.
-// the device table of XCD block orders for variant v with `chunks` y-chunks
-// (built and checked on the host once per lattice), or nullptr for chunks 1
-static int block_order_table(Lattice *L, int v, int chunks, const int **out)
-{
-    *out = nullptr;
-    if (chunks <= 1) return TMQ_OK;
-    const int key = v * 64 + chunks;
-    for (auto &t : L->border_tables)
-        if (t.first == key) {
-            *out = t.second;
-            return TMQ_OK;
-        }
-    const int nblk = hop_grid_variant(L->g, v), nb = nblk / 8;
-    std::vector<int> order((size_t)nblk);
-    hop_block_order(L->g, v, 1, chunks, order.data());
-    for (int j = 0; j < 8; j++) {  // each XCD's entries are a permutation of its blocks
-        std::vector<char> seen((size_t)nb, 0);
-        for (int i = 0; i < nb; i++) {
-            const int sb = order[(size_t)j * nb + i];
-            if (sb < 0 || sb >= nb || seen[(size_t)sb]) {
-                set_error("internal: block order table is not a permutation");
-                return TMQ_EINVAL;
-            }
-            seen[(size_t)sb] = 1;
-        }
-    }
-    int *d = nullptr;
-    if (hipMalloc((void **)&d, sizeof(int) * (size_t)nblk) != hipSuccess) {
-        set_error("device allocation of a block order table failed");
-        return TMQ_ENOMEM;
-    }
-    if (hipMemcpy(d, order.data(), sizeof(int) * (size_t)nblk, hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(d);
-        set_error("copy of a block order table failed");
-        return TMQ_EDEVICE;
-    }
-    L->border_tables.push_back({key, d});
-    *out = d;
-    return TMQ_OK;
-}
-
 static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
                       const RhsList &rl, bool norm, hipStream_t st, HopTune *res)
@@ -441,41 +394,29 @@ static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc
     base.lds = occ_lds(L, L->hop_occ[key]);
     float best_us = 0.f;
     const int max_rpl = multi_rhs_format(in.prec, lk.fmt) ? 2 : 1;
-    // y-chunked block orders only where the variant's blocks are its own and y splits
-    const bool own = hop_all_variants(in.prec, lk.fmt) && hop_variant_valid(L->g, base.variant);
-    std::vector<int> chunk_set = {1, 2, 4};
-    if (L->forced_chunks) chunk_set = {L->forced_chunks};
-    for (int chunks : chunk_set) {
-        if (chunks > 1 && (!own || L->g.LY < 2 * chunks)) chunks = 1;
-        const int *border = nullptr;
-        TMQ_TRY(block_order_table(L, base.variant, chunks, &border));
-        for (int rpl = 1; rpl <= max_rpl && rpl <= rl.n; rpl *= 2)
-            for (int G = rpl;; G *= 2) {
-                if (G > rl.n) G = rl.n;
-                HopTune tu = base;
-                tu.rpl = rpl;
-                tu.group = G;
-                tu.chunks = chunks;
-                tu.border = border;
+    for (int rpl = 1; rpl <= max_rpl && rpl <= rl.n; rpl *= 2)
+        for (int G = rpl;; G *= 2) {
+            if (G > rl.n) G = rl.n;
+            HopTune tu = base;
+            tu.rpl = rpl;
+            tu.group = G;
+            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
+            TMQ_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 2; r++)
                 TMQ_HIP(
                     launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
-                TMQ_HIP(hipEventRecord(e0, st));
-                for (int r = 0; r < 2; r++)
-                    TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr,
-                                       tu, st));
-                TMQ_HIP(hipEventRecord(e1, st));
-                TMQ_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-                const float us = ms * 1e3f / 2;
-                bt.tried.push_back({(float)rpl, (float)G, (float)chunks, us});
-                if (best_us == 0.f || us < best_us) {
-                    bt.tu = tu;
-                    best_us = us;
-                }
-                if (G == rl.n) break;
+            TMQ_HIP(hipEventRecord(e1, st));
+            TMQ_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const float us = ms * 1e3f / 2;
+            bt.tried.push_back({(float)rpl, (float)G, us});
+            if (best_us == 0.f || us < best_us) {
+                bt.tu = tu;
+                best_us = us;
             }
-    }
+            if (G == rl.n) break;
+        }
     L->event_pool.push_back(e0);
     L->event_pool.push_back(e1);
     *res = bt.tu;
@@ -514,12 +455,12 @@ std::string tuning_report(const Lattice *L)
         char buf[256];
         snprintf(buf, sizeof(buf),
                  "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"nrhs_class\": %d, \"rhs_per_lane\": %d, "
-                 "\"group\": %d, \"chunks\": %d, \"tried\": [",
-                 i ? ", " : "", pn[b.key / 4], ln[b.key % 4], b.cls, b.tu.rpl, b.tu.group, b.tu.chunks);
+                 "\"group\": %d, \"tried\": [",
+                 i ? ", " : "", pn[b.key / 4], ln[b.key % 4], b.cls, b.tu.rpl, b.tu.group);
         s += buf;
         for (size_t j = 0; j < b.tried.size(); j++) {
-            snprintf(buf, sizeof(buf), "%s[%d, %d, %d, %.1f]", j ? ", " : "", (int)b.tried[j][0],
-                     (int)b.tried[j][1], (int)b.tried[j][2], b.tried[j][3]);
+            snprintf(buf, sizeof(buf), "%s[%d, %d, %.1f]", j ? ", " : "", (int)b.tried[j][0], (int)b.tried[j][1],
+                     b.tried[j][2]);
             s += buf;
         }
         s += "]}";

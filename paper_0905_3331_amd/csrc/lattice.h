@@ -104,11 +104,8 @@ struct Lattice {
     struct BatchTune {
         int key, cls;
         HopTune tu;
-        std::vector<std::array<float, 4>> tried;  // (RHS per lane, group, y-chunks, us per launch)
+        std::vector<std::array<float, 3>> tried;  // (RHS per lane, group, us per launch)
     };
-    // block order tables (device) of batched launches: key variant * 64 + chunks
-    std::vector<std::pair<int, int *>> border_tables;
-    int forced_chunks = 0;  // TMQ_HOP_CHUNKS in the environment (batched launches)
     std::vector<BatchTune> hop_batch;
     int hop_blocks_last = 0;  // blocks (partial sums) of the last hop launch
 

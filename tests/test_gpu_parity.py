@@ -384,33 +384,6 @@ def test_batch_equals_alone(tmq, sloppy):
         assert infos[i].status == 0 and res <= 1e-10, (i, res)
 
 
-@pytest.mark.parametrize("chunks", [2, 4])
-@pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16"])
-def test_batch_chunked_block_order(tmq, sloppy, chunks, monkeypatch):
-    """Batched launches that run an XCD's site blocks y-chunk by y-chunk (a
-    block order table) give every RHS bit for bit the result of its solve alone,
-    which runs the variant's own order: the blocks, and so the partial sums, are
-    the same."""
-    monkeypatch.setenv("TMQ_HOP_CHUNKS", str(chunks))
-    dims = (16, 8, 16, 12)  # every block order permutes its blocks on this lattice (host replay tests)
-    U = synth.random_gauge(dims, eps=0.3, seed=109)
-    lat = tmq.Lattice(dims)
-    lat.load_gauge(U)
-    ps = [tmq.params(0.1632, mut, THETA) for mut in (0.002, 0.005, 0.01, 0.02, 0.004, 0.008)]
-    srcs = [synth.gaussian_odd(dims, seed=600 + k) for k in range(len(ps))]
-    opts = tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp16" if sloppy == "fp16" else "fp32")
-    xs, infos = lat.solve_batch(ps, [dev(b) for b in srcs], opts)
-    rep = [e for e in lat.tuning_report()["batch"] if e["nrhs_class"] == 8]
-    assert rep and all(e["chunks"] == chunks for e in rep), rep
-    for i in (0, 3, 5):
-        x1, i1 = lat.solve(ps[i], dev(srcs[i]), opts)
-        assert torch.equal(x1, xs[i]), f"rhs {i} differs from its solve alone"
-        assert i1.iters == infos[i].iters and i1.reliable_updates == infos[i].reliable_updates
-    res = oracle.true_residual(U, srcs[2], host(xs[2]), 0.1632, 0.01, THETA)
-    assert infos[2].status == 0 and res <= 1e-10
-    lat.close()
-
-
 @pytest.mark.parametrize("rpl", [1, 2])
 @pytest.mark.parametrize("sloppy", ["fp32", "fp16", "bf16"])
 def test_batch_rhs_per_lane(tmq, sloppy, rpl, monkeypatch):
