@@ -26,6 +26,12 @@
                after another; the one-end-trick pion
                correlator of one complex Z2 time-slice source (FP16-inner)
 
+  hopcache     the Qhat^+ half-sweeps at 32^3x64 and at 8x32^3 (the share of one
+               of 8 GPUs when 32^3x64 is split along t; periodic here), each
+               precision timed back to back and with a 1 GiB copy before every
+               operator application, which evicts L2 and the 256 MB Infinity
+               Cache: whether the bandwidth figures are HBM or cache figures
+
 Links are random SU(3) exp(i 0.3 H), reunitarised (seeds 1000 + workload);
 theta = (1, 0, 0, 0).  Prints one JSON object.  The solutions' accuracy
 against the FP64 oracle is checked by the GPU tests at these shapes.
@@ -260,10 +266,41 @@ def minv_24c48(tmq, torch, synth, reps):
     return out
 
 
+def hop_cache(tmq, torch, synth, reps):
+    big_a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    big_b = torch.empty_like(big_a)
+    p = tmq.params(0.1632, 0.004, THETA)
+    out = {}
+    for dims in ((64, 32, 32, 32), (8, 32, 32, 32)):
+        lat = tmq.Lattice(dims)
+        lat.load_gauge(synth.random_gauge(dims, eps=0.3, seed=1005))
+        b = torch.from_numpy(synth.gaussian_odd(dims, seed=2500)).cuda()
+        o = torch.empty_like(b)
+        key = "x".join(map(str, dims))
+        out[key] = {}
+        for prec in ("fp64", "fp32", "fp16"):
+            lat.apply_Qhat(p, +1, b, o, prec=prec)  # tunes the launches
+            torch.cuda.synchronize()
+            row = {}
+            for mode in ("back_to_back", "cache_evicted"):
+                lat.set_kernel_timing(True)
+                for _ in range(10 * reps):
+                    if mode == "cache_evicted":
+                        big_b.copy_(big_a)
+                    lat.apply_Qhat(p, +1, b, o, prec=prec)
+                st = lat.kernel_stats("hop")
+                lat.set_kernel_timing(False)
+                row[mode] = {"avg_us": st["ms"] / st["launches"] * 1e3,
+                             "GBps": st["bytes"] / (st["ms"] * 1e-3) / 1e9}
+            out[key][prec] = row
+        lat.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--only", default="full,eo,batch,nd,minv")
+    ap.add_argument("--only", default="full,eo,batch,nd,minv,hopcache")
     args = ap.parse_args(argv)
     import torch
 
@@ -289,6 +326,9 @@ def main(argv=None):
     if "minv" in want:
         log("24^3x48 full-lattice inversion, BiCGstab, correlator")
         res["minv_24c48"] = minv_24c48(tmq, torch, synth, args.reps)
+    if "hopcache" in want:
+        log("32^3x64 and 8x32^3 half-sweeps, back to back and with the caches evicted")
+        res["hop_cache"] = hop_cache(tmq, torch, synth, args.reps)
     print(json.dumps(res))
     return res
 
