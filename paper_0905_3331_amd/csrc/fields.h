@@ -399,17 +399,28 @@ struct L16R {
         uint32_t w[6];
         cx<float> r2[3];
     };
+    // the six words of rows 0 and 1 (load_link = load_raw + rebuild)
     template <bool NT>
-    __device__ __forceinline__ void load_link(int par, int mu, long h, Loaded &u) const
+    __device__ __forceinline__ void load_raw(int par, int mu, long h, uint32_t w[6]) const
     {
         const uint4 va = ld<NT>(a + par * 4 * vh + lidx(h, mu, 0, 1));
         const uint2 vb = ld<NT>(b + par * 4 * vh16(vh) + lidx16(h, mu));
-        u.w[0] = va.x;
-        u.w[1] = va.y;
-        u.w[2] = va.z;
-        u.w[3] = va.w;
-        u.w[4] = vb.x;
-        u.w[5] = vb.y;
+        w[0] = va.x;
+        w[1] = va.y;
+        w[2] = va.z;
+        w[3] = va.w;
+        w[4] = vb.x;
+        w[5] = vb.y;
+    }
+    template <bool NT>
+    __device__ __forceinline__ void load_link(int par, int mu, long h, Loaded &u) const
+    {
+        load_raw<NT>(par, mu, h, u.w);
+        rebuild(u);
+    }
+    // row 2 from the words of rows 0 and 1
+    __device__ __forceinline__ void rebuild(Loaded &u) const
+    {
         auto re = [&](int i, int j) { return code_lo<false>(u.w[3 * i + j]); };
         auto im = [&](int i, int j) { return code_hi<false>(u.w[3 * i + j]); };
         // row 2, column c: conj(u0a u1b - u0b u1a) with (a, b) the other two columns in cyclic order

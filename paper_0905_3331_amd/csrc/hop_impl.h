@@ -134,6 +134,27 @@ __device__ __forceinline__ void reconstruct_fma(spinor<float> &acc, const half<f
     }
 }
 
+// One hop of a 16-bit spinor (DIR 0 forward, 1 backward) from its codes and
+// scale and the loaded link: project the codes, multiply by the link, and
+// apply the site's scale (times the phase) when accumulating
+template <int MU, int DIR, class SP, class LK, typename R>
+__device__ __forceinline__ void coded_hop(const HopArgs<SP, LK> &a, const typename LK::Loaded &u,
+                                          const uint32_t (&c)[12], float sc, spinor<R> &acc)
+{
+    const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
+    half<R> p, w;
+    project_codes<MU, DIR == 0 ? +1 : -1, SP::bf>(c, a.one, p);
+    a.lk.template apply<DIR == 1>(u, p, w);
+    if (phase) {
+        const cx<R> ph = {(R)a.op.ph[MU][0], (R)a.op.ph[MU][1]};
+        const cx<R> phd = DIR == 0 ? ph : conj(ph);
+        half_scale(w, cx<R>{sc * phd.re, sc * phd.im});
+        reconstruct_add<MU, DIR == 0 ? +1 : -1>(acc, w);
+    } else {
+        reconstruct_fma<MU, DIR == 0 ? +1 : -1>(acc, w, sc);
+    }
+}
+
 // The contribution of direction MU (forward and backward hop) for the G
 // right-hand sides of a lane: each link is loaded once and applied to the
 // projected neighbour spinor of every RHS in turn; per RHS the operations are
@@ -155,34 +176,16 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)
 #pragma unroll
         for (int gi = 0; gi < G; gi++) {
             if (!live[gi]) continue;
-            half<R> p, w;
             if constexpr (SP::coded) {
-                // 16-bit spinors: project the codes, multiply by the link, and
-                // apply the site's scale (times the phase) when accumulating
                 uint32_t c[12];
                 float sc;
                 in[gi].load_codes(hn, c, sc);
                 if (dir == 0)
-                    project_codes<MU, +1, SP::bf>(c, a.one, p);
+                    coded_hop<MU, 0>(a, u, c, sc, acc[gi]);
                 else
-                    project_codes<MU, -1, SP::bf>(c, a.one, p);
-                if (dir == 0)
-                    a.lk.template apply<false>(u, p, w);
-                else
-                    a.lk.template apply<true>(u, p, w);
-                if (phase) {
-                    half_scale(w, cx<R>{sc * phd.re, sc * phd.im});
-                    if (dir == 0)
-                        reconstruct_add<MU, +1>(acc[gi], w);
-                    else
-                        reconstruct_add<MU, -1>(acc[gi], w);
-                } else {
-                    if (dir == 0)
-                        reconstruct_fma<MU, +1>(acc[gi], w, sc);
-                    else
-                        reconstruct_fma<MU, -1>(acc[gi], w, sc);
-                }
+                    coded_hop<MU, 1>(a, u, c, sc, acc[gi]);
             } else {
+                half<R> p, w;
                 spinor<R> sp;
                 in[gi].load(hn, sp);
                 if (dir == 0) {
@@ -199,6 +202,38 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)
                     reconstruct_add<MU, -1>(acc[gi], w);
             }
         }
+    }
+}
+
+// The loads of one direction of a 16-bit spinor with FP16 two-row links
+// (forward and backward hop), taken before any arithmetic on them
+struct Raw16 {
+    uint32_t lw[2][6];  // link rows 0 and 1
+    uint32_t c[2][12];  // neighbour codes
+    float sc[2];        // neighbour scales
+};
+template <int MU, bool NT, class SP, class LK>
+__device__ __forceinline__ void load16(const HopArgs<SP, LK> &a, const SP &in, long h, long hf, long hb, Raw16 &d)
+{
+    a.lk.template load_raw<NT>(a.out_par, MU, h, d.lw[0]);
+    in.load_codes(hf, d.c[0], d.sc[0]);
+    a.lk.template load_raw<NT>(a.out_par ^ 1, MU, hb, d.lw[1]);
+    in.load_codes(hb, d.c[1], d.sc[1]);
+}
+// the arithmetic of hop_dir for one RHS on loaded data
+template <int MU, class SP, class LK, typename R>
+__device__ __forceinline__ void math16(const HopArgs<SP, LK> &a, const Raw16 &d, spinor<R> &acc)
+{
+#pragma unroll
+    for (int dir = 0; dir < 2; dir++) {
+        typename LK::Loaded u;
+#pragma unroll
+        for (int k = 0; k < 6; k++) u.w[k] = d.lw[dir][k];
+        a.lk.rebuild(u);
+        if (dir == 0)
+            coded_hop<MU, 0>(a, u, d.c[0], d.sc[0], acc);
+        else
+            coded_hop<MU, 1>(a, u, d.c[1], d.sc[1], acc);
     }
 }
 
@@ -378,17 +413,36 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 #pragma unroll
                 for (int c = 0; c < 3; c++) acc[gi].c[i][c] = cx<R>{R(0), R(0)};
 
-        hop_dir<0, NT>(a, in, live, acc, h, t + 1 == g.T ? h - (g.T - 1) * stt : h + stt,
-                       t == 0 ? h + (g.T - 1) * stt : h - stt);
-        if (SB) __builtin_amdgcn_sched_barrier(0);
-        hop_dir<1, NT>(a, in, live, acc, h, row + ((x + 1 == g.LX ? 0 : x + 1) >> 1),
-                       row + ((x == 0 ? g.LX - 1 : x - 1) >> 1));
-        if (SB) __builtin_amdgcn_sched_barrier(0);
-        hop_dir<2, NT>(a, in, live, acc, h, y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy,
-                       y == 0 ? h + (g.LY - 1) * sy : h - sy);
-        if (SB) __builtin_amdgcn_sched_barrier(0);
-        hop_dir<3, NT>(a, in, live, acc, h, z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz,
-                       z == 0 ? h + (g.LZ - 1) * sz : h - sz);
+        // forward and backward neighbours in t, x, y, z (periodic)
+        const long f0 = t + 1 == g.T ? h - (g.T - 1) * stt : h + stt, b0 = t == 0 ? h + (g.T - 1) * stt : h - stt;
+        const long f1 = row + ((x + 1 == g.LX ? 0 : x + 1) >> 1), b1 = row + ((x == 0 ? g.LX - 1 : x - 1) >> 1);
+        const long f2 = y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy, b2 = y == 0 ? h + (g.LY - 1) * sy : h - sy;
+        const long f3 = z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz, b3 = z == 0 ? h + (g.LZ - 1) * sz : h - sz;
+        if constexpr (SP::coded && __is_same(LK, L16R) && G == 1 && !ND) {
+            // 16-bit spinors, one RHS per lane: the loads of two directions (four
+            // hops) are issued before their arithmetic, which shortens the chain
+            // of dependent memory waits of a lane; same arithmetic, same order
+            if (live[0]) {
+                Raw16 d0, d1;
+                load16<0, NT>(a, in[0], h, f0, b0, d0);
+                load16<1, NT>(a, in[0], h, f1, b1, d1);
+                math16<0>(a, d0, acc[0]);
+                math16<1>(a, d1, acc[0]);
+                if (SB) __builtin_amdgcn_sched_barrier(0);
+                load16<2, NT>(a, in[0], h, f2, b2, d0);
+                load16<3, NT>(a, in[0], h, f3, b3, d1);
+                math16<2>(a, d0, acc[0]);
+                math16<3>(a, d1, acc[0]);
+            }
+        } else {
+            hop_dir<0, NT>(a, in, live, acc, h, f0, b0);
+            if (SB) __builtin_amdgcn_sched_barrier(0);
+            hop_dir<1, NT>(a, in, live, acc, h, f1, b1);
+            if (SB) __builtin_amdgcn_sched_barrier(0);
+            hop_dir<2, NT>(a, in, live, acc, h, f2, b2);
+            if (SB) __builtin_amdgcn_sched_barrier(0);
+            hop_dir<3, NT>(a, in, live, acc, h, f3, b3);
+        }
 
         if constexpr (ND) {
             if (live[0]) nd_mix(a, acc[0], rhs[0], h);
