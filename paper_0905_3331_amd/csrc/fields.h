@@ -363,6 +363,13 @@ struct L32R {
     template <bool NT, typename R>
     __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
     {
+        load_rows<NT>(par, mu, h, u);
+        su3_third_row(u);
+    }
+    // rows 0 and 1 only (load = load_rows + su3_third_row)
+    template <bool NT, typename R>
+    __device__ __forceinline__ void load_rows(int par, int mu, long h, su3<R> &u) const
+    {
         const float4 *q = p + par * 12 * vh + lidx(h, mu, 0, 3);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
@@ -370,7 +377,6 @@ struct L32R {
             u.e[(2 * k) / 3][(2 * k) % 3] = cx<R>{(R)v.x, (R)v.y};
             u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = cx<R>{(R)v.z, (R)v.w};
         }
-        su3_third_row(u);
     }
     // a link held in registers, and out = U p or U^+ p with it
     using Loaded = su3<real>;

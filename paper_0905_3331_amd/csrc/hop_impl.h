@@ -237,6 +237,46 @@ __device__ __forceinline__ void math16(const HopArgs<SP, LK> &a, const Raw16 &d,
     }
 }
 
+// The same for FP32 spinors with FP32 two-row links, one direction at a time
+// (two directions at once need about 210 VGPRs and were slower)
+struct Raw32 {
+    su3<float> u[2];        // rows 0 and 1 of the forward and backward link
+    spinor<float> sp[2];    // forward and backward neighbour
+};
+template <int MU, bool NT, class SP, class LK>
+__device__ __forceinline__ void load32(const HopArgs<SP, LK> &a, const SP &in, long h, long hf, long hb, Raw32 &d)
+{
+    a.lk.template load_rows<NT>(a.out_par, MU, h, d.u[0]);
+    in.load(hf, d.sp[0]);
+    a.lk.template load_rows<NT>(a.out_par ^ 1, MU, hb, d.u[1]);
+    in.load(hb, d.sp[1]);
+}
+// the arithmetic of hop_dir for one RHS on loaded data
+template <int MU, class SP, class LK>
+__device__ __forceinline__ void math32(const HopArgs<SP, LK> &a, Raw32 &d, spinor<float> &acc)
+{
+    const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
+    const cx<float> ph = {(float)a.op.ph[MU][0], (float)a.op.ph[MU][1]};
+#pragma unroll
+    for (int dir = 0; dir < 2; dir++) {
+        su3_third_row(d.u[dir]);
+        const cx<float> phd = dir == 0 ? ph : conj(ph);
+        half<float> p, w;
+        if (dir == 0) {
+            project<MU, +1>(d.sp[0], p);
+            a.lk.template apply<false>(d.u[0], p, w);
+        } else {
+            project<MU, -1>(d.sp[1], p);
+            a.lk.template apply<true>(d.u[1], p, w);
+        }
+        if (phase) half_scale(w, phd);
+        if (dir == 0)
+            reconstruct_add<MU, +1>(acc, w);
+        else
+            reconstruct_add<MU, -1>(acc, w);
+    }
+}
+
 // The partner lane's value (lanes 2i and 2i+1 swap: DPP quad permutation
 // [1, 0, 3, 2]).  Both lanes of a pair are active or inactive together.
 __device__ __forceinline__ float pair_swap(float v)
@@ -418,10 +458,11 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         const long f1 = row + ((x + 1 == g.LX ? 0 : x + 1) >> 1), b1 = row + ((x == 0 ? g.LX - 1 : x - 1) >> 1);
         const long f2 = y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy, b2 = y == 0 ? h + (g.LY - 1) * sy : h - sy;
         const long f3 = z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz, b3 = z == 0 ? h + (g.LZ - 1) * sz : h - sz;
-        if constexpr (SP::coded && __is_same(LK, L16R) && G == 1 && !ND) {
-            // 16-bit spinors, one RHS per lane: the loads of two directions (four
+        if constexpr (SP::coded && __is_same(LK, L16R) && NT && G == 1 && !ND) {
+            // 16-bit spinors, single-RHS launch: the loads of two directions (four
             // hops) are issued before their arithmetic, which shortens the chain
             // of dependent memory waits of a lane; same arithmetic, same order
+            // (batched launches keep more waves resident instead)
             if (live[0]) {
                 Raw16 d0, d1;
                 load16<0, NT>(a, in[0], h, f0, b0, d0);
@@ -433,6 +474,22 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
                 load16<3, NT>(a, in[0], h, f3, b3, d1);
                 math16<2>(a, d0, acc[0]);
                 math16<3>(a, d1, acc[0]);
+            }
+        } else if constexpr (__is_same(SP, SpF32) && __is_same(LK, L32R) && NT && G == 1 && !ND) {
+            // FP32, single-RHS launch: the four loads of a direction before its arithmetic
+            if (live[0]) {
+                Raw32 d;
+                load32<0, NT>(a, in[0], h, f0, b0, d);
+                math32<0>(a, d, acc[0]);
+                if (SB) __builtin_amdgcn_sched_barrier(0);
+                load32<1, NT>(a, in[0], h, f1, b1, d);
+                math32<1>(a, d, acc[0]);
+                if (SB) __builtin_amdgcn_sched_barrier(0);
+                load32<2, NT>(a, in[0], h, f2, b2, d);
+                math32<2>(a, d, acc[0]);
+                if (SB) __builtin_amdgcn_sched_barrier(0);
+                load32<3, NT>(a, in[0], h, f3, b3, d);
+                math32<3>(a, d, acc[0]);
             }
         } else {
             hop_dir<0, NT>(a, in, live, acc, h, f0, b0);
