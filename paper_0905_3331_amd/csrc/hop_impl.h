@@ -453,11 +453,15 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 #pragma unroll
                 for (int c = 0; c < 3; c++) acc[gi].c[i][c] = cx<R>{R(0), R(0)};
 
-        // forward and backward neighbours in t, x, y, z (periodic)
-        const long f0 = t + 1 == g.T ? h - (g.T - 1) * stt : h + stt, b0 = t == 0 ? h + (g.T - 1) * stt : h - stt;
-        const long f1 = row + ((x + 1 == g.LX ? 0 : x + 1) >> 1), b1 = row + ((x == 0 ? g.LX - 1 : x - 1) >> 1);
-        const long f2 = y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy, b2 = y == 0 ? h + (g.LY - 1) * sy : h - sy;
-        const long f3 = z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz, b3 = z == 0 ? h + (g.LZ - 1) * sz : h - sz;
+        // forward and backward neighbours in t, x, y, z (periodic), formed where used
+        auto f0 = [&] { return t + 1 == g.T ? h - (g.T - 1) * stt : h + stt; };
+        auto b0 = [&] { return t == 0 ? h + (g.T - 1) * stt : h - stt; };
+        auto f1 = [&] { return row + ((x + 1 == g.LX ? 0 : x + 1) >> 1); };
+        auto b1 = [&] { return row + ((x == 0 ? g.LX - 1 : x - 1) >> 1); };
+        auto f2 = [&] { return y + 1 == g.LY ? h - (g.LY - 1) * sy : h + sy; };
+        auto b2 = [&] { return y == 0 ? h + (g.LY - 1) * sy : h - sy; };
+        auto f3 = [&] { return z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz; };
+        auto b3 = [&] { return z == 0 ? h + (g.LZ - 1) * sz : h - sz; };
         if constexpr (SP::coded && __is_same(LK, L16R) && NT && G == 1 && !ND) {
             // 16-bit spinors, single-RHS launch: the loads of two directions (four
             // hops) are issued before their arithmetic, which shortens the chain
@@ -465,13 +469,13 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
             // (batched launches keep more waves resident instead)
             if (live[0]) {
                 Raw16 d0, d1;
-                load16<0, NT>(a, in[0], h, f0, b0, d0);
-                load16<1, NT>(a, in[0], h, f1, b1, d1);
+                load16<0, NT>(a, in[0], h, f0(), b0(), d0);
+                load16<1, NT>(a, in[0], h, f1(), b1(), d1);
                 math16<0>(a, d0, acc[0]);
                 math16<1>(a, d1, acc[0]);
                 if (SB) __builtin_amdgcn_sched_barrier(0);
-                load16<2, NT>(a, in[0], h, f2, b2, d0);
-                load16<3, NT>(a, in[0], h, f3, b3, d1);
+                load16<2, NT>(a, in[0], h, f2(), b2(), d0);
+                load16<3, NT>(a, in[0], h, f3(), b3(), d1);
                 math16<2>(a, d0, acc[0]);
                 math16<3>(a, d1, acc[0]);
             }
@@ -479,26 +483,26 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
             // FP32, single-RHS launch: the four loads of a direction before its arithmetic
             if (live[0]) {
                 Raw32 d;
-                load32<0, NT>(a, in[0], h, f0, b0, d);
+                load32<0, NT>(a, in[0], h, f0(), b0(), d);
                 math32<0>(a, d, acc[0]);
                 if (SB) __builtin_amdgcn_sched_barrier(0);
-                load32<1, NT>(a, in[0], h, f1, b1, d);
+                load32<1, NT>(a, in[0], h, f1(), b1(), d);
                 math32<1>(a, d, acc[0]);
                 if (SB) __builtin_amdgcn_sched_barrier(0);
-                load32<2, NT>(a, in[0], h, f2, b2, d);
+                load32<2, NT>(a, in[0], h, f2(), b2(), d);
                 math32<2>(a, d, acc[0]);
                 if (SB) __builtin_amdgcn_sched_barrier(0);
-                load32<3, NT>(a, in[0], h, f3, b3, d);
+                load32<3, NT>(a, in[0], h, f3(), b3(), d);
                 math32<3>(a, d, acc[0]);
             }
         } else {
-            hop_dir<0, NT>(a, in, live, acc, h, f0, b0);
+            hop_dir<0, NT>(a, in, live, acc, h, f0(), b0());
             if (SB) __builtin_amdgcn_sched_barrier(0);
-            hop_dir<1, NT>(a, in, live, acc, h, f1, b1);
+            hop_dir<1, NT>(a, in, live, acc, h, f1(), b1());
             if (SB) __builtin_amdgcn_sched_barrier(0);
-            hop_dir<2, NT>(a, in, live, acc, h, f2, b2);
+            hop_dir<2, NT>(a, in, live, acc, h, f2(), b2());
             if (SB) __builtin_amdgcn_sched_barrier(0);
-            hop_dir<3, NT>(a, in, live, acc, h, f3, b3);
+            hop_dir<3, NT>(a, in, live, acc, h, f3(), b3());
         }
 
         if constexpr (ND) {
