@@ -462,11 +462,12 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         auto b2 = [&] { return y == 0 ? h + (g.LY - 1) * sy : h - sy; };
         auto f3 = [&] { return z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz; };
         auto b3 = [&] { return z == 0 ? h + (g.LZ - 1) * sz : h - sz; };
-        if constexpr (SP::coded && __is_same(LK, L16R) && NT && G == 1 && !ND) {
-            // 16-bit spinors, single-RHS launch: the loads of two directions (four
-            // hops) are issued before their arithmetic, which shortens the chain
-            // of dependent memory waits of a lane; same arithmetic, same order
-            // (batched launches keep more waves resident instead)
+        if constexpr (SP::coded && __is_same(LK, L16R) && NT && G == 1) {
+            // 16-bit spinors, single-RHS (or single-doublet) launch: the loads of
+            // two directions (four hops) are issued before their arithmetic,
+            // which shortens the chain of dependent memory waits of a lane; same
+            // arithmetic, same order (batched launches keep more waves resident
+            // instead)
             if (live[0]) {
                 Raw16 d0, d1;
                 load16<0, NT>(a, in[0], h, f0(), b0(), d0);
@@ -479,8 +480,9 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
                 math16<2>(a, d0, acc[0]);
                 math16<3>(a, d1, acc[0]);
             }
-        } else if constexpr (__is_same(SP, SpF32) && __is_same(LK, L32R) && NT && G == 1 && !ND) {
-            // FP32, single-RHS launch: the four loads of a direction before its arithmetic
+        } else if constexpr (__is_same(SP, SpF32) && __is_same(LK, L32R) && NT && G == 1) {
+            // FP32, single-RHS (or single-doublet) launch: the four loads of a
+            // direction before its arithmetic
             if (live[0]) {
                 Raw32 d;
                 load32<0, NT>(a, in[0], h, f0(), b0(), d);
