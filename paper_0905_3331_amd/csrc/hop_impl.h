@@ -155,6 +155,23 @@ __device__ __forceinline__ void coded_hop(const HopArgs<SP, LK> &a, const typena
     }
 }
 
+// One hop of an FP64 or FP32 spinor (DIR 0 forward, 1 backward) with the
+// loaded link: project, multiply by the link, apply the phase, accumulate
+template <int MU, int DIR, class SP, class LK, typename R>
+__device__ __forceinline__ void plain_hop(const HopArgs<SP, LK> &a, const typename LK::Loaded &u,
+                                          const spinor<R> &sp, spinor<R> &acc)
+{
+    const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
+    half<R> p, w;
+    project<MU, DIR == 0 ? +1 : -1>(sp, p);
+    a.lk.template apply<DIR == 1>(u, p, w);
+    if (phase) {
+        const cx<R> ph = {(R)a.op.ph[MU][0], (R)a.op.ph[MU][1]};
+        half_scale(w, DIR == 0 ? ph : conj(ph));
+    }
+    reconstruct_add<MU, DIR == 0 ? +1 : -1>(acc, w);
+}
+
 // The contribution of direction MU (forward and backward hop) for the G
 // right-hand sides of a lane: each link is loaded once and applied to the
 // projected neighbour spinor of every RHS in turn; per RHS the operations are
@@ -163,8 +180,6 @@ template <int MU, bool NT, int G, class SP, class LK, typename R>
 __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)[G], const bool (&live)[G],
                                         spinor<R> (&acc)[G], long h, long hf, long hb)
 {
-    const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
-    const cx<R> ph = {(R)a.op.ph[MU][0], (R)a.op.ph[MU][1]};
     typename LK::Loaded u;
 #pragma unroll
     for (int dir = 0; dir < 2; dir++) {
@@ -172,7 +187,6 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)
         // backward: e^{-i theta pi/L} U(x-mu,mu)^+ (1 - gamma_mu) psi(x-mu), U at the neighbour
         const long hn = dir == 0 ? hf : hb;
         a.lk.template load_link<NT>(dir == 0 ? a.out_par : a.out_par ^ 1, MU, dir == 0 ? h : hb, u);
-        const cx<R> phd = dir == 0 ? ph : conj(ph);
 #pragma unroll
         for (int gi = 0; gi < G; gi++) {
             if (!live[gi]) continue;
@@ -185,21 +199,12 @@ __device__ __forceinline__ void hop_dir(const HopArgs<SP, LK> &a, const SP (&in)
                 else
                     coded_hop<MU, 1>(a, u, c, sc, acc[gi]);
             } else {
-                half<R> p, w;
                 spinor<R> sp;
                 in[gi].load(hn, sp);
-                if (dir == 0) {
-                    project<MU, +1>(sp, p);
-                    a.lk.template apply<false>(u, p, w);
-                } else {
-                    project<MU, -1>(sp, p);
-                    a.lk.template apply<true>(u, p, w);
-                }
-                if (phase) half_scale(w, phd);
                 if (dir == 0)
-                    reconstruct_add<MU, +1>(acc[gi], w);
+                    plain_hop<MU, 0>(a, u, sp, acc[gi]);
                 else
-                    reconstruct_add<MU, -1>(acc[gi], w);
+                    plain_hop<MU, 1>(a, u, sp, acc[gi]);
             }
         }
     }
@@ -255,25 +260,13 @@ __device__ __forceinline__ void load32(const HopArgs<SP, LK> &a, const SP &in, l
 template <int MU, class SP, class LK>
 __device__ __forceinline__ void math32(const HopArgs<SP, LK> &a, Raw32 &d, spinor<float> &acc)
 {
-    const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
-    const cx<float> ph = {(float)a.op.ph[MU][0], (float)a.op.ph[MU][1]};
 #pragma unroll
     for (int dir = 0; dir < 2; dir++) {
         su3_third_row(d.u[dir]);
-        const cx<float> phd = dir == 0 ? ph : conj(ph);
-        half<float> p, w;
-        if (dir == 0) {
-            project<MU, +1>(d.sp[0], p);
-            a.lk.template apply<false>(d.u[0], p, w);
-        } else {
-            project<MU, -1>(d.sp[1], p);
-            a.lk.template apply<true>(d.u[1], p, w);
-        }
-        if (phase) half_scale(w, phd);
         if (dir == 0)
-            reconstruct_add<MU, +1>(acc, w);
+            plain_hop<MU, 0>(a, d.u[0], d.sp[0], acc);
         else
-            reconstruct_add<MU, -1>(acc, w);
+            plain_hop<MU, 1>(a, d.u[1], d.sp[1], acc);
     }
 }
 
