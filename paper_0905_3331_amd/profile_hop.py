@@ -17,6 +17,8 @@ Summaries (no GPU needed):
     python -m paper_0905_3331_amd.profile_hop --summarize-pmc FETCH_CSV WRITE_CSV --copy-bytes N \
         --cmd "..." --out profiles/hop_traffic.json
 
+    python -m paper_0905_3331_amd.profile_hop --summarize-valu COUNTER_CSV --cmd "..." --out FILE.md
+
 The traffic summary scales each counter by what it reads for the plain copy
 kernel (k_stream_copy, N bytes read and N written per launch), averages it
 over the dispatches of each hop family (hop16: FP16/BF16 spinors, hop32,
@@ -144,6 +146,47 @@ def summarize_trace(stats_csv, cmd, out):
     print("\n".join(lines))
 
 
+def summarize_valu(counter_csv, cmd, out, xcds=8, simds=1024, min_dispatches=20):
+    """VALU instructions per wave and VALU busy fraction of each hop kernel.
+
+    rocprofv3 reports each counter per dispatch summed over shader engines and
+    XCDs; a wave of a one-RHS launch holds 64 sites, so VALU instructions per
+    wave are those executed per site.  Busy = SQ_ACTIVE_INST_VALU (quad-cycles,
+    all waves) x 4 / SIMDs / the per-XCD GRBM_GUI_ACTIVE (the sum over XCDs
+    divided by their number).
+    """
+    acc = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for r in csv.DictReader(open(counter_csv)):
+        k = r["Kernel_Name"]
+        if "hop_kernel" not in k:
+            continue
+        acc[k][r["Counter_Name"]] += float(r["Counter_Value"])
+        disp[k].add(r["Dispatch_Id"])
+    lines = ["# VALU work of the hop kernels in the 32^3x64 mixed solve (rocprofv3 counters)", "",
+             "Command (repo root, one MI355X; kernels run serialised under counter collection, so only counts",
+             "and ratios are used, not times):", "", "    " + cmd, "",
+             f"Kernel sources hash: {kernel_hash()}.  Busy = SQ_ACTIVE_INST_VALU x 4 / {simds} SIMDs / "
+             f"(GRBM_GUI_ACTIVE / {xcds} XCDs); instructions per wave = SQ_INSTS_VALU / SQ_WAVES, which is",
+             "per site for launches with one right-hand side per lane (64 sites per wave).", "",
+             "| kernel (template args as in the traffic summary) | dispatches | waves | VALU instr per wave | VALU busy |",
+             "|---|---|---|---|---|"]
+    for k in sorted(acc, key=lambda k: -len(disp[k])):
+        n = len(disp[k])
+        if n < min_dispatches:
+            continue
+        v = acc[k]
+        waves = v["SQ_WAVES"] / n
+        per_wave = v["SQ_INSTS_VALU"] / v["SQ_WAVES"]
+        busy = v["SQ_ACTIVE_INST_VALU"] * 4 / simds / (v["GRBM_GUI_ACTIVE"] / xcds)
+        name = k.replace("tmq::", "").split("(")[0]
+        lines.append(f"| `{name}` | {n} | {waves:.0f} | {per_wave:.0f} | {100 * busy:.0f} % |")
+    lines.append("")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dims", default="64,32,32,32", help="T,LZ,LY,LX")
@@ -152,12 +195,15 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--summarize-trace", metavar="STATS_CSV")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--summarize-valu", metavar="COUNTER_CSV")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--cmd", default="")
     ap.add_argument("--out")
     args = ap.parse_args()
     if args.summarize_trace:
         return summarize_trace(args.summarize_trace, args.cmd, args.out)
+    if args.summarize_valu:
+        return summarize_valu(args.summarize_valu, args.cmd, args.out)
     if args.summarize_pmc:
         return summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.copy_bytes, args.cmd, args.out)
 
