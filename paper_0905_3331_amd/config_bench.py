@@ -8,7 +8,8 @@
   24^3x48 x48  48 right-hand sides in one batch: 12 spin-colour point sources
                at one odd site x 2 kappa mu in {0.002, 0.004, 0.008, 0.016},
                FP32 inner / FP64 outer, tol 1e-10 each; against the same 48
-               solved one after another
+               solved one after another; the same batch with FP16 inner spinors
+               and links
 
   doublet      the mass non-degenerate doublet of eq. (Dh) at 32^3x64 with the
                paper's doublet run parameters (kappa 0.17, 2 kappa mubar 0.1105,
@@ -158,6 +159,10 @@ def batch_24c48(tmq, torch, synth, reps):
         return inf
 
     t_alone, infos_alone = median_time(alone, 1)
+    # the same batch with FP16 spinors and links in the inner iteration
+    o16 = tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")
+    lat.solve_batch(ps, bs, o16, xs=xs)  # tunes the FP16 batched launches
+    t16, (_, inf16) = median_time(lambda: lat.solve_batch(ps, bs, o16, xs=xs), reps)
     report = lat.tuning_report()
     lat.close()
     return {"lattice": "24^3x48", "nrhs": len(bs), "point_site": site,
@@ -167,6 +172,9 @@ def batch_24c48(tmq, torch, synth, reps):
             "max_true_rel_residual": max(f.true_rel_residual for f in infos),
             "batch_hop_GBps_links_once": st["bytes"] / (st["ms"] * 1e-3) / 1e9,
             "batch_hop_launch_us": st["ms"] / st["launches"] * 1e3,
+            "fp16_inner_batch_ms": t16 * 1e3, "fp16_inner_iters": [f.iters for f in inf16],
+            "fp16_inner_all_converged": all(f.status == 0 for f in inf16),
+            "fp16_inner_max_true_rel_residual": max(f.true_rel_residual for f in inf16),
             "batch_tuning": report.get("batch")}
 
 
