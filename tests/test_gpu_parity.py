@@ -121,6 +121,34 @@ def test_qhatqhat_fp64(tmq):
     assert rel(got, oracle.QhatQhat(U, psi, 0.1632, 0.004, THETA)) < 1e-13
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_qhat_random_parameters(tmq, seed):
+    """Property test over the parameter space: random kappa, twisted mass of
+    either sign, boundary angles in every direction, sign of the operator and
+    lattice shape (ragged block tails included); Qhat and Qhat^+Qhat^- against
+    the oracle in FP64, and within the storage-precision bounds in FP32/FP16."""
+    rng = np.random.default_rng(7000 + seed)
+    shapes = [(4, 4, 4, 4), (6, 4, 2, 10), (8, 8, 6, 10), (2, 6, 4, 8), (10, 4, 6, 6), (12, 8, 6, 10)]
+    dims = shapes[seed % len(shapes)]
+    kappa = float(rng.uniform(0.05, 0.2))
+    mut = float(rng.uniform(-0.5, 0.5))
+    theta = rng.uniform(-1.0, 1.0, 4)
+    sign = int(rng.choice([-1, 1]))
+    lat, U = lattice(tmq, dims, seed=110 + seed)
+    psi = synth.gaussian_odd(dims, seed=7100 + seed)
+    p = tmq.params(kappa, mut, theta)
+    ref = oracle.Qhat(U, psi, kappa, mut, sign, theta)
+    errs = {}
+    for prec, bound in (("fp64", 1e-13), ("fp32", 2e-6), ("fp16", 3e-3)):
+        errs[prec] = rel(host(lat.apply_Qhat(p, sign, dev(psi), prec=prec)), ref)
+        assert errs[prec] < bound, (dims, kappa, mut, theta, sign, prec, errs[prec])
+    got = host(lat.apply_QhatQhat(p, dev(psi)))
+    e2 = rel(got, oracle.QhatQhat(U, psi, kappa, mut, theta))
+    print(f"{dims} kappa {kappa:.3f} mut {mut:+.3f} theta {np.round(theta, 2)} sign {sign:+d}: "
+          + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()) + f", QhatQhat fp64 {e2:.1e}")
+    assert e2 < 1e-13
+
+
 @pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("fp16", 3e-3), ("bf16", 2.5e-2)])
 def test_qhat_reduced_precision_error(tmq, prec, bound):
     dims = (8, 8, 8, 8)
