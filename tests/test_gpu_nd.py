@@ -70,6 +70,29 @@ def test_qhat_nd_fp64(tmq, dims, sign):
     assert rel(got, want) < 1e-13
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_qhat_nd_random_parameters(tmq, seed):
+    """Property test of the doublet operator: random kappa, mubar, epsbar (with
+    1 + mubar^2 - epsbar^2 > 0, so that A_ee is invertible), boundary angles,
+    operator sign and lattice shape, against the oracle in FP64 and FP16."""
+    rng = np.random.default_rng(7400 + seed)
+    dims = [(4, 4, 4, 4), (6, 4, 2, 10), (8, 8, 6, 10), (2, 6, 4, 8)][seed]
+    kappa = float(rng.uniform(0.05, 0.2))
+    mubar = float(rng.uniform(-0.4, 0.4))
+    epsbar = float(rng.uniform(-0.4, 0.4))
+    assert 1.0 + mubar * mubar - epsbar * epsbar > 0.5
+    theta = rng.uniform(-1.0, 1.0, 4)
+    sign = int(rng.choice([-1, 1]))
+    lat, U = lattice(tmq, dims, 310 + seed)
+    psi = doublet(dims, 7500 + seed)
+    p = tmq.nd_params(kappa, mubar, epsbar, theta)
+    want = oracle.Qhat_nd(U, psi, kappa, mubar, epsbar, sign, theta)
+    e64 = rel(host(lat.apply_Qhat_nd(p, sign, dev(psi))), want)
+    e16 = rel(host(lat.apply_Qhat_nd(p, sign, dev(psi), prec="fp16")), want)
+    print(f"{dims} kappa {kappa:.3f} mubar {mubar:+.3f} epsbar {epsbar:+.3f} sign {sign:+d}: fp64 {e64:.1e} fp16 {e16:.1e}")
+    assert e64 < 1e-13 and e16 < 3e-3
+
+
 @pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("fp16", 3e-3), ("bf16", 2.5e-2)])
 def test_qhat_nd_reduced_precision_error(tmq, prec, bound):
     dims = (8, 8, 6, 10)

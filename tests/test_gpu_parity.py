@@ -149,6 +149,30 @@ def test_qhat_random_parameters(tmq, seed):
     assert e2 < 1e-13
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_solve_random_parameters(tmq, seed):
+    """Property test of the solver: random kappa, twisted mass, boundary angles
+    and inner precision; the solution meets 1e-10 by the oracle's true residual
+    and FP64 CG takes the oracle's iteration count to within 2."""
+    rng = np.random.default_rng(7200 + seed)
+    dims = [(4, 4, 4, 4), (6, 4, 2, 10), (2, 6, 4, 8), (8, 4, 4, 6)][seed]
+    kappa = float(rng.uniform(0.05, 0.18))
+    mut = float(rng.uniform(0.002, 0.3))
+    theta = rng.uniform(-1.0, 1.0, 4)
+    sloppy = ["fp64", "fp32", "fp16", "bf16"][seed]
+    lat, U = lattice(tmq, dims, seed=120 + seed)
+    b = synth.gaussian_odd(dims, seed=7300 + seed)
+    p = tmq.params(kappa, mut, theta)
+    link = "fp16" if sloppy in ("fp16", "bf16") else "fp32"
+    x, info = lat.solve(p, dev(b), tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link=link))
+    res = oracle.true_residual(U, b, host(x), kappa, mut, theta)
+    _, io = oracle.cg(U, b, kappa, mut, theta, tol=1e-10)
+    print(f"{dims} kappa {kappa:.3f} mut {mut:.3f} {sloppy}: iters {info.iters} (oracle {io['iters']}) true res {res:.2e}")
+    assert info.status == 0 and res <= 1e-10
+    if sloppy == "fp64":
+        assert abs(info.iters - io["iters"]) <= 2
+
+
 @pytest.mark.parametrize("prec,bound", [("fp32", 2e-6), ("fp16", 3e-3), ("bf16", 2.5e-2)])
 def test_qhat_reduced_precision_error(tmq, prec, bound):
     dims = (8, 8, 8, 8)
