@@ -436,6 +436,30 @@ def test_batch_equals_alone(tmq, sloppy):
         assert infos[i].status == 0 and res <= 1e-10, (i, res)
 
 
+@pytest.mark.parametrize("sloppy", ["fp32", "fp16"])
+def test_batch_random_parameters(tmq, sloppy):
+    """A batch whose right-hand sides each have their own random kappa and
+    twisted mass (one random set of boundary angles for the batch): each meets
+    1e-10 by the oracle's true residual and equals its solve alone bit for bit."""
+    rng = np.random.default_rng(7600 + (sloppy == "fp16"))
+    dims = (6, 4, 2, 10)
+    lat, U = lattice(tmq, dims, seed=130)
+    theta = rng.uniform(-1.0, 1.0, 4)
+    ps, bs = [], []
+    for k in range(10):
+        ps.append(tmq.params(float(rng.uniform(0.05, 0.18)), float(rng.uniform(0.002, 0.3)), theta))
+        bs.append(synth.gaussian_odd(dims, seed=7700 + k))
+    opts = tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp16" if sloppy == "fp16" else "fp32")
+    xs, infos = lat.solve_batch(ps, [dev(b) for b in bs], opts)
+    for i in range(len(bs)):
+        res = oracle.true_residual(U, bs[i], host(xs[i]), ps[i].kappa, ps[i].mu_tilde, theta)
+        assert infos[i].status == 0 and res <= 1e-10, (i, res)
+    for i in (0, 4, 9):
+        x1, i1 = lat.solve(ps[i], dev(bs[i]), opts)
+        assert torch.equal(x1, xs[i]), f"rhs {i} differs from its solve alone"
+        assert i1.iters == infos[i].iters
+
+
 @pytest.mark.parametrize("rpl", [1, 2])
 @pytest.mark.parametrize("sloppy", ["fp32", "fp16", "bf16"])
 def test_batch_rhs_per_lane(tmq, sloppy, rpl, monkeypatch):
