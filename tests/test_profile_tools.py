@@ -1,0 +1,99 @@
+"""Host logic of the profile summaries (no GPU): the counter scaling behind
+`roofline.traffic`, the VALU summary, and the kernel-hash gate in bench.py."""
+import csv
+import json
+import os
+
+import pytest
+
+from paper_0905_3331_amd import profile_hop
+
+FIELDS = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+K1 = "void tmq::hop_kernel<tmq::Sp16<false>, tmq::L16R, false, false, true, 1, false, 1, 0, false>(args)"
+CAND = "void tmq::hop_kernel<tmq::Sp16<false>, tmq::L16R, false, false, true, 3, false, 1, 0, false>(args)"
+F64 = "void tmq::hop_kernel<tmq::SpF64, tmq::L64R, false, false, true, 1, false, 1, 0, false>(args)"
+COPY = "k_stream_copy(float4 const*, float4*, long)"
+
+
+def _write(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (k, c, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+
+
+def test_summarize_pmc_scales_by_the_copy_kernel(tmp_path):
+    copy_bytes = 1 << 30
+    # the copy reads and writes copy_bytes; FETCH_SIZE sees half of its reads (scale 2), WRITE_SIZE all
+    fetch = [(COPY, "FETCH_SIZE", copy_bytes / 2 / 1024)] * 2
+    write = [(COPY, "WRITE_SIZE", copy_bytes / 1024)] * 2
+    fetch += [(K1, "FETCH_SIZE", 100000.0)] * 32 + [(K1, "FETCH_SIZE", 120000.0)] * 8
+    write += [(K1, "WRITE_SIZE", 50000.0)] * 40
+    # an autotuner candidate (fewer than a tenth of the family's most-launched
+    # kernel's dispatches) stays out of the family average
+    fetch += [(CAND, "FETCH_SIZE", 9e9)]
+    write += [(CAND, "WRITE_SIZE", 9e9)]
+    fetch += [(F64, "FETCH_SIZE", 700000.0)] * 4
+    write += [(F64, "WRITE_SIZE", 200000.0)] * 4
+    _write(tmp_path / "f.csv", fetch)
+    _write(tmp_path / "w.csv", write)
+    out = tmp_path / "t.json"
+    profile_hop.summarize_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), copy_bytes, "cmd", str(out))
+    d = json.load(open(out))
+    assert d["kernel_hash"] == profile_hop.kernel_hash()
+    assert d["fetch_scale"] == pytest.approx(2.0) and d["write_scale"] == pytest.approx(1.0)
+    h16 = d["hop16"]
+    assert h16["dispatches"] == [40, 40]
+    assert h16["read_bytes_per_launch"] == pytest.approx((32 * 100000.0 + 8 * 120000.0) / 40 * 1024 * 2)
+    assert h16["write_bytes_per_launch"] == pytest.approx(50000.0 * 1024)
+    assert h16["hbm_bytes_per_launch"] == pytest.approx(h16["read_bytes_per_launch"] + h16["write_bytes_per_launch"])
+    assert d["hop64"]["read_bytes_per_launch"] == pytest.approx(700000.0 * 1024 * 2)
+    assert d["per_kernel"][CAND]["dispatches"] == 1  # listed, but not averaged
+
+
+def test_summarize_pmc_needs_the_copy_kernel(tmp_path):
+    _write(tmp_path / "f.csv", [(K1, "FETCH_SIZE", 1.0)])
+    _write(tmp_path / "w.csv", [(K1, "WRITE_SIZE", 1.0)])
+    with pytest.raises(SystemExit):
+        profile_hop.summarize_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 1 << 30, "cmd",
+                                  str(tmp_path / "t.json"))
+
+
+def test_summarize_valu_per_wave_and_busy(tmp_path):
+    waves, per_wave, busy, grbm_xcd = 16384.0, 1632.0, 0.68, 150000.0
+    rows = []
+    for _ in range(30):
+        rows += [(K1, "SQ_WAVES", waves), (K1, "SQ_INSTS_VALU", waves * per_wave),
+                 (K1, "SQ_ACTIVE_INST_VALU", busy * 1024 * grbm_xcd / 4), (K1, "GRBM_GUI_ACTIVE", 8 * grbm_xcd),
+                 (K1, "SQ_WAVE_CYCLES", 1.0)]
+    rows += [(CAND, "SQ_WAVES", 1.0), (CAND, "SQ_INSTS_VALU", 1.0), (CAND, "SQ_ACTIVE_INST_VALU", 1.0),
+             (CAND, "GRBM_GUI_ACTIVE", 1.0)]
+    # one dispatch per group of counter rows
+    with open(tmp_path / "v.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (k, c, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i // 5 if k == K1 else 10000, "Kernel_Name": k, "Counter_Name": c,
+                        "Counter_Value": v})
+    out = tmp_path / "v.md"
+    profile_hop.summarize_valu(str(tmp_path / "v.csv"), "cmd", str(out))
+    text = open(out).read()
+    line = [l for l in text.splitlines() if "Sp16<false>, L16R, false, false, true, 1" in l][0]
+    cells = [c.strip() for c in line.strip("|").split("|")]
+    assert cells[1:] == ["30", "16384", "1632", "68 %"]
+    assert "true, 3," not in text  # the one-dispatch candidate is left out
+
+
+def test_bench_takes_traffic_only_for_the_current_kernels(tmp_path, monkeypatch):
+    import bench
+
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    path = tmp_path / "profiles" / "hop_traffic.json"
+    path.write_text(json.dumps({"kernel_hash": profile_hop.kernel_hash(), "hop16": {"hbm_bytes_per_launch": 4.2e8}}))
+    assert bench.measured_traffic("hop16", "hbm_bytes_per_launch") == 4.2e8
+    path.write_text(json.dumps({"kernel_hash": "0" * 16, "hop16": {"hbm_bytes_per_launch": 4.2e8}}))
+    assert bench.measured_traffic("hop16", "hbm_bytes_per_launch") is None
+    os.remove(path)
+    assert bench.measured_traffic("hop16", "hbm_bytes_per_launch") is None
