@@ -97,3 +97,19 @@ def test_bench_takes_traffic_only_for_the_current_kernels(tmp_path, monkeypatch)
     assert bench.measured_traffic("hop16", "hbm_bytes_per_launch") is None
     os.remove(path)
     assert bench.measured_traffic("hop16", "hbm_bytes_per_launch") is None
+
+
+def test_summarize_trace_family_averages(tmp_path):
+    rows = [(K1, 100, 6.1e6), (CAND, 4, 0.3e6), (F64, 50, 11.0e6), (COPY, 2, 0.7e6)]
+    with open(tmp_path / "s.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "TotalDurationNs"])
+        w.writeheader()
+        for n, c, t in rows:
+            w.writerow({"Name": n, "Calls": c, "TotalDurationNs": t})
+    out = tmp_path / "s.md"
+    profile_hop.summarize_trace(str(tmp_path / "s.csv"), "cmd", str(out))
+    fam = {l.split("|")[1].strip(): l for l in open(out).read().splitlines() if l.startswith("| hop")}
+    # the family average counts every instantiation: (6.1 + 0.3) ms over 104 launches
+    assert fam["hop16"].split("|")[2].strip() == "104"
+    assert float(fam["hop16"].split("|")[3]) == pytest.approx(6.4e6 / 104 / 1e3, abs=0.01)
+    assert float(fam["hop64"].split("|")[3]) == pytest.approx(220.0, abs=0.01)
