@@ -561,6 +561,51 @@ def test_solve_M_oracle_residual(tmq, sign, sloppy, mode):
 
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_solve_M_random_parameters(tmq, seed):
+    """Full-lattice M^{+-} psi = phi at random kappa, twisted mass, boundary
+    angles and sign, in the three solver modes: the oracle's full-lattice
+    residual meets 1e-10."""
+    rng = np.random.default_rng(7800 + seed)
+    dims = [(4, 4, 4, 4), (6, 4, 2, 10), (2, 6, 4, 8)][seed]
+    sloppy, mode = [("fp64", "reliable"), ("fp16", "reliable"), ("fp64", "bicgstab")][seed]
+    kappa = float(rng.uniform(0.05, 0.18))
+    mut = float(rng.uniform(0.002, 0.3))
+    theta = rng.uniform(-1.0, 1.0, 4)
+    sign = int(rng.choice([-1, 1]))
+    lat, U = lattice(tmq, dims, seed=140 + seed)
+    phi = synth.gaussian_spinor(dims + (4, 3), seed=7900 + seed)
+    p = tmq.params(kappa, mut, theta)
+    psi, info = lat.solve_M(p, sign, dev(phi.reshape(-1, 4, 3)),
+                            tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link="fp16", mode=mode))
+    r = phi - oracle.M(U, host(psi).reshape(phi.shape), kappa, mut, sign, theta)
+    res = float(np.linalg.norm(r) / np.linalg.norm(phi))
+    print(f"{dims} kappa {kappa:.3f} mut {mut:.3f} sign {sign:+d} {sloppy}/{mode}: iters {info.iters} res {res:.2e}")
+    assert info.status == 0 and res <= 1e-10
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_bicgstab_random_parameters(tmq, seed):
+    """Qhat^{+-} x = b by BiCGstab at random kappa, twisted mass of either
+    sign, boundary angles and operator sign: the oracle's Qhat of the solution
+    reproduces b to 1e-10 and the solution agrees with the oracle's BiCGstab."""
+    rng = np.random.default_rng(8000 + seed)
+    dims = [(4, 4, 4, 4), (6, 4, 2, 10), (8, 4, 4, 6)][seed]
+    kappa = float(rng.uniform(0.05, 0.18))
+    mut = float(rng.uniform(-0.3, 0.3))
+    theta = rng.uniform(-1.0, 1.0, 4)
+    sign = int(rng.choice([-1, 1]))
+    lat, U = lattice(tmq, dims, seed=150 + seed)
+    b = synth.gaussian_odd(dims, seed=8100 + seed)
+    p = tmq.params(kappa, mut, theta)
+    x, info = lat.solve_Qhat(p, sign, dev(b), tmq.solver_opts(tol=1e-10))
+    res = rel(oracle.Qhat(U, host(x), kappa, mut, sign, theta), b)
+    xo, io = oracle.bicgstab(U, b, kappa, mut, sign, theta, tol=1e-10)
+    print(f"{dims} kappa {kappa:.3f} mut {mut:+.3f} sign {sign:+d}: iters {info.iters} (oracle {io['iters']}) res {res:.2e}")
+    assert info.status == 0 and res <= 1e-10
+    assert rel(host(x), xo) < 1e-7
+
+
 @pytest.mark.parametrize("dims", [(2, 2, 2, 2), (6, 4, 2, 10)], ids=lambda d: "x".join(map(str, d)))
 def test_split_merge_eo(tmq, dims):
     """Split of a full field into its parities and the merge back are exact
