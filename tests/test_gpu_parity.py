@@ -344,6 +344,28 @@ def test_cg_full_lattice_one_workgroup(tmq, dims, monkeypatch):
     assert i_n.status == tmq.TMQ_ENAN
 
 
+def test_qhat_degenerate_parameters(tmq):
+    """Degenerate cases of the operator: kappa = 0 leaves the site term
+    gamma_5 (1 +- i mut gamma_5) psi (closed form); mut = 0 makes Qhat^+ and
+    Qhat^- the same operator; theta = 0 is the fully periodic lattice."""
+    dims = (6, 4, 2, 10)
+    lat, U = lattice(tmq, dims, seed=101)
+    psi = synth.gaussian_odd(dims, seed=31)
+    g5 = np.array([1.0, 1.0, -1.0, -1.0])[None, :, None]
+    for sign in (+1, -1):
+        got = host(lat.apply_Qhat(tmq.params(0.0, 0.3, THETA_GEN), sign, dev(psi)))
+        # gamma_5 (1 + sign i mut gamma_5) psi = gamma_5 psi + sign i mut psi
+        assert rel(got, g5 * psi + sign * 0.3j * psi) < 1e-15, sign
+    p0 = tmq.params(0.1632, 0.0, THETA_GEN)
+    qp = host(lat.apply_Qhat(p0, +1, dev(psi)))
+    qm = host(lat.apply_Qhat(p0, -1, dev(psi)))
+    assert np.array_equal(qp, qm)
+    assert rel(qp, oracle.Qhat(U, psi, 0.1632, 0.0, +1, THETA_GEN)) < 1e-13
+    zero = np.zeros(4)
+    got = host(lat.apply_Qhat(tmq.params(0.1632, 0.004, zero), +1, dev(psi)))
+    assert rel(got, oracle.Qhat(U, psi, 0.1632, 0.004, +1, zero)) < 1e-13
+
+
 def test_cg_edge_cases(tmq):
     dims = (4, 4, 4, 4)
     lat, U = lattice(tmq, dims, seed=106)
