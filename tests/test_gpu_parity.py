@@ -522,6 +522,27 @@ def test_batch_host_api_and_validation(tmq):
                         tmq.solver_opts())
 
 
+def test_batch_maximum_size(tmq):
+    """The largest batch (64 right-hand sides, 8 twisted masses): every RHS
+    meets 1e-10 by the oracle, samples equal their solves alone bit for bit,
+    and one more RHS is refused."""
+    dims = (4, 4, 4, 4)
+    lat, U = lattice(tmq, dims, seed=106)
+    n = tmq.MAX_RHS
+    bs = [synth.gaussian_odd(dims, seed=8200 + i) for i in range(n)]
+    ps = [tmq.params(0.1632, 0.002 * (1 + i % 8), THETA) for i in range(n)]
+    opts = tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")
+    xs, infos = lat.solve_batch(ps, [dev(b) for b in bs], opts)
+    for i in range(n):
+        res = oracle.true_residual(U, bs[i], host(xs[i]), 0.1632, ps[i].mu_tilde, THETA)
+        assert infos[i].status == 0 and res <= 1e-10, (i, res)
+    for i in (0, 31, n - 1):
+        x1, _ = lat.solve(ps[i], dev(bs[i]), opts)
+        assert torch.equal(x1, xs[i]), i
+    with pytest.raises(ValueError):
+        lat.solve_batch(ps + ps[:1], [dev(b) for b in bs + bs[:1]], opts)
+
+
 @pytest.mark.parametrize("sloppy", ["fp16", "bf16"])
 def test_point_source_16bit_far_decay(tmq, sloppy):
     """Point source on 24^3x48: far from the source the Krylov vectors decay
