@@ -163,6 +163,28 @@ def test_cg_nd_matches_oracle_solution(tmq):
     assert abs(info.iters - io["iters"]) <= 2
 
 
+def test_nd_batch_maximum_size(tmq):
+    """The largest doublet batch (32 doublets, i.e. 64 flavour fields): every
+    doublet meets 1e-10 by the oracle, samples equal their solves alone bit for
+    bit, and one more doublet is refused."""
+    dims = (4, 4, 4, 4)
+    lat, U = lattice(tmq, dims, 301)
+    n = tmq.MAX_RHS // 2
+    o = tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")
+    ps = [tmq.nd_params(KAPPA, 0.05 + 0.01 * (k % 8), 0.02 + 0.005 * (k % 4), THETA) for k in range(n)]
+    bs = [dev(doublet(dims, 8300 + 2 * k)) for k in range(n)]
+    xs, infos = lat.solve_nd_batch(ps, bs, o)
+    for k in range(n):
+        pk = ps[k]
+        res = oracle.true_residual_nd(U, host(bs[k]), host(xs[k]), KAPPA, pk.mubar_tilde, pk.epsbar_tilde, THETA)
+        assert infos[k].status == 0 and res <= 1e-10, (k, res)
+    for k in (0, n - 1):
+        x1, _ = lat.solve_nd(ps[k], bs[k], o)
+        assert torch.equal(x1, xs[k]), k
+    with pytest.raises(ValueError):
+        lat.solve_nd_batch(ps + ps[:1], bs + bs[:1], o)
+
+
 @pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16"])
 def test_nd_batch_equals_alone(tmq, sloppy):
     dims = (8, 8, 6, 10)
