@@ -586,3 +586,145 @@ def test_heatbath_and_force_solves():
     assert info["converged"]
     assert rel(Y, r) < 1e-9
     assert abs(np.vdot(phi, X).real - np.vdot(r, r).real) < 1e-9 * np.vdot(r, r).real
+
+
+# ---------------------------------------------- the acceptance checker
+# Every solve is accepted on the FP64 true residual |b - A x| / |b| (Sec. 4.4,
+# last paragraph).  These pins fix its value against dense matrices assembled
+# from eq. (eo0) by brute force, at residuals far from the converged regime
+# (so a missing square root, a squared or doubly normalised result, or the
+# wrong operator order would show), not only on converged solutions.
+
+
+def _dense_normal(U, kappa, mut, theta, eo):
+    dims = U.shape[:4]
+    Mp = dense.M_hopping(U, kappa, mut, +1, theta)
+    Mm = dense.M_hopping(U, kappa, mut, -1, theta)
+    if eo:
+        return dense.schur_Qhat(Mp, dims) @ dense.schur_Qhat(Mm, dims)  # Qhat^- first
+    V = int(np.prod(dims))
+    g5 = np.kron(np.eye(V), np.kron(dense.G5, dense.I3))
+    return (g5 @ Mp) @ (g5 @ Mm)  # Q^+ Q^- = g5 M^+ g5 M^-
+
+
+@pytest.mark.parametrize("eo", [True, False], ids=["eo", "full"])
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 2, 2, 2)], ids=lambda d: "x".join(map(str, d)))
+def test_true_residual_matches_dense(dims, eo):
+    U = synth.random_gauge(dims, eps=0.5, seed=131)
+    kappa, mut = 0.1632, 0.004
+    A = _dense_normal(U, kappa, mut, THETA_GEN, eo)
+    n_sites = int(np.prod(dims)) // (2 if eo else 1)
+    shape = (n_sites, 4, 3)
+    b = synth.gaussian_spinor(shape, seed=132)
+    # x = 0: the residual is b itself, exactly 1
+    assert oracle.true_residual(U, b, np.zeros_like(b), kappa, mut, THETA_GEN, eo=eo) == 1.0
+    xs = np.linalg.solve(A, b.ravel())
+    rng = np.random.default_rng(133)
+    for scale in (0.0, 1e-9, 1e-3, 0.3):
+        # x* plus a perturbation: residuals from rounding level up to O(1)
+        d = rng.normal(size=xs.shape) + 1j * rng.normal(size=xs.shape)
+        x = xs + scale * np.linalg.norm(xs) / np.linalg.norm(d) * d
+        want = np.linalg.norm(b.ravel() - A @ x) / np.linalg.norm(b.ravel())
+        got = oracle.true_residual(U, b, x.reshape(shape), kappa, mut, THETA_GEN, eo=eo)
+        if scale == 0.0:
+            assert got < 1e-13  # the exact solution, up to rounding
+        else:
+            # rounding of A x in either computation is ~1e-16 |b| in absolute terms
+            assert abs(got - want) <= 1e-12 * want + 1e-14, (scale, got, want)
+    # with |b| = 1 the value is the plain |b - A x|
+    bn = b / np.linalg.norm(b.ravel())
+    x = rng.normal(size=xs.shape) * 1e-2
+    want = np.linalg.norm(bn.ravel() - A @ x)
+    got = oracle.true_residual(U, bn, x.reshape(shape), kappa, mut, THETA_GEN, eo=eo)
+    assert abs(got - want) <= 1e-12 * want
+
+
+def test_true_residual_nd_matches_dense():
+    """The doublet's checker against the dense doublet Schur complement (eq. (Dh),
+    App. B), Qhat_h^- applied first, at residuals from 1e-9 to O(1)."""
+    dims = (2, 2, 2, 2)
+    V = int(np.prod(dims))
+    U = synth.random_gauge(dims, eps=0.5, seed=134)
+    args = (ND_KAPPA, ND_MUBAR, ND_EPSBAR)
+    e, o = dense.eo_blocks(dims)
+    e2 = np.concatenate([e, 12 * V + e])
+    o2 = np.concatenate([o, 12 * V + o])
+    g5 = np.kron(np.eye(V), np.kron(dense.G5, dense.I3))
+
+    def schur(sign):
+        M = _dense_Mh(U, ND_KAPPA, sign * ND_MUBAR, ND_EPSBAR, THETA_GEN)
+        S = M[np.ix_(o2, o2)] - M[np.ix_(o2, e2)] @ np.linalg.solve(M[np.ix_(e2, e2)], M[np.ix_(e2, o2)])
+        return g5 @ S
+
+    A = schur(+1) @ schur(-1)
+    b = np.stack([synth.gaussian_odd(dims, seed=135), synth.gaussian_odd(dims, seed=136)])
+    assert oracle.true_residual_nd(U, b, np.zeros_like(b), *args, THETA_GEN) == 1.0
+    xs = np.linalg.solve(A, b.ravel())
+    rng = np.random.default_rng(137)
+    for scale in (1e-9, 1e-3, 0.3):
+        d = rng.normal(size=xs.shape) + 1j * rng.normal(size=xs.shape)
+        x = xs + scale * np.linalg.norm(xs) / np.linalg.norm(d) * d
+        want = np.linalg.norm(b.ravel() - A @ x) / np.linalg.norm(b.ravel())
+        got = oracle.true_residual_nd(U, b, x.reshape(b.shape), *args, THETA_GEN)
+        assert abs(got - want) <= 1e-12 * want + 1e-14, (scale, got, want)
+
+
+# ------------------------------------------------- C_PGamma of the one-end trick
+
+
+def _cpg_gammas():
+    g = dense.G
+    g5 = dense.G5
+    rng = np.random.default_rng(141)
+    rand = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    # <PP>, <PA> and <PV> with mu = t (A = g5 g0, V = g0), and a generic matrix
+    return {"P": g5, "A0": g5 @ g[0], "V0": g[0], "V2": g[2], "random": rand}
+
+
+@pytest.mark.parametrize("name", list(_cpg_gammas()))
+def test_bilinear_gives_the_papers_C_PGamma(name):
+    """The one-end trick of eqs. (source)/(oneend): for phi = (M^+)^-1 xi with the
+    noise on time slice t0, the time-slice bilinear sum_x phi^+ (g5 Gamma) phi,
+    summed over the 12 unit sources of a site y (the complete spin-colour
+    basis, for which the noise average of eq. (source) is exact), equals
+    C_PGamma = sum_x tr[G_u(x, y) g5 G_d(y, x) Gamma] built from the two dense
+    propagators G_u = (M^+)^-1 and G_d = (M^-)^-1.  So Gamma sits at the point
+    where the bilinear is formed (the paper's "source" 0), the noise at the
+    other end, and g5 Gamma is the matrix the bilinear takes; Gamma = g5 gives
+    the pion correlator.  The gamma_5-hermiticity step G_u(x,y) = g5 G_d(y,x)^+ g5
+    that the paper uses is checked on the way."""
+    gam = _cpg_gammas()[name]
+    dims = (4, 2, 2, 2)
+    T = dims[0]
+    U = synth.random_gauge(dims, seed=142)
+    kappa, mut = 0.16, 0.05
+    V = int(np.prod(dims))
+    Gu = np.linalg.inv(dense.M_hopping(U, kappa, mut, +1, THETA_AP))
+    Gd = np.linalg.inv(dense.M_hopping(U, kappa, mut, -1, THETA_AP))
+    g5f = np.kron(np.eye(V), np.kron(dense.G5, dense.I3))
+    assert rel(Gu, g5f @ Gd.conj().T @ g5f) < 1e-13
+    Gu4 = Gu.reshape(V, 4, 3, V, 4, 3)
+    Gd4 = Gd.reshape(V, 4, 3, V, 4, 3)
+    per_slice = V // T
+    for t0 in (0, 1):
+        y = t0 * per_slice + 3  # a site of time slice t0
+        want = np.zeros(T, dtype=np.complex128)
+        for x in range(V):
+            # tr over spin and colour of G_u(x, y) g5 G_d(y, x) Gamma
+            c = np.einsum("aibj,bc,cjdi,da->", Gu4[x, :, :, y], dense.G5, Gd4[y, :, :, x], gam, optimize=True)
+            want[(x // per_slice - t0) % T] += c
+        got = np.zeros(T, dtype=np.complex128)
+        for k in range(12):
+            xi = np.zeros((V, 12), dtype=np.complex128)
+            xi[y, k] = 1.0
+            phi = (Gu @ xi.ravel()).reshape(dims + (4, 3))
+            got += oracle.timeslice_bilinear(phi, dense.G5 @ gam, t0)
+        assert rel(got, want) < 1e-12, (t0, got, want)
+        # the same through the oracle's own solve (pion_correlator's path for Gamma = g5)
+        if name == "P":
+            tot = np.zeros(T)
+            for k in range(12):
+                xi = np.zeros((V, 12), dtype=np.complex128)
+                xi[y, k] = 1.0
+                tot += oracle.pion_correlator(U, xi.reshape(dims + (4, 3)), kappa, mut, THETA_AP, t0=t0)[0]
+            assert rel(tot, want.real) < 1e-10 and np.abs(want.imag).max() < 1e-12 * np.abs(want).max()
