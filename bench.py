@@ -6,10 +6,14 @@ A step is one solve of Qhat^+ Qhat^- x = b to a true relative residual of
 FP16 two-row links, FP32 arithmetic, FP64 reliable updates), with the gauge
 field and the source already resident in HBM.  The hopping half-sweeps inside
 the timed steps are timed with HIP events on their launch stream; the
-reported value is their algorithmic bandwidth (each input spinor, link and
-output counted once).  The same solve in plain FP64 CG is timed beside it for
-the mixed-vs-FP64 time-to-solution, and the FP64 oracle is timed on the host
-cores on a bounded sample of the same operator.
+reported value is the algorithmic bandwidth (each input spinor, link and
+output counted once) of the plain half-sweeps of the inner operator, K1 and K2
+of eqs. (eo3)/(eo4) in 16-bit storage; the half-sweeps that carry the fused
+CG update and the FP64 half-sweeps of the reliable updates are reported
+beside it.  The same solve in plain FP64 CG is timed beside it for the
+mixed-vs-FP64 time-to-solution, and the FP64 oracle is timed on the host
+cores on a bounded sample of the same operator and on the whole CG of the
+24^3 x 48 workload.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -42,6 +46,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "logical_cpus": os.cpu_count(),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
 def measured_traffic(family, key):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
@@ -58,10 +81,11 @@ def measured_traffic(family, key):
     return d.get(family, {}).get(key)
 
 
-def cpu_baseline(U, b, w, budget_s):
+def cpu_baseline(U, b, w, budget_s, full):
     import numpy as np
 
     import oracle
+    import synth
 
     vh = b.shape[0]
     bytes_qq = 2 * (1536 + 1728) * vh  # same algorithmic model, full 3x3 links (what the oracle reads)
@@ -74,10 +98,26 @@ def cpu_baseline(U, b, w, budget_s):
         if el >= budget_s or n >= 50:
             break
         log(f"cpu oracle Qhat^+Qhat^- #{n}: {el:.1f}s")
+    # the oracle's whole CG to 1e-10 on the 24^3x48 workload (kappa 0.1632,
+    # 2 kappa mu 0.004, links eps 0.3 seed 1001, Gaussian source seed 2100)
+    d1 = (48, 24, 24, 24)
+    log("cpu oracle: CG to 1e-10 on 24^3x48 (inputs generated first, not timed)")
+    U1 = synth.random_gauge(d1, eps=0.3, seed=1001)
+    b1 = synth.gaussian_odd(d1, seed=2100)
+    t1 = time.perf_counter()
+    x1, i1 = oracle.cg(U1, b1, w["kappa"], w["mu_tilde"], w["theta"], tol=1e-10)
+    cg1 = time.perf_counter() - t1
+    del U1, b1, x1
+    log(f"cpu oracle CG 24^3x48: {cg1:.1f} s, {i1['iters']} iterations")
+    cgfull = None
+    if full:
+        log("cpu oracle: CG to 1e-10 on the 32^3x64 workload")
+        t2 = time.perf_counter()
+        _, i2 = oracle.cg(U, b, w["kappa"], w["mu_tilde"], w["theta"], tol=1e-10)
+        cgfull = {"s": round(time.perf_counter() - t2, 2), "iters": i2["iters"]}
+        log(f"cpu oracle CG 32^3x64: {cgfull}")
     # the oracle's own CG to 1e-10 on the small full-lattice workload (4^4, kappa 0.16,
     # 2 kappa mu 0.01), timed whole
-    import synth
-
     d4 = (4, 4, 4, 4)
     U4 = synth.random_gauge(d4, eps=0.3, seed=1000)
     b4 = synth.gaussian_spinor(d4 + (4, 3), seed=2000).reshape(-1, 4, 3)
@@ -92,8 +132,13 @@ def cpu_baseline(U, b, w, budget_s):
         "sample": f"{n} applications of the FP64 oracle's Qhat^+Qhat^- (4 hopping half-sweeps) on the "
                   f"32^3x64 workload, {el:.1f} s; bytes counted with the same algorithmic model",
         "seconds_per_QhatQhat": round(el / n, 3),
+        "cg_24c48_s_to_1e-10": round(cg1, 2),
+        "cg_24c48_iters": i1["iters"],
+        "cg_32c64_s_to_1e-10": cgfull["s"] if cgfull else None,
+        "cg_32c64_iters": cgfull["iters"] if cgfull else None,
         "cg_4444_full_ms_to_1e-10": round(cg4 * 1e3, 2),
         "cg_4444_full_iters": i4["iters"],
+        **host_cpu(),
     }
 
 
@@ -104,7 +149,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sloppy", default="fp16", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--link", default="fp16", choices=["fp32", "fp16"])
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=6.0, help="budget of the CPU oracle's operator sample")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the CPU oracle's whole CG on the 32^3x64 workload (about 35 s on 16 cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     args = ap.parse_args()
@@ -155,13 +202,23 @@ def main():
         infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stats = {f: lat.kernel_stats(f) for f in ("hop", "hop64", "hop16" if args.sloppy != "fp32" else "hop32")}
+    inner = "hop16" if args.sloppy != "fp32" else "hop32"
+    fams = ("hop", "hop64", inner, inner + ":pure", inner + ":k1", inner + ":k2", inner + ":fused")
+    stats = {f: lat.kernel_stats(f) for f in fams}
     lat.set_kernel_timing(False)
     ms_per_step = (t1 - t0) / args.steps * 1e3
+
+    def gbs(st):
+        return st["bytes"] / (st["ms"] * 1e-3) / 1e9 if st["ms"] > 0 else None
+
+    def avg_us(st):
+        return round(st["ms"] / st["launches"] * 1e3, 2) if st["launches"] else None
+
     hop = stats["hop"]
-    value = hop["bytes"] / (hop["ms"] * 1e-3) / 1e9
+    pure = stats[inner + ":pure"]
+    value = gbs(pure)
     log(f"mixed: {ms_per_step:.2f} ms/solve, {infos[-1].iters} iters, {infos[-1].reliable_updates} reliable updates, "
-        f"hop {value:.0f} GB/s")
+        f"inner half-sweeps {value:.0f} GB/s, all hop launches {gbs(hop):.0f} GB/s")
 
     # un-instrumented time to solution, mixed and FP64
     def timed_solves(opts, k):
@@ -191,9 +248,9 @@ def main():
     x_fp64 = xd.cpu().numpy()
     log(f"fp64: {fp64_ms:.2f} ms/solve, {fp64_info.iters} iters")
 
-    dom_name = "hop16" if args.sloppy != "fp32" else "hop32"
-    dom = stats[dom_name]
-    dom_gbs = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    dom_name = inner + ":pure"
+    dom = pure
+    dom_gbs = value
     per_launch_bytes = dom["bytes"] / max(dom["launches"], 1)
     traffic = measured_traffic(dom_name, "hbm_bytes_per_launch")
 
@@ -209,8 +266,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        log(f"cpu baseline: oracle on the host cores for ~{args.cpu_seconds:.0f} s")
-        cpu = cpu_baseline(U, b, w, args.cpu_seconds)
+        log(f"cpu baseline: oracle on the host cores for ~{args.cpu_seconds:.0f} s, then its 24^3x48 CG")
+        cpu = cpu_baseline(U, b, w, args.cpu_seconds, args.cpu_full)
 
     # ------------------------------------------ outside the timed region
     # gauge ingest (canonical FP64 links -> the resident copies, with the SU(3)
@@ -262,7 +319,17 @@ def main():
             "tol": w["tol"],
         },
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
-        "hop_gflops": round(hop["flops"] / (hop["ms"] * 1e-3) / 1e9, 1),
+        "value_kernels": f"the plain {args.sloppy} half-sweeps K1 and K2 (no fused epilogue) of the timed solves",
+        "hop_gflops": round(pure["flops"] / (pure["ms"] * 1e-3) / 1e9, 1),
+        "inner_hop": {part: {"GBps": round(gbs(stats[f"{inner}:{part}"]) or 0.0, 1),
+                             "avg_us": avg_us(stats[f"{inner}:{part}"]),
+                             "launches": stats[f"{inner}:{part}"]["launches"],
+                             "algorithmic_bytes_per_launch": round(stats[f"{inner}:{part}"]["bytes"] /
+                                                                   max(stats[f"{inner}:{part}"]["launches"], 1))}
+                      for part in ("k1", "k2", "fused")},
+        "reliable_update_hop64": {"GBps": round(gbs(stats["hop64"]) or 0.0, 1), "avg_us": avg_us(stats["hop64"]),
+                                  "launches": stats["hop64"]["launches"]},
+        "all_hop_launches_GBps": round(gbs(hop), 1),
         "hop_launches": hop["launches"],
         "mixed_ms_to_1e-10": round(mixed_ms, 3),
         "mixed_iters": mixed_info.iters,
@@ -275,7 +342,7 @@ def main():
         "paper_switch_mode_true_rel_residual": switch_info.true_rel_residual,
         "fp64_hop_GBps": round(st64["bytes"] / (st64["ms"] * 1e-3) / 1e9, 1) if st64["ms"] > 0 else None,
         "roofline": {
-            "kernel": f"hop half-sweep ({dom_name}: {args.sloppy} spinors, {args.link} two-row links)",
+            "kernel": f"hop half-sweeps K1 and K2 ({dom_name}: {args.sloppy} spinors, {args.link} two-row links)",
             "bound": "hbm",
             "achieved": round(dom_gbs, 1),
             "peak": HBM_PEAK_GBS,
@@ -283,7 +350,7 @@ def main():
             "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": round(per_launch_bytes),
-            "avg_launch_us": round(dom["ms"] / max(dom["launches"], 1) * 1e3, 2),
+            "avg_launch_us": avg_us(dom),
             "launches": dom["launches"],
             "copy_kernel_GBps": round(copy_gbs, 1),
             "frac_of_copy": round(dom_gbs / copy_gbs, 4),

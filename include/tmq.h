@@ -135,10 +135,14 @@ void tmq_lattice_destroy(tmq_lattice *lat);
 /* Load a gauge field (canonical complex128 [site][mu][3][3], periodic in every
  * direction, Sec. 2.4) and build the device copies sorted for the operator:
  * per (parity, direction) structure-of-arrays, FP64 full links, and two-row
- * FP64/FP32/FP16 copies when the links are SU(3) to within 1e-12 (the third
- * row is rebuilt as conj(row0 x row1) in the kernels).  This is the paper's
- * "double copy of the gauge field sorted in access order" (Sec. 4.1).  The
- * boundary phases are never folded into the links. */
+ * FP64/FP32/FP16 copies (the third row is rebuilt as conj(row0 x row1) in the
+ * kernels), which every operator uses when the links are SU(3) to within 1e-12.
+ * A field that fails that check (eq. (eo0) holds for any U) gets a full 3x3
+ * FP32 copy as well, and then every operator keeps all three rows: FP64 full
+ * links for the FP64 operator, FP32 full links for every reduced precision
+ * (whatever sloppy_link asks for).  This is the paper's "double copy of the
+ * gauge field sorted in access order" (Sec. 4.1).  The boundary phases are
+ * never folded into the links. */
 int tmq_load_gauge(tmq_lattice *lat, const double *U_host);
 int tmq_load_gauge_dev(tmq_lattice *lat, const double *U_dev, void *stream);
 
@@ -150,7 +154,8 @@ int tmq_gauge_is_su3(const tmq_lattice *lat);
 /* out_odd = Qhat^{sign} in_odd (sign = +1 or -1), odd-site fields.  prec
  * selects the device storage: TMQ_FP64 (FP64 arithmetic, two-row FP64 links
  * when SU(3)), or FP32/FP16/BF16 spinors with FP32 arithmetic and FP32
- * (prec = FP32) or FP16 (prec = FP16/BF16) two-row links; the input is
+ * (prec = FP32) or FP16 (prec = FP16/BF16) two-row links (full FP32 links
+ * when the field is not SU(3), see tmq_load_gauge); the input is
  * encoded to that storage and the result decoded back to complex128.
  * in and out must not overlap. */
 int tmq_apply_Qhat(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec,
@@ -438,8 +443,12 @@ void tmq_server_destroy(tmq_server *srv);
  * synchronises the device and clears the records.  tmq_kernel_stats returns,
  * for the launches recorded since then, their number, total time in ms, and
  * the algorithmic bytes and flops they move (each input spinor, link and
- * output counted once; 1320 flop per output site per half-sweep).  family is
- * "hop" (all), "hop64", "hop32" or "hop16" (FP16 and BF16 spinor storage).
+ * output counted once; 1320 flop per output site per half-sweep; a fused CG
+ * epilogue adds its reads of r and p and its read and write of x, a fused
+ * residual its read of b).  family is "hop" (all), "hop64", "hop32" or "hop16"
+ * (FP16 and BF16 spinor storage), optionally followed by ":pure" (the plain
+ * half-sweeps K1 and K2 of eqs. (eo3)/(eo4) only), ":k1", ":k2" or ":fused"
+ * (the half-sweeps whose epilogue carries the CG update or the true residual).
  * Reading the stats synchronises the device. */
 int tmq_set_kernel_timing(tmq_lattice *lat, int on);
 int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double *total_ms,

@@ -805,13 +805,23 @@ int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double
                      double *flops)
 {
     TMQ_TRY(check_lat(lat, false));
+    // family = base[:part]; base selects the spinor storage, part the epilogue
+    std::string base = family ? family : "", part;
+    const size_t colon = base.find(':');
+    if (colon != std::string::npos) {
+        part = base.substr(colon + 1);
+        base = base.substr(0, colon);
+    }
     int want = -2;  // -1: every hop launch
-    if (family && strcmp(family, "hop") == 0) want = -1;
-    if (family && strcmp(family, "hop64") == 0) want = P64;
-    if (family && strcmp(family, "hop32") == 0) want = P32;
-    if (family && strcmp(family, "hop16") == 0) want = P16;
-    if (want == -2) {
-        set_error("tmq_kernel_stats: unknown kernel family (hop, hop64, hop32, hop16)");
+    if (base == "hop") want = -1;
+    if (base == "hop64") want = P64;
+    if (base == "hop32") want = P32;
+    if (base == "hop16") want = P16;
+    // 0 all, 1 the plain half-sweeps (K1, K2), 2 K1, 3 K2, 4 the fused CG and residual epilogues
+    const int sel = part.empty() ? 0 : part == "pure" ? 1 : part == "k1" ? 2 : part == "k2" ? 3 : part == "fused" ? 4 : -1;
+    if (want == -2 || sel < 0) {
+        set_error("tmq_kernel_stats: unknown kernel family (hop, hop64, hop32, hop16, optionally :pure, :k1, :k2 "
+                  "or :fused)");
         return TMQ_EINVAL;
     }
     Lattice *L = lat->L;
@@ -822,6 +832,10 @@ int tmq_kernel_stats(tmq_lattice *lat, const char *family, int *launches, double
     for (auto &t : L->timed) {
         const int fam = t.prec == PB16 ? P16 : t.prec;
         if (want >= 0 && fam != want) continue;
+        const bool fused = t.epi == EPI_K2_CG || t.epi == EPI_K2_RES;
+        if ((sel == 1 && fused) || (sel == 2 && t.epi != EPI_K1) || (sel == 3 && t.epi != EPI_K2) ||
+            (sel == 4 && !fused))
+            continue;
         float e = 0.f;
         TMQ_HIP(hipEventElapsedTime(&e, t.a, t.b));
         ms += e;

@@ -202,6 +202,12 @@ __global__ __launch_bounds__(BLAS_BLOCK) void k_gauge_ingest(Geom g, const doubl
                     q[k * 8] = make_float4((float)a.re, (float)a.im, (float)b.re, (float)b.im);
                 }
             }
+            if (o.full32) {
+                float2 *q = o.full32 + par * 36 * st + lidx(h, mu, 0, 9);
+#pragma unroll
+                for (int k = 0; k < 9; k++)
+                    q[k * 8] = make_float2((float)u.e[k / 3][k % 3].re, (float)u.e[k / 3][k % 3].im);
+            }
             if (o.row16a) {
                 uint32_t w[6];
 #pragma unroll

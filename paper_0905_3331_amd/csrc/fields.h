@@ -23,6 +23,7 @@
 //     L32R : 3 blocks of float4 (rows 0, 1)                            48 B/link
 //     L16R : one block of 8 x fp16 (in array a) and one of 4 x fp16
 //            (array b, 8-byte elements in 16-site chunks, lidx16)      24 B/link
+//     L32F : 9 blocks of float2 (full 3x3; links that are not SU(3))   72 B/link
 //   A field of n sites (n a multiple of 8) stacked from two parities is one
 //   such array of 2 * V/2 sites: the odd sites start at site V/2.
 #pragma once
@@ -55,6 +56,7 @@ typedef double nv_d2 __attribute__((ext_vector_type(2)));
 typedef float nv_f4 __attribute__((ext_vector_type(4)));
 typedef unsigned int nv_u4 __attribute__((ext_vector_type(4)));
 typedef unsigned int nv_u2 __attribute__((ext_vector_type(2)));
+typedef float nv_f2 __attribute__((ext_vector_type(2)));
 
 template <bool NT>
 __device__ __forceinline__ double2 ld(const double2 *p)
@@ -71,6 +73,15 @@ __device__ __forceinline__ float4 ld(const float4 *p)
     if (NT) {
         nv_f4 v = __builtin_nontemporal_load((const nv_f4 *)p);
         return make_float4(v.x, v.y, v.z, v.w);
+    }
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ float2 ld(const float2 *p)
+{
+    if (NT) {
+        nv_f2 v = __builtin_nontemporal_load((const nv_f2 *)p);
+        return make_float2(v.x, v.y);
     }
     return *p;
 }
@@ -379,6 +390,35 @@ struct L32R {
         }
     }
     // a link held in registers, and out = U p or U^+ p with it
+    using Loaded = su3<real>;
+    template <bool NT>
+    __device__ __forceinline__ void load_link(int par, int mu, long h, Loaded &u) const
+    {
+        load<NT>(par, mu, h, u);
+    }
+    template <bool DAG>
+    __device__ __forceinline__ void apply(const Loaded &u, const half<real> &p, half<real> &out) const
+    {
+        link_mul<DAG>(u, p, out);
+    }
+};
+
+// FP32 copy of links that are not SU(3): all three rows stored (row 2 cannot
+// be rebuilt from rows 0 and 1), the reduced-precision operator of any U
+struct L32F {
+    using real = float;
+    const float2 *p;
+    long vh;
+    template <bool NT, typename R>
+    __device__ __forceinline__ void load(int par, int mu, long h, su3<R> &u) const
+    {
+        const float2 *q = p + par * 36 * vh + lidx(h, mu, 0, 9);
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            float2 v = ld<NT>(q + k * 8);
+            u.e[k / 3][k % 3] = cx<R>{(R)v.x, (R)v.y};
+        }
+    }
     using Loaded = su3<real>;
     template <bool NT>
     __device__ __forceinline__ void load_link(int par, int mu, long h, Loaded &u) const

@@ -10,6 +10,7 @@ hipError_t launch_hop_f16(const Geom &g, int out_par, const FieldDesc &in, const
 #define GO(SPT, LKT, ALL, MULTI) return go<SPT, LKT, ALL, MULTI>(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st, cg)
     if (lk.fmt == LK16R) GO(SpH16, L16R, true, true);
     if (lk.fmt == LK32R) GO(SpH16, L32R, false, false);
+    if (lk.fmt == LK32F) GO(SpH16, L32F, false, false);
 #undef GO
     return hipErrorInvalidValue;
 }

@@ -10,6 +10,7 @@ hipError_t launch_hop_f32(const Geom &g, int out_par, const FieldDesc &in, const
 #define GO(SPT, LKT, ALL, MULTI) return go<SPT, LKT, ALL, MULTI>(g, out_par, in, self, out, lk, op, epi, sign, rl, partial, pstride, scal, tu, st, cg)
     if (lk.fmt == LK32R) GO(SpF32, L32R, true, true);
     if (lk.fmt == LK16R) GO(SpF32, L16R, false, false);
+    if (lk.fmt == LK32F) GO(SpF32, L32F, false, false);
 #undef GO
     return hipErrorInvalidValue;
 }

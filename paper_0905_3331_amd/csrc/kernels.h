@@ -17,7 +17,10 @@
 namespace tmq {
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };  // same values as tmq_prec
-enum LinkFmt { LK64F = 0, LK64R = 1, LK32R = 2, LK16R = 3 };
+// LK32F: FP32 full 3x3 links, the reduced-precision copy of a gauge field
+// that is not SU(3) (two-row storage rebuilds row 2 assuming SU(3))
+enum LinkFmt { LK64F = 0, LK64R = 1, LK32R = 2, LK16R = 3, LK32F = 4 };
+constexpr int N_LINK_FMT = 8;  // stride of the (spinor precision, link format) tuning keys
 
 constexpr int MAX_RHS = 64;
 
@@ -272,6 +275,7 @@ struct GaugeOut {
     float4 *row32;    // LK32R
     uint4 *row16a;    // LK16R
     uint2 *row16b;
+    float2 *full32;   // LK32F
 };
 hipError_t launch_gauge_ingest(const Geom &g, const double2 *U, const GaugeOut &o, double *partial_max,
                                hipStream_t st);

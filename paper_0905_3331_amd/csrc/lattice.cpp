@@ -70,7 +70,7 @@ Lattice::~Lattice()
     if (own) hipStreamSynchronize(own);
     for (Engine *e : engines) delete e;
     for (auto &w : work) field_free(w.second);
-    for (void *p : {(void *)u64f, (void *)u64r, (void *)u32r, (void *)u16a, (void *)u16b})
+    for (void *p : {(void *)u64f, (void *)u64r, (void *)u32r, (void *)u16a, (void *)u16b, (void *)u32f})
         if (p) hipFree(p);
     for (double *p : partial)
         if (p) hipFree(p);
@@ -116,7 +116,7 @@ int lattice_create(const int dims[4], int device, Lattice **out)
     }
     Lattice *L = new Lattice();
     L->device = device;
-    for (int k = 0; k < 16; k++) {
+    for (int k = 0; k < Lattice::NKEY; k++) {
         L->hop_variant[k] = -1;
         L->hop_occ[k] = 0;
         for (int v = 0; v < HOP_VARIANTS; v++) L->hop_tune_us[k][v] = -1.f;
@@ -231,7 +231,8 @@ int lattice_load_gauge(Lattice *L, const double2 *U, hipStream_t st)
     TMQ_TRY(alloc((void **)&L->u32r, (size_t)8 * 3 * vh * sizeof(float4)));
     TMQ_TRY(alloc((void **)&L->u16a, (size_t)8 * vh * sizeof(uint4)));
     TMQ_TRY(alloc((void **)&L->u16b, (size_t)8 * ((vh + 15) & ~15L) * sizeof(uint2)));  // 16-site chunks
-    GaugeOut o{L->u64f, L->u64r, L->u32r, L->u16a, L->u16b};
+    GaugeOut o{L->u64f, L->u64r, L->u32r, L->u16a, L->u16b, nullptr};
+    L->gauge = false;
     TMQ_HIP(launch_gauge_ingest(L->g, U, o, L->partial[0], st));
     TMQ_HIP(launch_max(L->partial[0], blas_grid(2 * vh), L->partial[1], st));
     double dev = 0.0;
@@ -239,6 +240,14 @@ int lattice_load_gauge(Lattice *L, const double2 *U, hipStream_t st)
     TMQ_HIP(hipStreamSynchronize(st));
     L->su3_dev = dev;
     L->su3 = std::isfinite(dev) && dev < 1e-12;
+    if (!L->su3) {
+        // two-row copies cannot represent these links (row 2 is rebuilt as
+        // conj(row0 x row1)): the reduced-precision operators use a full FP32 copy
+        TMQ_TRY(alloc((void **)&L->u32f, (size_t)8 * 9 * vh * sizeof(float2)));
+        GaugeOut f{nullptr, nullptr, nullptr, nullptr, nullptr, L->u32f};
+        TMQ_HIP(launch_gauge_ingest(L->g, U, f, L->partial[0], st));
+        TMQ_HIP(hipStreamSynchronize(st));
+    }
     L->gauge = true;
     return TMQ_OK;
 }
@@ -253,6 +262,7 @@ LinkDesc lattice_links(const Lattice *L, int fmt)
     case LK64R: d.a = L->u64r; break;
     case LK32R: d.a = L->u32r; break;
     case LK16R: d.a = L->u16a; d.b = L->u16b; break;
+    case LK32F: d.a = L->u32f; break;
     }
     return d;
 }
@@ -260,6 +270,7 @@ LinkDesc lattice_links(const Lattice *L, int fmt)
 int link_fmt_for(const Lattice *L, int prec, int sloppy_link)
 {
     if (prec == P64) return L->su3 ? LK64R : LK64F;
+    if (!L->su3) return LK32F;  // any U: rows 0-2 stored, whatever the link precision asked for
     if (prec == P32 && sloppy_link != P16) return LK32R;
     if (sloppy_link == P32) return LK32R;
     return LK16R;
@@ -286,7 +297,11 @@ OpParams make_op(const Lattice *L, const tmq_params *p, int n)
 double hop_bytes_per_site(int prec, int link_fmt, bool self, int nrhs)
 {
     const double sp = prec == P64 ? 192.0 : prec == P32 ? 96.0 : 52.0;
-    const double lk = link_fmt == LK64F ? 144.0 : link_fmt == LK64R ? 96.0 : link_fmt == LK32R ? 48.0 : 24.0;
+    const double lk = link_fmt == LK64F   ? 144.0
+                      : link_fmt == LK64R ? 96.0
+                      : link_fmt == LK32F ? 72.0
+                      : link_fmt == LK32R ? 48.0
+                                          : 24.0;
     return 8.0 * lk + nrhs * (sp + sp + (self ? sp : 0.0));
 }
 
@@ -427,14 +442,15 @@ static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc
 std::string tuning_report(const Lattice *L)
 {
     static const char *pn[4] = {"fp64", "fp32", "fp16", "bf16"};
-    static const char *ln[4] = {"fp64_full", "fp64_two_row", "fp32_two_row", "fp16_two_row"};
+    static const char *ln[N_LINK_FMT] = {"fp64_full", "fp64_two_row", "fp32_two_row", "fp16_two_row",
+                                         "fp32_full",  "?",            "?",            "?"};
     std::string s = "{\"hop\": [";
     bool first = true;
-    for (int k = 0; k < 16; k++) {
+    for (int k = 0; k < Lattice::NKEY; k++) {
         if (L->hop_variant[k] < 0) continue;
         char buf[256];
         snprintf(buf, sizeof(buf), "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"variant\": %d, \"us\": [",
-                 first ? "" : ", ", pn[k / 4], ln[k % 4], L->hop_variant[k]);
+                 first ? "" : ", ", pn[k / N_LINK_FMT], ln[k % N_LINK_FMT], L->hop_variant[k]);
         s += buf;
         for (int v = 0; v < HOP_VARIANTS; v++) {
             snprintf(buf, sizeof(buf), "%s%.2f", v ? ", " : "", L->hop_tune_us[k][v]);
@@ -456,7 +472,7 @@ std::string tuning_report(const Lattice *L)
         snprintf(buf, sizeof(buf),
                  "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"nrhs_class\": %d, \"rhs_per_lane\": %d, "
                  "\"group\": %d, \"tried\": [",
-                 i ? ", " : "", pn[b.key / 4], ln[b.key % 4], b.cls, b.tu.rpl, b.tu.group);
+                 i ? ", " : "", pn[b.key / N_LINK_FMT], ln[b.key % N_LINK_FMT], b.cls, b.tu.rpl, b.tu.group);
         s += buf;
         for (size_t j = 0; j < b.tried.size(); j++) {
             snprintf(buf, sizeof(buf), "%s[%d, %d, %.1f]", j ? ", " : "", (int)b.tried[j][0], (int)b.tried[j][1],
@@ -484,11 +500,12 @@ static FieldDesc flavour_view(const FieldDesc &f)
 
 static double fused_extra_bytes(int prec, int epi)
 {
-    // the epilogue's own vectors instead of the output: CG reads r, p, x and writes r, x
-    // (the output is not stored); the residual reads b and writes r
+    // the epilogue's own vectors beside the half-sweep's (whose output write
+    // stands for the write of r): CG reads r and p and reads and writes x;
+    // the residual reads b
     const double sp = prec == P64 ? 192.0 : prec == P32 ? 96.0 : 52.0;
     const double xsp = prec == P64 ? 192.0 : 96.0;
-    return epi == EPI_K2_CG ? (sp + 2 * xsp) : epi == EPI_K2_RES ? sp : 0.0;
+    return epi == EPI_K2_CG ? (2 * sp + 2 * xsp) : epi == EPI_K2_RES ? sp : 0.0;
 }
 
 // hop half-sweep of a batch of doublets (op.nd): the two flavours of a site
@@ -517,7 +534,7 @@ static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc 
         fl.idx[2 * i] = (unsigned char)(2 * rl.idx[i]);
         fl.idx[2 * i + 1] = (unsigned char)(2 * rl.idx[i] + 1);
     }
-    const int key = in.prec * 4 + lk.fmt;
+    const int key = in.prec * N_LINK_FMT + lk.fmt;
     if (L->forced_variant >= 0) {
         L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;
         if (L->forced_cap >= 0) L->hop_occ[key] = occ_lds(L, L->forced_cap) == ~0u ? 0 : L->forced_cap;
@@ -546,6 +563,7 @@ static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc 
         t.flops = 1320.0 * (double)L->g.vh * fl.n;
         t.prec = in.prec;
         t.nrhs = fl.n;
+        t.epi = epi;
         TMQ_HIP(hipEventRecord(t.a, st));
     }
     TMQ_HIP(launch_hop(L->g, out_par, fi, fs, fo, lk, op, epi, sign, fl, partial, L->pstride, scal, tu, st,
@@ -565,7 +583,7 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
 {
     if (rl.n <= 0) return TMQ_OK;
     if (op.nd) return hop_nd(L, out_par, in, self, out, lk, op, epi, sign, rl, partial, scal, st, cg);
-    const int key = in.prec * 4 + lk.fmt;
+    const int key = in.prec * N_LINK_FMT + lk.fmt;
     const bool fused = epi == EPI_K2_CG || epi == EPI_K2_RES;
     if (fused && L->forced_variant < 0 && L->hop_variant[key] < 0) {
         // the tuner re-runs its launch, which a fused epilogue must not (it
@@ -610,6 +628,7 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
         t.flops = 1320.0 * (double)L->g.vh * rl.n;
         t.prec = in.prec;
         t.nrhs = rl.n;
+        t.epi = epi;
         TMQ_HIP(hipEventRecord(t.a, st));
     }
     TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal, tu, st, cg));

@@ -49,6 +49,7 @@ struct TimedLaunch {
     double bytes, flops;
     int prec;  // spinor storage of the launch
     int nrhs;  // right-hand sides in the launch
+    int epi;   // epilogue (HopEpi)
 };
 
 struct Lattice {
@@ -64,6 +65,7 @@ struct Lattice {
     float4 *u32r = nullptr;
     uint4 *u16a = nullptr;
     uint2 *u16b = nullptr;
+    float2 *u32f = nullptr;  // FP32 full links, built only for fields that fail the SU(3) check
 
     // reductions and solver scalars: partial sums of RHS r at partial[k] + r * pstride
     double *partial[3] = {nullptr, nullptr, nullptr};
@@ -89,15 +91,16 @@ struct Lattice {
     void *stage[2] = {nullptr, nullptr};
     size_t stage_bytes[2] = {0, 0};
 
-    // autotuned hop variant per (spinor precision, link format); -1 = not tuned yet
-    int hop_variant[16];
-    float hop_tune_us[16][HOP_VARIANTS];
+    // autotuned hop variant per key = spinor precision * N_LINK_FMT + link format; -1 = not tuned yet
+    static constexpr int NKEY = 4 * N_LINK_FMT;
+    int hop_variant[NKEY];
+    float hop_tune_us[NKEY][HOP_VARIANTS];
     int forced_variant = -1;  // TMQ_HOP_VARIANT in the environment
     int forced_cap = -1;      // TMQ_HOP_CAP in the environment
     int forced_rpl = 0;       // TMQ_HOP_RPL in the environment (RHS per lane of batched hops)
     // blocks-per-CU cap tuned for that variant (0: none; see launch_hop's lds)
-    int hop_occ[16];
-    float hop_occ_us[16][6];
+    int hop_occ[NKEY];
+    float hop_occ_us[NKEY][6];
     int lds_per_cu = 65536;
     // autotuned launch shape of batched hops, per (spinor precision, link
     // format) key and power-of-two batch size class
@@ -120,7 +123,8 @@ struct Lattice {
 int lattice_create(const int dims[4], int device, Lattice **out);
 int lattice_load_gauge(Lattice *L, const double2 *U_dev, hipStream_t st);
 LinkDesc lattice_links(const Lattice *L, int fmt);
-// link format used for a spinor precision (sloppy_link: P32 or P16 for the inner links)
+// link format used for a spinor precision (sloppy_link: P32 or P16 for the inner
+// links); the full-link formats when the loaded field is not SU(3)
 int link_fmt_for(const Lattice *L, int prec, int sloppy_link);
 
 // a work field of the given role, precision, site count and RHS count (allocated once, reused)

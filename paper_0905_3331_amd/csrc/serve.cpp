@@ -85,6 +85,7 @@ struct Server {
     std::vector<hipEvent_t> ev_pool;
 
     // statistics (under mu)
+    int n_engines = 0;  // engines.size(), kept here for the stats readers
     size_t bytes_in_use = 0, peak_bytes = 0;
     int running = 0, peak_running = 0;
     long submitted = 0, completed = 0, failed_n = 0, rejected = 0, steps = 0;
@@ -98,6 +99,8 @@ struct Server {
     bool pass();
     void admit(std::vector<Request *> &pending, std::vector<Request *> &failed_join);
     EngineRec *engine_for(Request *r, bool may_create, int *err = nullptr);
+    int link_fmt_of(const Request *r);
+    bool same_key(const EngineRec *er, const Request *r, int lkf) const;
     void fail_engine(EngineRec *er, const std::string &msg);
     void complete(Request *r, int status);
     hipEvent_t get_event();
@@ -144,6 +147,26 @@ void Server::fail_engine(EngineRec *er, const std::string &msg)
         }
 }
 
+// The inner link format a request's solve uses (its engine key's last part).
+int Server::link_fmt_of(const Request *r)
+{
+    Lattice *L = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        L = lats[r->lat]->L.get();
+    }
+    const int sp = r->o.sloppy;
+    return sp == P64 ? link_fmt_for(L, P64, P64) : link_fmt_for(L, sp, r->o.sloppy_link);
+}
+
+// Whether engine er serves requests like r: same lattice, inner spinor
+// precision, inner link format and solver mode (theta is checked apart,
+// since an empty engine takes on the theta of the request that joins it).
+bool Server::same_key(const EngineRec *er, const Request *r, int lkf) const
+{
+    return er->lat == r->lat && er->sloppy == r->o.sloppy && er->link_fmt == lkf && er->mode == r->o.mode;
+}
+
 // An engine with a free slot for r; may create one within the budget,
 // releasing idle engines of other keys for it.  Called without mu.
 EngineRec *Server::engine_for(Request *r, bool may_create, int *err)
@@ -155,12 +178,9 @@ EngineRec *Server::engine_for(Request *r, bool may_create, int *err)
         L = lats[r->lat]->L.get();
     }
     const int sp = r->o.sloppy;
-    const int lkf = sp == P64 ? link_fmt_for(L, P64, P64) : link_fmt_for(L, sp, r->o.sloppy_link);
-    auto same_key = [&](const EngineRec *er) {
-        return er->lat == r->lat && er->sloppy == sp && er->link_fmt == lkf && er->mode == r->o.mode;
-    };
+    const int lkf = link_fmt_of(r);
     for (auto &er : engines) {
-        if (er->broken || !same_key(er.get()) || er->E->body_pending) continue;
+        if (er->broken || !same_key(er.get(), r, lkf) || er->E->body_pending) continue;
         if (engine_free_slot(er->E.get()) < 0) continue;
         const bool empty = engine_occupied(er->E.get()) == 0;
         if (!empty && memcmp(er->theta, r->p.theta, sizeof(er->theta)) != 0) continue;
@@ -178,15 +198,16 @@ EngineRec *Server::engine_for(Request *r, bool may_create, int *err)
         // release idle engines (no occupied slot, nothing in flight) of other keys
         for (size_t i = 0; i < engines.size();) {
             EngineRec *er = engines[i].get();
-            if (engine_occupied(er->E.get()) == 0 && !er->E->body_pending && !same_key(er)) {
+            if (engine_occupied(er->E.get()) == 0 && !er->E->body_pending && !same_key(er, r, lkf)) {
                 bool copying_from = false;
                 for (Request *q : copying) copying_from |= q->eng == er;
                 if (!copying_from) {
                     const size_t b = er->E->bytes;
                     er->E.reset();
                     hipStreamDestroy(er->st);
-                    engines.erase(engines.begin() + (long)i);
                     std::lock_guard<std::mutex> lk(mu);
+                    engines.erase(engines.begin() + (long)i);
+                    n_engines = (int)engines.size();
                     bytes_in_use -= b;
                     in_use = bytes_in_use;
                     continue;
@@ -217,12 +238,11 @@ EngineRec *Server::engine_for(Request *r, bool may_create, int *err)
     er->mode = r->o.mode;
     memcpy(er->theta, r->p.theta, sizeof(er->theta));
     er->slot_req.assign(cap, nullptr);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        bytes_in_use += E->bytes;
-        peak_bytes = std::max(peak_bytes, bytes_in_use);
-    }
+    std::lock_guard<std::mutex> lk(mu);
+    bytes_in_use += E->bytes;
+    peak_bytes = std::max(peak_bytes, bytes_in_use);
     engines.push_back(std::move(er));
+    n_engines = (int)engines.size();
     return engines.back().get();
 }
 
@@ -238,10 +258,13 @@ void Server::admit(std::vector<Request *> &pending, std::vector<Request *> &fail
     for (Request *r : pending) {
         EngineRec *er = blocked ? nullptr : engine_for(r, false);
         if (!er && !blocked) {
+            // an engine of the request's own key (the key engine_for matches on)
+            // that will free a slot: wait for it; otherwise create one
+            const int lkf = link_fmt_of(r);
             bool has_engine = false;
             for (auto &e : engines)
-                has_engine |= !e->broken && e->lat == r->lat && e->sloppy == r->o.sloppy &&
-                              e->mode == r->o.mode && memcmp(e->theta, r->p.theta, sizeof(e->theta)) == 0;
+                has_engine |= !e->broken && same_key(e.get(), r, lkf) &&
+                              memcmp(e->theta, r->p.theta, sizeof(e->theta)) == 0;
             if (!has_engine) {
                 int err = TMQ_OK;
                 er = engine_for(r, true, &err);
@@ -626,7 +649,7 @@ int tmq_server_get_stats(tmq_server *srv, tmq_server_stats *out)
     o.budget_bytes = S.budget;
     o.bytes_in_use = S.bytes_in_use;
     o.peak_bytes = S.peak_bytes;
-    o.engines = (int)S.engines.size();
+    o.engines = S.n_engines;
     o.peak_running = S.peak_running;
     o.steps = S.steps;
     *out = o;

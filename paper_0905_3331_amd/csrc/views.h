@@ -26,6 +26,8 @@ template <>
 inline L32R make_lk<L32R>(const LinkDesc &l) { return L32R{(const float4 *)l.a, l.vh}; }
 template <>
 inline L16R make_lk<L16R>(const LinkDesc &l) { return L16R{(const uint4 *)l.a, (const uint2 *)l.b, l.vh}; }
+template <>
+inline L32F make_lk<L32F>(const LinkDesc &l) { return L32F{(const float2 *)l.a, l.vh}; }
 
 // the view of RHS r of a batch (elems / sites: offsets of RHS r)
 __device__ __forceinline__ SpF64 rhs_view(const SpF64 &v, long elems, long) { return SpF64{v.p + elems}; }

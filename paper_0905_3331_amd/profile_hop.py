@@ -62,6 +62,42 @@ def hop_family(name: str):
     return None
 
 
+def hop_template_args(name: str):
+    """Template arguments of a hop_kernel instantiation, in order: spinor format,
+    link format, SELF, NORM, NT, ORD, SB, G, EP, ND (as text)."""
+    i = name.find("hop_kernel<")
+    if i < 0:
+        return None
+    depth, cur, args = 0, "", []
+    for ch in name[i + len("hop_kernel<"):]:
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            if depth == 0:
+                args.append(cur.strip())
+                return args
+            depth -= 1
+        if ch == "," and depth == 0:
+            args.append(cur.strip())
+            cur = ""
+        else:
+            cur += ch
+    return None
+
+
+def hop_part(name: str):
+    """Which half-sweep an instantiation is: "k1" (no site term of its own
+    parity: K1 of eq. (eo3)), "k2" (K2 of eq. (eo4) storing its output),
+    "fused" (K2 with the CG update or the true residual fused), or None."""
+    a = hop_template_args(name)
+    if not a or len(a) < 10:
+        return None
+    self_, ep = a[2] == "true", a[8]
+    if ep != "0":
+        return "fused"
+    return "k2" if self_ else "k1"
+
+
 def _counter_rows(path, counter):
     out = collections.defaultdict(list)
     for r in csv.DictReader(open(path)):
@@ -93,19 +129,31 @@ def summarize_pmc(fetch_csv, write_csv, copy_bytes, cmd, out):
     fam = collections.defaultdict(lambda: {"fetch": [], "write": []})
     per_kernel = {}
     fu, wu = used(f), used(w)
+    def groups(k):
+        # the family, and its parts: ":pure" (K1 and K2), ":k1", ":k2", ":fused"
+        fa, part = hop_family(k), hop_part(k)
+        out = [fa]
+        if part:
+            out.append(f"{fa}:{part}")
+            if part != "fused":
+                out.append(f"{fa}:pure")
+        return out
+
     for k, v in f.items():
         fa = hop_family(k)
         if fa:
             per_kernel.setdefault(k, {})["read_bytes_per_launch"] = sum(v) / len(v) * 1024.0 * fscale
             per_kernel[k]["dispatches"] = len(v)
             if k in fu:
-                fam[fa]["fetch"] += [x * 1024.0 * fscale for x in v]
+                for gname in groups(k):
+                    fam[gname]["fetch"] += [x * 1024.0 * fscale for x in v]
     for k, v in w.items():
         fa = hop_family(k)
         if fa:
             per_kernel.setdefault(k, {})["write_bytes_per_launch"] = sum(v) / len(v) * 1024.0 * wscale
             if k in wu:
-                fam[fa]["write"] += [x * 1024.0 * wscale for x in v]
+                for gname in groups(k):
+                    fam[gname]["write"] += [x * 1024.0 * wscale for x in v]
     res = {"kernel_hash": kernel_hash(), "command": cmd, "copy_bytes": copy_bytes,
            "fetch_scale": fscale, "write_scale": wscale, "per_kernel": per_kernel}
     for fa, d in fam.items():

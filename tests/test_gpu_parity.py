@@ -28,6 +28,28 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
+def site_err(a, b):
+    """Element-wise (per site) error: the largest |a_x - b_x| over sites x (12
+    complex components each), relative to the RMS site norm of b.  A normwise
+    ratio over N sites hides a few wrong sites (one wrong site adds about
+    1/sqrt(N) to it); this one sees each: a mis-indexed site scores about 1.4."""
+    d = np.asarray(a).reshape(-1, 12) - np.asarray(b).reshape(-1, 12)
+    rms = np.sqrt(np.mean(np.sum(np.abs(np.asarray(b).reshape(-1, 12)) ** 2, axis=1)))
+    return float(np.sqrt(np.max(np.sum(np.abs(d) ** 2, axis=1))) / max(rms, 1e-300))
+
+
+# Per-site bounds, derived from the storage: an output site of Qhat is its own
+# input site plus kappa^2 times 8 hops (projection: 2 terms, link: 3 terms) of
+# the even-site field, itself 8 hops of the input, each value stored with unit
+# roundoff u relative to its site's scale (16-bit) or its own size (FP32/FP64
+# storage with FP32/FP64 arithmetic).  Counting every term at full size,
+# |error_x| <= (1 + kappa^2 * 8 * 6 * (1 + 8 * 6)) u * s ~ 64 u s for kappa
+# near 0.16, with s the largest site scale, about the RMS site norm for
+# Gaussian fields.  So 64 u: FP16 (u = 2^-11) 3.1e-2, BF16 (2^-8) 0.25, FP32
+# (2^-24) 3.8e-6; FP64 1e-12 (the normwise 1e-13 with room for the maximum).
+SITE_BOUND = {"fp64": 1e-12, "fp32": 64 * 2.0 ** -24, "fp16": 64 * 2.0 ** -11, "bf16": 64 * 2.0 ** -8}
+
+
 @pytest.fixture(scope="module")
 def tmq():
     if not torch.cuda.is_available():
@@ -92,6 +114,51 @@ def test_qhat_fp64_full_links_non_su3(tmq, dims):
     lat.close()
 
 
+@pytest.mark.parametrize("kind", ["u3_phase", "general"])
+def test_non_su3_links_every_precision(tmq, kind):
+    """eq. (eo0) holds for any link matrices; two-row storage assumes SU(3).
+    With links that fail the SU(3) check (U(3) with a phase, or a general
+    complex matrix near one), every reduced precision must use full links:
+    Qhat in FP32, FP16 and BF16 within its storage bounds (normwise and per
+    site), a mixed FP16 and an FP32 solve to 1e-10 by the oracle, and the
+    doublet operator in FP16."""
+    dims = (8, 4, 4, 6)
+    U = synth.random_gauge(dims, seed=109)
+    if kind == "u3_phase":
+        U = U * np.exp(0.37j)
+    else:
+        rng = np.random.default_rng(110)
+        U = U + 0.05 * (rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape))
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(U)
+    assert not lat.su3
+    psi = synth.gaussian_odd(dims, seed=111)
+    kappa, mut = 0.15, 0.02
+    p = tmq.params(kappa, mut, THETA_GEN)
+    for sign in (+1, -1):
+        ref = oracle.Qhat(U, psi, kappa, mut, sign, THETA_GEN)
+        for prec, bound in (("fp64", 1e-13), ("fp32", 2e-6), ("fp16", 3e-3), ("bf16", 2.5e-2)):
+            got = host(lat.apply_Qhat(p, sign, dev(psi), prec=prec))
+            print(f"{kind} Qhat{sign:+d} {prec}: rel {rel(got, ref):.2e} site {site_err(got, ref):.2e}")
+            assert rel(got, ref) < bound, (prec, sign, rel(got, ref))
+            assert site_err(got, ref) < SITE_BOUND[prec], (prec, sign, site_err(got, ref))
+    b = synth.gaussian_odd(dims, seed=112)
+    for sloppy, link in (("fp16", "fp16"), ("fp32", "fp32")):
+        x, info = lat.solve(p, dev(b), tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link=link))
+        res = oracle.true_residual(U, b, host(x), kappa, mut, THETA_GEN)
+        print(f"{kind} {sloppy} solve: {info.iters} iterations, oracle true residual {res:.2e}")
+        assert info.status == 0 and res <= 1e-10
+    pn = tmq.nd_params(0.15, 0.11, 0.09, THETA_GEN)
+    psi2 = np.stack([psi, synth.gaussian_odd(dims, seed=113)])
+    for sign in (+1, -1):
+        ref = oracle.Qhat_nd(U, psi2, 0.15, 0.11, 0.09, sign, THETA_GEN)
+        got = host(lat.apply_Qhat_nd(pn, sign, dev(psi2), prec="fp16"))
+        assert rel(got, ref) < 3e-3 and site_err(got, ref) < SITE_BOUND["fp16"]
+    rep = lat.tuning_report()["hop"]
+    assert all(e["links"] in ("fp64_full", "fp32_full") for e in rep), rep
+    lat.close()
+
+
 def test_qhat_host_pointer_api(tmq):
     dims = (4, 4, 4, 4)
     lat, U = lattice(tmq, dims, seed=101)
@@ -140,8 +207,10 @@ def test_qhat_random_parameters(tmq, seed):
     ref = oracle.Qhat(U, psi, kappa, mut, sign, theta)
     errs = {}
     for prec, bound in (("fp64", 1e-13), ("fp32", 2e-6), ("fp16", 3e-3)):
-        errs[prec] = rel(host(lat.apply_Qhat(p, sign, dev(psi), prec=prec)), ref)
+        got = host(lat.apply_Qhat(p, sign, dev(psi), prec=prec))
+        errs[prec] = rel(got, ref)
         assert errs[prec] < bound, (dims, kappa, mut, theta, sign, prec, errs[prec])
+        assert site_err(got, ref) < SITE_BOUND[prec], (dims, prec, site_err(got, ref))
     got = host(lat.apply_QhatQhat(p, dev(psi)))
     e2 = rel(got, oracle.QhatQhat(U, psi, kappa, mut, theta))
     print(f"{dims} kappa {kappa:.3f} mut {mut:+.3f} theta {np.round(theta, 2)} sign {sign:+d}: "
@@ -419,7 +488,9 @@ def test_every_hop_variant(tmq, variant, dims, monkeypatch):
     for prec, tol in (("fp64", 1e-13), ("fp32", 2e-6), ("fp16", 3e-3)):
         for sign in (+1, -1):
             got = host(lat.apply_Qhat(p, sign, dev(psi), prec=prec))
-            assert rel(got, oracle.Qhat(U, psi, 0.1632, 0.004, sign, THETA_GEN)) < tol, (prec, sign)
+            ref = oracle.Qhat(U, psi, 0.1632, 0.004, sign, THETA_GEN)
+            assert rel(got, ref) < tol, (prec, sign)
+            assert site_err(got, ref) < SITE_BOUND[prec], (prec, sign, site_err(got, ref))
     # the norm reduction of the variant feeds CG: a solve still converges
     b = synth.gaussian_odd(dims, seed=20)
     x, info = lat.solve(p, dev(b), tmq.solver_opts(tol=1e-10))

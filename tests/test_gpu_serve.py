@@ -231,3 +231,29 @@ def test_serve_threads_poll_and_destroy(tmq):
         srv.submit(lid, tmq.params(KAPPA, 0.01, THETA), bd[i], o)
     srv.close()
 
+
+
+def test_serve_same_spinor_precision_different_link_formats(tmq):
+    """Requests with the same inner spinor precision but different inner link
+    formats (FP32 spinors with FP16 links, and with FP32 links) need engines of
+    their own: both kinds complete, each meets its tolerance, and the server
+    holds one engine per link format."""
+    d = (8, 4, 4, 6)
+    U = gauge(d, 3150)
+    with tmq.Server(max_batch=4) as srv:
+        lid = srv.add_lattice(d, dev(U))
+        reqs = []
+        for i in range(6):
+            link = "fp16" if i % 2 == 0 else "fp32"
+            o = tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link=link)
+            b = synth.gaussian_odd(d, seed=4150 + i)
+            mut = 0.004 + 0.002 * i
+            t = srv.submit(lid, tmq.params(KAPPA, mut, THETA), dev(b), o)
+            reqs.append((t, b, mut, link))
+        for t, b, mut, link in reqs:
+            x, info = srv.wait(t, timeout=60)
+            assert info.status == tmq.TMQ_OK, (link, info)
+            assert oracle.true_residual(U, b, host(x), KAPPA, mut, THETA) <= 1e-10
+        st = srv.stats()
+        assert st["completed"] == 6 and st["failed"] == 0
+        assert st["engines"] == 2
