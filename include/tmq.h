@@ -163,6 +163,27 @@ int tmq_apply_Qhat(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec pre
 int tmq_apply_Qhat_dev(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec,
                        const double *in_odd, double *out_odd, void *stream);
 
+/* The same operator for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): identical arguments and result (the same kernels; the output
+ * equals tmq_apply_Qhat_dev's bit for bit), but its three work fields (the
+ * encoded input, the even-site intermediate and the encoded output) live in a
+ * fixed array of TMQ_NOALLOC_SCRATCH_BYTES that the library's code object
+ * holds on every GPU it runs on until the process ends, and the call makes no
+ * hipMalloc, hipFree, event creation or other allocating call (a format the
+ * autotuner has not timed on this lattice runs its default kernel variant,
+ * without tuning; kernel timing is not recorded).  Device pointers only.
+ * The array is shared by every lattice on the device and keeps the last
+ * call's contents (each call writes all it reads): calls on one GPU must not
+ * overlap in time (serialise them on one stream or wait in between).
+ * TMQ_EINVAL when the three fields of this lattice in storage prec exceed the
+ * array: 3 x V/2 x (192 B FP64, 96 B FP32, 52 B FP16/BF16), each rounded up to
+ * 256 B (FP64 up to 16^3 x 32, FP16 up to 24^3 x 48); TMQ_EDEVICE if the
+ * array's address could not be obtained when the lattice was created. */
+#define TMQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int tmq_apply_Qhat_noalloc_dev(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec,
+                               const double *in_odd, double *out_odd, void *stream);
+
 /* out_odd = Qhat^+ Qhat^- in_odd in FP64. */
 int tmq_apply_QhatQhat_dev(tmq_lattice *lat, const tmq_params *p, const double *in_odd,
                            double *out_odd, void *stream);

@@ -221,6 +221,51 @@ int tmq_apply_Qhat_dev(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec
     return qhat_dev(lat->L, p, sign, prec, in, out, (hipStream_t)stream);
 }
 
+int tmq_apply_Qhat_noalloc_dev(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec, const double *in,
+                               double *out, void *stream)
+{
+    TMQ_TRY(check_lat(lat, true));
+    TMQ_TRY(check_params(p));
+    TMQ_TRY(check_sign(sign));
+    TMQ_TRY(check_prec(prec));
+    TMQ_TRY(check_ptrs(in, out));
+    Lattice *L = lat->L;
+    DeviceGuard dg(L->device);
+    size_t cap = 0;
+    char *base = (char *)noalloc_scratch(L->device, &cap);
+    if (!base) {
+        set_error("tmq_apply_Qhat_noalloc_dev: the device address of the fixed work space is unknown "
+                  "(hipGetSymbolAddress failed when the lattice was created)");
+        return TMQ_EDEVICE;
+    }
+    // the three work fields of qhat_dev, one after the other in the array
+    const long vh = L->g.vh;
+    size_t b0 = 0, b1 = 0, b2 = 0;
+    const FieldDesc fi = field_at(base, prec, vh, &b0);
+    const FieldDesc fo = field_at(base + b0, prec, vh, &b1);
+    const FieldDesc te = field_at(base + b0 + b1, prec, vh, &b2);
+    if (b0 + b1 + b2 > cap) {
+        char msg[256];
+        snprintf(msg, sizeof(msg),
+                 "tmq_apply_Qhat_noalloc_dev: this lattice needs %zu bytes of work space in this precision, "
+                 "above the fixed %zu (TMQ_NOALLOC_SCRATCH_BYTES)",
+                 b0 + b1 + b2, cap);
+        set_error(msg);
+        return TMQ_EINVAL;
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    const LinkDesc lk = lattice_links(L, link_fmt_for(L, prec, prec == TMQ_FP32 ? P32 : P16));
+    struct NoAllocScope {
+        Lattice *L;
+        ~NoAllocScope() { L->no_alloc = false; }
+    } scope{L};
+    L->no_alloc = true;
+    TMQ_HIP(launch_from_canonical((const double2 *)in, fi, st));
+    TMQ_TRY(apply_Qhat(L, make_op(L, p, 1), sign, fi, fo, te, lk, rhs_all(1), nullptr, nullptr, st));
+    TMQ_HIP(launch_to_canonical(fo, (double2 *)out, st));
+    return TMQ_OK;
+}
+
 int tmq_apply_Qhat(tmq_lattice *lat, const tmq_params *p, int sign, tmq_prec prec, const double *in, double *out)
 {
     TMQ_TRY(check_lat(lat, true));

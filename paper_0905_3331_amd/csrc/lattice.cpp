@@ -53,6 +53,23 @@ int field_alloc(Field &f, int prec, long n, int nrhs)
     return TMQ_OK;
 }
 
+FieldDesc field_at(void *mem, int prec, long n, size_t *bytes)
+{
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t data = up((size_t)n * field_blocks(prec) * 16);
+    const bool coded = prec == P16 || prec == PB16;
+    FieldDesc d;
+    d.prec = prec;
+    d.data = mem;
+    d.scale = coded ? (float *)((char *)mem + data) : nullptr;
+    d.n = n;
+    d.nrhs = 1;
+    d.rhs_elems = n * field_blocks(prec);
+    d.rhs_sites = n;
+    if (bytes) *bytes = data + (coded ? up((size_t)n * sizeof(float)) : 0);
+    return d;
+}
+
 void field_free(Field &f)
 {
     if (f.mem) hipFree(f.mem);
@@ -151,6 +168,9 @@ int lattice_create(const int dims[4], int device, Lattice **out)
         return code;
     };
     if (hipSetDevice(device) != hipSuccess) return fail(TMQ_EDEVICE, "hipSetDevice failed");
+    // the device's copy of the allocation-free work space (a failure is
+    // reported by the allocation-free call only)
+    (void)noalloc_scratch_init(device);
     if (hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking) != hipSuccess)
         return fail(TMQ_EDEVICE, "hipStreamCreate failed");
     int lds = 0;
@@ -590,6 +610,21 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
         // updates vectors in place); the plain half-sweeps before it tune the format
         set_error("internal: fused hop epilogue before the format was tuned");
         return TMQ_ESTATE;
+    }
+    if (L->no_alloc) {
+        // an allocation-free call: the tuned shape if there is one, else variant 0
+        if (rl.n != 1) {
+            set_error("internal: allocation-free hop launches take one right-hand side");
+            return TMQ_EINVAL;
+        }
+        HopTune tu;
+        const bool tuned = L->forced_variant < 0 && L->hop_variant[key] >= 0;
+        tu.variant = tuned ? L->hop_variant[key] : 0;
+        tu.lds = tuned ? occ_lds(L, L->hop_occ[key]) : 0;
+        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, partial, L->pstride, scal, tu, st,
+                           cg));
+        L->hop_blocks_last = hop_grid_variant(L->g, hop_all_variants(in.prec, lk.fmt) ? tu.variant : 0);
+        return TMQ_OK;
     }
     if (L->forced_variant >= 0) {
         L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;

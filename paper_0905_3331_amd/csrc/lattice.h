@@ -41,6 +41,9 @@ struct Field {
 };
 
 int field_alloc(Field &f, int prec, long n, int nrhs = 1);
+// a one-RHS field of n sites placed at mem (16-bit scales after the codes,
+// 256-byte aligned); *bytes receives the bytes it occupies from mem
+FieldDesc field_at(void *mem, int prec, long n, size_t *bytes);
 void field_free(Field &f);
 size_t field_bytes(int prec, long n);
 
@@ -112,6 +115,10 @@ struct Lattice {
     std::vector<BatchTune> hop_batch;
     int hop_blocks_last = 0;  // blocks (partial sums) of the last hop launch
 
+    // set for the duration of an allocation-free call: hop launches neither
+    // tune (an untuned format runs variant 0) nor record timing events
+    bool no_alloc = false;
+
     // kernel timing
     bool timing = false;
     std::vector<TimedLaunch> timed;
@@ -121,6 +128,9 @@ struct Lattice {
 };
 
 int lattice_create(const int dims[4], int device, Lattice **out);
+// device address of the allocation-free work space (noalloc.hip)
+hipError_t noalloc_scratch_init(int device);
+void *noalloc_scratch(int device, size_t *bytes);
 int lattice_load_gauge(Lattice *L, const double2 *U_dev, hipStream_t st);
 LinkDesc lattice_links(const Lattice *L, int fmt);
 // link format used for a spinor precision (sloppy_link: P32 or P16 for the inner

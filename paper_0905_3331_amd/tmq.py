@@ -27,6 +27,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 MAX_RHS = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20  # TMQ_NOALLOC_SCRATCH_BYTES
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 
 TMQ_OK, TMQ_EINVAL, TMQ_ENOMEM, TMQ_ENOCONV, TMQ_EDEVICE, TMQ_ENAN, TMQ_ESTATE = 0, -1, -2, -3, -4, -5, -6
@@ -81,6 +82,7 @@ _SIGS = {
     "tmq_gauge_is_su3": (_ip, [_vp]),
     "tmq_apply_Qhat": (_ip, [_vp, _P(tmq_params), _ip, _ip, _vp, _vp]),
     "tmq_apply_Qhat_dev": (_ip, [_vp, _P(tmq_params), _ip, _ip, _vp, _vp, _vp]),
+    "tmq_apply_Qhat_noalloc_dev": (_ip, [_vp, _P(tmq_params), _ip, _ip, _vp, _vp, _vp]),
     "tmq_apply_QhatQhat_dev": (_ip, [_vp, _P(tmq_params), _vp, _vp, _vp]),
     "tmq_apply_Q_full": (_ip, [_vp, _P(tmq_params), _ip, _vp, _vp]),
     "tmq_apply_Q_full_dev": (_ip, [_vp, _P(tmq_params), _ip, _vp, _vp, _vp]),
@@ -309,6 +311,16 @@ class Lattice:
         out = torch.empty_like(src) if out is None else out
         _check(_lib.tmq_apply_Qhat_dev(self._h, ctypes.byref(p), sign, pr, _dptr(src, n, "in"),
                                        _dptr(out, n, "out"), _stream(stream)), "tmq_apply_Qhat_dev")
+        return out
+
+    def apply_Qhat_noalloc(self, p: tmq_params, sign: int, src, out, prec="fp64", stream=None):
+        """Qhat^{sign} through tmq_apply_Qhat_noalloc_dev: device tensors only, the
+        output tensor given (the call allocates nothing; its work fields are the
+        library's fixed device array)."""
+        pr = PREC[prec] if isinstance(prec, str) else int(prec)
+        n = self.V // 2 * 12
+        _check(_lib.tmq_apply_Qhat_noalloc_dev(self._h, ctypes.byref(p), sign, pr, _dptr(src, n, "in"),
+                                               _dptr(out, n, "out"), _stream(stream)), "tmq_apply_Qhat_noalloc_dev")
         return out
 
     def apply_QhatQhat(self, p: tmq_params, src, out=None, stream=None):
