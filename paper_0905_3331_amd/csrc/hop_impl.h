@@ -136,12 +136,12 @@ __device__ __forceinline__ void reconstruct_fma(spinor<float> &acc, const half<f
 
 // One hop of a 16-bit spinor (DIR 0 forward, 1 backward) from its codes and
 // scale and the loaded link: project the codes, multiply by the link, and
-// apply the site's scale (times the phase) when accumulating
-template <int MU, int DIR, class SP, class LK, typename R>
-__device__ __forceinline__ void coded_hop(const HopArgs<SP, LK> &a, const typename LK::Loaded &u,
-                                          const uint32_t (&c)[12], float sc, spinor<R> &acc)
+// apply the site's scale (times the phase when PH) when accumulating
+template <int MU, int DIR, bool PH, class SP, class LK, typename R>
+__device__ __forceinline__ void coded_hop_ph(const HopArgs<SP, LK> &a, const typename LK::Loaded &u,
+                                             const uint32_t (&c)[12], float sc, spinor<R> &acc)
 {
-    const bool phase = (a.phase_mask >> MU) & 1;  // uniform over the launch
+    constexpr bool phase = PH;
     half<R> p, w;
     project_codes<MU, DIR == 0 ? +1 : -1, SP::bf>(c, a.one, p);
     a.lk.template apply<DIR == 1>(u, p, w);
@@ -153,6 +153,16 @@ __device__ __forceinline__ void coded_hop(const HopArgs<SP, LK> &a, const typena
     } else {
         reconstruct_fma<MU, DIR == 0 ? +1 : -1>(acc, w, sc);
     }
+}
+// the same with the phase flag of direction MU read from the launch (uniform)
+template <int MU, int DIR, class SP, class LK, typename R>
+__device__ __forceinline__ void coded_hop(const HopArgs<SP, LK> &a, const typename LK::Loaded &u,
+                                          const uint32_t (&c)[12], float sc, spinor<R> &acc)
+{
+    if ((a.phase_mask >> MU) & 1)
+        coded_hop_ph<MU, DIR, true>(a, u, c, sc, acc);
+    else
+        coded_hop_ph<MU, DIR, false>(a, u, c, sc, acc);
 }
 
 // One hop of an FP64 or FP32 spinor (DIR 0 forward, 1 backward) with the
@@ -325,6 +335,109 @@ __device__ __forceinline__ void nd_mix(const HopArgs<SP, LK> &a, spinor<R> &acc,
                 acc.c[i][c3] = i < 2 ? o : -o;
             }
     }
+}
+
+// The epilogue of a half-sweep at output site h for right-hand side rhs (batch
+// index) from the hop sum acc_in: the site terms of the launch's epilogue
+// (HopEpi), then the store or the fused CG / residual update; returns |out|^2
+// when NORM (else 0).
+template <class SP, class LK, bool SELF, bool NORM, int EP, bool ND, typename R>
+__device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const spinor<R> &acc_in, int rhs, long h)
+{
+    double nrm = 0.0;
+    const int si = ND ? rhs >> 1 : rhs;  // index of the scalars
+    // epilogue coefficients of this RHS (upper spins: gamma_5 = +1, lower: -1)
+    const double kap = a.op.kappa[rhs], m = a.sign * a.op.mut[rhs];
+    cx<R> Au, Ad, Bu, Bd;
+    if (a.epi == EPI_K1) {
+        const double c = kap * kap / (1.0 + m * m);
+        Au = Ad = cx<R>{R(0), R(0)};
+        Bu = cx<R>{(R)c, (R)(-c * m)};
+        Bd = cx<R>{(R)c, (R)(c * m)};
+    } else if (a.epi == EPI_SRC) {
+        Au = Ad = cx<R>{R(1), R(0)};
+        Bu = Bd = cx<R>{(R)kap, R(0)};
+    } else if (a.epi == EPI_REC) {
+        const double c = 1.0 / (1.0 + m * m);
+        Au = cx<R>{(R)c, (R)(-c * m)};
+        Ad = cx<R>{(R)c, (R)(c * m)};
+        Bu = cx<R>{(R)(kap * c), (R)(-kap * c * m)};
+        Bd = cx<R>{(R)(kap * c), (R)(kap * c * m)};
+    } else {
+        const double b = a.epi == EPI_FULL ? kap : 1.0;
+        Au = cx<R>{R(1), (R)m};
+        Ad = cx<R>{R(-1), (R)m};
+        Bu = cx<R>{(R)(-b), R(0)};
+        Bd = cx<R>{(R)b, R(0)};
+    }
+    const spinor<R> &ac = acc_in;
+    spinor<R> o;
+    if (ND) {
+        o = ac;  // the doublet's site terms are applied already
+    } else if (SELF) {
+        spinor<R> sf;
+        a.self.at(rhs).load(h, sf);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            o.c[0][c] = fma(Au, sf.c[0][c], Bu * ac.c[0][c]);
+            o.c[1][c] = fma(Au, sf.c[1][c], Bu * ac.c[1][c]);
+            o.c[2][c] = fma(Ad, sf.c[2][c], Bd * ac.c[2][c]);
+            o.c[3][c] = fma(Ad, sf.c[3][c], Bd * ac.c[3][c]);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            o.c[0][c] = Bu * ac.c[0][c];
+            o.c[1][c] = Bu * ac.c[1][c];
+            o.c[2][c] = Bd * ac.c[2][c];
+            o.c[3][c] = Bd * ac.c[3][c];
+        }
+    }
+    if (EP == EP_CG) {
+        // CG update: x += alpha p ; r -= alpha (A p) ; |r|^2
+        using XS = typename XsOf<SP>::type;
+        using RX = typename XS::real;
+        const double al = a.scal[si].alpha;
+        const R ar = (R)al;
+        const RX ax = (RX)al;
+        spinor<R> rr, pp;
+        spinor<RX> xx;
+        a.cg_r.at(rhs).load(h, rr);
+        a.cg_p.at(rhs).load(h, pp);
+        a.cg_x.at(rhs).load(h, xx);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                xx.c[i][c].re = fmad(ax, (RX)pp.c[i][c].re, xx.c[i][c].re);
+                xx.c[i][c].im = fmad(ax, (RX)pp.c[i][c].im, xx.c[i][c].im);
+                rr.c[i][c].re = fmad(-ar, o.c[i][c].re, rr.c[i][c].re);
+                rr.c[i][c].im = fmad(-ar, o.c[i][c].im, rr.c[i][c].im);
+            }
+        a.cg_x.at(rhs).store(h, xx);
+        a.cg_r.at(rhs).store(h, rr);
+        o = rr;
+    } else if (EP == EP_RES) {
+        // true residual r = b - A x
+        spinor<R> bb;
+        a.cg_p.at(rhs).load(h, bb);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) o.c[i][c] = bb.c[i][c] - o.c[i][c];
+        a.cg_r.at(rhs).store(h, o);
+    } else {
+        a.out.at(rhs).template store<true>(h, o);
+    }
+    if (NORM) {
+        R n2 = R(0);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) n2 += norm2(o.c[i][c]);
+        nrm = (double)n2;
+    }
+    return nrm;
 }
 
 // Variant bits: ORD is the order in which an XCD's blocks walk the lattice
@@ -506,98 +619,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 #pragma unroll
         for (int gi = 0; gi < G; gi++) {
             if (!live[gi]) continue;
-            const int si = ND ? rhs[gi] >> 1 : rhs[gi];  // index of the scalars
-            // epilogue coefficients of this RHS (upper spins: gamma_5 = +1, lower: -1)
-            const double kap = a.op.kappa[rhs[gi]], m = a.sign * a.op.mut[rhs[gi]];
-            cx<R> Au, Ad, Bu, Bd;
-            if (a.epi == EPI_K1) {
-                const double c = kap * kap / (1.0 + m * m);
-                Au = Ad = cx<R>{R(0), R(0)};
-                Bu = cx<R>{(R)c, (R)(-c * m)};
-                Bd = cx<R>{(R)c, (R)(c * m)};
-            } else if (a.epi == EPI_SRC) {
-                Au = Ad = cx<R>{R(1), R(0)};
-                Bu = Bd = cx<R>{(R)kap, R(0)};
-            } else if (a.epi == EPI_REC) {
-                const double c = 1.0 / (1.0 + m * m);
-                Au = cx<R>{(R)c, (R)(-c * m)};
-                Ad = cx<R>{(R)c, (R)(c * m)};
-                Bu = cx<R>{(R)(kap * c), (R)(-kap * c * m)};
-                Bd = cx<R>{(R)(kap * c), (R)(kap * c * m)};
-            } else {
-                const double b = a.epi == EPI_FULL ? kap : 1.0;
-                Au = cx<R>{R(1), (R)m};
-                Ad = cx<R>{R(-1), (R)m};
-                Bu = cx<R>{(R)(-b), R(0)};
-                Bd = cx<R>{(R)b, R(0)};
-            }
-            const spinor<R> &ac = acc[gi];
-            spinor<R> o;
-            if (ND) {
-                o = ac;  // the doublet's site terms are applied already
-            } else if (SELF) {
-                spinor<R> sf;
-                a.self.at(rhs[gi]).load(h, sf);
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    o.c[0][c] = fma(Au, sf.c[0][c], Bu * ac.c[0][c]);
-                    o.c[1][c] = fma(Au, sf.c[1][c], Bu * ac.c[1][c]);
-                    o.c[2][c] = fma(Ad, sf.c[2][c], Bd * ac.c[2][c]);
-                    o.c[3][c] = fma(Ad, sf.c[3][c], Bd * ac.c[3][c]);
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    o.c[0][c] = Bu * ac.c[0][c];
-                    o.c[1][c] = Bu * ac.c[1][c];
-                    o.c[2][c] = Bd * ac.c[2][c];
-                    o.c[3][c] = Bd * ac.c[3][c];
-                }
-            }
-            if (EP == EP_CG) {
-                // CG update: x += alpha p ; r -= alpha (A p) ; |r|^2
-                using XS = typename XsOf<SP>::type;
-                using RX = typename XS::real;
-                const double al = a.scal[si].alpha;
-                const R ar = (R)al;
-                const RX ax = (RX)al;
-                spinor<R> rr, pp;
-                spinor<RX> xx;
-                a.cg_r.at(rhs[gi]).load(h, rr);
-                a.cg_p.at(rhs[gi]).load(h, pp);
-                a.cg_x.at(rhs[gi]).load(h, xx);
-#pragma unroll
-                for (int i = 0; i < 4; i++)
-#pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        xx.c[i][c].re = fmad(ax, (RX)pp.c[i][c].re, xx.c[i][c].re);
-                        xx.c[i][c].im = fmad(ax, (RX)pp.c[i][c].im, xx.c[i][c].im);
-                        rr.c[i][c].re = fmad(-ar, o.c[i][c].re, rr.c[i][c].re);
-                        rr.c[i][c].im = fmad(-ar, o.c[i][c].im, rr.c[i][c].im);
-                    }
-                a.cg_x.at(rhs[gi]).store(h, xx);
-                a.cg_r.at(rhs[gi]).store(h, rr);
-                o = rr;
-            } else if (EP == EP_RES) {
-                // true residual r = b - A x
-                spinor<R> bb;
-                a.cg_p.at(rhs[gi]).load(h, bb);
-#pragma unroll
-                for (int i = 0; i < 4; i++)
-#pragma unroll
-                    for (int c = 0; c < 3; c++) o.c[i][c] = bb.c[i][c] - o.c[i][c];
-                a.cg_r.at(rhs[gi]).store(h, o);
-            } else {
-                a.out.at(rhs[gi]).template store<true>(h, o);
-            }
-            if (NORM) {
-                R n2 = R(0);
-#pragma unroll
-                for (int i = 0; i < 4; i++)
-#pragma unroll
-                    for (int c = 0; c < 3; c++) n2 += norm2(o.c[i][c]);
-                nrm[gi] = (double)n2;
-            }
+            nrm[gi] = hop_epilogue<SP, LK, SELF, NORM, EP, ND>(a, acc[gi], rhs[gi], h);
         }
     }
     if (NORM) {
@@ -609,6 +631,281 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
             const double s = block_sum(nrm[gi], sh[gi]);
             if (threadIdx.x == 0) a.partial[(ND ? rhs[gi] >> 1 : rhs[gi]) * a.pstride + pidx] = s;
         }
+    }
+}
+
+// ------------------------------------------------ 16-bit single-field kernel
+//
+// 16-bit spinors with FP16 two-row links, one right-hand side (or one
+// doublet) per launch: the arithmetic of hop_kernel's two-direction preload
+// path (the same functions in the same order, so the results are identical
+// bit for bit), with
+//   * every offset 32-bit from a base that is uniform over the launch (the
+//     field of the right-hand side, the link arrays of a parity), so that a
+//     load is one instruction with a scalar base and the component blocks of
+//     a site are immediate offsets: no 64-bit address arithmetic per hop;
+//   * the boundary phases known at compile time (PM: bit mu set when direction
+//     mu carries a phase; the launch's phase mask must equal it), so the
+//     accumulation has no branches.
+// Used when every byte offset fits 32 bits (V/2 < 2^26) and PM is 0 or 1 (no
+// phase, or a phase in time only, as for antiperiodic fermions).
+
+// byte offsets: 16-bit codes (3 blocks of 16 B per site, 8-site chunks), the
+// 16-byte link block of direction 0 (4 per site), the 8-byte link block of
+// direction 0 (16-site chunks); direction mu adds mu * 128 to both link offsets
+__device__ __forceinline__ uint32_t off_codes(uint32_t h) { return ((h >> 3) * 384u) | ((h & 7u) << 4); }
+__device__ __forceinline__ uint32_t off_link16a(uint32_t h) { return ((h >> 3) << 9) | ((h & 7u) << 4); }
+__device__ __forceinline__ uint32_t off_link16b(uint32_t h) { return ((h >> 4) << 9) | ((h & 15u) << 3); }
+
+// an ordering point: the values of s are final here, and no memory access
+// moves across it (emits no instruction)
+__device__ __forceinline__ void pin_order(spinor<float> &s)
+{
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) asm volatile("" : "+v"(s.c[i][c].re), "+v"(s.c[i][c].im)::"memory");
+}
+
+template <bool NT>
+__device__ __forceinline__ uint4 ld_u4(const char *p)
+{
+    return ld<NT>((const uint4 *)p);
+}
+template <bool NT>
+__device__ __forceinline__ uint2 ld_u2(const char *p)
+{
+    return ld<NT>((const uint2 *)p);
+}
+
+// uniform bases of a launch
+struct Bases16 {
+    const char *codes, *scale;   // input field (parity out_par ^ 1)
+    const char *fa, *fb;         // links of the output parity (forward hops)
+    const char *ba, *bb;         // links of the input parity (backward hops)
+};
+
+// the loads of direction MU (both hops) into d: the link of site h (its
+// offsets oa, ob precomputed), the neighbour hf, the link of hb and the
+// neighbour hb
+template <int MU, bool NT>
+__device__ __forceinline__ void load16o(const Bases16 &B, uint32_t oa, uint32_t ob, uint32_t hf, uint32_t hb, Raw16 &d)
+{
+    {
+        const uint4 va = ld_u4<NT>(B.fa + oa + MU * 128);
+        const uint2 vb = ld_u2<NT>(B.fb + ob + MU * 128);
+        d.lw[0][0] = va.x, d.lw[0][1] = va.y, d.lw[0][2] = va.z, d.lw[0][3] = va.w, d.lw[0][4] = vb.x, d.lw[0][5] = vb.y;
+    }
+    {
+        const char *q = B.codes + off_codes(hf);
+        d.sc[0] = *(const float *)(B.scale + (hf << 2));
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint4 v = *(const uint4 *)(q + k * 128);
+            d.c[0][4 * k] = v.x, d.c[0][4 * k + 1] = v.y, d.c[0][4 * k + 2] = v.z, d.c[0][4 * k + 3] = v.w;
+        }
+    }
+    {
+        const uint4 va = ld_u4<NT>(B.ba + off_link16a(hb) + MU * 128);
+        const uint2 vb = ld_u2<NT>(B.bb + off_link16b(hb) + MU * 128);
+        d.lw[1][0] = va.x, d.lw[1][1] = va.y, d.lw[1][2] = va.z, d.lw[1][3] = va.w, d.lw[1][4] = vb.x, d.lw[1][5] = vb.y;
+    }
+    {
+        const char *q = B.codes + off_codes(hb);
+        d.sc[1] = *(const float *)(B.scale + (hb << 2));
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint4 v = *(const uint4 *)(q + k * 128);
+            d.c[1][4 * k] = v.x, d.c[1][4 * k + 1] = v.y, d.c[1][4 * k + 2] = v.z, d.c[1][4 * k + 3] = v.w;
+        }
+    }
+}
+// math16 with the phase of direction MU fixed at compile time
+template <int MU, bool PH, class SP, class LK, typename R>
+__device__ __forceinline__ void math16p(const HopArgs<SP, LK> &a, const Raw16 &d, spinor<R> &acc)
+{
+#pragma unroll
+    for (int dir = 0; dir < 2; dir++) {
+        typename LK::Loaded u;
+#pragma unroll
+        for (int k = 0; k < 6; k++) u.w[k] = d.lw[dir][k];
+        a.lk.rebuild(u);
+        if (dir == 0)
+            coded_hop_ph<MU, 0, PH>(a, u, d.c[0], d.sc[0], acc);
+        else
+            coded_hop_ph<MU, 1, PH>(a, u, d.c[1], d.sc[1], acc);
+    }
+}
+
+template <class SP, bool SELF, bool NORM, int ORD, bool SB, int EP, bool ND, int PM>
+__global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
+{
+    using LK = L16R;
+    using R = float;
+    constexpr int SPB = ND ? HOP_BLOCK / 2 : HOP_BLOCK;                    // sites per block
+    const uint32_t ls = ND ? (threadIdx.x >> 1) : threadIdx.x;             // site of the lane in the block
+    const Geom &g = a.g;
+    const int j = blockIdx.x & 7;
+    const uint32_t sb = blockIdx.x >> 3;  // site block within the XCD's share (one tuple per launch)
+    const int rhs = a.rl.idx[ND ? (int)(threadIdx.x & 1) : 0];
+    if (a.scal && a.scal[ND ? rhs >> 1 : rhs].done) return;
+    const uint32_t XH = (uint32_t)g.XH, LY = (uint32_t)g.LY, LZ = (uint32_t)g.LZ, T = (uint32_t)g.T;
+    const uint32_t plane = LY * XH;  // sites of one (t, z) plane
+    uint32_t h, t, z, y, xh, pidx;
+    bool active;
+    if (ORD == ORD_ZSLAB) {
+        const uint32_t zb = LZ >> 3, zr = LZ & 7;
+        const uint32_t zc = zb + ((uint32_t)j < zr ? 1 : 0), z0 = j * zb + ((uint32_t)j < zr ? j : zr);
+        const uint32_t S = zc * plane;  // sites of one time-slice of this slab
+        const uint32_t l = sb * SPB + ls;
+        active = l < T * S;
+        const uint32_t lu = active ? l : 0u;
+        t = lu / S;
+        const uint32_t rem = lu - t * S;
+        z = z0 + rem / plane;
+        const uint32_t r2 = rem - (z - z0) * plane;
+        y = r2 / XH;
+        xh = r2 - y * XH;
+        h = ((t * LZ + z) * LY + y) * XH + xh;
+        pidx = 8 * sb + j;
+    } else if (ORD == ORD_TSLAB) {
+        const uint32_t tb = T >> 3, tr = T & 7;
+        const uint32_t tc = tb + ((uint32_t)j < tr ? 1 : 0), t0 = j * tb + ((uint32_t)j < tr ? j : tr);
+        const uint32_t P = tc * plane;  // sites of one z-plane of this block of time-slices
+        const uint32_t l = sb * SPB + ls;
+        active = l < LZ * P;
+        const uint32_t lu = active ? l : 0u;
+        z = lu / P;
+        const uint32_t rem = lu - z * P;
+        t = t0 + rem / plane;
+        const uint32_t r2 = rem - (t - t0) * plane;
+        y = r2 / XH;
+        xh = r2 - y * XH;
+        h = ((t * LZ + z) * LY + y) * XH + xh;
+        pidx = 8 * sb + j;
+    } else {
+        const uint32_t lb = j * ((uint32_t)a.nblk >> 3) + sb;
+        h = lb * SPB + ls;
+        active = h < (uint32_t)g.vh;
+        const uint32_t hu = active ? h : 0u;
+        xh = hu % XH;
+        uint32_t r = hu / XH;
+        y = r % LY;
+        r /= LY;
+        z = r % LZ;
+        t = r / LZ;
+        pidx = lb;
+    }
+    double nrm = 0.0;
+    if (active) {
+        const int ip = a.out_par ^ 1;
+        const SP in = a.in.at(rhs);
+        const uint32_t vh = (uint32_t)g.vh, vh16q = (uint32_t)vh16(g.vh);
+        Bases16 B;
+        B.codes = (const char *)in.p;
+        B.scale = (const char *)in.scale;
+        B.fa = (const char *)(a.lk.a + (uint32_t)a.out_par * 4u * vh);
+        B.fb = (const char *)(a.lk.b + (uint32_t)a.out_par * 4u * vh16q);
+        B.ba = (const char *)(a.lk.a + (uint32_t)ip * 4u * vh);
+        B.bb = (const char *)(a.lk.b + (uint32_t)ip * 4u * vh16q);
+        const uint32_t x = 2 * xh + ((a.out_par + t + z + y) & 1);
+        const uint32_t row = h - xh;
+        const uint32_t sy = XH, sz = plane, stt = LZ * plane;
+        const uint32_t LX = (uint32_t)g.LX;
+        spinor<R> acc;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc.c[i][c] = cx<R>{R(0), R(0)};
+        const uint32_t oa = off_link16a(h), ob = off_link16b(h);
+        // neighbours (periodic), with the wrap as a select of uniform values
+        // (no branches): h +- stride -+ (extent * stride at the boundary)
+        const uint32_t tf = h + stt - (t + 1 == T ? T * stt : 0u), tb = h - stt + (t == 0 ? T * stt : 0u);
+        const uint32_t xf = row + ((x + 1 == LX ? 0u : x + 1) >> 1), xb = row + ((x == 0 ? LX - 1 : x - 1) >> 1);
+        const uint32_t yf = h + sy - (y + 1 == LY ? LY * sy : 0u), yb = h - sy + (y == 0 ? LY * sy : 0u);
+        const uint32_t zf = h + sz - (z + 1 == LZ ? LZ * sz : 0u), zb = h - sz + (z == 0 ? LZ * sz : 0u);
+        Raw16 d0, d1;
+        load16o<0, true>(B, oa, ob, tf, tb, d0);
+        load16o<1, true>(B, oa, ob, xf, xb, d1);
+        __builtin_amdgcn_sched_barrier(0);  // every load of the group issued before its arithmetic
+        math16p<0, (PM & 1) != 0>(a, d0, acc);
+        math16p<1, (PM & 2) != 0>(a, d1, acc);
+        // the loads of the other two directions after this arithmetic: two
+        // directions in flight keep the lane within 128 registers (all four at
+        // once need about 200, half the waves per SIMD).  The empty asm takes
+        // the accumulators as operands, so the arithmetic above completes
+        // before it, and clobbers memory, so the loads below stay after it.
+        pin_order(acc);
+        if (SB) __builtin_amdgcn_sched_barrier(0);
+        load16o<2, true>(B, oa, ob, yf, yb, d0);
+        load16o<3, true>(B, oa, ob, zf, zb, d1);
+        __builtin_amdgcn_sched_barrier(0);
+        math16p<2, (PM & 4) != 0>(a, d0, acc);
+        math16p<3, (PM & 8) != 0>(a, d1, acc);
+        if constexpr (ND) nd_mix(a, acc, rhs, (long)h);
+        nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND>(a, acc, rhs, (long)h);
+    }
+    if (NORM) {
+        // (doublets: the block's lanes hold both flavours, so the sum is over the doublet)
+        __shared__ double sh[HOP_BLOCK / 64];
+        const double s = block_sum(nrm, sh);
+        if (threadIdx.x == 0) a.partial[(ND ? rhs >> 1 : rhs) * a.pstride + pidx] = s;
+    }
+}
+
+// launches of hop16_kernel: the block order of the variant, the epilogue
+// flavours of go_w / go_nd, and the compile-time phase mask
+template <class SP, int ORD, bool SB, bool ND, int PM>
+void go16_e(const HopArgs<SP, L16R> &a, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
+{
+    if (ep == EP_CG)
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_CG, ND, PM>), grid, block, lds, st, a);
+    else if (ep == EP_RES)
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_RES, ND, PM>), grid, block, lds, st, a);
+    else if (s && n)
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
+    else if (s)
+        hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
+    else if (n && !ND)
+        hipLaunchKernelGGL((hop16_kernel<SP, false, true, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
+    else
+        hipLaunchKernelGGL((hop16_kernel<SP, false, false, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
+}
+template <class SP, bool ND, int PM>
+void go16_v(const HopArgs<SP, L16R> &a, int variant, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds,
+            hipStream_t st)
+{
+    switch (variant) {
+    case 1: go16_e<SP, ORD_ZSLAB, false, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
+    case 2: go16_e<SP, ORD_ZSLAB, true, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
+    case 3: go16_e<SP, ORD_TSLAB, false, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
+    case 4: go16_e<SP, ORD_TSLAB, true, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
+    default: go16_e<SP, ORD_PLAIN, false, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
+    }
+}
+// whether a single-field 16-bit launch can use hop16_kernel
+inline bool hop16_ok(const Geom &g, int phase_mask) { return g.vh < (1L << 26) && (phase_mask == 0 || phase_mask == 1); }
+
+// the launches of hop16_kernel, instantiated in hop16_f16.hip / hop16_b16.hip
+// (own translation units, compiled in parallel with the others)
+void launch_hop16(const HopArgs<SpH16, L16R> &a, bool nd, int variant, bool s, bool n, int ep, dim3 grid,
+                  dim3 block, unsigned lds, hipStream_t st);
+void launch_hop16(const HopArgs<SpB16, L16R> &a, bool nd, int variant, bool s, bool n, int ep, dim3 grid,
+                  dim3 block, unsigned lds, hipStream_t st);
+template <class SP>
+void launch_hop16_impl(const HopArgs<SP, L16R> &a, bool nd, int variant, bool s, bool n, int ep, dim3 grid,
+                       dim3 block, unsigned lds, hipStream_t st)
+{
+    if (nd) {
+        if (a.phase_mask)
+            go16_v<SP, true, 1>(a, variant, s, n, ep, grid, block, lds, st);
+        else
+            go16_v<SP, true, 0>(a, variant, s, n, ep, grid, block, lds, st);
+    } else {
+        if (a.phase_mask)
+            go16_v<SP, false, 1>(a, variant, s, n, ep, grid, block, lds, st);
+        else
+            go16_v<SP, false, 0>(a, variant, s, n, ep, grid, block, lds, st);
     }
 }
 
@@ -724,6 +1021,12 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         const dim3 grid(a.nblk * ntup), block(HOP_BLOCK);
         const int ord = variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB;
         const bool nt = ntup == 1;
+        if constexpr (ALL && SP::coded && __is_same(LK, L16R)) {
+            if (nt && hop16_ok(g, a.phase_mask)) {
+                launch_hop16(a, true, variant, s, n, ep, grid, block, tu.lds, st);
+                return hipGetLastError();
+            }
+        }
 #define GON(ORD)                                                                \
     do {                                                                        \
         if (nt)                                                                 \
@@ -779,6 +1082,12 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         if constexpr (MULTI) GOM(2);
 #undef GOM
         return hipGetLastError();
+    }
+    if constexpr (SP::coded && __is_same(LK, L16R)) {
+        if (nt && hop16_ok(g, a.phase_mask)) {
+            launch_hop16(a, false, variant, s, n, ep, grid, block, lds, st);
+            return hipGetLastError();
+        }
     }
 #define GOV(ORD, SB)                                                          \
     do {                                                                      \

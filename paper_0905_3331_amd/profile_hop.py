@@ -39,6 +39,7 @@ if ROOT not in sys.path:
 
 # sources that determine the hop kernels' memory traffic
 KERNEL_SOURCES = ("hop_impl.h", "hop.hip", "hop_f64.hip", "hop_f32.hip", "hop_f16.hip", "hop_b16.hip",
+                  "hop16_f16.hip", "hop16_b16.hip",
                   "fields.h", "spin.h", "views.h", "kernels.h", "devutil.h")
 
 
