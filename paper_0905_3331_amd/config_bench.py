@@ -42,6 +42,7 @@ against the FP64 oracle is checked by the GPU tests at these shapes.
 from __future__ import annotations
 
 import argparse
+import os
 import json
 import sys
 import time
@@ -163,6 +164,19 @@ def batch_24c48(tmq, torch, synth, reps):
     o16 = tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")
     lat.solve_batch(ps, bs, o16, xs=xs)  # tunes the FP16 batched launches
     t16, (_, inf16) = median_time(lambda: lat.solve_batch(ps, bs, o16, xs=xs), reps)
+    x16 = [x.clone() for x in xs]
+    lat.solve_batch(ps, bs, opts, xs=xs)
+    x32 = [x.clone() for x in xs]
+    # both again with the iteration bodies captured as HIP graphs (the first
+    # solve runs each body once plainly, then captures one graph per ring entry)
+    os.environ["TMQ_ENGINE_GRAPHS"] = "1"
+    lat.solve_batch(ps, bs, opts, xs=xs)
+    tg32, _ = median_time(lambda: lat.solve_batch(ps, bs, opts, xs=xs), reps)
+    same32 = all(torch.equal(a, b) for a, b in zip(xs, x32))
+    lat.solve_batch(ps, bs, o16, xs=xs)
+    tg16, _ = median_time(lambda: lat.solve_batch(ps, bs, o16, xs=xs), reps)
+    same16 = all(torch.equal(a, b) for a, b in zip(xs, x16))
+    del os.environ["TMQ_ENGINE_GRAPHS"]
     report = lat.tuning_report()
     lat.close()
     return {"lattice": "24^3x48", "nrhs": len(bs), "point_site": site,
@@ -175,6 +189,40 @@ def batch_24c48(tmq, torch, synth, reps):
             "fp16_inner_batch_ms": t16 * 1e3, "fp16_inner_iters": [f.iters for f in inf16],
             "fp16_inner_all_converged": all(f.status == 0 for f in inf16),
             "fp16_inner_max_true_rel_residual": max(f.true_rel_residual for f in inf16),
+            "hip_graph_bodies": {"fp32_inner_batch_ms": tg32 * 1e3, "fp16_inner_batch_ms": tg16 * 1e3,
+                                 "same_solutions_bit_for_bit": same32 and same16},
+            "batch_tuning": report.get("batch")}
+
+
+def batch_profile(tmq, torch, synth, reps):
+    """One tuned 48-right-hand-side batch solve of the batch workload (FP32
+    inner) for counter runs: rocprofv3 --pmc FETCH_SIZE (or WRITE_SIZE) --
+    python3 -m paper_0905_3331_amd.config_bench --only batchprof.  The copy
+    kernel runs first for the counters' calibration (1 GiB read and written)."""
+    gbs = tmq.stream_copy_gbps(1 << 30, reps=1)
+    dims = (48, 24, 24, 24)
+    lat = tmq.Lattice(dims)
+    lat.load_gauge(synth.random_gauge(dims, eps=0.3, seed=1003))
+    vh = int(np.prod(dims)) // 2
+    site = int(np.random.default_rng(2300).integers(0, vh))
+    ps, bs = [], []
+    for mut in (0.002, 0.004, 0.008, 0.016):
+        for k in range(12):
+            bs.append(torch.from_numpy(synth.point_source_odd(dims, site, k // 3, k % 3)).cuda())
+            ps.append(tmq.params(0.1632, mut, THETA))
+    opts = tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")
+    xs = [torch.empty_like(b) for b in bs]
+    lat.solve_batch(ps, bs, opts, xs=xs)  # tunes
+    lat.set_kernel_timing(True)
+    _, infos = lat.solve_batch(ps, bs, opts, xs=xs)
+    st = {k: lat.kernel_stats("hop32:" + k) for k in ("k1", "k2", "fused")}
+    lat.set_kernel_timing(False)
+    report = lat.tuning_report()
+    lat.close()
+    return {"copy_GBps": gbs, "iters": [f.iters for f in infos],
+            "fp32_half_sweeps": {k: {"launches": v["launches"], "avg_us": v["ms"] / max(v["launches"], 1) * 1e3,
+                                     "algorithmic_bytes_per_launch": v["bytes"] / max(v["launches"], 1)}
+                                 for k, v in st.items()},
             "batch_tuning": report.get("batch")}
 
 
@@ -328,6 +376,9 @@ def main(argv=None):
     if "batch" in want:
         log("24^3x48 batch of 48")
         res["batch_24c48_48rhs"] = batch_24c48(tmq, torch, synth, args.reps)
+    if "batchprof" in want:
+        log("24^3x48 batch of 48, one solve for counter runs")
+        res["batch_profile"] = batch_profile(tmq, torch, synth, args.reps)
     if "nd" in want:
         log("32^3x64 flavour doublet")
         res["doublet_32c64"] = nd_32c64(tmq, torch, synth, args.reps)

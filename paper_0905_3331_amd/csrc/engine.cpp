@@ -51,6 +51,9 @@ double engine_default_delta(int sloppy, int sloppy_link)
 Engine::~Engine()
 {
     if (st) hipStreamSynchronize(st);
+    for (auto &g : graph)
+        if (g.exec) hipGraphExecDestroy(g.exec);
+    if (cap_st) hipStreamDestroy(cap_st);
     for (auto &e : step_ev)
         if (e) hipEventDestroy(e);
     for (auto &f : fields) field_free(f);
@@ -257,20 +260,22 @@ static int body_switched(Engine *E, const RhsList &al, CgScalars *pub)
     return TMQ_OK;
 }
 
-int engine_begin_step(Engine *E)
+// the launches of one iteration body for the slots of `all` (the reduced
+// precision or FP64 operator) and `sw` (switch mode, on the reduced
+// operator), publishing their scalars to pub; every launch goes to st
+static int enqueue_body(Engine *E, const std::vector<int> &all, const std::vector<int> &sw, CgScalars *pub,
+                        hipStream_t st)
 {
-    if (E->body_pending) return TMQ_OK;
     Lattice *L = E->L;
-    std::vector<int> all = body_slots(E), sw;
-    if (E->switching) {
-        std::vector<int> keep;
-        for (int r : all) (E->slots[r].switched ? sw : keep).push_back(r);
-        all.swap(keep);
-    }
     const RhsList al = list_of(all);
-    hipStream_t st = E->st;
     CgScalars *S = E->scal;
-    CgScalars *pub = E->ring_dev + (size_t)(E->step_no % Lattice::RING) * E->cap;
+    const hipStream_t keep = E->st;
+    E->st = st;  // body_switched launches on E->st
+    struct Restore {
+        Engine *E;
+        hipStream_t s;
+        ~Restore() { E->st = s; }
+    } restore{E, keep};
     if (!sw.empty()) TMQ_TRY(body_switched(E, list_of(sw), pub));
     if (al.n > 0 && E->switching) {
         // switch mode, slots still on the FP64 operator
@@ -296,6 +301,73 @@ int engine_begin_step(Engine *E)
         TMQ_TRY(apply_Qhat_cg(L, E->op, E->tos, E->tes, E->lks, al, cg, E->partial[1], S, st));
         TMQ_HIP(launch_scalar(SC_BETA, al, E->partial[1], L->pstride, L->hop_blocks_last, S, 0, 0, true, pub, st));
     }
+    return TMQ_OK;
+}
+
+int engine_set_graphs(Engine *E, bool on)
+{
+    if (on && !E->cap_st)
+        if (hipStreamCreateWithFlags(&E->cap_st, hipStreamNonBlocking) != hipSuccess) {
+            E->cap_st = nullptr;
+            set_error("engine: capture stream creation failed");
+            return TMQ_EDEVICE;
+        }
+    E->graphs = on;
+    return TMQ_OK;
+}
+
+int engine_begin_step(Engine *E)
+{
+    if (E->body_pending) return TMQ_OK;
+    Lattice *L = E->L;
+    std::vector<int> all = body_slots(E), sw;
+    if (E->switching) {
+        std::vector<int> keep;
+        for (int r : all) (E->slots[r].switched ? sw : keep).push_back(r);
+        all.swap(keep);
+    }
+    const int ring = (int)(E->step_no % Lattice::RING);
+    CgScalars *pub = E->ring_dev + (size_t)ring * E->cap;
+    if (!E->graphs || L->timing || (all.empty() && sw.empty())) {
+        TMQ_TRY(enqueue_body(E, all, sw, pub, E->st));
+        E->body_pending = true;
+        return TMQ_OK;
+    }
+    // what the body's launches depend on besides the engine's fixed buffers
+    std::vector<double> key;
+    key.push_back((double)all.size());
+    for (int r : all) key.insert(key.end(), {(double)r, E->op.kappa[r], E->op.mut[r], E->op.eps[r]});
+    key.push_back((double)sw.size());
+    for (int r : sw) key.insert(key.end(), {(double)r, E->op.kappa[r], E->op.mut[r], E->op.eps[r]});
+    for (int mu = 0; mu < 4; mu++) key.insert(key.end(), {E->op.ph[mu][0], E->op.ph[mu][1]});
+    Engine::StepGraph &gr = E->graph[ring];
+    if (!(gr.exec && gr.key == key)) {
+        if (key != E->last_eager_key) {
+            // first time for this body: plain launches (tunes any new launch shape)
+            TMQ_TRY(enqueue_body(E, all, sw, pub, E->st));
+            E->last_eager_key = key;
+            E->body_pending = true;
+            return TMQ_OK;
+        }
+        if (gr.exec) hipGraphExecDestroy(gr.exec);
+        gr.exec = nullptr;
+        hipGraph_t g = nullptr;
+        TMQ_HIP(hipStreamBeginCapture(E->cap_st, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_body(E, all, sw, pub, E->cap_st);
+        const hipError_t ec = hipStreamEndCapture(E->cap_st, &g);
+        if (rc != TMQ_OK) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        TMQ_HIP(ec);
+        const hipError_t ei = hipGraphInstantiate(&gr.exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        TMQ_HIP(ei);
+        gr.key = key;
+        E->graph_captures++;
+    }
+    TMQ_HIP(hipGraphLaunch(gr.exec, E->st));
+    E->graph_launches++;
     E->body_pending = true;
     return TMQ_OK;
 }

@@ -76,6 +76,20 @@ struct Engine {
     long step_no = 0;           // steps begun
     bool body_pending = false;  // begin_step() done, end_step() not yet
 
+    // HIP graphs of the iteration body (engine_set_graphs): one per scalar
+    // ring entry, keyed by the body's slot lists and their parameters; a key
+    // is captured only after it ran once without a graph (so every launch
+    // shape it needs has been tuned)
+    struct StepGraph {
+        std::vector<double> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    bool graphs = false;
+    hipStream_t cap_st = nullptr;  // capture stream (default priority)
+    StepGraph graph[Lattice::RING];
+    std::vector<double> last_eager_key;
+    long graph_launches = 0, graph_captures = 0;
+
     Engine() = default;
     Engine(const Engine &) = delete;
     Engine &operator=(const Engine &) = delete;
@@ -106,6 +120,8 @@ int engine_join(Engine *E, int slot, const tmq_params &p, const tmq_solver_opts 
                 double epsbar = 0.0);
 int engine_free_slot(const Engine *E);  // a free slot, or -1
 int engine_begin_step(Engine *E);
+// Run the iteration bodies as captured HIP graphs (on) or as plain launches.
+int engine_set_graphs(Engine *E, bool on);
 // True when the scalars end_step() reads are on the host (never blocks).
 bool engine_ready(Engine *E);
 // Blocks until ready, then decides; `finished` receives the slots that ended.

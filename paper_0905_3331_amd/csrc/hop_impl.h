@@ -339,9 +339,9 @@ __device__ __forceinline__ void nd_mix(const HopArgs<SP, LK> &a, spinor<R> &acc,
 
 // The epilogue of a half-sweep at output site h for right-hand side rhs (batch
 // index) from the hop sum acc_in: the site terms of the launch's epilogue
-// (HopEpi), then the store or the fused CG / residual update; returns |out|^2
-// when NORM (else 0).
-template <class SP, class LK, bool SELF, bool NORM, int EP, bool ND, typename R>
+// (HopEpi), then the store (non-temporal when NTOUT) or the fused CG /
+// residual update; returns |out|^2 when NORM (else 0).
+template <class SP, class LK, bool SELF, bool NORM, int EP, bool ND, bool NTOUT = true, typename R>
 __device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const spinor<R> &acc_in, int rhs, long h)
 {
     double nrm = 0.0;
@@ -427,7 +427,7 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const s
             for (int c = 0; c < 3; c++) o.c[i][c] = bb.c[i][c] - o.c[i][c];
         a.cg_r.at(rhs).store(h, o);
     } else {
-        a.out.at(rhs).template store<true>(h, o);
+        a.out.at(rhs).template store<NTOUT>(h, o);
     }
     if (NORM) {
         R n2 = R(0);
@@ -843,7 +843,9 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         math16p<2, (PM & 4) != 0>(a, d0, acc);
         math16p<3, (PM & 8) != 0>(a, d1, acc);
         if constexpr (ND) nd_mix(a, acc, rhs, (long)h);
-        nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND>(a, acc, rhs, (long)h);
+        // the output is stored through the caches: the next half-sweep reads it
+        // (measured 2 % faster than non-temporal stores for both K1 and K2)
+        nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, false>(a, acc, rhs, (long)h);
     }
     if (NORM) {
         // (doublets: the block's lanes hold both flavours, so the sum is over the doublet)

@@ -66,6 +66,9 @@ int solve_batch(Lattice *L, int n, const tmq_params *p, const tmq_solver_opts &o
     TMQ_TRY(lattice_engine(L, o, n, eps != nullptr, &E));
     E->st = st;
     EngineScope scope{E};
+    // TMQ_ENGINE_GRAPHS=1: run the iteration bodies as captured HIP graphs
+    const char *eg = getenv("TMQ_ENGINE_GRAPHS");
+    TMQ_TRY(engine_set_graphs(E, eg && eg[0] == '1'));
     for (int r = 0; r < n; r++) TMQ_TRY(engine_join(E, r, p[r], o, (const double2 *)b[r], eps ? eps[r] : 0.0));
     while (engine_running(E) > 0) {
         TMQ_TRY(engine_begin_step(E));

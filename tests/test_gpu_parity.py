@@ -505,6 +505,32 @@ def test_every_hop_variant(tmq, variant, dims, monkeypatch):
 
 # --------------------------------------------------------- batched solves
 
+@pytest.mark.parametrize("sloppy", ["fp32", "fp16"])
+def test_batch_graph_bodies_equal_plain(tmq, sloppy, monkeypatch):
+    """The CG iteration bodies captured as HIP graphs (TMQ_ENGINE_GRAPHS=1) give
+    the plain launches' solutions bit for bit: over repeated solves (graphs
+    replayed), after the twisted masses change (graphs re-captured), and when
+    right-hand sides finish at different steps (the body's slot list changes)."""
+    dims = (8, 8, 6, 10)
+    lat, U = lattice(tmq, dims, seed=108)
+    link = "fp16" if sloppy == "fp16" else "fp32"
+    opts = tmq.solver_opts(tol=1e-10, sloppy=sloppy, sloppy_link=link)
+    bs = [dev(synth.gaussian_odd(dims, seed=8100 + i)) for i in range(6)]
+    for muts in ((0.004,) * 6, (0.002, 0.004, 0.008, 0.016, 0.1, 0.3)):
+        ps = [tmq.params(0.1632, m, THETA) for m in muts]
+        monkeypatch.delenv("TMQ_ENGINE_GRAPHS", raising=False)
+        plain, pinfo = lat.solve_batch(ps, bs, opts)
+        plain = [x.clone() for x in plain]
+        monkeypatch.setenv("TMQ_ENGINE_GRAPHS", "1")
+        for rep in range(3):
+            xs, infos = lat.solve_batch(ps, bs, opts)
+            for i in range(len(bs)):
+                assert torch.equal(xs[i], plain[i]), (muts, rep, i)
+                assert infos[i].iters == pinfo[i].iters and infos[i].status == 0
+        for i in (0, len(bs) - 1):
+            assert oracle.true_residual(U, host(bs[i]), host(xs[i]), 0.1632, muts[i], THETA) <= 1e-10
+
+
 @pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16"])
 def test_batch_equals_alone(tmq, sloppy):
     """12 point sources x several twisted masses in one batch; each RHS meets the
