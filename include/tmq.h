@@ -460,7 +460,8 @@ void tmq_server_destroy(tmq_server *srv);
 /* ---------------------------------------------------------- diagnostics */
 
 /* Per-kernel timing with HIP events recorded on the launch stream around each
- * hopping half-sweep launch, off by default.  tmq_set_kernel_timing
+ * hopping half-sweep launch (timing-only events, without the system-scope
+ * cache writeback a default event performs), off by default.  tmq_set_kernel_timing
  * synchronises the device and clears the records.  tmq_kernel_stats returns,
  * for the launches recorded since then, their number, total time in ms, and
  * the algorithmic bytes and flops they move (each input spinor, link and

@@ -914,8 +914,10 @@ int tmq_stream_copy(int device, size_t bytes, int reps, double *gbps)
     if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
         set_error("tmq_stream_copy: allocation failed");
         status = TMQ_ENOMEM;
-    } else if (hipMemset(a, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-               hipEventCreate(&e1) != hipSuccess || launch_stream_copy(a, b, bytes, nullptr) != hipSuccess ||
+    } else if (hipMemset(a, 0, bytes) != hipSuccess ||
+               hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+               hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess ||
+               launch_stream_copy(a, b, bytes, nullptr) != hipSuccess ||
                hipEventRecord(e0, nullptr) != hipSuccess) {
         set_error("tmq_stream_copy: HIP call failed");
         status = TMQ_EDEVICE;

@@ -332,8 +332,11 @@ static hipEvent_t pool_event(Lattice *L)
         L->event_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence when the event completes (the
+    // default one writes back and invalidates the caches, which lengthens
+    // the measured interval and makes the next kernel start cold)
     hipEvent_t e = nullptr;
-    hipEventCreate(&e);
+    hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
 }
 
@@ -653,6 +656,11 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
             TMQ_TRY(tune_batch(L, key, cls, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st,
                                &tu));
         if (L->forced_rpl) tu.rpl = L->forced_rpl;
+        // TMQ_HOP_GROUP (diagnostics): right-hand sides per L2 group of batched launches
+        if (const char *fg = getenv("TMQ_HOP_GROUP")) {
+            const int gsz = atoi(fg);
+            if (gsz >= 1 && gsz <= MAX_RHS) tu.group = gsz;
+        }
     }
     TimedLaunch t{};
     if (L->timing) {

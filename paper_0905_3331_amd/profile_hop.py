@@ -51,8 +51,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def is_hop(name: str) -> bool:
+    """A hop half-sweep kernel: the general hop_kernel or the 16-bit single-field hop16_kernel."""
+    return "hop_kernel<" in name or "hop16_kernel<" in name
+
+
 def hop_family(name: str):
-    if "hop_kernel" not in name:
+    if not is_hop(name):
         return None
     if "Sp16" in name:
         return "hop16"
@@ -64,13 +69,15 @@ def hop_family(name: str):
 
 
 def hop_template_args(name: str):
-    """Template arguments of a hop_kernel instantiation, in order: spinor format,
-    link format, SELF, NORM, NT, ORD, SB, G, EP, ND (as text)."""
-    i = name.find("hop_kernel<")
+    """Template arguments of a hop kernel instantiation, as text, in order:
+    hop_kernel: spinor format, link format, SELF, NORM, NT, ORD, SB, G, EP, ND;
+    hop16_kernel: spinor format, SELF, NORM, ORD, SB, EP, ND, PM."""
+    key = "hop16_kernel<" if "hop16_kernel<" in name else "hop_kernel<"
+    i = name.find(key)
     if i < 0:
         return None
     depth, cur, args = 0, "", []
-    for ch in name[i + len("hop_kernel<"):]:
+    for ch in name[i + len(key):]:
         if ch == "<":
             depth += 1
         elif ch == ">":
@@ -91,9 +98,12 @@ def hop_part(name: str):
     parity: K1 of eq. (eo3)), "k2" (K2 of eq. (eo4) storing its output),
     "fused" (K2 with the CG update or the true residual fused), or None."""
     a = hop_template_args(name)
-    if not a or len(a) < 10:
+    if a and "hop16_kernel<" in name and len(a) == 8:
+        self_, ep = a[1] == "true", a[5]
+    elif a and len(a) >= 10:
+        self_, ep = a[2] == "true", a[8]
+    else:
         return None
-    self_, ep = a[2] == "true", a[8]
     if ep != "0":
         return "fused"
     return "k2" if self_ else "k1"
@@ -105,6 +115,36 @@ def _counter_rows(path, counter):
         if r["Counter_Name"] == counter:
             out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
     return out
+
+
+def traffic_markdown(res, title, algorithmic=None):
+    """Markdown of a traffic summary (summarize_pmc's result): the family and
+    half-sweep averages, then every instantiation.  algorithmic: optional
+    {family or part: algorithmic bytes per launch} printed beside them."""
+    algorithmic = algorithmic or {}
+    lines = [f"# {title}", "", "Commands (GPU box, repo root; one pass per counter):", "", "    " + res["command"], "",
+             f"Calibration: the plain copy kernel (k_stream_copy) reads and writes {res['copy_bytes']} bytes per launch; "
+             f"HBM read bytes = FETCH_SIZE x 1024 x {res['fetch_scale']:.4f}, write bytes = WRITE_SIZE x 1024 x "
+             f"{res['write_scale']:.4f}.", "",
+             f"Kernel sources hash: {res['kernel_hash']} (bench.py reports these figures as `roofline.traffic` only while "
+             "the hash matches the sources).", "",
+             "| family or half-sweep | dispatches (fetch, write) | HBM read MB/launch | HBM write MB/launch | "
+             "total MB/launch | algorithmic MB/launch |", "|---|---|---|---|---|---|"]
+    for k in sorted(x for x in res if x.startswith("hop")):
+        d = res[k]
+        alg = algorithmic.get(k)
+        lines.append(f"| {k} | {d['dispatches'][0]}, {d['dispatches'][1]} | {d['read_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{d['write_bytes_per_launch'] / 1e6:.1f} | {d['hbm_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{'%.1f' % (alg / 1e6) if alg else '-'} |")
+    lines += ["", "Per instantiation (the few-dispatch rows are autotuner candidates):", "",
+              "| kernel | dispatches | read MB | write MB |", "|---|---|---|---|"]
+    for k in sorted(res["per_kernel"]):
+        v = res["per_kernel"][k]
+        name = k.replace("tmq::", "").split("(")[0]
+        lines.append(f"| `{name}` | {v.get('dispatches', 0)} | {v.get('read_bytes_per_launch', 0) / 1e6:.1f} | "
+                     f"{v.get('write_bytes_per_launch', 0) / 1e6:.1f} |")
+    lines.append("")
+    return "\n".join(lines)
 
 
 def summarize_pmc(fetch_csv, write_csv, copy_bytes, cmd, out):
@@ -208,7 +248,7 @@ def summarize_valu(counter_csv, cmd, out, xcds=8, simds=1024, min_dispatches=20)
     disp = collections.defaultdict(set)
     for r in csv.DictReader(open(counter_csv)):
         k = r["Kernel_Name"]
-        if "hop_kernel" not in k:
+        if not is_hop(k):
             continue
         acc[k][r["Counter_Name"]] += float(r["Counter_Value"])
         disp[k].add(r["Dispatch_Id"])

@@ -113,3 +113,40 @@ def test_summarize_trace_family_averages(tmp_path):
     assert fam["hop16"].split("|")[2].strip() == "104"
     assert float(fam["hop16"].split("|")[3]) == pytest.approx(6.4e6 / 104 / 1e3, abs=0.01)
     assert float(fam["hop64"].split("|")[3]) == pytest.approx(220.0, abs=0.01)
+
+
+H16K1 = "void tmq::hop16_kernel<tmq::Sp16<false>, false, false, 1, true, 0, false, 1>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
+H16K2 = "void tmq::hop16_kernel<tmq::Sp16<false>, true, true, 1, true, 0, false, 1>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
+H16CG = "void tmq::hop16_kernel<tmq::Sp16<false>, true, true, 1, true, 1, false, 1>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
+GK2 = "void tmq::hop_kernel<tmq::SpF64, tmq::L64R, true, true, true, 1, false, 1, 0, false>(args)"
+GRES = "void tmq::hop_kernel<tmq::SpF64, tmq::L64R, true, true, true, 1, false, 1, 2, false>(args)"
+
+
+def test_hop_parts_of_both_kernels():
+    """The half-sweep kind is read from the template arguments of either kernel:
+    K1 (no own-parity site term), K2 (storing its output), fused (CG or residual)."""
+    assert profile_hop.hop_family(H16K1) == "hop16" and profile_hop.hop_family(F64) == "hop64"
+    assert [profile_hop.hop_part(k) for k in (H16K1, H16K2, H16CG)] == ["k1", "k2", "fused"]
+    assert [profile_hop.hop_part(k) for k in (F64, GK2, GRES)] == ["k1", "k2", "fused"]
+    assert profile_hop.hop_part(COPY) is None and profile_hop.hop_family(COPY) is None
+
+
+def test_summarize_pmc_parts(tmp_path):
+    """Family averages split into ":pure" (K1 and K2), ":k1", ":k2", ":fused"."""
+    copy_bytes = 1 << 30
+    fetch = [(COPY, "FETCH_SIZE", copy_bytes / 2 / 1024)] * 2
+    write = [(COPY, "WRITE_SIZE", copy_bytes / 1024)] * 2
+    fetch += [(H16K1, "FETCH_SIZE", 100.0)] * 20 + [(H16K2, "FETCH_SIZE", 200.0)] * 10 + [(H16CG, "FETCH_SIZE", 400.0)] * 10
+    write += [(H16K1, "WRITE_SIZE", 10.0)] * 20 + [(H16K2, "WRITE_SIZE", 10.0)] * 10 + [(H16CG, "WRITE_SIZE", 30.0)] * 10
+    _write(tmp_path / "f.csv", fetch)
+    _write(tmp_path / "w.csv", write)
+    out = tmp_path / "t.json"
+    profile_hop.summarize_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), copy_bytes, "cmd", str(out))
+    d = json.load(open(out))
+    k = 1024.0
+    assert d["hop16:k1"]["read_bytes_per_launch"] == pytest.approx(200.0 * k)
+    assert d["hop16:k2"]["read_bytes_per_launch"] == pytest.approx(400.0 * k)
+    assert d["hop16:fused"]["write_bytes_per_launch"] == pytest.approx(30.0 * k)
+    # pure: 20 K1 and 10 K2 launches averaged per launch
+    assert d["hop16:pure"]["read_bytes_per_launch"] == pytest.approx((20 * 200.0 + 10 * 400.0) / 30 * k)
+    assert d["hop16:pure"]["dispatches"] == [30, 30]
