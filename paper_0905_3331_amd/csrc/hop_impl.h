@@ -337,11 +337,38 @@ __device__ __forceinline__ void nd_mix(const HopArgs<SP, LK> &a, spinor<R> &acc,
     }
 }
 
+// K2 of eq. (eo4) with the own-site term first: out = g5[(1 + s i mut g5) self - H]
+// is Au self - H on the upper spins and Ad self + H on the lower (Au = 1 + s i mut,
+// Ad = -1 + s i mut, H the hop sum), so the accumulator starts from -Au self
+// (upper) and Ad self (lower), the hops are added to it, and the epilogue only
+// flips the sign of the upper spins.  The own-site spinor is then dead before the hops, which keeps the
+// half-sweep within fewer registers; every K2 store launch, single-field or
+// batched, sums in this order, so their results agree bit for bit.
+template <typename R, class SP, class LK>
+__device__ __forceinline__ spinor<R> k2_self_first(const HopArgs<SP, LK> &a, int rhs, long h)
+{
+    spinor<R> sf, acc;
+    a.self.at(rhs).load(h, sf);
+    const double m = a.sign * a.op.mut[rhs];
+    const cx<R> Au = cx<R>{R(1), (R)m}, Ad = cx<R>{R(-1), (R)m};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        acc.c[0][c] = -(Au * sf.c[0][c]);
+        acc.c[1][c] = -(Au * sf.c[1][c]);
+        acc.c[2][c] = Ad * sf.c[2][c];
+        acc.c[3][c] = Ad * sf.c[3][c];
+    }
+    return acc;
+}
+
 // The epilogue of a half-sweep at output site h for right-hand side rhs (batch
 // index) from the hop sum acc_in: the site terms of the launch's epilogue
 // (HopEpi), then the store (non-temporal when NTOUT) or the fused CG /
-// residual update; returns |out|^2 when NORM (else 0).
-template <class SP, class LK, bool SELF, bool NORM, int EP, bool ND, bool NTOUT = true, typename R>
+// residual update; returns |out|^2 when NORM (else 0).  PRESELF: the launch is
+// EPI_K2 and acc_in already holds the own-site term (k2_self_first), so out =
+// B acc with B = -1 on the upper spins and +1 on the lower.
+template <class SP, class LK, bool SELF, bool NORM, int EP, bool ND, bool NTOUT = true, bool PRESELF = false,
+          typename R>
 __device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const spinor<R> &acc_in, int rhs, long h)
 {
     double nrm = 0.0;
@@ -374,6 +401,14 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const s
     spinor<R> o;
     if (ND) {
         o = ac;  // the doublet's site terms are applied already
+    } else if (PRESELF) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            o.c[0][c] = -ac.c[0][c];
+            o.c[1][c] = -ac.c[1][c];
+            o.c[2][c] = ac.c[2][c];
+            o.c[3][c] = ac.c[3][c];
+        }
     } else if (SELF) {
         spinor<R> sf;
         a.self.at(rhs).load(h, sf);
@@ -551,13 +586,20 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         const long row = h - xh;  // eo index of (t, z, y, 0)
         const long sy = g.XH, sz = plane, stt = (long)g.LZ * plane;
 
+        // K2 store launches start from the own-site term (k2_self_first)
+        const bool pre = SELF && !ND && EP == EP_STORE && a.epi == EPI_K2;
         spinor<R> acc[G];
 #pragma unroll
-        for (int gi = 0; gi < G; gi++)
+        for (int gi = 0; gi < G; gi++) {
+            if (pre && live[gi]) {
+                acc[gi] = k2_self_first<R>(a, rhs[gi], h);
+                continue;
+            }
 #pragma unroll
             for (int i = 0; i < 4; i++)
 #pragma unroll
                 for (int c = 0; c < 3; c++) acc[gi].c[i][c] = cx<R>{R(0), R(0)};
+        }
 
         // forward and backward neighbours in t, x, y, z (periodic), formed where used
         auto f0 = [&] { return t + 1 == g.T ? h - (g.T - 1) * stt : h + stt; };
@@ -619,7 +661,8 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
 #pragma unroll
         for (int gi = 0; gi < G; gi++) {
             if (!live[gi]) continue;
-            nrm[gi] = hop_epilogue<SP, LK, SELF, NORM, EP, ND>(a, acc[gi], rhs[gi], h);
+            nrm[gi] = pre ? hop_epilogue<SP, LK, SELF, NORM, EP, ND, true, true>(a, acc[gi], rhs[gi], h)
+                          : hop_epilogue<SP, LK, SELF, NORM, EP, ND, true, false>(a, acc[gi], rhs[gi], h);
         }
     }
     if (NORM) {
@@ -737,7 +780,8 @@ __device__ __forceinline__ void math16p(const HopArgs<SP, LK> &a, const Raw16 &d
     }
 }
 
-template <class SP, bool SELF, bool NORM, int ORD, bool SB, int EP, bool ND, int PM>
+// K2F: a K2 store launch (a.epi == EPI_K2), which starts from the own-site term
+template <class SP, bool SELF, bool NORM, int ORD, bool SB, int EP, bool ND, int PM, bool K2F = false>
 __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
 {
     using LK = L16R;
@@ -813,10 +857,26 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         const uint32_t sy = XH, sz = plane, stt = LZ * plane;
         const uint32_t LX = (uint32_t)g.LX;
         spinor<R> acc;
+        if constexpr (K2F) {
+            // the operations of k2_self_first, written out: through the
+            // helper the compiler keeps about 30 more registers live here
+            spinor<R> sf;
+            a.self.at(rhs).load((long)h, sf);
+            const double m = a.sign * a.op.mut[rhs];
+            const cx<R> Au = cx<R>{R(1), (R)m}, Ad = cx<R>{R(-1), (R)m};
 #pragma unroll
-        for (int i = 0; i < 4; i++)
+            for (int c = 0; c < 3; c++) {
+                acc.c[0][c] = -(Au * sf.c[0][c]);
+                acc.c[1][c] = -(Au * sf.c[1][c]);
+                acc.c[2][c] = Ad * sf.c[2][c];
+                acc.c[3][c] = Ad * sf.c[3][c];
+            }
+        } else {
 #pragma unroll
-            for (int c = 0; c < 3; c++) acc.c[i][c] = cx<R>{R(0), R(0)};
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) acc.c[i][c] = cx<R>{R(0), R(0)};
+        }
         const uint32_t oa = off_link16a(h), ob = off_link16b(h);
         // neighbours (periodic), with the wrap as a select of uniform values
         // (no branches): h +- stride -+ (extent * stride at the boundary)
@@ -845,7 +905,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         if constexpr (ND) nd_mix(a, acc, rhs, (long)h);
         // the output is stored through the caches: the next half-sweep reads it
         // (measured 2 % faster than non-temporal stores for both K1 and K2)
-        nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, false>(a, acc, rhs, (long)h);
+        nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, false, K2F>(a, acc, rhs, (long)h);
     }
     if (NORM) {
         // (doublets: the block's lanes hold both flavours, so the sum is over the doublet)
@@ -864,7 +924,13 @@ void go16_e(const HopArgs<SP, L16R> &a, bool s, bool n, int ep, dim3 grid, dim3 
         hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_CG, ND, PM>), grid, block, lds, st, a);
     else if (ep == EP_RES)
         hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_RES, ND, PM>), grid, block, lds, st, a);
-    else if (s && n)
+    else if (s && !ND && a.epi == EPI_K2) {
+        if (n)
+            hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM, true>), grid, block, lds, st, a);
+        else
+            hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM, true>), grid, block, lds, st,
+                               a);
+    } else if (s && n)
         hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
     else if (s)
         hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
