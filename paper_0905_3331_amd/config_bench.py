@@ -194,6 +194,45 @@ def batch_24c48(tmq, torch, synth, reps):
             "batch_tuning": report.get("batch")}
 
 
+def batch_sweep(tmq, torch, synth, reps):
+    """The batched FP32 half-sweeps of 48 right-hand sides at 24^3x48 for every
+    block order (z-slabs, t-slabs, plain) and RHS group size: short solves
+    (three iterations) with the variant and group forced (TMQ_HOP_VARIANT,
+    TMQ_HOP_GROUP), each preceded by a 1 MiB copy-kernel launch pair that
+    marks it in a counter run (profile_hop --summarize-batch-sweep), and its
+    half-sweeps timed with events.  Under rocprofv3 --pmc FETCH_SIZE this
+    gives each configuration's HBM reads per launch."""
+    dims = (48, 24, 24, 24)
+    vh = int(np.prod(dims)) // 2
+    U = synth.random_gauge(dims, eps=0.3, seed=1003)
+    bs = [torch.from_numpy(synth.gaussian_odd(dims, seed=5000 + i)).cuda() for i in range(48)]
+    ps = [tmq.params(0.1632, 0.002 * (1 + i % 4), THETA) for i in range(48)]
+    opts = tmq.solver_opts(tol=1e-14, sloppy="fp32", sloppy_link="fp32", max_iter=3)
+    rows = []
+    for var in (1, 3, 0):
+        os.environ["TMQ_HOP_VARIANT"] = str(var)
+        lat = tmq.Lattice(dims)
+        lat.load_gauge(U)
+        for g in (1, 2, 4, 8, 16, 32, 48):
+            os.environ["TMQ_HOP_GROUP"] = str(g)
+            lat.solve_batch(ps, bs, opts, check=False)  # tunes (first time) and warms
+            tmq.stream_copy_gbps(1 << 20, reps=1)       # marker
+            lat.set_kernel_timing(True)
+            lat.solve_batch(ps, bs, opts, check=False)
+            st = {k: lat.kernel_stats("hop32:" + k) for k in ("k1", "k2", "fused")}
+            lat.set_kernel_timing(False)
+            rows.append({"variant": var, "group": g,
+                         **{f"{k}_us": v["ms"] / max(v["launches"], 1) * 1e3 for k, v in st.items()},
+                         **{f"{k}_algorithmic_bytes": v["bytes"] / max(v["launches"], 1) for k, v in st.items()}})
+            # reads of a K1 launch: its bytes less the 48 FP32 outputs it writes
+            rows[-1]["k1_algorithmic_read_bytes"] = rows[-1]["k1_algorithmic_bytes"] - 48 * vh * 96.0
+            log(f"variant {var} group {g}: K1 {rows[-1]['k1_us']:.0f} us")
+        del os.environ["TMQ_HOP_GROUP"]
+        lat.close()
+    del os.environ["TMQ_HOP_VARIANT"]
+    return {"lattice": "24^3x48", "nrhs": 48, "rows": rows}
+
+
 def batch_profile(tmq, torch, synth, reps):
     """One tuned 48-right-hand-side batch solve of the batch workload (FP32
     inner) for counter runs: rocprofv3 --pmc FETCH_SIZE (or WRITE_SIZE) --
@@ -376,6 +415,9 @@ def main(argv=None):
     if "batch" in want:
         log("24^3x48 batch of 48")
         res["batch_24c48_48rhs"] = batch_24c48(tmq, torch, synth, args.reps)
+    if "batchsweep" in want:
+        log("24^3x48 batch of 48, block orders x RHS groups")
+        res["batch_sweep"] = batch_sweep(tmq, torch, synth, args.reps)
     if "batchprof" in want:
         log("24^3x48 batch of 48, one solve for counter runs")
         res["batch_profile"] = batch_profile(tmq, torch, synth, args.reps)

@@ -71,7 +71,7 @@ def hop_family(name: str):
 def hop_template_args(name: str):
     """Template arguments of a hop kernel instantiation, as text, in order:
     hop_kernel: spinor format, link format, SELF, NORM, NT, ORD, SB, G, EP, ND;
-    hop16_kernel: spinor format, SELF, NORM, ORD, SB, EP, ND, PM."""
+    hop16_kernel: spinor format, SELF, NORM, ORD, SB, EP, ND, PM, K2F."""
     key = "hop16_kernel<" if "hop16_kernel<" in name else "hop_kernel<"
     i = name.find(key)
     if i < 0:
@@ -98,7 +98,7 @@ def hop_part(name: str):
     parity: K1 of eq. (eo3)), "k2" (K2 of eq. (eo4) storing its output),
     "fused" (K2 with the CG update or the true residual fused), or None."""
     a = hop_template_args(name)
-    if a and "hop16_kernel<" in name and len(a) == 8:
+    if a and "hop16_kernel<" in name and len(a) >= 8:
         self_, ep = a[1] == "true", a[5]
     elif a and len(a) >= 10:
         self_, ep = a[2] == "true", a[8]
@@ -276,6 +276,54 @@ def summarize_valu(counter_csv, cmd, out, xcds=8, simds=1024, min_dispatches=20)
     print("\n".join(lines))
 
 
+def summarize_batch_sweep(fetch_csv, sweep_json, cmd, out):
+    """HBM reads per launch of the batched FP32 half-sweeps of each (block
+    order, RHS group) configuration of config_bench's batchsweep section: the
+    dispatches after each copy-kernel marker pair belong to the next row of
+    the sweep (in order); reads are scaled by the marker copy's own reading."""
+    res = json.load(open(sweep_json))
+    rows = res["batch_sweep"]["rows"] if "batch_sweep" in res else res["rows"]
+    disp = collections.OrderedDict()
+    for r in csv.DictReader(open(fetch_csv)):
+        if r["Counter_Name"] != "FETCH_SIZE":
+            continue
+        d = int(r["Dispatch_Id"])
+        disp.setdefault(d, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+    seq = [disp[d] for d in sorted(disp)]
+    copies = [v for k, v in seq if "k_stream_copy" in k]
+    if not copies:
+        raise SystemExit("no copy-kernel markers in the counter file")
+    scale = (1 << 20) / (sorted(copies)[len(copies) // 2] * 1024.0)  # the 1 MiB marker copies
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    ci, prev = -1, False
+    for k, v in seq:
+        if "k_stream_copy" in k:
+            ci += not prev
+            prev = True
+            continue
+        prev = False
+        part = hop_part(k)
+        if ci >= 0 and hop_family(k) == "hop32" and part:
+            acc[ci][part].append(v * 1024.0 * scale)
+    lines = ["# Batched FP32 half-sweeps, 48 right-hand sides at 24^3x48: block order x RHS group", "",
+             "Commands (GPU box; the sweep, then one counter pass over the same sweep):", "", "    " + cmd, "",
+             f"Kernel sources hash: {kernel_hash()}.  Reads scaled by the 1 MiB marker copies (x {scale:.4f}); "
+             "times from events in a run without the profiler.", "",
+             "| block order | RHS group | K1 us | K2 us | fused K2 us | K1 HBM read MB | K1 algorithmic read MB | ratio |",
+             "|---|---|---|---|---|---|---|---|"]
+    names = {1: "z-slabs", 3: "t-slabs", 0: "plain"}
+    for i, r in enumerate(rows):
+        k1 = acc[i].get("k1", [])
+        rd = sum(k1) / len(k1) if k1 else float("nan")
+        alg = r.get("k1_algorithmic_read_bytes", float("nan"))
+        lines.append(f"| {names.get(r['variant'], r['variant'])} | {r['group']} | {r['k1_us']:.0f} | {r['k2_us']:.0f} | "
+                     f"{r['fused_us']:.0f} | {rd / 1e6:.0f} | {alg / 1e6:.0f} | {rd / alg:.2f} |")
+    lines.append("")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--dims", default="64,32,32,32", help="T,LZ,LY,LX")
@@ -285,6 +333,7 @@ def main():
     ap.add_argument("--summarize-trace", metavar="STATS_CSV")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--summarize-valu", metavar="COUNTER_CSV")
+    ap.add_argument("--summarize-batch-sweep", nargs=2, metavar=("FETCH_CSV", "SWEEP_JSON"))
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--cmd", default="")
     ap.add_argument("--out")
@@ -293,6 +342,8 @@ def main():
         return summarize_trace(args.summarize_trace, args.cmd, args.out)
     if args.summarize_valu:
         return summarize_valu(args.summarize_valu, args.cmd, args.out)
+    if args.summarize_batch_sweep:
+        return summarize_batch_sweep(args.summarize_batch_sweep[0], args.summarize_batch_sweep[1], args.cmd, args.out)
     if args.summarize_pmc:
         return summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.copy_bytes, args.cmd, args.out)
 

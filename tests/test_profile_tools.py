@@ -116,7 +116,7 @@ def test_summarize_trace_family_averages(tmp_path):
 
 
 H16K1 = "void tmq::hop16_kernel<tmq::Sp16<false>, false, false, 1, true, 0, false, 1>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
-H16K2 = "void tmq::hop16_kernel<tmq::Sp16<false>, true, true, 1, true, 0, false, 1>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
+H16K2 = "void tmq::hop16_kernel<tmq::Sp16<false>, true, true, 1, true, 0, false, 1, true>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
 H16CG = "void tmq::hop16_kernel<tmq::Sp16<false>, true, true, 1, true, 1, false, 1>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
 GK2 = "void tmq::hop_kernel<tmq::SpF64, tmq::L64R, true, true, true, 1, false, 1, 0, false>(args)"
 GRES = "void tmq::hop_kernel<tmq::SpF64, tmq::L64R, true, true, true, 1, false, 1, 2, false>(args)"
@@ -150,3 +150,22 @@ def test_summarize_pmc_parts(tmp_path):
     # pure: 20 K1 and 10 K2 launches averaged per launch
     assert d["hop16:pure"]["read_bytes_per_launch"] == pytest.approx((20 * 200.0 + 10 * 400.0) / 30 * k)
     assert d["hop16:pure"]["dispatches"] == [30, 30]
+
+
+def test_summarize_batch_sweep_attributes_dispatches(tmp_path):
+    """Each configuration's half-sweeps are the dispatches after its marker copy pair."""
+    sweep = {"rows": [{"variant": 1, "group": 8, "k1_us": 1.0, "k2_us": 2.0, "fused_us": 3.0,
+                       "k1_algorithmic_read_bytes": 1000.0 * 1024},
+                      {"variant": 0, "group": 48, "k1_us": 1.0, "k2_us": 2.0, "fused_us": 3.0,
+                       "k1_algorithmic_read_bytes": 1000.0 * 1024}]}
+    K1_32 = "void tmq::hop_kernel<tmq::SpF32, tmq::L32R, false, false, false, 1, false, 1, 0, false>(args)"
+    marker = (1 << 20) / 1024.0  # KiB the 1 MiB marker copy reads (scale 1)
+    rows = [(COPY, "FETCH_SIZE", marker)] * 2 + [(K1_32, "FETCH_SIZE", 2000.0)] * 3
+    rows += [(COPY, "FETCH_SIZE", marker)] * 2 + [(K1_32, "FETCH_SIZE", 3000.0)] * 3
+    _write(tmp_path / "f.csv", rows)
+    (tmp_path / "s.json").write_text(json.dumps(sweep))
+    out = tmp_path / "o.md"
+    profile_hop.summarize_batch_sweep(str(tmp_path / "f.csv"), str(tmp_path / "s.json"), "cmd", str(out))
+    text = out.read_text()
+    assert "| z-slabs | 8 | 1 | 2 | 3 | 2 | 1 | 2.00 |" in text
+    assert "| plain | 48 | 1 | 2 | 3 | 3 | 1 | 3.00 |" in text
