@@ -492,8 +492,12 @@ int tmq_stream_copy(int device, size_t bytes, int reps, double *gbps);
  * scheduling barriers between directions; 3 each XCD walks its own range of
  * time-slices z-plane by z-plane (needs T >= 8); 4 as 3 with barriers.  The
  * tuner runs at the first launch of each format on a lattice;
- * TMQ_HOP_VARIANT=0..4 in the environment forces a variant, and then
- * TMQ_HOP_CAP=0..5 a cap.  TMQ_EINVAL if buf (len bytes) is too small. */
+ * TMQ_HOP_VARIANT=0..4 in the environment forces a variant and
+ * TMQ_HOP_CAP=0..5 a cap (single-field and batched launches).  Batched
+ * launches list, per (format, power-of-two batch size class), the RHS per
+ * lane, the RHS group and the cap picked, the time of the picked shape under
+ * each cap tried, and every (RHS per lane, group, us) tried.  TMQ_EINVAL if
+ * buf (len bytes) is too small. */
 int tmq_tuning_report(tmq_lattice *lat, char *buf, size_t len);
 
 /* Encode n_sites canonical complex128 sites (12 complex each) into the device

@@ -177,6 +177,8 @@ int lattice_create(const int dims[4], int device, Lattice **out)
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess &&
         lds > 0)
         L->lds_per_cu = lds;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        L->lds_per_block = lds;
     // per RHS: at least as many partials as any hop variant or vector kernel writes
     L->pstride = hop_grid(2 * L->g.vh) + 64;
     for (auto &p : L->partial)
@@ -341,12 +343,12 @@ static hipEvent_t pool_event(Lattice *L)
 }
 
 // LDS bytes per block that let at most c blocks share a CU (0: no cap);
-// ~0u when that needs more than a block may reserve (64 KB)
+// ~0u when that needs more than a block may reserve
 static unsigned occ_lds(const Lattice *L, int c)
 {
     if (c <= 0) return 0;
     const unsigned b = (unsigned)(L->lds_per_cu / (c + 1)) + 256u;
-    return b > 65536u ? ~0u : b;
+    return b > (unsigned)L->lds_per_block ? ~0u : b;
 }
 
 // Time every valid variant of this hop launch (same operands, the reduction
@@ -391,7 +393,7 @@ static int tune_hop(Lattice *L, int key, int out_par, const FieldDesc &in, const
     // flight per XCD: a smaller working set in its L2)
     int occ = 0;
     L->hop_occ_us[key][0] = best_us;
-    for (int c = 2; c <= 5; c++) {
+    for (int c = 1; c <= 5; c++) {
         const unsigned lds = occ_lds(L, c);
         if (lds == ~0u) continue;
         float us = 0.f;
@@ -416,8 +418,9 @@ static bool multi_rhs_format(int prec, int link_fmt)
 }
 
 // For a batched launch, time the RHS per lane (1, or 2 where the format has
-// them) and RHS groups (the variant and cap fixed), and keep the fastest for
-// this format and batch size class.  Neither changes any result.
+// them) and RHS groups (the variant and cap of the single-field tuning), then
+// caps on the resident blocks per CU for the fastest of those, and keep the
+// fastest for this format and batch size class.  None changes any result.
 static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc &in, const FieldDesc &self,
                       const FieldDesc &out, const LinkDesc &lk, const OpParams &op, int epi, int sign,
                       const RhsList &rl, bool norm, hipStream_t st, HopTune *res)
@@ -430,7 +433,20 @@ static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc
     HopTune base;
     base.variant = L->hop_variant[key];
     base.lds = occ_lds(L, L->hop_occ[key]);
+    bt.cap = L->hop_occ[key];
     float best_us = 0.f;
+    auto time_one = [&](const HopTune &tu, float *us) -> int {
+        TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
+        TMQ_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 2; r++)
+            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
+        TMQ_HIP(hipEventRecord(e1, st));
+        TMQ_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        *us = ms * 1e3f / 2;
+        return TMQ_OK;
+    };
     const int max_rpl = multi_rhs_format(in.prec, lk.fmt) ? 2 : 1;
     for (int rpl = 1; rpl <= max_rpl && rpl <= rl.n; rpl *= 2)
         for (int G = rpl;; G *= 2) {
@@ -438,16 +454,8 @@ static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc
             HopTune tu = base;
             tu.rpl = rpl;
             tu.group = G;
-            TMQ_HIP(launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
-            TMQ_HIP(hipEventRecord(e0, st));
-            for (int r = 0; r < 2; r++)
-                TMQ_HIP(
-                    launch_hop(L->g, out_par, in, self, out, lk, op, epi, sign, rl, tp, L->pstride, nullptr, tu, st));
-            TMQ_HIP(hipEventRecord(e1, st));
-            TMQ_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            TMQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-            const float us = ms * 1e3f / 2;
+            float us = 0.f;
+            TMQ_TRY(time_one(tu, &us));
             bt.tried.push_back({(float)rpl, (float)G, us});
             if (best_us == 0.f || us < best_us) {
                 bt.tu = tu;
@@ -455,6 +463,26 @@ static int tune_batch(Lattice *L, int key, int cls, int out_par, const FieldDesc
             }
             if (G == rl.n) break;
         }
+    // fewer resident blocks shrink the set of (site, RHS) pairs in flight per
+    // XCD, whose neighbour spinors compete for its L2
+    bt.cap_us[bt.cap] = best_us;
+    if (L->forced_cap < 0) {
+        const HopTune shape = bt.tu;
+        for (int c = 0; c <= 5; c++) {
+            if (c == bt.cap) continue;
+            HopTune tu = shape;
+            tu.lds = occ_lds(L, c);
+            if (tu.lds == ~0u) continue;
+            float us = 0.f;
+            TMQ_TRY(time_one(tu, &us));
+            bt.cap_us[c] = us;
+            if (us < best_us) {
+                bt.tu = tu;
+                bt.cap = c;
+                best_us = us;
+            }
+        }
+    }
     L->event_pool.push_back(e0);
     L->event_pool.push_back(e1);
     *res = bt.tu;
@@ -494,9 +522,14 @@ std::string tuning_report(const Lattice *L)
         char buf[256];
         snprintf(buf, sizeof(buf),
                  "%s{\"spinor\": \"%s\", \"links\": \"%s\", \"nrhs_class\": %d, \"rhs_per_lane\": %d, "
-                 "\"group\": %d, \"tried\": [",
-                 i ? ", " : "", pn[b.key / N_LINK_FMT], ln[b.key % N_LINK_FMT], b.cls, b.tu.rpl, b.tu.group);
+                 "\"group\": %d, \"blocks_per_cu_cap\": %d, \"cap_us\": [",
+                 i ? ", " : "", pn[b.key / N_LINK_FMT], ln[b.key % N_LINK_FMT], b.cls, b.tu.rpl, b.tu.group, b.cap);
         s += buf;
+        for (int c = 0; c < 6; c++) {
+            snprintf(buf, sizeof(buf), "%s%.1f", c ? ", " : "", b.cap_us[c]);
+            s += buf;
+        }
+        s += "], \"tried\": [";
         for (size_t j = 0; j < b.tried.size(); j++) {
             snprintf(buf, sizeof(buf), "%s[%d, %d, %.1f]", j ? ", " : "", (int)b.tried[j][0], (int)b.tried[j][1],
                      b.tried[j][2]);
@@ -560,7 +593,6 @@ static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc 
     const int key = in.prec * N_LINK_FMT + lk.fmt;
     if (L->forced_variant >= 0) {
         L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;
-        if (L->forced_cap >= 0) L->hop_occ[key] = occ_lds(L, L->forced_cap) == ~0u ? 0 : L->forced_cap;
     } else if (L->hop_variant[key] < 0) {
         if (fused) {
             set_error("internal: fused hop epilogue before the format was tuned");
@@ -574,6 +606,7 @@ static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc 
         one.idx[0] = fl.idx[0];
         TMQ_TRY(tune_hop(L, key, out_par, fi, fs, fo, lk, o1, epi, sign, one, false, st));
     }
+    if (L->forced_cap >= 0) L->hop_occ[key] = occ_lds(L, L->forced_cap) == ~0u ? 0 : L->forced_cap;
     HopTune tu;
     tu.variant = L->hop_variant[key];
     tu.lds = occ_lds(L, L->hop_occ[key]);
@@ -629,12 +662,11 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
         L->hop_blocks_last = hop_grid_variant(L->g, hop_all_variants(in.prec, lk.fmt) ? tu.variant : 0);
         return TMQ_OK;
     }
-    if (L->forced_variant >= 0) {
+    if (L->forced_variant >= 0)
         L->hop_variant[key] = hop_variant_valid(L->g, L->forced_variant) ? L->forced_variant : 0;
-        if (L->forced_cap >= 0) L->hop_occ[key] = occ_lds(L, L->forced_cap) == ~0u ? 0 : L->forced_cap;
-    }
     else if (L->hop_variant[key] < 0)
         TMQ_TRY(tune_hop(L, key, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st));
+    if (L->forced_cap >= 0) L->hop_occ[key] = occ_lds(L, L->forced_cap) == ~0u ? 0 : L->forced_cap;
     // batches use the launch shape tuned for their power-of-two size class
     HopTune tu;
     tu.variant = L->hop_variant[key];
@@ -656,6 +688,7 @@ int hop(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc &self, con
             TMQ_TRY(tune_batch(L, key, cls, out_par, in, self, out, lk, op, epi, sign, rl, partial != nullptr, st,
                                &tu));
         if (L->forced_rpl) tu.rpl = L->forced_rpl;
+        if (L->forced_cap >= 0) tu.lds = occ_lds(L, L->forced_cap) == ~0u ? 0 : occ_lds(L, L->forced_cap);
         // TMQ_HOP_GROUP (diagnostics): right-hand sides per L2 group of batched launches
         if (const char *fg = getenv("TMQ_HOP_GROUP")) {
             const int gsz = atoi(fg);

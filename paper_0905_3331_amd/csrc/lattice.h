@@ -105,12 +105,15 @@ struct Lattice {
     int hop_occ[NKEY];
     float hop_occ_us[NKEY][6];
     int lds_per_cu = 65536;
+    int lds_per_block = 65536;  // largest LDS reservation of one block
     // autotuned launch shape of batched hops, per (spinor precision, link
     // format) key and power-of-two batch size class
     struct BatchTune {
         int key, cls;
         HopTune tu;
+        int cap = 0;                              // blocks-per-CU cap of tu (0: none)
         std::vector<std::array<float, 3>> tried;  // (RHS per lane, group, us per launch)
+        float cap_us[6] = {-1.f, -1.f, -1.f, -1.f, -1.f, -1.f};  // the chosen shape per cap
     };
     std::vector<BatchTune> hop_batch;
     int hop_blocks_last = 0;  // blocks (partial sums) of the last hop launch
