@@ -811,18 +811,37 @@ __device__ __forceinline__ void math16h(const HopArgs<SP, LK> &a, const Hop16 &d
     coded_hop_ph<MU, DIR, PH>(a, u, d.c, d.sc, acc);
 }
 
-// K2F: a K2 store launch (a.epi == EPI_K2), which starts from the own-site term
-template <class SP, bool SELF, bool NORM, int ORD, bool SB, int EP, bool ND, int PM, bool K2F = false>
+// K2F: a K2 store launch (a.epi == EPI_K2), which starts from the own-site term.
+// BATCH: the launch covers several tuples (right-hand sides, or doublets), one
+// per block, in the RHS groups of hop_kernel, with the link loads cached (the
+// blocks of a group read the same links); otherwise one tuple, links streamed.
+template <class SP, bool SELF, bool NORM, int ORD, bool SB, int EP, bool ND, int PM, bool K2F = false,
+          bool BATCH = false>
 __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
 {
     using LK = L16R;
     using R = float;
+    constexpr bool LNT = !BATCH;                                           // links non-temporal
     constexpr int SPB = ND ? HOP_BLOCK / 2 : HOP_BLOCK;                    // sites per block
     const uint32_t ls = ND ? (threadIdx.x >> 1) : threadIdx.x;             // site of the lane in the block
     const Geom &g = a.g;
     const int j = blockIdx.x & 7;
-    const uint32_t sb = blockIdx.x >> 3;  // site block within the XCD's share (one tuple per launch)
-    const int rhs = a.rl.idx[ND ? (int)(threadIdx.x & 1) : 0];
+    uint32_t sb;  // site block within the XCD's share
+    int tup;      // tuple of the block
+    if constexpr (BATCH) {
+        const int k = blockIdx.x >> 3;
+        const int nb = a.nblk >> 3;
+        const int ntup = ND ? a.rl.n / 2 : a.rl.n;
+        const int GR = a.group, gr = k / (nb * GR);
+        const int gsize = min(GR, ntup - gr * GR);  // the last group may be smaller
+        const int within = k - gr * nb * GR;
+        sb = (uint32_t)(within / gsize);
+        tup = gr * GR + (within - (int)sb * gsize);
+    } else {
+        sb = blockIdx.x >> 3;
+        tup = 0;
+    }
+    const int rhs = a.rl.idx[ND ? 2 * tup + (int)(threadIdx.x & 1) : tup];
     if (a.scal && a.scal[ND ? rhs >> 1 : rhs].done) return;
     const uint32_t XH = (uint32_t)g.XH, LY = (uint32_t)g.LY, LZ = (uint32_t)g.LZ, T = (uint32_t)g.T;
     const uint32_t plane = LY * XH;  // sites of one (t, z) plane
@@ -920,40 +939,40 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
             // two hops ahead, within 96 registers (5 waves per SIMD; the
             // grouping below measured 10 % slower for them)
             Hop16 b0, b1;
-            load16h<0, 0, true>(B, oa, ob, tf, b0);
-            load16h<0, 1, true>(B, oa, ob, tb, b1);
+            load16h<0, 0, LNT>(B, oa, ob, tf, b0);
+            load16h<0, 1, LNT>(B, oa, ob, tb, b1);
             __builtin_amdgcn_sched_barrier(0);
             math16h<0, 0, (PM & 1) != 0>(a, b0, acc);
             pin_order(acc);
-            load16h<1, 0, true>(B, oa, ob, xf, b0);
+            load16h<1, 0, LNT>(B, oa, ob, xf, b0);
             __builtin_amdgcn_sched_barrier(0);
             math16h<0, 1, (PM & 1) != 0>(a, b1, acc);
             pin_order(acc);
-            load16h<1, 1, true>(B, oa, ob, xb, b1);
+            load16h<1, 1, LNT>(B, oa, ob, xb, b1);
             __builtin_amdgcn_sched_barrier(0);
             math16h<1, 0, (PM & 2) != 0>(a, b0, acc);
             pin_order(acc);
-            load16h<2, 0, true>(B, oa, ob, yf, b0);
+            load16h<2, 0, LNT>(B, oa, ob, yf, b0);
             __builtin_amdgcn_sched_barrier(0);
             math16h<1, 1, (PM & 2) != 0>(a, b1, acc);
             pin_order(acc);
-            load16h<2, 1, true>(B, oa, ob, yb, b1);
+            load16h<2, 1, LNT>(B, oa, ob, yb, b1);
             __builtin_amdgcn_sched_barrier(0);
             math16h<2, 0, (PM & 4) != 0>(a, b0, acc);
             pin_order(acc);
-            load16h<3, 0, true>(B, oa, ob, zf, b0);
+            load16h<3, 0, LNT>(B, oa, ob, zf, b0);
             __builtin_amdgcn_sched_barrier(0);
             math16h<2, 1, (PM & 4) != 0>(a, b1, acc);
             pin_order(acc);
-            load16h<3, 1, true>(B, oa, ob, zb, b1);
+            load16h<3, 1, LNT>(B, oa, ob, zb, b1);
             __builtin_amdgcn_sched_barrier(0);
             math16h<3, 0, (PM & 8) != 0>(a, b0, acc);
             math16h<3, 1, (PM & 8) != 0>(a, b1, acc);
         } else {
             // one flavour: two directions (four hops) loaded at a time
             Raw16 d0, d1;
-            load16o<0, true>(B, oa, ob, tf, tb, d0);
-            load16o<1, true>(B, oa, ob, xf, xb, d1);
+            load16o<0, LNT>(B, oa, ob, tf, tb, d0);
+            load16o<1, LNT>(B, oa, ob, xf, xb, d1);
             __builtin_amdgcn_sched_barrier(0);  // every load of the group issued before its arithmetic
             math16p<0, (PM & 1) != 0>(a, d0, acc);
             math16p<1, (PM & 2) != 0>(a, d1, acc);
@@ -964,16 +983,18 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
             // before it, and clobbers memory, so the loads below stay after it.
             pin_order(acc);
             if (SB) __builtin_amdgcn_sched_barrier(0);
-            load16o<2, true>(B, oa, ob, yf, yb, d0);
-            load16o<3, true>(B, oa, ob, zf, zb, d1);
+            load16o<2, LNT>(B, oa, ob, yf, yb, d0);
+            load16o<3, LNT>(B, oa, ob, zf, zb, d1);
             __builtin_amdgcn_sched_barrier(0);
             math16p<2, (PM & 4) != 0>(a, d0, acc);
             math16p<3, (PM & 8) != 0>(a, d1, acc);
         }
         if constexpr (ND) nd_mix(a, acc, rhs, (long)h);
-        // the output is stored through the caches: the next half-sweep reads it
-        // (measured 2 % faster than non-temporal stores for both K1 and K2)
-        nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, false, K2F>(a, acc, rhs, (long)h);
+        // one tuple: the output is stored through the caches, since the next
+        // half-sweep reads it (measured 2 % faster than non-temporal stores for
+        // both K1 and K2); a batch's outputs are read again only after the
+        // whole batch, so they are stored non-temporally
+        nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acc, rhs, (long)h);
     }
     if (NORM) {
         // (doublets: the block's lanes hold both flavours, so the sum is over the doublet)
@@ -984,64 +1005,83 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
 }
 
 // launches of hop16_kernel: the block order of the variant, the epilogue
-// flavours of go_w / go_nd, and the compile-time phase mask
-template <class SP, int ORD, bool SB, bool ND, int PM>
+// flavours of go_w / go_nd, the compile-time phase mask, and single-tuple or
+// batched (BATCH) launches
+template <class SP, int ORD, bool SB, bool ND, int PM, bool BATCH>
 void go16_e(const HopArgs<SP, L16R> &a, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
     if (ep == EP_CG)
-        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_CG, ND, PM>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_CG, ND, PM, false, BATCH>), grid, block, lds, st,
+                           a);
     else if (ep == EP_RES)
-        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_RES, ND, PM>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_RES, ND, PM, false, BATCH>), grid, block, lds,
+                           st, a);
     else if (s && !ND && a.epi == EPI_K2) {
         if (n)
-            hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM, true>), grid, block, lds, st, a);
+            hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM, true, BATCH>), grid, block,
+                               lds, st, a);
         else
-            hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM, true>), grid, block, lds, st,
-                               a);
+            hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM, true, BATCH>), grid, block,
+                               lds, st, a);
     } else if (s && n)
-        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM, false, BATCH>), grid, block, lds,
+                           st, a);
     else if (s)
-        hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM, false, BATCH>), grid, block, lds,
+                           st, a);
     else if (n && !ND)
-        hipLaunchKernelGGL((hop16_kernel<SP, false, true, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop16_kernel<SP, false, true, ORD, SB, EP_STORE, ND, PM, false, BATCH>), grid, block, lds,
+                           st, a);
     else
-        hipLaunchKernelGGL((hop16_kernel<SP, false, false, ORD, SB, EP_STORE, ND, PM>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((hop16_kernel<SP, false, false, ORD, SB, EP_STORE, ND, PM, false, BATCH>), grid, block,
+                           lds, st, a);
 }
-template <class SP, bool ND, int PM>
+template <class SP, bool ND, int PM, bool BATCH>
 void go16_v(const HopArgs<SP, L16R> &a, int variant, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds,
             hipStream_t st)
 {
     switch (variant) {
-    case 1: go16_e<SP, ORD_ZSLAB, false, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
-    case 2: go16_e<SP, ORD_ZSLAB, true, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
-    case 3: go16_e<SP, ORD_TSLAB, false, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
-    case 4: go16_e<SP, ORD_TSLAB, true, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
-    default: go16_e<SP, ORD_PLAIN, false, ND, PM>(a, s, n, ep, grid, block, lds, st); break;
+    case 1: go16_e<SP, ORD_ZSLAB, false, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
+    case 2: go16_e<SP, ORD_ZSLAB, true, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
+    case 3: go16_e<SP, ORD_TSLAB, false, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
+    case 4: go16_e<SP, ORD_TSLAB, true, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
+    default: go16_e<SP, ORD_PLAIN, false, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
     }
 }
-// whether a single-field 16-bit launch can use hop16_kernel
+// whether a 16-bit launch can use hop16_kernel
 inline bool hop16_ok(const Geom &g, int phase_mask) { return g.vh < (1L << 26) && (phase_mask == 0 || phase_mask == 1); }
 
 // the launches of hop16_kernel, instantiated in hop16_f16.hip / hop16_b16.hip
-// (own translation units, compiled in parallel with the others)
-void launch_hop16(const HopArgs<SpH16, L16R> &a, bool nd, int variant, bool s, bool n, int ep, dim3 grid,
-                  dim3 block, unsigned lds, hipStream_t st);
-void launch_hop16(const HopArgs<SpB16, L16R> &a, bool nd, int variant, bool s, bool n, int ep, dim3 grid,
-                  dim3 block, unsigned lds, hipStream_t st);
+// (own translation units, compiled in parallel with the others); batch: more
+// than one tuple (right-hand side or doublet) in the launch
+void launch_hop16(const HopArgs<SpH16, L16R> &a, bool nd, bool batch, int variant, bool s, bool n, int ep,
+                  dim3 grid, dim3 block, unsigned lds, hipStream_t st);
+void launch_hop16(const HopArgs<SpB16, L16R> &a, bool nd, bool batch, int variant, bool s, bool n, int ep,
+                  dim3 grid, dim3 block, unsigned lds, hipStream_t st);
 template <class SP>
-void launch_hop16_impl(const HopArgs<SP, L16R> &a, bool nd, int variant, bool s, bool n, int ep, dim3 grid,
-                       dim3 block, unsigned lds, hipStream_t st)
+void launch_hop16_impl(const HopArgs<SP, L16R> &a, bool nd, bool batch, int variant, bool s, bool n, int ep,
+                       dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
-    if (nd) {
+    if (nd && batch) {
         if (a.phase_mask)
-            go16_v<SP, true, 1>(a, variant, s, n, ep, grid, block, lds, st);
+            go16_v<SP, true, 1, true>(a, variant, s, n, ep, grid, block, lds, st);
         else
-            go16_v<SP, true, 0>(a, variant, s, n, ep, grid, block, lds, st);
+            go16_v<SP, true, 0, true>(a, variant, s, n, ep, grid, block, lds, st);
+    } else if (nd) {
+        if (a.phase_mask)
+            go16_v<SP, true, 1, false>(a, variant, s, n, ep, grid, block, lds, st);
+        else
+            go16_v<SP, true, 0, false>(a, variant, s, n, ep, grid, block, lds, st);
+    } else if (batch) {
+        if (a.phase_mask)
+            go16_v<SP, false, 1, true>(a, variant, s, n, ep, grid, block, lds, st);
+        else
+            go16_v<SP, false, 0, true>(a, variant, s, n, ep, grid, block, lds, st);
     } else {
         if (a.phase_mask)
-            go16_v<SP, false, 1>(a, variant, s, n, ep, grid, block, lds, st);
+            go16_v<SP, false, 1, false>(a, variant, s, n, ep, grid, block, lds, st);
         else
-            go16_v<SP, false, 0>(a, variant, s, n, ep, grid, block, lds, st);
+            go16_v<SP, false, 0, false>(a, variant, s, n, ep, grid, block, lds, st);
     }
 }
 
@@ -1158,8 +1198,8 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         const int ord = variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB;
         const bool nt = ntup == 1;
         if constexpr (ALL && SP::coded && __is_same(LK, L16R)) {
-            if (nt && hop16_ok(g, a.phase_mask)) {
-                launch_hop16(a, true, variant, s, n, ep, grid, block, tu.lds, st);
+            if (hop16_ok(g, a.phase_mask)) {
+                launch_hop16(a, true, !nt, variant, s, n, ep, grid, block, tu.lds, st);
                 return hipGetLastError();
             }
         }
@@ -1220,8 +1260,9 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         return hipGetLastError();
     }
     if constexpr (SP::coded && __is_same(LK, L16R)) {
-        if (nt && hop16_ok(g, a.phase_mask)) {
-            launch_hop16(a, false, variant, s, n, ep, grid, block, lds, st);
+        // one RHS per lane: the 16-bit kernel, for one RHS or a batch
+        if (hop16_ok(g, a.phase_mask)) {
+            launch_hop16(a, false, !nt, variant, s, n, ep, grid, block, lds, st);
             return hipGetLastError();
         }
     }

@@ -555,6 +555,37 @@ def test_batch_equals_alone(tmq, sloppy):
         assert infos[i].status == 0 and res <= 1e-10, (i, res)
 
 
+@pytest.mark.parametrize("cap", [1, 3])
+def test_batch_blocks_per_cu_cap(tmq, cap, monkeypatch):
+    """A cap on the resident blocks per CU (the batch tuner tries them per
+    size class; TMQ_HOP_CAP forces one) changes only how many blocks share a
+    CU: a 9-RHS FP32-inner batch (a ragged last group) equals the uncapped
+    batch bit for bit, and the cap is the one the tuning report shows."""
+    dims = (8, 8, 6, 10)
+    U = synth.random_gauge(dims, seed=131)
+    bs = [dev(synth.gaussian_odd(dims, seed=7800 + k)) for k in range(9)]
+    ps = [tmq.params(0.1632, 0.002 * (1 + k % 3), THETA) for k in range(9)]
+    opts = tmq.solver_opts(tol=1e-10, sloppy="fp32", sloppy_link="fp32")
+    runs = []
+    for forced in (None, cap):
+        if forced is None:
+            monkeypatch.delenv("TMQ_HOP_CAP", raising=False)
+        else:
+            monkeypatch.setenv("TMQ_HOP_CAP", str(forced))
+        lat = tmq.Lattice(dims)
+        lat.load_gauge(U)
+        xs, infos = lat.solve_batch(ps, bs, opts)
+        runs.append(([x.clone() for x in xs], [i.iters for i in infos]))
+        if forced is not None:
+            rep = lat.tuning_report()
+            assert all(e["blocks_per_cu_cap"] == forced for e in rep["hop"]), rep["hop"]
+        lat.close()
+    for i in range(len(bs)):
+        assert torch.equal(runs[0][0][i], runs[1][0][i]), f"rhs {i} differs under cap {cap}"
+        assert runs[0][1][i] == runs[1][1][i]
+    assert oracle.true_residual(U, host(bs[8]), host(runs[1][0][8]), 0.1632, 0.006, THETA) <= 1e-10
+
+
 @pytest.mark.parametrize("sloppy", ["fp32", "fp16"])
 def test_batch_random_parameters(tmq, sloppy):
     """A batch whose right-hand sides each have their own random kappa and
