@@ -478,12 +478,13 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const s
 }
 
 // The order in which a half-sweep sums its directions (t, x, y, z = 0..3):
-// t, x, y, z, except for K1 of 16-bit spinors (no own-site term), which takes
-// x, y, t, z.  The 16-bit kernel loads two directions at a time in this order,
-// and its K1 measured 2.5 % faster at 32^3x64 with the x and y neighbours (the
-// nearest in memory) in the first group; its K2 was 1 % slower that way.
-// Every kernel sums in this order, so a batch equals its solves alone bit for
-// bit whichever kernel runs each.
+// t, x, y, z, except for K1 (no own-site term) of 16-bit and FP64 spinors,
+// which takes x, y, t, z.  The 16-bit kernel loads two directions at a time in
+// this order, and its K1 measured 2.5 % faster at 32^3x64 with the x and y
+// neighbours (the nearest in memory) in the first group, FP64 K1 1.6 %
+// faster; 16-bit K2 was 1 % slower that way, FP32 K1 1.4 % slower.  Every
+// kernel sums in this order, so a batch equals its solves alone bit for bit
+// whichever kernel runs each.
 template <bool XY_FIRST>
 __host__ __device__ constexpr int k1_order(int i)
 {
@@ -626,8 +627,8 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
         auto f3 = [&] { return z + 1 == g.LZ ? h - (g.LZ - 1) * sz : h + sz; };
         auto b3 = [&] { return z == 0 ? h + (g.LZ - 1) * sz : h - sz; };
         // the directions in the order of the sum (K1_ORDER), neighbours by index
-        constexpr int D0 = k1_order<SP::coded && !SELF>(0), D1 = k1_order<SP::coded && !SELF>(1),
-                      D2 = k1_order<SP::coded && !SELF>(2), D3 = k1_order<SP::coded && !SELF>(3);
+        constexpr bool XY1 = (SP::coded || __is_same(SP, SpF64)) && !SELF;
+        constexpr int D0 = k1_order<XY1>(0), D1 = k1_order<XY1>(1), D2 = k1_order<XY1>(2), D3 = k1_order<XY1>(3);
         auto fn = [&](auto m) -> long {
             constexpr int M = decltype(m)::value;
             if constexpr (M == 0) return f0();
