@@ -714,12 +714,12 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop_kernel(HopArgs<SP, LK> a)
     }
 }
 
-// ------------------------------------------------ 16-bit single-field kernel
+// ---------------------------------------------------------- 16-bit kernel
 //
 // 16-bit spinors with FP16 two-row links, one right-hand side (or one
-// doublet) per launch: the arithmetic of hop_kernel's two-direction preload
-// path (the same functions in the same order, so the results are identical
-// bit for bit), with
+// doublet) per lane, for single fields and batches (BATCH): the arithmetic of
+// hop_kernel's 16-bit paths (the same functions, the directions in the order
+// of k1_order, so the results are identical bit for bit), with
 //   * every offset 32-bit from a base that is uniform over the launch (the
 //     field of the right-hand side, the link arrays of a parity), so that a
 //     load is one instruction with a scalar base and the component blocks of

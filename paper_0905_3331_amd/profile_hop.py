@@ -31,6 +31,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -43,16 +44,26 @@ KERNEL_SOURCES = ("hop_impl.h", "hop.hip", "hop_f64.hip", "hop_f32.hip", "hop_f1
                   "fields.h", "spin.h", "views.h", "kernels.h", "devutil.h")
 
 
+def code_text(src: str) -> str:
+    """The code of a C++ source without its comments and blank lines, so that
+    editing a comment leaves the kernel hash unchanged (string literals in
+    these sources hold no comment markers)."""
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in src.splitlines())
+    return "\n".join(ln for ln in lines if ln.strip())
+
+
 def kernel_hash() -> str:
+    """Hash of the code (comments aside) of the sources that make the hop kernels."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_0905_3331_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0905_3331_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
 def is_hop(name: str) -> bool:
-    """A hop half-sweep kernel: the general hop_kernel or the 16-bit single-field hop16_kernel."""
+    """A hop half-sweep kernel: the general hop_kernel or the 16-bit hop16_kernel."""
     return "hop_kernel<" in name or "hop16_kernel<" in name
 
 

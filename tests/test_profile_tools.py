@@ -169,3 +169,12 @@ def test_summarize_batch_sweep_attributes_dispatches(tmp_path):
     text = out.read_text()
     assert "| z-slabs | 8 | 1 | 2 | 3 | 2 | 1 | 2.00 |" in text
     assert "| plain | 48 | 1 | 2 | 3 | 3 | 1 | 3.00 |" in text
+
+
+def test_kernel_hash_ignores_comments():
+    """The kernel hash covers code, not comments: a comment edit keeps it, a code edit changes it."""
+    src = "int a = 1;  // one\n/* block\n comment */\nint b = 2;\n\n"
+    assert profile_hop.code_text(src) == "int a = 1;\nint b = 2;"
+    assert profile_hop.code_text(src.replace("one", "two")) == profile_hop.code_text(src)
+    assert profile_hop.code_text(src.replace("2;", "3;")) != profile_hop.code_text(src)
+
