@@ -82,7 +82,7 @@ def hop_family(name: str):
 def hop_template_args(name: str):
     """Template arguments of a hop kernel instantiation, as text, in order:
     hop_kernel: spinor format, link format, SELF, NORM, NT, ORD, SB, G, EP, ND;
-    hop16_kernel: spinor format, SELF, NORM, ORD, SB, EP, ND, PM, K2F."""
+    hop16_kernel: spinor format, SELF, NORM, ORD, SB, EP, ND, PM, K2F, BATCH."""
     key = "hop16_kernel<" if "hop16_kernel<" in name else "hop_kernel<"
     i = name.find(key)
     if i < 0:

@@ -118,6 +118,10 @@ def test_summarize_trace_family_averages(tmp_path):
 H16K1 = "void tmq::hop16_kernel<tmq::Sp16<false>, false, false, 1, true, 0, false, 1>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
 H16K2 = "void tmq::hop16_kernel<tmq::Sp16<false>, true, true, 1, true, 0, false, 1, true>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
 H16CG = "void tmq::hop16_kernel<tmq::Sp16<false>, true, true, 1, true, 1, false, 1>(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)"
+H16BK1 = ("void tmq::hop16_kernel<tmq::Sp16<false>, false, false, 2, false, 0, false, 1, false, true>"
+          "(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)")
+H16BCG = ("void tmq::hop16_kernel<tmq::Sp16<false>, true, true, 1, true, 1, false, 1, false, true>"
+          "(tmq::HopArgs<tmq::Sp16<false>, tmq::L16R>)")
 GK2 = "void tmq::hop_kernel<tmq::SpF64, tmq::L64R, true, true, true, 1, false, 1, 0, false>(args)"
 GRES = "void tmq::hop_kernel<tmq::SpF64, tmq::L64R, true, true, true, 1, false, 1, 2, false>(args)"
 
@@ -127,6 +131,7 @@ def test_hop_parts_of_both_kernels():
     K1 (no own-parity site term), K2 (storing its output), fused (CG or residual)."""
     assert profile_hop.hop_family(H16K1) == "hop16" and profile_hop.hop_family(F64) == "hop64"
     assert [profile_hop.hop_part(k) for k in (H16K1, H16K2, H16CG)] == ["k1", "k2", "fused"]
+    assert [profile_hop.hop_part(k) for k in (H16BK1, H16BCG)] == ["k1", "fused"]  # batched launches
     assert [profile_hop.hop_part(k) for k in (F64, GK2, GRES)] == ["k1", "k2", "fused"]
     assert profile_hop.hop_part(COPY) is None and profile_hop.hop_family(COPY) is None
 
