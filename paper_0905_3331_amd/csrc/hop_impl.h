@@ -848,10 +848,92 @@ __device__ __forceinline__ void math16h(const HopArgs<SP, LK> &a, const Hop16 &d
     coded_hop_ph<MU, DIR, PH>(a, u, d.c, d.sc, acc);
 }
 
+// The loads of one hop of a doublet site for both flavours: the link once and
+// the neighbour codes and scales of each flavour (codes and scales of the
+// lower flavour from its own bases)
+struct Hop16N {
+    uint32_t lw[6];
+    uint32_t c[2][12];
+    float sc[2];
+};
+template <int MU, int DIR, bool NT>
+__device__ __forceinline__ void load16n(const Bases16 &B, const char *codes_d, const char *scale_d, uint32_t oa,
+                                        uint32_t ob, uint32_t hn, Hop16N &d)
+{
+    const uint4 va = DIR == 0 ? ld_u4<NT>(B.fa + oa + MU * 128) : ld_u4<NT>(B.ba + off_link16a(hn) + MU * 128);
+    const uint2 vb = DIR == 0 ? ld_u2<NT>(B.fb + ob + MU * 128) : ld_u2<NT>(B.bb + off_link16b(hn) + MU * 128);
+    d.lw[0] = va.x, d.lw[1] = va.y, d.lw[2] = va.z, d.lw[3] = va.w, d.lw[4] = vb.x, d.lw[5] = vb.y;
+#pragma unroll
+    for (int f = 0; f < 2; f++) {
+        const char *q = (f == 0 ? B.codes : codes_d) + off_codes(hn);
+        d.sc[f] = *(const float *)((f == 0 ? B.scale : scale_d) + (hn << 2));
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint4 v = *(const uint4 *)(q + k * 128);
+            d.c[f][4 * k] = v.x, d.c[f][4 * k + 1] = v.y, d.c[f][4 * k + 2] = v.z, d.c[f][4 * k + 3] = v.w;
+        }
+    }
+}
+// the hop for both flavours: row 2 of the link formed once, then each
+// flavour's projection, product and accumulation as for one flavour
+template <int MU, int DIR, bool PH, class SP, class LK, typename R>
+__device__ __forceinline__ void math16n(const HopArgs<SP, LK> &a, const Hop16N &d, spinor<R> &au, spinor<R> &ad)
+{
+    typename LK::Loaded u;
+#pragma unroll
+    for (int k = 0; k < 6; k++) u.w[k] = d.lw[k];
+    a.lk.rebuild(u);
+    coded_hop_ph<MU, DIR, PH>(a, u, d.c[0], d.sc[0], au);
+    coded_hop_ph<MU, DIR, PH>(a, u, d.c[1], d.sc[1], ad);
+}
+
+// nd_mix for both flavours of a site held by one lane (au upper, ad lower
+// flavour of doublet rhs_u >> 1): the same operations, the partner's values
+// taken from the other accumulator instead of the other lane
+template <class SP, class LK, typename R>
+__device__ __forceinline__ void nd_mix2(const HopArgs<SP, LK> &a, spinor<R> &au, spinor<R> &ad, int rhs_u, int rhs_d,
+                                        long h)
+{
+    const int d = rhs_u >> 1;
+    const double kap = a.op.kappa[d], m = a.sign * a.op.mut[d], e = a.op.eps[d];
+    if (a.epi == EPI_K1) {
+        const double c = kap * kap / (1.0 + m * m - e * e);
+        const cx<R> pm = {(R)c, (R)(-c * m)}, pp = {(R)c, (R)(c * m)};  // c (1 - i m), c (1 + i m)
+        const R ce = (R)(-c * e);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c3 = 0; c3 < 3; c3++) {
+                const cx<R> ou = au.c[i][c3], od = ad.c[i][c3];
+                // c (1 -+ i m g5) own - c e other (upper / lower flavour)
+                au.c[i][c3] = fma(i < 2 ? pm : pp, ou, ce * od);
+                ad.c[i][c3] = fma(i < 2 ? pp : pm, od, ce * ou);
+            }
+    } else {
+        spinor<R> su, sd;
+        a.self.at(rhs_u).load(h, su);
+        a.self.at(rhs_d).load(h, sd);
+        const cx<R> one_pm = {R(1), (R)m}, one_mm = {R(1), (R)(-m)};  // 1 + i m, 1 - i m
+        const R ee = (R)e;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int c3 = 0; c3 < 3; c3++) {
+                // A self = (1 +- i m g5) own + e other
+                const cx<R> asu = fma(i < 2 ? one_pm : one_mm, su.c[i][c3], ee * sd.c[i][c3]);
+                const cx<R> asd = fma(i < 2 ? one_mm : one_pm, sd.c[i][c3], ee * su.c[i][c3]);
+                const cx<R> ou = asu - au.c[i][c3], od = asd - ad.c[i][c3];
+                au.c[i][c3] = i < 2 ? ou : -ou;
+                ad.c[i][c3] = i < 2 ? od : -od;
+            }
+    }
+}
+
 // K2F: a K2 store launch (a.epi == EPI_K2), which starts from the own-site term.
 // BATCH: the launch covers several tuples (right-hand sides, or doublets), one
 // per block, in the RHS groups of hop_kernel, with the link loads cached (the
 // blocks of a group read the same links); otherwise one tuple, links streamed.
+// ND: doublets, both flavours of a site in one lane (tuple = RHS pair 2d, 2d + 1).
 template <class SP, bool SELF, bool NORM, int ORD, bool SB, int EP, bool ND, int PM, bool K2F = false,
           bool BATCH = false>
 __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
@@ -859,8 +941,8 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
     using LK = L16R;
     using R = float;
     constexpr bool LNT = !BATCH;                                           // links non-temporal
-    constexpr int SPB = ND ? HOP_BLOCK / 2 : HOP_BLOCK;                    // sites per block
-    const uint32_t ls = ND ? (threadIdx.x >> 1) : threadIdx.x;             // site of the lane in the block
+    constexpr int SPB = HOP_BLOCK;    // sites per block
+    const uint32_t ls = threadIdx.x;  // site of the lane in the block
     const Geom &g = a.g;
     const int j = blockIdx.x & 7;
     uint32_t sb;  // site block within the XCD's share
@@ -878,7 +960,8 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         sb = blockIdx.x >> 3;
         tup = 0;
     }
-    const int rhs = a.rl.idx[ND ? 2 * tup + (int)(threadIdx.x & 1) : tup];
+    const int rhs = a.rl.idx[ND ? 2 * tup : tup];        // (doublets: the upper flavour)
+    const int rhs_d = ND ? a.rl.idx[2 * tup + 1] : rhs;  // the lower flavour
     if (a.scal && a.scal[ND ? rhs >> 1 : rhs].done) return;
     const uint32_t XH = (uint32_t)g.XH, LY = (uint32_t)g.LY, LZ = (uint32_t)g.LZ, T = (uint32_t)g.T;
     const uint32_t plane = LY * XH;  // sites of one (t, z) plane
@@ -943,7 +1026,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         const uint32_t row = h - xh;
         const uint32_t sy = XH, sz = plane, stt = LZ * plane;
         const uint32_t LX = (uint32_t)g.LX;
-        spinor<R> acc;
+        spinor<R> acc, acd;  // (acd: the lower flavour of a doublet)
         if constexpr (K2F) {
             // the operations of k2_self_first, written out: through the
             // helper the compiler keeps about 30 more registers live here
@@ -962,7 +1045,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
 #pragma unroll
             for (int i = 0; i < 4; i++)
 #pragma unroll
-                for (int c = 0; c < 3; c++) acc.c[i][c] = cx<R>{R(0), R(0)};
+                for (int c = 0; c < 3; c++) acc.c[i][c] = acd.c[i][c] = cx<R>{R(0), R(0)};
         }
         const uint32_t oa = off_link16a(h), ob = off_link16b(h);
         // neighbours (periodic), with the wrap as a select of uniform values
@@ -976,39 +1059,49 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
                       D3 = k1_order<!SELF>(3);
         const uint32_t nf[4] = {tf, xf, yf, zf}, nbk[4] = {tb, xb, yb, zb};
         if constexpr (ND) {
-            // doublets (VALU-bound, a lane pair per site): one hop at a time,
-            // two hops ahead, within 96 registers (5 waves per SIMD; the
-            // grouping below measured 10 % slower for them)
-            Hop16 b0, b1;
-            load16h<D0, 0, LNT>(B, oa, ob, nf[D0], b0);
-            load16h<D0, 1, LNT>(B, oa, ob, nbk[D0], b1);
+            // doublets (VALU-bound): both flavours of the site in this lane, so
+            // the link is loaded and its row 2 formed once for the two; one hop
+            // at a time with the next one in flight (158 registers, 3 waves per
+            // SIMD; a lane pair per site, one flavour each, took 1811 VALU
+            // instructions per lane against 2582 here for both flavours)
+            const SP ind = a.in.at(rhs_d);
+            const char *cd = (const char *)ind.p, *sd = (const char *)ind.scale;
+            Hop16N b0, b1;
+            load16n<D0, 0, LNT>(B, cd, sd, oa, ob, nf[D0], b0);
+            load16n<D0, 1, LNT>(B, cd, sd, oa, ob, nbk[D0], b1);
             __builtin_amdgcn_sched_barrier(0);
-            math16h<D0, 0, ((PM >> D0) & 1) != 0>(a, b0, acc);
+            math16n<D0, 0, ((PM >> D0) & 1) != 0>(a, b0, acc, acd);
             pin_order(acc);
-            load16h<D1, 0, LNT>(B, oa, ob, nf[D1], b0);
+            pin_order(acd);
+            load16n<D1, 0, LNT>(B, cd, sd, oa, ob, nf[D1], b0);
             __builtin_amdgcn_sched_barrier(0);
-            math16h<D0, 1, ((PM >> D0) & 1) != 0>(a, b1, acc);
+            math16n<D0, 1, ((PM >> D0) & 1) != 0>(a, b1, acc, acd);
             pin_order(acc);
-            load16h<D1, 1, LNT>(B, oa, ob, nbk[D1], b1);
+            pin_order(acd);
+            load16n<D1, 1, LNT>(B, cd, sd, oa, ob, nbk[D1], b1);
             __builtin_amdgcn_sched_barrier(0);
-            math16h<D1, 0, ((PM >> D1) & 1) != 0>(a, b0, acc);
+            math16n<D1, 0, ((PM >> D1) & 1) != 0>(a, b0, acc, acd);
             pin_order(acc);
-            load16h<D2, 0, LNT>(B, oa, ob, nf[D2], b0);
+            pin_order(acd);
+            load16n<D2, 0, LNT>(B, cd, sd, oa, ob, nf[D2], b0);
             __builtin_amdgcn_sched_barrier(0);
-            math16h<D1, 1, ((PM >> D1) & 1) != 0>(a, b1, acc);
+            math16n<D1, 1, ((PM >> D1) & 1) != 0>(a, b1, acc, acd);
             pin_order(acc);
-            load16h<D2, 1, LNT>(B, oa, ob, nbk[D2], b1);
+            pin_order(acd);
+            load16n<D2, 1, LNT>(B, cd, sd, oa, ob, nbk[D2], b1);
             __builtin_amdgcn_sched_barrier(0);
-            math16h<D2, 0, ((PM >> D2) & 1) != 0>(a, b0, acc);
+            math16n<D2, 0, ((PM >> D2) & 1) != 0>(a, b0, acc, acd);
             pin_order(acc);
-            load16h<D3, 0, LNT>(B, oa, ob, nf[D3], b0);
+            pin_order(acd);
+            load16n<D3, 0, LNT>(B, cd, sd, oa, ob, nf[D3], b0);
             __builtin_amdgcn_sched_barrier(0);
-            math16h<D2, 1, ((PM >> D2) & 1) != 0>(a, b1, acc);
+            math16n<D2, 1, ((PM >> D2) & 1) != 0>(a, b1, acc, acd);
             pin_order(acc);
-            load16h<D3, 1, LNT>(B, oa, ob, nbk[D3], b1);
+            pin_order(acd);
+            load16n<D3, 1, LNT>(B, cd, sd, oa, ob, nbk[D3], b1);
             __builtin_amdgcn_sched_barrier(0);
-            math16h<D3, 0, ((PM >> D3) & 1) != 0>(a, b0, acc);
-            math16h<D3, 1, ((PM >> D3) & 1) != 0>(a, b1, acc);
+            math16n<D3, 0, ((PM >> D3) & 1) != 0>(a, b0, acc, acd);
+            math16n<D3, 1, ((PM >> D3) & 1) != 0>(a, b1, acc, acd);
         } else {
             // one flavour: two directions (four hops) loaded at a time, in the
             // order of the sum
@@ -1031,15 +1124,20 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
             math16p<D2, ((PM >> D2) & 1) != 0>(a, d0, acc);
             math16p<D3, ((PM >> D3) & 1) != 0>(a, d1, acc);
         }
-        if constexpr (ND) nd_mix(a, acc, rhs, (long)h);
         // one tuple: the output is stored through the caches, since the next
         // half-sweep reads it (measured 2 % faster than non-temporal stores for
         // both K1 and K2); a batch's outputs are read again only after the
         // whole batch, so they are stored non-temporally
-        nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acc, rhs, (long)h);
+        if constexpr (ND) {
+            nd_mix2(a, acc, acd, rhs, rhs_d, (long)h);
+            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, false>(a, acc, rhs, (long)h);
+            nrm += hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, false>(a, acd, rhs_d, (long)h);
+        } else {
+            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acc, rhs, (long)h);
+        }
     }
     if (NORM) {
-        // (doublets: the block's lanes hold both flavours, so the sum is over the doublet)
+        // (doublets: each lane's value covers both flavours, so the sum is over the doublet)
         __shared__ double sh[HOP_BLOCK / 64];
         const double s = block_sum(nrm, sh);
         if (threadIdx.x == 0) a.partial[(ND ? rhs >> 1 : rhs) * a.pstride + pidx] = s;
@@ -1090,8 +1188,6 @@ void go16_v(const HopArgs<SP, L16R> &a, int variant, bool s, bool n, int ep, dim
     default: go16_e<SP, ORD_PLAIN, false, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
     }
 }
-// whether a 16-bit launch can use hop16_kernel
-inline bool hop16_ok(const Geom &g, int phase_mask) { return g.vh < (1L << 26) && (phase_mask == 0 || phase_mask == 1); }
 
 // the launches of hop16_kernel, instantiated in hop16_f16.hip / hop16_b16.hip
 // (own translation units, compiled in parallel with the others); batch: more
@@ -1200,9 +1296,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     a.out_par = out_par;
     a.epi = epi;
     a.sign = sign;
-    a.phase_mask = 0;
-    for (int mu = 0; mu < 4; mu++)
-        if (op.ph[mu][0] != 1.0 || op.ph[mu][1] != 0.0) a.phase_mask |= 1 << mu;
+    a.phase_mask = hop_phase_mask(op);
     a.in = make_bv<SP>(in);
     a.self = self.data ? make_bv<SP>(self) : a.in;
     a.out = make_bv<SP>(out);
@@ -1230,7 +1324,8 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         const bool s = epi != EPI_K1, n = partial != nullptr;
         if (s && !self.data) return hipErrorInvalidValue;
         if (!s && n) return hipErrorInvalidValue;
-        a.nblk = hop_grid_variant(g, variant, 2);  // blocks of HOP_BLOCK / 2 sites
+        const int lanes = hop_nd_lanes(g, in.prec, lk.fmt, op);  // per doublet site
+        a.nblk = hop_grid_variant(g, variant, lanes);
         const int ntup = rl.n / 2;
         const int grp = tu.group > 0 ? tu.group : rhs_group(g, in.prec, rl.n);
         a.group = (grp + 1) / 2;
@@ -1240,7 +1335,8 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         const int ord = variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB;
         const bool nt = ntup == 1;
         if constexpr (ALL && SP::coded && __is_same(LK, L16R)) {
-            if (hop16_ok(g, a.phase_mask)) {
+            if (lanes == 1) {
+                // the 16-bit kernel: both flavours of a site in one lane
                 launch_hop16(a, true, !nt, variant, s, n, ep, grid, block, tu.lds, st);
                 return hipGetLastError();
             }

@@ -143,8 +143,27 @@ bool hop_variant_valid(const Geom &g, int v);
 // others always run variant 0 whatever HopTune asks for
 bool hop_all_variants(int prec, int link_fmt);
 // blocks per RHS (= per-block partial sums written with a norm) of variant v;
-// lanes_per_site = 2 for doublets (a lane pair per site)
+// lanes_per_site = 2 for doublets in the general kernel (a lane pair per site)
 int hop_grid_variant(const Geom &g, int v, int lanes_per_site = 1);
+
+// bit mu set when the boundary phase of direction mu is not 1
+inline int hop_phase_mask(const OpParams &op)
+{
+    int m = 0;
+    for (int mu = 0; mu < 4; mu++)
+        if (op.ph[mu][0] != 1.0 || op.ph[mu][1] != 0.0) m |= 1 << mu;
+    return m;
+}
+// whether a launch of 16-bit spinors on FP16 two-row links runs in the 16-bit
+// kernel (hop16_kernel): 32-bit offsets (V/2 < 2^26) and a boundary phase in
+// time only, or none
+inline bool hop16_ok(const Geom &g, int phase_mask) { return g.vh < (1L << 26) && (phase_mask == 0 || phase_mask == 1); }
+// lanes per site of a doublet launch: 1 in the 16-bit kernel (both flavours
+// in a lane), 2 in the general kernel (a lane pair)
+inline int hop_nd_lanes(const Geom &g, int prec, int link_fmt, const OpParams &op)
+{
+    return (prec == P16 || prec == PB16) && link_fmt == LK16R && hop16_ok(g, hop_phase_mask(op)) ? 1 : 2;
+}
 
 // Hop half-sweep: out(h) over the V/2 sites of parity out_par for every RHS
 // of rl; `in` holds parity 1 - out_par; `self` (data may be nullptr unless

@@ -625,7 +625,8 @@ static int hop_nd(Lattice *L, int out_par, const FieldDesc &in, const FieldDesc 
     TMQ_HIP(launch_hop(L->g, out_par, fi, fs, fo, lk, op, epi, sign, fl, partial, L->pstride, scal, tu, st,
                        cg ? &c2 : nullptr));
     // partial sums of the launch: its blocks per field, from the variant it ran
-    L->hop_blocks_last = hop_grid_variant(L->g, hop_all_variants(in.prec, lk.fmt) ? L->hop_variant[key] : 0, 2);
+    L->hop_blocks_last = hop_grid_variant(L->g, hop_all_variants(in.prec, lk.fmt) ? L->hop_variant[key] : 0,
+                                          hop_nd_lanes(L->g, in.prec, lk.fmt, op));
     if (L->timing) {
         TMQ_HIP(hipEventRecord(t.b, st));
         L->timed.push_back(t);
