@@ -4,10 +4,10 @@
 
 namespace tmq {
 
-void launch_hop16(const HopArgs<SpH16, L16R> &a, bool nd, bool batch, int variant, bool s, bool n, int ep,
+void launch_hop16(const HopArgs<SpH16, L16R> &a, bool nd, bool batch, bool two, int variant, bool s, bool n, int ep,
                   dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
-    launch_hop16_impl<SpH16>(a, nd, batch, variant, s, n, ep, grid, block, lds, st);
+    launch_hop16_impl<SpH16>(a, nd, batch, two, variant, s, n, ep, grid, block, lds, st);
 }
 
 }  // namespace tmq

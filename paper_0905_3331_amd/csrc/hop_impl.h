@@ -934,10 +934,14 @@ __device__ __forceinline__ void nd_mix2(const HopArgs<SP, LK> &a, spinor<R> &au,
 // per block, in the RHS groups of hop_kernel, with the link loads cached (the
 // blocks of a group read the same links); otherwise one tuple, links streamed.
 // ND: doublets, both flavours of a site in one lane (tuple = RHS pair 2d, 2d + 1).
+// TWO (batches): two right-hand sides per lane (tuple = RHS 2i, 2i + 1 of the
+// list), sharing the link loads and row 2 as the flavours of a doublet do.
 template <class SP, bool SELF, bool NORM, int ORD, bool SB, int EP, bool ND, int PM, bool K2F = false,
-          bool BATCH = false>
+          bool BATCH = false, bool TWO = false>
 __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
 {
+    static_assert(!TWO || (BATCH && !ND), "two right-hand sides per lane are a batched single-flavour launch");
+    constexpr bool DUAL = ND || TWO;  // two accumulators per lane
     using LK = L16R;
     using R = float;
     constexpr bool LNT = !BATCH;                                           // links non-temporal
@@ -950,7 +954,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
     if constexpr (BATCH) {
         const int k = blockIdx.x >> 3;
         const int nb = a.nblk >> 3;
-        const int ntup = ND ? a.rl.n / 2 : a.rl.n;
+        const int ntup = ND ? a.rl.n / 2 : TWO ? (a.rl.n + 1) / 2 : a.rl.n;
         const int GR = a.group, gr = k / (nb * GR);
         const int gsize = min(GR, ntup - gr * GR);  // the last group may be smaller
         const int within = k - gr * nb * GR;
@@ -960,9 +964,27 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         sb = blockIdx.x >> 3;
         tup = 0;
     }
-    const int rhs = a.rl.idx[ND ? 2 * tup : tup];        // (doublets: the upper flavour)
-    const int rhs_d = ND ? a.rl.idx[2 * tup + 1] : rhs;  // the lower flavour
-    if (a.scal && a.scal[ND ? rhs >> 1 : rhs].done) return;
+    int rhs, rhs_d;    // the tuple's right-hand sides (doublets: upper, lower flavour)
+    bool two = DUAL;  // (TWO: whether the second one is live)
+    if constexpr (TWO) {
+        // a finished or missing second RHS leaves the lane with the first; a
+        // finished first one hands its place to the second
+        int r0 = a.rl.idx[2 * tup];
+        const int r1 = 2 * tup + 1 < a.rl.n ? a.rl.idx[2 * tup + 1] : -1;
+        bool l0 = !(a.scal && a.scal[r0].done), l1 = r1 >= 0 && !(a.scal && a.scal[r1].done);
+        if (!l0 && !l1) return;
+        if (!l0) {
+            r0 = r1;
+            l1 = false;
+        }
+        rhs = r0;
+        rhs_d = l1 ? r1 : r0;
+        two = l1;
+    } else {
+        rhs = a.rl.idx[ND ? 2 * tup : tup];
+        rhs_d = ND ? a.rl.idx[2 * tup + 1] : rhs;
+        if (a.scal && a.scal[ND ? rhs >> 1 : rhs].done) return;
+    }
     const uint32_t XH = (uint32_t)g.XH, LY = (uint32_t)g.LY, LZ = (uint32_t)g.LZ, T = (uint32_t)g.T;
     const uint32_t plane = LY * XH;  // sites of one (t, z) plane
     uint32_t h, t, z, y, xh, pidx;
@@ -1010,7 +1032,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         t = r / LZ;
         pidx = lb;
     }
-    double nrm = 0.0;
+    double nrm = 0.0, nrm2 = 0.0;
     if (active) {
         const int ip = a.out_par ^ 1;
         const SP in = a.in.at(rhs);
@@ -1030,16 +1052,21 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         if constexpr (K2F) {
             // the operations of k2_self_first, written out: through the
             // helper the compiler keeps about 30 more registers live here
-            spinor<R> sf;
-            a.self.at(rhs).load((long)h, sf);
-            const double m = a.sign * a.op.mut[rhs];
-            const cx<R> Au = cx<R>{R(1), (R)m}, Ad = cx<R>{R(-1), (R)m};
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                acc.c[0][c] = -(Au * sf.c[0][c]);
-                acc.c[1][c] = -(Au * sf.c[1][c]);
-                acc.c[2][c] = Ad * sf.c[2][c];
-                acc.c[3][c] = Ad * sf.c[3][c];
+            for (int q = 0; q < (TWO ? 2 : 1); q++) {
+                const int r = q == 0 ? rhs : rhs_d;
+                spinor<R> sf;
+                a.self.at(r).load((long)h, sf);
+                const double m = a.sign * a.op.mut[r];
+                const cx<R> Au = cx<R>{R(1), (R)m}, Ad = cx<R>{R(-1), (R)m};
+                spinor<R> &t = q == 0 ? acc : acd;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    t.c[0][c] = -(Au * sf.c[0][c]);
+                    t.c[1][c] = -(Au * sf.c[1][c]);
+                    t.c[2][c] = Ad * sf.c[2][c];
+                    t.c[3][c] = Ad * sf.c[3][c];
+                }
             }
         } else {
 #pragma unroll
@@ -1058,9 +1085,10 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         constexpr int D0 = k1_order<!SELF>(0), D1 = k1_order<!SELF>(1), D2 = k1_order<!SELF>(2),
                       D3 = k1_order<!SELF>(3);
         const uint32_t nf[4] = {tf, xf, yf, zf}, nbk[4] = {tb, xb, yb, zb};
-        if constexpr (ND) {
-            // doublets (VALU-bound): both flavours of the site in this lane, so
-            // the link is loaded and its row 2 formed once for the two; one hop
+        if constexpr (DUAL) {
+            // doublets (VALU-bound), or two right-hand sides: both fields of the
+            // site in this lane, so the link is loaded and its row 2 formed once
+            // for the two; one hop
             // at a time with the next one in flight (158 registers, 3 waves per
             // SIMD; a lane pair per site, one flavour each, took 1811 VALU
             // instructions per lane against 2582 here for both flavours)
@@ -1132,6 +1160,9 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
             nd_mix2(a, acc, acd, rhs, rhs_d, (long)h);
             nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, false>(a, acc, rhs, (long)h);
             nrm += hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, false>(a, acd, rhs_d, (long)h);
+        } else if constexpr (TWO) {
+            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acc, rhs, (long)h);
+            if (two) nrm2 = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acd, rhs_d, (long)h);
         } else {
             nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acc, rhs, (long)h);
         }
@@ -1141,66 +1172,77 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         __shared__ double sh[HOP_BLOCK / 64];
         const double s = block_sum(nrm, sh);
         if (threadIdx.x == 0) a.partial[(ND ? rhs >> 1 : rhs) * a.pstride + pidx] = s;
+        if (TWO && two) {  // (uniform over the block)
+            __shared__ double sh2[HOP_BLOCK / 64];
+            const double s2 = block_sum(nrm2, sh2);
+            if (threadIdx.x == 0) a.partial[rhs_d * a.pstride + pidx] = s2;
+        }
     }
 }
 
 // launches of hop16_kernel: the block order of the variant, the epilogue
 // flavours of go_w / go_nd, the compile-time phase mask, and single-tuple or
 // batched (BATCH) launches
-template <class SP, int ORD, bool SB, bool ND, int PM, bool BATCH>
+template <class SP, int ORD, bool SB, bool ND, int PM, bool BATCH, bool TWO = false>
 void go16_e(const HopArgs<SP, L16R> &a, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
     if (ep == EP_CG)
-        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_CG, ND, PM, false, BATCH>), grid, block, lds, st,
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_CG, ND, PM, false, BATCH, TWO>), grid, block, lds, st,
                            a);
     else if (ep == EP_RES)
-        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_RES, ND, PM, false, BATCH>), grid, block, lds,
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_RES, ND, PM, false, BATCH, TWO>), grid, block, lds,
                            st, a);
     else if (s && !ND && a.epi == EPI_K2) {
         if (n)
-            hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM, true, BATCH>), grid, block,
+            hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM, true, BATCH, TWO>), grid, block,
                                lds, st, a);
         else
-            hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM, true, BATCH>), grid, block,
+            hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM, true, BATCH, TWO>), grid, block,
                                lds, st, a);
     } else if (s && n)
-        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM, false, BATCH>), grid, block, lds,
+        hipLaunchKernelGGL((hop16_kernel<SP, true, true, ORD, SB, EP_STORE, ND, PM, false, BATCH, TWO>), grid, block, lds,
                            st, a);
     else if (s)
-        hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM, false, BATCH>), grid, block, lds,
+        hipLaunchKernelGGL((hop16_kernel<SP, true, false, ORD, SB, EP_STORE, ND, PM, false, BATCH, TWO>), grid, block, lds,
                            st, a);
     else if (n && !ND)
-        hipLaunchKernelGGL((hop16_kernel<SP, false, true, ORD, SB, EP_STORE, ND, PM, false, BATCH>), grid, block, lds,
+        hipLaunchKernelGGL((hop16_kernel<SP, false, true, ORD, SB, EP_STORE, ND, PM, false, BATCH, TWO>), grid, block, lds,
                            st, a);
     else
-        hipLaunchKernelGGL((hop16_kernel<SP, false, false, ORD, SB, EP_STORE, ND, PM, false, BATCH>), grid, block,
+        hipLaunchKernelGGL((hop16_kernel<SP, false, false, ORD, SB, EP_STORE, ND, PM, false, BATCH, TWO>), grid, block,
                            lds, st, a);
 }
-template <class SP, bool ND, int PM, bool BATCH>
+template <class SP, bool ND, int PM, bool BATCH, bool TWO = false>
 void go16_v(const HopArgs<SP, L16R> &a, int variant, bool s, bool n, int ep, dim3 grid, dim3 block, unsigned lds,
             hipStream_t st)
 {
     switch (variant) {
-    case 1: go16_e<SP, ORD_ZSLAB, false, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
-    case 2: go16_e<SP, ORD_ZSLAB, true, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
-    case 3: go16_e<SP, ORD_TSLAB, false, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
-    case 4: go16_e<SP, ORD_TSLAB, true, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
-    default: go16_e<SP, ORD_PLAIN, false, ND, PM, BATCH>(a, s, n, ep, grid, block, lds, st); break;
+    case 1: go16_e<SP, ORD_ZSLAB, false, ND, PM, BATCH, TWO>(a, s, n, ep, grid, block, lds, st); break;
+    case 2: go16_e<SP, ORD_ZSLAB, true, ND, PM, BATCH, TWO>(a, s, n, ep, grid, block, lds, st); break;
+    case 3: go16_e<SP, ORD_TSLAB, false, ND, PM, BATCH, TWO>(a, s, n, ep, grid, block, lds, st); break;
+    case 4: go16_e<SP, ORD_TSLAB, true, ND, PM, BATCH, TWO>(a, s, n, ep, grid, block, lds, st); break;
+    default: go16_e<SP, ORD_PLAIN, false, ND, PM, BATCH, TWO>(a, s, n, ep, grid, block, lds, st); break;
     }
 }
 
 // the launches of hop16_kernel, instantiated in hop16_f16.hip / hop16_b16.hip
 // (own translation units, compiled in parallel with the others); batch: more
-// than one tuple (right-hand side or doublet) in the launch
-void launch_hop16(const HopArgs<SpH16, L16R> &a, bool nd, bool batch, int variant, bool s, bool n, int ep,
+// than one tuple (right-hand side or doublet) in the launch; two: batched, two
+// right-hand sides per lane
+void launch_hop16(const HopArgs<SpH16, L16R> &a, bool nd, bool batch, bool two, int variant, bool s, bool n, int ep,
                   dim3 grid, dim3 block, unsigned lds, hipStream_t st);
-void launch_hop16(const HopArgs<SpB16, L16R> &a, bool nd, bool batch, int variant, bool s, bool n, int ep,
+void launch_hop16(const HopArgs<SpB16, L16R> &a, bool nd, bool batch, bool two, int variant, bool s, bool n, int ep,
                   dim3 grid, dim3 block, unsigned lds, hipStream_t st);
 template <class SP>
-void launch_hop16_impl(const HopArgs<SP, L16R> &a, bool nd, bool batch, int variant, bool s, bool n, int ep,
-                       dim3 grid, dim3 block, unsigned lds, hipStream_t st)
+void launch_hop16_impl(const HopArgs<SP, L16R> &a, bool nd, bool batch, bool two, int variant, bool s, bool n,
+                       int ep, dim3 grid, dim3 block, unsigned lds, hipStream_t st)
 {
-    if (nd && batch) {
+    if (two) {
+        if (a.phase_mask)
+            go16_v<SP, false, 1, true, true>(a, variant, s, n, ep, grid, block, lds, st);
+        else
+            go16_v<SP, false, 0, true, true>(a, variant, s, n, ep, grid, block, lds, st);
+    } else if (nd && batch) {
         if (a.phase_mask)
             go16_v<SP, true, 1, true>(a, variant, s, n, ep, grid, block, lds, st);
         else
@@ -1337,7 +1379,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         if constexpr (ALL && SP::coded && __is_same(LK, L16R)) {
             if (lanes == 1) {
                 // the 16-bit kernel: both flavours of a site in one lane
-                launch_hop16(a, true, !nt, variant, s, n, ep, grid, block, tu.lds, st);
+                launch_hop16(a, true, !nt, false, variant, s, n, ep, grid, block, tu.lds, st);
                 return hipGetLastError();
             }
         }
@@ -1382,6 +1424,13 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         return hipGetLastError();
     }
     if (MULTI && G > 1) {
+        if constexpr (SP::coded && __is_same(LK, L16R)) {
+            // two RHS per lane of 16-bit spinors: the 16-bit kernel
+            if (hop16_ok(g, a.phase_mask)) {
+                launch_hop16(a, false, true, true, variant, s, n, ep, grid, block, lds, st);
+                return hipGetLastError();
+            }
+        }
         // several RHS per lane: no scheduling-barrier flavours (same block order)
         const int ord = variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB;
 #define GOM(GG)                                                                                \
@@ -1400,7 +1449,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     if constexpr (SP::coded && __is_same(LK, L16R)) {
         // one RHS per lane: the 16-bit kernel, for one RHS or a batch
         if (hop16_ok(g, a.phase_mask)) {
-            launch_hop16(a, false, !nt, variant, s, n, ep, grid, block, lds, st);
+            launch_hop16(a, false, !nt, false, variant, s, n, ep, grid, block, lds, st);
             return hipGetLastError();
         }
     }
