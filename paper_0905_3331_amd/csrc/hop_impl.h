@@ -1048,7 +1048,7 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         const uint32_t row = h - xh;
         const uint32_t sy = XH, sz = plane, stt = LZ * plane;
         const uint32_t LX = (uint32_t)g.LX;
-        spinor<R> acc, acd;  // (acd: the lower flavour of a doublet)
+        spinor<R> acc, acd;  // (acd: a doublet's lower flavour, or the second right-hand side)
         if constexpr (K2F) {
             // the operations of k2_self_first, written out: through the
             // helper the compiler keeps about 30 more registers live here
@@ -1059,13 +1059,13 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
                 a.self.at(r).load((long)h, sf);
                 const double m = a.sign * a.op.mut[r];
                 const cx<R> Au = cx<R>{R(1), (R)m}, Ad = cx<R>{R(-1), (R)m};
-                spinor<R> &t = q == 0 ? acc : acd;
+                spinor<R> &dst = q == 0 ? acc : acd;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    t.c[0][c] = -(Au * sf.c[0][c]);
-                    t.c[1][c] = -(Au * sf.c[1][c]);
-                    t.c[2][c] = Ad * sf.c[2][c];
-                    t.c[3][c] = Ad * sf.c[3][c];
+                    dst.c[0][c] = -(Au * sf.c[0][c]);
+                    dst.c[1][c] = -(Au * sf.c[1][c]);
+                    dst.c[2][c] = Ad * sf.c[2][c];
+                    dst.c[3][c] = Ad * sf.c[3][c];
                 }
             }
         } else {
@@ -1088,10 +1088,11 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         if constexpr (DUAL) {
             // doublets (VALU-bound), or two right-hand sides: both fields of the
             // site in this lane, so the link is loaded and its row 2 formed once
-            // for the two; one hop
-            // at a time with the next one in flight (158 registers, 3 waves per
-            // SIMD; a lane pair per site, one flavour each, took 1811 VALU
-            // instructions per lane against 2582 here for both flavours)
+            // for the two; one hop at a time with the next one in flight (about
+            // 155 registers, 3 waves per SIMD).  A doublet K1 executes 2557 VALU
+            // instructions per site this way, 3098 with a lane per flavour.
+            // (TWO with one live RHS repeats it in the second accumulator, which
+            // is not stored.)
             const SP ind = a.in.at(rhs_d);
             const char *cd = (const char *)ind.p, *sd = (const char *)ind.scale;
             Hop16N b0, b1;
