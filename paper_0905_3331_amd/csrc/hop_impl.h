@@ -21,6 +21,7 @@
 // slab of the lattice and its private L2 sees the y/z/t neighbours of its
 // own sites.
 #pragma once
+#include <algorithm>
 #include <type_traits>
 
 #include "devutil.h"
@@ -46,6 +47,44 @@ struct XsOf<SpF64> {
 
 enum HopEp { EP_STORE = 0, EP_CG = 1, EP_RES = 2 };
 
+// Divisors of a batched 16-bit launch's block and site decode (FastDiv): the
+// blocks of an RHS group per XCD (grp), the group size (gsz) and the size of
+// the last group (glast); the x-row and (t, z) plane lengths, LY and LZ, and
+// the sites of one time-slice of an XCD's z-slab (or of one z-plane of its
+// t-slab), which come in two sizes: slab[1] for the XCDs that take one plane
+// (or slice) more.
+struct SiteDiv {
+    FastDiv grp, gsz, glast;
+    FastDiv xh, ly, lz, plane, slab[2];
+};
+inline SiteDiv make_site_div(const Geom &g, int ord, int nblk, int group, int ntup)
+{
+    SiteDiv d;
+    d.grp = make_fastdiv((uint32_t)(nblk >> 3) * (uint32_t)group);
+    d.gsz = make_fastdiv((uint32_t)group);
+    d.glast = make_fastdiv((uint32_t)(ntup - (ntup - 1) / group * group));
+    const uint32_t plane = (uint32_t)g.LY * (uint32_t)g.XH;
+    d.xh = make_fastdiv((uint32_t)g.XH);
+    d.ly = make_fastdiv((uint32_t)g.LY);
+    d.lz = make_fastdiv((uint32_t)g.LZ);
+    d.plane = make_fastdiv(plane);
+    const uint32_t ext = ord == ORD_TSLAB ? (uint32_t)g.T : (uint32_t)g.LZ;
+    d.slab[0] = make_fastdiv(std::max(1u, ext >> 3) * plane);
+    d.slab[1] = make_fastdiv(((ext >> 3) + 1) * plane);
+    return d;
+}
+// n / d for the divisor of f (FastDiv; n < 2^31)
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) { return (__umulhi(n, f.m) + n) >> f.s; }
+
+// Site-term coefficients of a batched 16-bit launch, per right-hand side
+// (doublets: per doublet), formed on the host in FP64 by the operations the
+// single-field launches perform in each lane and rounded to FP32 once, so the
+// two agree bit for bit: m = sigma mut, e = eps, c = kappa^2 / (1 + m^2)
+// (doublets: kappa^2 / (1 + m^2 - e^2)), cm = c m, ce = c e
+struct EpiCoef {
+    float c, cm, ce, m, e;
+};
+
 template <class SP, class LK>
 struct HopArgs {
     Geom g;
@@ -65,6 +104,9 @@ struct HopArgs {
     // fused epilogues (EPI_K2_CG, EPI_K2_RES)
     BatchView<SP> cg_r, cg_p;
     BatchView<typename XsOf<SP>::type> cg_x;
+    // batched 16-bit launches
+    SiteDiv dv;
+    EpiCoef ec[MAX_RHS];
 };
 
 // x + C y for C = 1, -1, i, -i (selector 0..3), x and y complex 16-bit codes
@@ -368,9 +410,10 @@ __device__ __forceinline__ spinor<R> k2_self_first(const HopArgs<SP, LK> &a, int
 // (HopEpi), then the store (non-temporal when NTOUT) or the fused CG /
 // residual update; returns |out|^2 when NORM (else 0).  PRESELF: the launch is
 // EPI_K2 and acc_in already holds the own-site term (k2_self_first), so out =
-// B acc with B = -1 on the upper spins and +1 on the lower.
+// B acc with B = -1 on the upper spins and +1 on the lower.  TAB: the
+// coefficients come from the launch's table (EpiCoef; batched 16-bit launches).
 template <class SP, class LK, bool SELF, bool NORM, int EP, bool ND, bool NTOUT = true, bool PRESELF = false,
-          typename R>
+          bool TAB = false, typename R>
 __device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const spinor<R> &acc_in, int rhs, long h)
 {
     double nrm = 0.0;
@@ -379,10 +422,16 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const s
     const double kap = a.op.kappa[rhs], m = a.sign * a.op.mut[rhs];
     cx<R> Au, Ad, Bu, Bd;
     if (a.epi == EPI_K1) {
-        const double c = kap * kap / (1.0 + m * m);
         Au = Ad = cx<R>{R(0), R(0)};
-        Bu = cx<R>{(R)c, (R)(-c * m)};
-        Bd = cx<R>{(R)c, (R)(c * m)};
+        if constexpr (TAB && !ND) {
+            const EpiCoef &k = a.ec[rhs];
+            Bu = cx<R>{k.c, -k.cm};
+            Bd = cx<R>{k.c, k.cm};
+        } else {
+            const double c = kap * kap / (1.0 + m * m);
+            Bu = cx<R>{(R)c, (R)(-c * m)};
+            Bd = cx<R>{(R)c, (R)(c * m)};
+        }
     } else if (a.epi == EPI_SRC) {
         Au = Ad = cx<R>{R(1), R(0)};
         Bu = Bd = cx<R>{(R)kap, R(0)};
@@ -394,8 +443,13 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs<SP, LK> &a, const s
         Bd = cx<R>{(R)(kap * c), (R)(kap * c * m)};
     } else {
         const double b = a.epi == EPI_FULL ? kap : 1.0;
-        Au = cx<R>{R(1), (R)m};
-        Ad = cx<R>{R(-1), (R)m};
+        R mr;
+        if constexpr (TAB && !ND)
+            mr = a.ec[rhs].m;
+        else
+            mr = (R)m;
+        Au = cx<R>{R(1), mr};
+        Ad = cx<R>{R(-1), mr};
         Bu = cx<R>{(R)(-b), R(0)};
         Bd = cx<R>{(R)b, R(0)};
     }
@@ -889,17 +943,36 @@ __device__ __forceinline__ void math16n(const HopArgs<SP, LK> &a, const Hop16N &
 
 // nd_mix for both flavours of a site held by one lane (au upper, ad lower
 // flavour of doublet rhs_u >> 1): the same operations, the partner's values
-// taken from the other accumulator instead of the other lane
-template <class SP, class LK, typename R>
+// taken from the other accumulator instead of the other lane (TAB: the
+// coefficients from the launch's table, as in hop_epilogue)
+template <bool TAB, class SP, class LK, typename R>
 __device__ __forceinline__ void nd_mix2(const HopArgs<SP, LK> &a, spinor<R> &au, spinor<R> &ad, int rhs_u, int rhs_d,
                                         long h)
 {
     const int d = rhs_u >> 1;
-    const double kap = a.op.kappa[d], m = a.sign * a.op.mut[d], e = a.op.eps[d];
+    const double kap = a.op.kappa[d], md = a.sign * a.op.mut[d], ed = a.op.eps[d];
+    R m, e;
+    if constexpr (TAB) {
+        m = a.ec[d].m;
+        e = a.ec[d].e;
+    } else {
+        m = (R)md;
+        e = (R)ed;
+    }
     if (a.epi == EPI_K1) {
-        const double c = kap * kap / (1.0 + m * m - e * e);
-        const cx<R> pm = {(R)c, (R)(-c * m)}, pp = {(R)c, (R)(c * m)};  // c (1 - i m), c (1 + i m)
-        const R ce = (R)(-c * e);
+        cx<R> pm, pp;  // c (1 - i m), c (1 + i m)
+        R ce;
+        if constexpr (TAB) {
+            const EpiCoef &k = a.ec[d];
+            pm = {k.c, -k.cm};
+            pp = {k.c, k.cm};
+            ce = -k.ce;
+        } else {
+            const double c = kap * kap / (1.0 + md * md - ed * ed);
+            pm = {(R)c, (R)(-c * md)};
+            pp = {(R)c, (R)(c * md)};
+            ce = (R)(-c * ed);
+        }
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -952,14 +1025,16 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
     uint32_t sb;  // site block within the XCD's share
     int tup;      // tuple of the block
     if constexpr (BATCH) {
-        const int k = blockIdx.x >> 3;
+        // (the divisions by launch constants through the host's multipliers, a.dv)
+        const uint32_t k = blockIdx.x >> 3;
         const int nb = a.nblk >> 3;
         const int ntup = ND ? a.rl.n / 2 : TWO ? (a.rl.n + 1) / 2 : a.rl.n;
-        const int GR = a.group, gr = k / (nb * GR);
+        const int GR = a.group;
+        const int gr = (int)fdiv(k, a.dv.grp);      // k / (nb GR)
         const int gsize = min(GR, ntup - gr * GR);  // the last group may be smaller
-        const int within = k - gr * nb * GR;
-        sb = (uint32_t)(within / gsize);
-        tup = gr * GR + (within - (int)sb * gsize);
+        const uint32_t within = k - (uint32_t)(gr * nb * GR);
+        sb = fdiv(within, gsize == GR ? a.dv.gsz : a.dv.glast);  // within / gsize
+        tup = gr * GR + (int)(within - sb * (uint32_t)gsize);
     } else {
         sb = blockIdx.x >> 3;
         tup = 0;
@@ -996,11 +1071,11 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         const uint32_t l = sb * SPB + ls;
         active = l < T * S;
         const uint32_t lu = active ? l : 0u;
-        t = lu / S;
+        t = BATCH ? fdiv(lu, a.dv.slab[(uint32_t)j < zr ? 1 : 0]) : lu / S;
         const uint32_t rem = lu - t * S;
-        z = z0 + rem / plane;
+        z = z0 + (BATCH ? fdiv(rem, a.dv.plane) : rem / plane);
         const uint32_t r2 = rem - (z - z0) * plane;
-        y = r2 / XH;
+        y = BATCH ? fdiv(r2, a.dv.xh) : r2 / XH;
         xh = r2 - y * XH;
         h = ((t * LZ + z) * LY + y) * XH + xh;
         pidx = 8 * sb + j;
@@ -1011,11 +1086,11 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         const uint32_t l = sb * SPB + ls;
         active = l < LZ * P;
         const uint32_t lu = active ? l : 0u;
-        z = lu / P;
+        z = BATCH ? fdiv(lu, a.dv.slab[(uint32_t)j < tr ? 1 : 0]) : lu / P;
         const uint32_t rem = lu - z * P;
-        t = t0 + rem / plane;
+        t = t0 + (BATCH ? fdiv(rem, a.dv.plane) : rem / plane);
         const uint32_t r2 = rem - (t - t0) * plane;
-        y = r2 / XH;
+        y = BATCH ? fdiv(r2, a.dv.xh) : r2 / XH;
         xh = r2 - y * XH;
         h = ((t * LZ + z) * LY + y) * XH + xh;
         pidx = 8 * sb + j;
@@ -1024,12 +1099,20 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         h = lb * SPB + ls;
         active = h < (uint32_t)g.vh;
         const uint32_t hu = active ? h : 0u;
-        xh = hu % XH;
-        uint32_t r = hu / XH;
-        y = r % LY;
-        r /= LY;
-        z = r % LZ;
-        t = r / LZ;
+        if constexpr (BATCH) {
+            const uint32_t r = fdiv(hu, a.dv.xh), r1 = fdiv(r, a.dv.ly);
+            xh = hu - r * XH;
+            y = r - r1 * LY;
+            t = fdiv(r1, a.dv.lz);
+            z = r1 - t * LZ;
+        } else {
+            xh = hu % XH;
+            uint32_t r = hu / XH;
+            y = r % LY;
+            r /= LY;
+            z = r % LZ;
+            t = r / LZ;
+        }
         pidx = lb;
     }
     double nrm = 0.0, nrm2 = 0.0;
@@ -1057,8 +1140,12 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
                 const int r = q == 0 ? rhs : rhs_d;
                 spinor<R> sf;
                 a.self.at(r).load((long)h, sf);
-                const double m = a.sign * a.op.mut[r];
-                const cx<R> Au = cx<R>{R(1), (R)m}, Ad = cx<R>{R(-1), (R)m};
+                R m;
+                if constexpr (BATCH)
+                    m = a.ec[r].m;
+                else
+                    m = (R)(a.sign * a.op.mut[r]);
+                const cx<R> Au = cx<R>{R(1), m}, Ad = cx<R>{R(-1), m};
                 spinor<R> &dst = q == 0 ? acc : acd;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
@@ -1158,14 +1245,14 @@ __global__ __launch_bounds__(HOP_BLOCK) void hop16_kernel(HopArgs<SP, L16R> a)
         // both K1 and K2); a batch's outputs are read again only after the
         // whole batch, so they are stored non-temporally
         if constexpr (ND) {
-            nd_mix2(a, acc, acd, rhs, rhs_d, (long)h);
-            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, false>(a, acc, rhs, (long)h);
-            nrm += hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, false>(a, acd, rhs_d, (long)h);
+            nd_mix2<BATCH>(a, acc, acd, rhs, rhs_d, (long)h);
+            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, false, BATCH>(a, acc, rhs, (long)h);
+            nrm += hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, false, BATCH>(a, acd, rhs_d, (long)h);
         } else if constexpr (TWO) {
-            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acc, rhs, (long)h);
-            if (two) nrm2 = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acd, rhs_d, (long)h);
+            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F, BATCH>(a, acc, rhs, (long)h);
+            if (two) nrm2 = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F, BATCH>(a, acd, rhs_d, (long)h);
         } else {
-            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F>(a, acc, rhs, (long)h);
+            nrm = hop_epilogue<SP, LK, SELF, NORM, EP, ND, BATCH, K2F, BATCH>(a, acc, rhs, (long)h);
         }
     }
     if (NORM) {
@@ -1334,6 +1421,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         if (cg->r.prec != in.prec || cg->p.prec != in.prec) return hipErrorInvalidValue;
         if (ep == EP_CG && cg->x.prec != (in.prec == P64 ? P64 : P32)) return hipErrorInvalidValue;
     }
+    static_assert(sizeof(HopArgs<SP, LK>) <= 4096, "kernel arguments are limited to 4 KB");
     HopArgs<SP, LK> a;
     a.g = g;
     a.out_par = out_par;
@@ -1358,6 +1446,21 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     if (ALL != hop_all_variants(in.prec, lk.fmt)) return hipErrorInvalidValue;  // tables out of step
     int variant = tu.variant;
     if (!ALL || !hop_variant_valid(g, variant)) variant = 0;
+    // the divisors and site-term table of a batched 16-bit launch of ntup tuples
+    auto batch16 = [&](int ntup) {
+        if constexpr (SP::coded && __is_same(LK, L16R)) {
+            a.dv = make_site_div(g, variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB, a.nblk, a.group,
+                                 ntup);
+            for (int i = 0; i < rl.n; i++) {
+                const int r = op.nd ? rl.idx[i] >> 1 : rl.idx[i];
+                if (r >= MAX_RHS) return false;
+                const double kap = op.kappa[r], m = sign * op.mut[r], e = op.nd ? op.eps[r] : 0.0;
+                const double c = op.nd ? kap * kap / (1.0 + m * m - e * e) : kap * kap / (1.0 + m * m);
+                a.ec[r] = EpiCoef{(float)c, (float)(c * m), (float)(c * e), (float)m, (float)e};
+            }
+        }
+        return true;
+    };
     if (op.nd) {
         // doublets: the two flavours of a site in a lane pair (RHS pairs 2d, 2d + 1 of rl)
         if (rl.n % 2) return hipErrorInvalidValue;
@@ -1373,6 +1476,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
         const int grp = tu.group > 0 ? tu.group : rhs_group(g, in.prec, rl.n);
         a.group = (grp + 1) / 2;
         if (a.group > ntup) a.group = ntup;
+        if (ntup > 1 && !batch16(ntup)) return hipErrorInvalidValue;
         a.epi = ep == EP_STORE ? epi : EPI_K2;
         const dim3 grid(a.nblk * ntup), block(HOP_BLOCK);
         const int ord = variant == 0 ? ORD_PLAIN : variant <= 2 ? ORD_ZSLAB : ORD_TSLAB;
@@ -1411,6 +1515,7 @@ hipError_t go(const Geom &g, int out_par, const FieldDesc &in, const FieldDesc &
     const int grp = tu.group > 0 ? tu.group : rhs_group(g, in.prec, rl.n);  // in RHS
     a.group = (grp + G - 1) / G;
     if (a.group > ntup) a.group = ntup;
+    if (rl.n > 1 && !batch16(ntup)) return hipErrorInvalidValue;
     dim3 grid(a.nblk * ntup), block(HOP_BLOCK);
     const bool s = epi != EPI_K1, n = partial != nullptr;
     if (s && !self.data) return hipErrorInvalidValue;

@@ -14,6 +14,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "fastdiv.h"
+
 namespace tmq {
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };  // same values as tmq_prec

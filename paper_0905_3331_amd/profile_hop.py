@@ -41,7 +41,7 @@ if ROOT not in sys.path:
 # sources that determine the hop kernels' memory traffic
 KERNEL_SOURCES = ("hop_impl.h", "hop.hip", "hop_f64.hip", "hop_f32.hip", "hop_f16.hip", "hop_b16.hip",
                   "hop16_f16.hip", "hop16_b16.hip",
-                  "fields.h", "spin.h", "views.h", "kernels.h", "devutil.h")
+                  "fields.h", "spin.h", "views.h", "kernels.h", "devutil.h", "fastdiv.h")
 
 
 def code_text(src: str) -> str:

@@ -118,6 +118,32 @@ def test_su3_two_row_reconstruction(spinlib):
         assert np.max(np.abs(third - u[2])) < 1e-15
 
 
+def test_fastdiv_multipliers(tmp_path):
+    """The 16-bit hop kernel decodes a site index by multiply-high divisions
+    (Granlund-Montgomery round-up multipliers).  Against plain integer division:
+    every divisor up to 4096 and the lattice-sized ones around powers of two,
+    numerators at random below 2^31 and at the quotient boundaries q d - 1, q d."""
+    out = tmp_path / "libfastdiv.so"
+    src = os.path.join(ROOT, "tests", "cpu_helpers", "fastdiv_check.cpp")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-o", str(out), src])
+    lib = ctypes.CDLL(str(out))
+    up = ctypes.POINTER(ctypes.c_uint32)
+    rng = np.random.default_rng(11)
+    divisors = list(range(1, 4097))
+    for p in range(12, 32):
+        divisors += [(1 << p) - 1, 1 << p, (1 << p) + 1, 3 << (p - 2), 5 << (p - 3)]
+    divisors += [int(v) for v in rng.integers(1, 1 << 26, 200)]
+    for d in [d for d in divisors if d <= 1 << 31]:  # the documented range
+        qmax = ((1 << 31) - 1) // d
+        qs = np.unique(np.concatenate([[0, 1, 2, qmax], rng.integers(0, qmax + 1, 16)]))
+        edge = np.concatenate([qs * d, qs * d - 1, qs * d + d - 1])
+        n = np.concatenate([rng.integers(0, 1 << 31, 64), edge])
+        n = n[(n >= 0) & (n < (1 << 31))].astype(np.uint32)
+        q = np.zeros_like(n)
+        lib.fastdiv_quotients(d, n.ctypes.data_as(up), q.ctypes.data_as(up), len(n))
+        assert np.array_equal(q, n // np.uint32(d)), d
+
+
 # ------------------------------------------------ hop block orders (host replay)
 # A replay of the hop kernel's map from (block, lane) to output site for each
 # block order, as written in hop_impl.h / hop.hip: every site of the parity is
