@@ -185,6 +185,33 @@ def test_nd_batch_maximum_size(tmq):
         lat.solve_nd_batch(ps + ps[:1], bs + bs[:1], o)
 
 
+@pytest.mark.parametrize("variant", range(5))
+def test_nd_batch16_block_orders(tmq, variant, monkeypatch):
+    """Batched 16-bit doublet launches (both flavours in a lane) decode blocks
+    and sites by multiply-high division and take the site terms of eq. (Dh)
+    from a host-side table; on a lattice with XCD slabs of two sizes, a forced
+    block order and a smaller last group, each doublet equals its solve alone
+    bit for bit."""
+    monkeypatch.setenv("TMQ_HOP_VARIANT", str(variant))
+    monkeypatch.setenv("TMQ_HOP_GROUP", "4")
+    dims = (10, 10, 4, 6)
+    U = synth.random_gauge(dims, eps=0.3, seed=302)
+    lat = tmq.Lattice(dims)  # a lattice of its own: the forced variant is read at creation
+    lat.load_gauge(U)
+    o = tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")
+    ps = [tmq.nd_params(KAPPA, mb, eb, THETA) for mb, eb in ((0.1105, 0.0935), (0.05, 0.02), (0.2, 0.15))]
+    bs = [dev(doublet(dims, 320 + 2 * k)) for k in range(3)]
+    xs, infos = lat.solve_nd_batch(ps, bs, o)
+    for k in range(3):
+        x1, i1 = lat.solve_nd(ps[k], bs[k], o)
+        assert torch.equal(x1, xs[k]), k
+        assert (i1.iters, i1.reliable_updates) == (infos[k].iters, infos[k].reliable_updates)
+        pk = ps[k]
+        res = oracle.true_residual_nd(U, host(bs[k]), host(xs[k]), KAPPA, pk.mubar_tilde, pk.epsbar_tilde, THETA)
+        assert infos[k].status == 0 and res <= 1e-10, (k, res)
+    lat.close()
+
+
 @pytest.mark.parametrize("sloppy", ["fp64", "fp32", "fp16"])
 def test_nd_batch_equals_alone(tmq, sloppy):
     dims = (8, 8, 6, 10)

@@ -637,6 +637,37 @@ def test_batch_rhs_per_lane(tmq, sloppy, rpl, monkeypatch):
     lat.close()
 
 
+@pytest.mark.parametrize("rpl", [1, 2])
+@pytest.mark.parametrize("variant", range(5))
+def test_batch16_block_orders(tmq, variant, rpl, monkeypatch):
+    """Batched 16-bit launches decode their block and site indices by
+    multiply-high division and take the site terms from a host-side table;
+    single-field launches divide in the lane.  On a lattice where T and LZ are
+    not multiples of 8 (XCD slabs of two sizes) and XH = 3, with a forced block
+    order and RHS groups whose last one is smaller, every right-hand side must
+    equal its solve alone bit for bit."""
+    monkeypatch.setenv("TMQ_HOP_VARIANT", str(variant))
+    monkeypatch.setenv("TMQ_HOP_RPL", str(rpl))
+    monkeypatch.setenv("TMQ_HOP_GROUP", str(2 * rpl))
+    dims = (10, 10, 4, 6)
+    U = synth.random_gauge(dims, seed=111)
+    lat = tmq.Lattice(dims)  # a lattice of its own: the forced variant is read at creation
+    lat.load_gauge(U)
+    ps = [tmq.params(0.1632, 0.003 + 0.004 * i, THETA) for i in range(5)]
+    bs = [dev(synth.gaussian_odd(dims, seed=60 + i)) for i in range(5)]
+    opts = tmq.solver_opts(tol=1e-10, sloppy="fp16", sloppy_link="fp16")
+    xs, infos = lat.solve_batch(ps, bs, opts)
+    for i in (0, 2, 4):
+        x1, i1 = lat.solve(ps[i], bs[i], opts)
+        assert torch.equal(x1, xs[i]), f"rhs {i} differs from its solve alone"
+        assert (i1.iters, i1.reliable_updates) == (infos[i].iters, infos[i].reliable_updates)
+    for i in range(5):
+        res = oracle.true_residual(U, host(bs[i]), host(xs[i]), 0.1632, ps[i].mu_tilde, THETA)
+        assert infos[i].status == 0 and res <= 1e-10, (i, res)
+    assert all(e["variant"] == variant for e in lat.tuning_report()["hop"] if e["spinor"] == "fp16")
+    lat.close()
+
+
 def test_batch_host_api_and_validation(tmq):
     dims = (4, 4, 4, 4)
     lat, U = lattice(tmq, dims, seed=106)
